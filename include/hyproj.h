@@ -1,0 +1,165 @@
+/*
+ * hyproj: hybrid CNN + Jacobi pressure projection on a 2D MAC grid, for
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The operation (arXiv 2109.09363, Sec. 2.2 and Sec. 3.3): given the
+ * intermediate velocity u* on a MAC grid with obstacle flags, solve the
+ * pressure Poisson equation (Eq. 3) and subtract the pressure gradient
+ * (Eq. 2) so that the mean |div u| over fluid cells falls below a user
+ * threshold (the hybrid criterion E_1 of Sec. 4.1).  The pressure is first
+ * predicted by a multi-scale CNN (Sec. 3.1) and then refined by Jacobi
+ * iterations (Sec. 2.2); plain Jacobi and Jacobi-preconditioned CG are the
+ * baselines.
+ *
+ * Grid conventions (all arrays row-major, x fastest, no padding):
+ *   cells      (ny, nx)      index j*nx + i, j = 0 is the bottom row
+ *   u faces    (ny, nx+1)    u[j*(nx+1) + i] is the x-face left of cell (i,j)
+ *   v faces    (ny+1, nx)    v[j*nx + i] is the y-face below cell (i,j)
+ *   flags      (ny, nx) u8   bit0 = solid obstacle cell,
+ *                            bit1 = the face below this row-0 cell is an inflow
+ *                                   face with a prescribed velocity
+ * The left, right and bottom domain edges are walls; the top edge is open
+ * (a ghost row of cells with pressure 0 above row ny-1).  Enclosed fluid
+ * pockets (no 4-connected path to the open top) are treated as solid.
+ *
+ * Ownership: the caller owns every device buffer, including the workspace
+ * (size from hyp_workspace_size).  The library allocates no device memory
+ * in any call.  A context holds host state only.  Calls are asynchronous on
+ * the given HIP stream; one context/workspace pair must not be used by two
+ * streams at once.
+ *
+ * Errors: a negative return value means the call was rejected before
+ * anything was enqueued (HYP_E*).  Conditions found on the device are
+ * reported in hyp_result.status (HYP_STATUS_*).
+ */
+#ifndef HYPROJ_H
+#define HYPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYP_VERSION 10000
+
+/* return codes */
+#define HYP_OK             0
+#define HYP_EINVAL        -1  /* null pointer, bad size or option */
+#define HYP_EUNSUPPORTED  -2  /* e.g. grid side not divisible by 2^(scales-1) */
+#define HYP_EWORKSPACE    -3  /* workspace too small */
+#define HYP_EHIP          -4  /* a HIP launch or API call failed */
+#define HYP_EINTERNAL     -5  /* unexpected host-side failure */
+#define HYP_ENOWEIGHTS    -6  /* CNN method requested without a network */
+
+/* device-side statuses (hyp_result.status) */
+#define HYP_STATUS_OK         0  /* threshold reached (or fixed_iters done) */
+#define HYP_STATUS_MAXITER    1  /* max_iters reached; last iterate returned */
+#define HYP_STATUS_NONFINITE  2  /* NaN/Inf in the residual; iterate returned */
+
+/* methods */
+#define HYP_METHOD_HYBRID  0  /* CNN initial guess, then Jacobi (Sec. 3.3) */
+#define HYP_METHOD_JACOBI  1  /* Jacobi from p_init or zero (Sec. 2.2) */
+#define HYP_METHOD_PCG     2  /* Jacobi-preconditioned CG from p_init or zero */
+#define HYP_METHOD_CNN     3  /* CNN prediction only, no iterations */
+
+/* CNN precision */
+#define HYP_PREC_FP32  0  /* FP32 activations/weights, FP32 MFMA */
+#define HYP_PREC_BF16  1  /* BF16 3x3 layers on MFMA with FP32 accumulation;
+                             1x1 output, pressure and solvers in FP32 */
+
+typedef struct hyp_ctx hyp_ctx;
+
+/* Multi-scale network shape.  scales in 1..5, channels in {16, 32, 64}. */
+typedef struct {
+  int32_t scales;
+  int32_t channels;
+  int32_t precision;  /* HYP_PREC_* */
+  int32_t reserved;
+} hyp_net_desc;
+
+typedef struct {
+  int32_t nx, ny;  /* cells */
+  double dx;       /* cell size */
+  double dt;       /* time step: p = rho0 * phi / dt */
+  double rho0;     /* reference density of Eq. (2) */
+} hyp_grid;
+
+typedef struct {
+  float* u;              /* (ny, nx+1) in/out: corrected in place */
+  float* v;              /* (ny+1, nx) in/out: corrected in place */
+  const float* rho;      /* (ny, nx) density; accepted, not read by the
+                            constant-coefficient operator of Eq. (3) */
+  const uint8_t* flags;  /* (ny, nx) input flags (bit0 solid, bit1 inflow) */
+  float* p;              /* (ny, nx) out: pressure p = rho0 * phi / dt */
+  const float* p_init;   /* nullable: warm start (as p, same scaling) for
+                            the JACOBI / PCG methods */
+} hyp_fields;
+
+typedef struct {
+  int32_t method;       /* HYP_METHOD_* */
+  int32_t max_iters;    /* cap on sweeps / CG iterations (>= 0) */
+  int32_t check_every;  /* test E_1 every k updates (>= 1) and at max_iters */
+  int32_t fixed_iters;  /* > 0: ignore the threshold, do exactly this many */
+  float omega;          /* Jacobi weight, 1 = the paper's undamped form */
+  int32_t reserved[3];
+} hyp_opts;
+
+/* Written by the device when the projection's last kernel completes. */
+typedef struct {
+  int32_t iters;       /* sweeps or CG iterations performed */
+  int32_t status;      /* HYP_STATUS_* */
+  double e1_init;      /* mean |div u*| over fluid cells before projection */
+  double e1_cnn;       /* mean |d - L phi0| of the initial guess */
+  double e1_final;     /* mean |div u| recomputed from the returned faces */
+  double einf_final;   /* max  |div u| recomputed from the returned faces */
+  double s;            /* CNN input scale sqrt(mean d^2) (0 without CNN) */
+  int32_t n_fluid;     /* fluid cells after the pocket fill */
+  int32_t reserved;
+} hyp_result;
+
+int hyp_version(void);
+const char* hyp_status_str(int code);
+
+/* Create a context.  `net` may be NULL (no CNN: JACOBI and PCG only).
+ * Host allocation only.  Returns HYP_EINVAL on a bad shape. */
+int hyp_create(hyp_ctx** out, const hyp_net_desc* net);
+int hyp_destroy(hyp_ctx* ctx);
+
+/* Number of float32 parameters of the context's network (0 without one). */
+int64_t hyp_param_count(const hyp_ctx* ctx);
+
+/* Point the context at caller-owned FP32 parameters on the device, in the
+ * packed layout: for each scale k = 0 (finest) .. S-1, four 3x3 layers as
+ * W[Cout][3][3][Cin] then bias[Cout] (Cin = 2 for the first layer: the
+ * normalised divergence and the solid mask; C after), then the 1x1 output
+ * as w[C] then bias[1].  The buffer is read at every projection and must
+ * stay valid; it is never copied.  n_params must equal hyp_param_count. */
+int hyp_set_weights(hyp_ctx* ctx, const float* dev_params, int64_t n_params);
+
+/* Workspace bytes for a grid (and the context's network).  The workspace
+ * holds the planned cell flags, the divergence, the solver state, the CNN
+ * activations and the reduction scratch. */
+int hyp_workspace_size(const hyp_ctx* ctx, const hyp_grid* g, size_t* bytes);
+
+/* Planning (once per geometry): pocket fill and neighbour structure of the
+ * flags into the workspace.  Must precede hyp_project on that workspace
+ * whenever the flags change.  Asynchronous on `stream`. */
+int hyp_plan(hyp_ctx* ctx, const hyp_grid* g, const uint8_t* flags,
+             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One projection (Eq. 2-3): enforce the boundary faces, divergence, initial
+ * guess, iterate until E_1 < threshold (strict; tested before the first
+ * update, every check_every updates and at max_iters), subtract the
+ * gradient, write p and the result.  `res` must be device memory or
+ * host-pinned memory; it is valid once `stream` has completed the call. */
+int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f,
+                double threshold, const hyp_opts* o, void* ws,
+                size_t ws_bytes, hipStream_t stream, hyp_result* res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYPROJ_H */

@@ -1,0 +1,148 @@
+"""Python binding of the hyproj C ABI: torch tensors in, raw device pointers
+and the current HIP stream out.  PyTorch supplies device memory and streams
+only; the projection itself runs in the HIP library."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class ProjectionResult:
+    iters: int
+    status: int
+    e1_init: float
+    e1_cnn: float
+    e1_final: float
+    einf_final: float
+    s: float
+    n_fluid: int
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {shape}, "
+                         f"got {t.dtype} {tuple(t.shape)}")
+
+
+class Projector:
+    """One context + workspace for a grid shape (and optionally a network).
+
+    The workspace is a caller-owned torch uint8 tensor; the library allocates
+    no device memory."""
+
+    def __init__(self, nx: int, ny: int, dx: float, dt: float = 1.0, rho0: float = 1.0,
+                 scales: int = 0, channels: int = 0, precision: str = "fp32", device=None):
+        self.lib = L.lib()
+        self.nx, self.ny = int(nx), int(ny)
+        self.grid = L.Grid(self.nx, self.ny, float(dx), float(dt), float(rho0))
+        self.device = torch.device("cuda" if device is None else device)
+        ctx = ctypes.c_void_p()
+        desc = None
+        if scales > 0:
+            desc = L.NetDesc(int(scales), int(channels), L.PRECISIONS[precision], 0)
+        L.check("hyp_create", self.lib.hyp_create(ctypes.byref(ctx), ctypes.byref(desc) if desc else None))
+        self.ctx = ctx
+        self.scales, self.channels, self.precision = scales, channels, precision
+        nbytes = ctypes.c_size_t()
+        L.check("hyp_workspace_size",
+                self.lib.hyp_workspace_size(self.ctx, ctypes.byref(self.grid), ctypes.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.res = torch.zeros(ctypes.sizeof(L.Result), dtype=torch.uint8, device=self.device)
+        self.params = None
+        self.planned = False
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.hyp_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    @property
+    def param_count(self) -> int:
+        return int(self.lib.hyp_param_count(self.ctx))
+
+    def set_dt(self, dt: float):
+        self.grid.dt = float(dt)
+
+    def set_weights(self, params: torch.Tensor):
+        _need(params, torch.float32, (self.param_count,), "params")
+        L.check("hyp_set_weights", self.lib.hyp_set_weights(self.ctx, _ptr(params), params.numel()))
+        self.params = params  # keep alive: the library reads it at every call
+
+    def plan(self, flags: torch.Tensor):
+        _need(flags, torch.uint8, (self.ny, self.nx), "flags")
+        L.check("hyp_plan", self.lib.hyp_plan(self.ctx, ctypes.byref(self.grid), _ptr(flags),
+                                              _ptr(self.ws), self.ws.numel(), _stream()))
+        self.planned = True
+
+    def project_async(self, u, v, flags, p, threshold: float, method: str = "hybrid",
+                      max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
+                      omega: float = 1.0, rho=None, p_init=None):
+        """Enqueue one projection on the current stream; u, v corrected in
+        place, p written.  Read the result with `result()` after a sync."""
+        nx, ny = self.nx, self.ny
+        _need(u, torch.float32, (ny, nx + 1), "u")
+        _need(v, torch.float32, (ny + 1, nx), "v")
+        _need(flags, torch.uint8, (ny, nx), "flags")
+        _need(p, torch.float32, (ny, nx), "p")
+        if rho is not None:
+            _need(rho, torch.float32, (ny, nx), "rho")
+        if p_init is not None:
+            _need(p_init, torch.float32, (ny, nx), "p_init")
+        if not self.planned:
+            raise RuntimeError("call plan(flags) before project")
+        f = L.Fields(_ptr(u), _ptr(v), _ptr(rho), _ptr(flags), _ptr(p), _ptr(p_init))
+        o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
+                   float(omega), (ctypes.c_int32 * 3)())
+        L.check("hyp_project", self.lib.hyp_project(
+            self.ctx, ctypes.byref(self.grid), ctypes.byref(f), float(threshold), ctypes.byref(o),
+            _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
+
+    def result(self) -> ProjectionResult:
+        raw = bytes(self.res.cpu().numpy().tobytes())
+        r = L.Result.from_buffer_copy(raw)
+        return ProjectionResult(r.iters, r.status, r.e1_init, r.e1_cnn, r.e1_final,
+                                r.einf_final, r.s, r.n_fluid)
+
+
+_CACHE: dict = {}
+
+
+def project(u, v, rho, flags, threshold: float, *, dx: float, dt: float = 1.0, rho0: float = 1.0,
+            method: str = "hybrid", params=None, scales: int = 0, channels: int = 0,
+            precision: str = "fp32", **opts):
+    """project(u, v, rho, flags, threshold) -> (p, u, v, iters).
+
+    u, v are corrected in place (and returned); p is a new tensor.  A context
+    and workspace are cached per (shape, network) and re-planned per call."""
+    ny, nx = flags.shape
+    key = (nx, ny, scales, channels, precision, u.device)
+    pr = _CACHE.get(key)
+    if pr is None:
+        pr = Projector(nx, ny, dx, dt, rho0, scales, channels, precision, device=u.device)
+        _CACHE[key] = pr
+    pr.grid.dx, pr.grid.dt, pr.grid.rho0 = float(dx), float(dt), float(rho0)
+    if params is not None:
+        pr.set_weights(params)
+    pr.plan(flags)
+    p = torch.empty((ny, nx), dtype=torch.float32, device=u.device)
+    pr.project_async(u, v, flags, p, threshold, method=method, rho=rho, **opts)
+    res = pr.result()
+    return p, u, v, res.iters

@@ -1,0 +1,222 @@
+// C-ABI entry points of hyproj: context, workspace layout, planning and the
+// projection pipeline (boundary faces + divergence, initial guess, solver,
+// gradient correction).  Host code only; every step of the projection runs
+// in the kernels of stencil.hip, solvers.hip and cnn.hip.
+#include <new>
+#include <string.h>
+
+#include "../../include/hyproj.h"
+#include "internal.h"
+
+struct hyp_ctx {
+  hyp::NetShape net;
+  hyp::Device dev;
+  const float* params = nullptr;
+  int64_t n_params_set = 0;
+};
+
+namespace hyp {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int64_t cnn_param_count(int S, int C) {
+  return (int64_t)S * ((int64_t)C * 9 * 2 + C + 3 * ((int64_t)C * 9 * C + C) + C + 1);
+}
+
+WsLayout make_layout(int nx, int ny, const NetShape& net) {
+  WsLayout L;
+  const size_t n = (size_t)nx * ny;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  L.nblocks_stream = (int)((n + kStreamBlock - 1) / kStreamBlock);
+  L.scalars = take(sizeof(Scalars));
+  L.partial = take(sizeof(double) * 4 * kMaxCoopBlocks);
+  L.blockpart = take(sizeof(double) * 2 * (size_t)L.nblocks_stream);
+  L.cell = take(n);
+  L.reach = take(n);
+  L.d = take(4 * n);
+  L.phi = take(4 * n);
+  L.exch = take(8 * n);
+  if (net.scales > 0) {
+    size_t px = 0;
+    for (int k = 0; k < net.scales; ++k) {
+      L.sc_h[k] = ny >> k;
+      L.sc_w[k] = nx >> k;
+      L.sc_off_px[k] = px;
+      px += (size_t)L.sc_h[k] * L.sc_w[k];
+    }
+    L.total_px = px;
+    const size_t act_elt = net.precision == HYP_PREC_BF16 ? 2 : 4;
+    L.cnn_in = take(px * 2 * act_elt);
+    L.cnn_act0 = take(px * net.channels * act_elt);
+    L.cnn_act1 = take(px * net.channels * act_elt);
+    L.cnn_y = take(px * 4);
+    L.cnn_t = take(px * 4);
+    L.cnn_w = take((size_t)cnn_param_count(net.scales, net.channels) * act_elt);
+  }
+  L.total = o;
+  return L;
+}
+
+Ws ws_view(void* base, const WsLayout& L) {
+  char* b = (char*)base;
+  Ws w;
+  w.sc = (Scalars*)(b + L.scalars);
+  w.partial = (double*)(b + L.partial);
+  w.blockpart = (double*)(b + L.blockpart);
+  w.cell = (uint8_t*)(b + L.cell);
+  w.reach = (uint8_t*)(b + L.reach);
+  w.d = (float*)(b + L.d);
+  w.phi = (float*)(b + L.phi);
+  w.exch = (float*)(b + L.exch);
+  w.pcg = nullptr;
+  w.cnn_in = L.cnn_in ? b + L.cnn_in : nullptr;
+  w.cnn_act0 = L.cnn_act0 ? b + L.cnn_act0 : nullptr;
+  w.cnn_act1 = L.cnn_act1 ? b + L.cnn_act1 : nullptr;
+  w.cnn_y = L.cnn_y ? (float*)(b + L.cnn_y) : nullptr;
+  w.cnn_t = L.cnn_t ? (float*)(b + L.cnn_t) : nullptr;
+  w.cnn_w = L.cnn_w ? b + L.cnn_w : nullptr;
+  return w;
+}
+
+}  // namespace hyp
+
+using namespace hyp;
+
+static int grid_ok(const hyp_grid* g) {
+  if (!g) return 0;
+  if (g->nx < 2 || g->ny < 2 || g->nx > 16384 || g->ny > 16384) return 0;
+  if ((int64_t)g->nx * g->ny > (int64_t)1 << 28) return 0;
+  if (!(g->dx > 0.0) || !(g->dt > 0.0) || !(g->rho0 > 0.0)) return 0;
+  return 1;
+}
+
+extern "C" {
+
+int hyp_version(void) { return HYP_VERSION; }
+
+const char* hyp_status_str(int code) {
+  switch (code) {
+    case HYP_OK: return "ok";
+    case HYP_EINVAL: return "invalid argument";
+    case HYP_EUNSUPPORTED: return "unsupported shape or option";
+    case HYP_EWORKSPACE: return "workspace too small";
+    case HYP_EHIP: return "HIP error";
+    case HYP_EINTERNAL: return "internal error";
+    case HYP_ENOWEIGHTS: return "CNN method without network weights";
+    default: return "unknown";
+  }
+}
+
+int hyp_create(hyp_ctx** out, const hyp_net_desc* net) {
+  if (!out) return HYP_EINVAL;
+  *out = nullptr;
+  NetShape ns;
+  if (net) {
+    if (net->scales < 1 || net->scales > 5) return HYP_EINVAL;
+    if (net->channels != 16 && net->channels != 32 && net->channels != 64) return HYP_EINVAL;
+    if (net->precision != HYP_PREC_FP32 && net->precision != HYP_PREC_BF16) return HYP_EINVAL;
+    ns.scales = net->scales;
+    ns.channels = net->channels;
+    ns.precision = net->precision;
+  }
+  hyp_ctx* c = new (std::nothrow) hyp_ctx;
+  if (!c) return HYP_EINTERNAL;
+  c->net = ns;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int cu = 0, lds = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+      c->dev.cu = cu;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        lds > 0)
+      c->dev.max_lds = lds;
+  }
+  *out = c;
+  return HYP_OK;
+}
+
+int hyp_destroy(hyp_ctx* ctx) {
+  delete ctx;
+  return HYP_OK;
+}
+
+int64_t hyp_param_count(const hyp_ctx* ctx) {
+  if (!ctx || ctx->net.scales == 0) return 0;
+  return cnn_param_count(ctx->net.scales, ctx->net.channels);
+}
+
+int hyp_set_weights(hyp_ctx* ctx, const float* dev_params, int64_t n_params) {
+  if (!ctx || !dev_params) return HYP_EINVAL;
+  if (ctx->net.scales == 0) return HYP_ENOWEIGHTS;
+  if (n_params != hyp_param_count(ctx)) return HYP_EINVAL;
+  ctx->params = dev_params;
+  ctx->n_params_set = n_params;
+  return HYP_OK;
+}
+
+int hyp_workspace_size(const hyp_ctx* ctx, const hyp_grid* g, size_t* bytes) {
+  if (!ctx || !bytes || !grid_ok(g)) return HYP_EINVAL;
+  *bytes = make_layout(g->nx, g->ny, ctx->net).total;
+  return HYP_OK;
+}
+
+int hyp_plan(hyp_ctx* ctx, const hyp_grid* g, const uint8_t* flags, void* ws, size_t ws_bytes,
+             hipStream_t stream) {
+  if (!ctx || !flags || !ws || !grid_ok(g)) return HYP_EINVAL;
+  const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
+  if (ws_bytes < L.total) return HYP_EWORKSPACE;
+  const Ws w = ws_view(ws, L);
+  if (run_plan(ctx->dev, g->nx, g->ny, flags, w, stream) != hipSuccess) return HYP_EHIP;
+  return HYP_OK;
+}
+
+int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double threshold,
+                const hyp_opts* o, void* ws, size_t ws_bytes, hipStream_t stream,
+                hyp_result* res) {
+  if (!ctx || !f || !o || !ws || !res || !grid_ok(g)) return HYP_EINVAL;
+  if (!f->u || !f->v || !f->flags || !f->p) return HYP_EINVAL;
+  if (o->method < HYP_METHOD_HYBRID || o->method > HYP_METHOD_CNN) return HYP_EINVAL;
+  if (o->max_iters < 0 || o->check_every < 1 || o->fixed_iters < 0) return HYP_EINVAL;
+  if (!(threshold >= 0.0)) return HYP_EINVAL;
+  const bool use_cnn = o->method == HYP_METHOD_HYBRID || o->method == HYP_METHOD_CNN;
+  if (use_cnn) {
+    if (ctx->net.scales == 0 || !ctx->params) return HYP_ENOWEIGHTS;
+    const int m = 1 << (ctx->net.scales - 1);
+    if (g->nx % m || g->ny % m) return HYP_EUNSUPPORTED;
+  }
+  const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
+  if (ws_bytes < L.total) return HYP_EWORKSPACE;
+  const Ws w = ws_view(ws, L);
+  const int nx = g->nx, ny = g->ny;
+  if (run_div(nx, ny, g->dx, f->u, f->v, w, L.nblocks_stream, stream) != hipSuccess) return HYP_EHIP;
+  if (use_cnn) {
+    if (run_cnn(ctx->net, L, nx, ny, g->dx, ctx->params, w, stream) != hipSuccess) return HYP_EHIP;
+  } else {
+    if (run_init_phi(nx, ny, f->p_init, g->dt / g->rho0, w, stream) != hipSuccess) return HYP_EHIP;
+  }
+  hipError_t e = hipSuccess;
+  switch (o->method) {
+    case HYP_METHOD_HYBRID:
+    case HYP_METHOD_JACOBI:
+      e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,
+                     o->fixed_iters, w, stream);
+      break;
+    case HYP_METHOD_PCG:
+      e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
+                  o->fixed_iters, w, stream);
+      break;
+    case HYP_METHOD_CNN:
+      // no sweeps: a zero-length Jacobi pass records E_1 of the prediction
+      e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, w, stream);
+      break;
+  }
+  if (e == hipErrorInvalidValue) return HYP_EUNSUPPORTED;
+  if (e != hipSuccess) return HYP_EHIP;
+  if (run_grad_and_finish(nx, ny, g->dx, g->rho0 / g->dt, f->u, f->v, f->p, w, L.nblocks_stream,
+                          res, stream) != hipSuccess)
+    return HYP_EHIP;
+  return HYP_OK;
+}
+
+}  // extern "C"

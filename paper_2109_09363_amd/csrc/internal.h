@@ -1,0 +1,86 @@
+// Internal declarations of the hyproj library: workspace layout and the
+// launch wrappers that the C-ABI entry points call.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hyp {
+
+// Device-resident scalars of one projection (lives in the workspace).
+struct Scalars {
+  double sum_abs_d;   // sum over fluid cells of |d|
+  double sum_d2;      // sum over fluid cells of d^2
+  double e1_init;     // sum_abs_d / nF
+  double s;           // sqrt(sum_d2 / nF): CNN input scale
+  double e1_cnn;      // E_1 of the initial guess
+  double e1_solve;    // E_1 of the returned iterate as the solver saw it
+  int32_t nF;         // fluid cells after the pocket fill
+  int32_t iters;
+  int32_t status;
+  int32_t plan_rounds;
+  unsigned bar;       // grid-barrier counter (zeroed before each launch)
+  unsigned pad[3];
+};
+
+constexpr int kMaxCoopBlocks = 1024;   // partial-sum slots per parity
+constexpr int kStreamBlock = 256;      // threads of the streaming kernels
+
+struct NetShape {
+  int scales = 0, channels = 0, precision = 0;
+};
+
+// Byte offsets into the caller's workspace (all 256-byte aligned).
+struct WsLayout {
+  size_t cell = 0, d = 0, phi = 0, exch = 0, blockpart = 0, partial = 0,
+         scalars = 0, reach = 0, pcg = 0;
+  size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0;
+  size_t total = 0;
+  int nblocks_stream = 0;
+  // per-scale offsets (elements) into the CNN buffers
+  int sc_h[6] = {0}, sc_w[6] = {0};
+  size_t sc_off_px[6] = {0};  // pixel offset of scale k in the concatenated pyramid
+  size_t total_px = 0;
+};
+
+WsLayout make_layout(int nx, int ny, const NetShape& net);
+
+// Views of the workspace for one grid.
+struct Ws {
+  uint8_t* cell;
+  float* d;
+  float* phi;
+  float* exch;        // 2 x nx*ny (halo exchange ping-pong)
+  double* blockpart;  // streaming-kernel block partials
+  double* partial;    // 2 x kMaxCoopBlocks x 4 cooperative partials
+  Scalars* sc;
+  uint8_t* reach;
+  float* pcg;         // PCG scratch
+  void* cnn_in; void* cnn_act0; void* cnn_act1; float* cnn_y; float* cnn_t; void* cnn_w;
+};
+Ws ws_view(void* base, const WsLayout& L);
+
+struct Device {
+  int cu = 256;           // compute units
+  int max_lds = 65536;    // LDS bytes per work-group
+};
+
+// ---- launch wrappers (return hipSuccess or the first error) ----
+hipError_t run_plan(const Device& dev, int nx, int ny, const uint8_t* flags, const Ws& w,
+                    hipStream_t s);
+hipError_t run_div(int nx, int ny, double dx, float* u, float* v, const Ws& w,
+                   int nblocks, hipStream_t s);
+hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const Ws& w,
+                        hipStream_t s);
+hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
+                      int max_iters, int check_every, int fixed_iters, const Ws& w,
+                      hipStream_t s);
+hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
+                   int check_every, int fixed_iters, const Ws& w, hipStream_t s);
+hipError_t run_grad_and_finish(int nx, int ny, double dx, double p_scale, float* u, float* v,
+                               float* p, const Ws& w, int nblocks, void* res,
+                               hipStream_t s);
+hipError_t run_cnn(const NetShape& net, const WsLayout& L, int nx, int ny, double dx,
+                   const float* params, const Ws& w, hipStream_t s);
+
+}  // namespace hyp

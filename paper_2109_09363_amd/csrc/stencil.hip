@@ -1,0 +1,308 @@
+// Streaming stencil kernels of the projection: planner (pocket fill and
+// neighbour bits), boundary faces + divergence, initial guess, gradient
+// correction (Eq. 2) and the final divergence check.
+#include "common.h"
+#include "internal.h"
+#include "../../include/hyproj.h"
+
+namespace hyp {
+
+// ---------------------------------------------------------------------------
+// Planner.  State per cell in `reach`: 0 solid/outside, 1 fluid not yet
+// linked to the open top, 2 fluid linked.  Seeds are the fluid cells of the
+// top row; a cooperative flood fill over 32x32 tiles propagates in LDS until
+// no work-group changes a cell in a whole round.
+// ---------------------------------------------------------------------------
+constexpr int PT = 32;
+constexpr int PE = PT + 2;
+
+__global__ __launch_bounds__(256) void plan_init(int nx, int ny, const uint8_t* __restrict__ flags,
+                                                 uint8_t* __restrict__ reach, Scalars* sc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) {
+    sc->bar = 0;
+    sc->nF = 0;
+    sc->plan_rounds = 0;
+  }
+  if (c >= nx * ny) return;
+  const int j = c / nx;
+  const bool solid = flags[c] & 1;
+  reach[c] = solid ? 0 : (j == ny - 1 ? 2 : 1);
+}
+
+__global__ __launch_bounds__(256) void plan_flood(int nx, int ny, uint8_t* reach, double* partial,
+                                                  Scalars* sc, int ntx, int nty,
+                                                  unsigned max_rounds) {
+  __shared__ uint8_t s[PE * PE];
+  __shared__ int changed;
+  __shared__ double red[4];
+  const int G = gridDim.x;
+  const int ntiles = ntx * nty;
+  unsigned round = 0;
+  for (;;) {
+    double my_changes = 0.0;
+    for (int t = blockIdx.x; t < ntiles; t += G) {
+      const int x0 = (t % ntx) * PT, y0 = (t / ntx) * PT;
+      for (int c = threadIdx.x; c < PE * PE; c += blockDim.x) {
+        const int gx = x0 - 1 + c % PE, gy = y0 - 1 + c / PE;
+        uint8_t st = 0;
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) st = reach[gy * nx + gx];
+        s[c] = st;
+      }
+      __syncthreads();
+      for (int pass = 0; pass < PT * PT; ++pass) {  // each pass marks >= 1 cell or ends
+        if (threadIdx.x == 0) changed = 0;
+        __syncthreads();
+        for (int c = threadIdx.x; c < PT * PT; c += blockDim.x) {
+          const int idx = (1 + c / PT) * PE + 1 + c % PT;
+          if (s[idx] == 1 && (s[idx - 1] == 2 || s[idx + 1] == 2 || s[idx - PE] == 2 ||
+                              s[idx + PE] == 2)) {
+            s[idx] = 2;
+            changed = 1;
+            my_changes += 1.0;
+          }
+        }
+        __syncthreads();
+        const bool any = changed != 0;
+        __syncthreads();
+        if (!any) break;
+      }
+      for (int c = threadIdx.x; c < PT * PT; c += blockDim.x) {
+        const int gx = x0 + c % PT, gy = y0 + c / PT;
+        if (gx < nx && gy < ny) reach[gy * nx + gx] = s[(1 + c / PT) * PE + 1 + c % PT];
+      }
+      __syncthreads();
+    }
+    const double tot_local = block_sum(my_changes, red);
+    double* part = partial + (round & 1) * kMaxCoopBlocks;
+    if (threadIdx.x == 0) part[blockIdx.x] = tot_local;
+    ++round;
+    grid_barrier(&sc->bar, round * (unsigned)G);
+    const double tot = sum_partials(part, G, red);
+    if (tot == 0.0 || round >= max_rounds) break;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->plan_rounds = (int)round;
+}
+
+__global__ __launch_bounds__(256) void plan_finalize(int nx, int ny, const uint8_t* __restrict__ flags,
+                                                     const uint8_t* __restrict__ reach,
+                                                     uint8_t* __restrict__ cell, Scalars* sc) {
+  __shared__ double red[4];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  double fl_count = 0.0;
+  if (c < nx * ny) {
+    const int i = c % nx, j = c / nx;
+    const bool fl = reach[c] == 2;
+    uint8_t out = fl ? 0 : C_SOLID;
+    if (fl) {
+      if (i + 1 < nx && reach[c + 1] == 2) out |= C_E;
+      if (i > 0 && reach[c - 1] == 2) out |= C_W;
+      if (j + 1 >= ny || reach[c + nx] == 2) out |= C_N;
+      if (j > 0 && reach[c - nx] == 2) out |= C_S;
+      if (j == 0 && (flags[c] & 2)) out |= C_INFLOW;
+      fl_count = 1.0;
+    }
+    cell[c] = out;
+  }
+  const double n = block_sum(fl_count, red);
+  if (threadIdx.x == 0 && n > 0.0) atomicAdd(&sc->nF, (int)n);
+}
+
+hipError_t run_plan(const Device& dev, int nx, int ny, const uint8_t* flags, const Ws& w,
+                    hipStream_t s) {
+  const int n = nx * ny;
+  const int nb = (n + 255) / 256;
+  plan_init<<<nb, 256, 0, s>>>(nx, ny, flags, w.reach, w.sc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int ntx = (nx + PT - 1) / PT, nty = (ny + PT - 1) / PT;
+  int G = ntx * nty;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, plan_flood, 256, 0);
+  if (e != hipSuccess) return e;
+  const int cap = per_cu * dev.cu;
+  if (G > cap) G = cap;
+  if (G > kMaxCoopBlocks) G = kMaxCoopBlocks;
+  unsigned max_rounds = (unsigned)n + 2u;
+  int nx_ = nx, ny_ = ny;
+  uint8_t* reach = w.reach;
+  double* partial = w.partial;
+  Scalars* sc = w.sc;
+  int ntx_ = ntx, nty_ = nty;
+  void* args[] = {&nx_, &ny_, &reach, &partial, &sc, &ntx_, &nty_, &max_rounds};
+  e = hipLaunchCooperativeKernel((const void*)plan_flood, dim3(G), dim3(256), args, 0, s);
+  if (e != hipSuccess) return e;
+  plan_finalize<<<nb, 256, 0, s>>>(nx, ny, flags, w.reach, w.cell, w.sc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Boundary faces + divergence (forward differences) + FP64 sums of |d| and
+// d^2 over fluid cells.  Each thread owns one cell and writes its west and
+// south faces (plus the east wall face of the last column and the open top
+// face of the last row).  A cell reads its east/north faces, which their
+// owners may rewrite concurrently with the identical masked value.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void div_kernel(int nx, int ny, float inv_dx,
+                                                  const uint8_t* __restrict__ cell, float* u,
+                                                  float* v, float* __restrict__ d,
+                                                  double* __restrict__ blockpart, Scalars* sc) {
+  __shared__ double red[4];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) sc->bar = 0;
+  double a = 0.0, q = 0.0;
+  if (c < nx * ny) {
+    const int i = c % nx, j = c / nx, U = nx + 1;
+    const uint8_t ci = cell[c];
+    const bool fl = !(ci & C_SOLID);
+    float uw = u[j * U + i], ue = u[j * U + i + 1];
+    float vs = v[j * nx + i], vn = v[(j + 1) * nx + i];
+    uw = (fl && (ci & C_W)) ? uw : 0.f;
+    ue = (fl && (ci & C_E)) ? ue : 0.f;
+    vn = (fl && (ci & C_N)) ? vn : 0.f;
+    vs = (j == 0) ? ((fl && (ci & C_INFLOW)) ? vs : 0.f) : ((fl && (ci & C_S)) ? vs : 0.f);
+    u[j * U + i] = uw;
+    v[j * nx + i] = vs;
+    if (i == nx - 1) u[j * U + nx] = 0.f;
+    if (j == ny - 1) v[ny * nx + i] = vn;
+    const float dv = fl ? ((ue - uw) + (vn - vs)) * inv_dx : 0.f;
+    d[c] = dv;
+    a = fabs((double)dv);
+    q = (double)dv * (double)dv;
+  }
+  a = block_sum(a, red);
+  q = block_sum(q, red);
+  if (threadIdx.x == 0) {
+    blockpart[2 * blockIdx.x] = a;
+    blockpart[2 * blockIdx.x + 1] = q;
+  }
+}
+
+__global__ __launch_bounds__(256) void div_finish(int nblocks, const double* __restrict__ blockpart,
+                                                  Scalars* sc) {
+  __shared__ double red[4];
+  double a = 0.0, q = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    a += blockpart[2 * b];
+    q += blockpart[2 * b + 1];
+  }
+  a = block_sum(a, red);
+  q = block_sum(q, red);
+  if (threadIdx.x == 0) {
+    const int nF = sc->nF;
+    sc->sum_abs_d = a;
+    sc->sum_d2 = q;
+    sc->e1_init = nF > 0 ? a / nF : 0.0;
+    sc->s = nF > 0 ? sqrt(q / nF) : 0.0;
+    sc->e1_cnn = sc->e1_init;
+    sc->iters = 0;
+    sc->status = 0;
+  }
+}
+
+hipError_t run_div(int nx, int ny, double dx, float* u, float* v, const Ws& w, int nblocks,
+                   hipStream_t s) {
+  div_kernel<<<nblocks, 256, 0, s>>>(nx, ny, (float)(1.0 / dx), w.cell, u, v, w.d, w.blockpart,
+                                     w.sc);
+  div_finish<<<1, 256, 0, s>>>(nblocks, w.blockpart, w.sc);
+  return hipGetLastError();
+}
+
+// phi = scale * p_init on fluid cells (0 elsewhere), or phi = 0.
+__global__ __launch_bounds__(256) void init_phi_kernel(int n, const float* __restrict__ p_init,
+                                                       float scale, const uint8_t* __restrict__ cell,
+                                                       float* __restrict__ phi) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const bool fl = !(cell[c] & C_SOLID);
+  phi[c] = (fl && p_init) ? p_init[c] * scale : 0.f;
+}
+
+hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const Ws& w,
+                        hipStream_t s) {
+  const int n = nx * ny;
+  init_phi_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, p_init, (float)scale, w.cell, w.phi);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gradient correction, Eq. (2): each open face between two non-solid cells
+// (and each open top face, ghost phi = 0) loses (phi_R - phi_L)/dx.  Each
+// thread rewrites only the faces it owns, so no face is read after another
+// thread's update.  p = rho0 phi / dt.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void grad_kernel(int nx, int ny, float inv_dx, float p_scale,
+                                                   const uint8_t* __restrict__ cell,
+                                                   const float* __restrict__ phi, float* u,
+                                                   float* v, float* __restrict__ p) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nx * ny) return;
+  const int i = c % nx, j = c / nx, U = nx + 1;
+  const uint8_t ci = cell[c];
+  const bool fl = !(ci & C_SOLID);
+  const float pc = phi[c];
+  if (fl && (ci & C_W)) u[j * U + i] -= (pc - phi[c - 1]) * inv_dx;
+  if (fl && (ci & C_S)) v[j * nx + i] -= (pc - phi[c - nx]) * inv_dx;
+  if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= (0.f - pc) * inv_dx;
+  p[c] = fl ? pc * p_scale : 0.f;
+}
+
+// Divergence of the returned faces: FP64 sum of |div| and max |div|.
+__global__ __launch_bounds__(256) void check_kernel(int nx, int ny, float inv_dx,
+                                                    const uint8_t* __restrict__ cell,
+                                                    const float* __restrict__ u,
+                                                    const float* __restrict__ v,
+                                                    double* __restrict__ blockpart) {
+  __shared__ double red[4];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  double a = 0.0;
+  if (c < nx * ny) {
+    const int i = c % nx, j = c / nx, U = nx + 1;
+    if (!(cell[c] & C_SOLID)) {
+      const float dv = ((u[j * U + i + 1] - u[j * U + i]) + (v[(j + 1) * nx + i] - v[j * nx + i])) * inv_dx;
+      a = fabs((double)dv);
+    }
+  }
+  const double sum = block_sum(a, red);
+  const double mx = block_max(a, red);
+  if (threadIdx.x == 0) {
+    blockpart[2 * blockIdx.x] = sum;
+    blockpart[2 * blockIdx.x + 1] = mx;
+  }
+}
+
+__global__ __launch_bounds__(256) void finish_kernel(int nblocks, const double* __restrict__ blockpart,
+                                                     const Scalars* sc, hyp_result* res) {
+  __shared__ double red[4];
+  double a = 0.0, m = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    a += blockpart[2 * b];
+    m = fmax(m, blockpart[2 * b + 1]);
+  }
+  a = block_sum(a, red);
+  m = block_max(m, red);
+  if (threadIdx.x == 0) {
+    hyp_result r;
+    r.iters = sc->iters;
+    r.status = sc->status;
+    r.e1_init = sc->e1_init;
+    r.e1_cnn = sc->e1_cnn;
+    r.e1_final = sc->nF > 0 ? a / sc->nF : 0.0;
+    r.einf_final = m;
+    r.s = sc->s;
+    r.n_fluid = sc->nF;
+    r.reserved = 0;
+    *res = r;
+  }
+}
+
+hipError_t run_grad_and_finish(int nx, int ny, double dx, double p_scale, float* u, float* v,
+                               float* p, const Ws& w, int nblocks, void* res, hipStream_t s) {
+  const float inv_dx = (float)(1.0 / dx);
+  grad_kernel<<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, (float)p_scale, w.cell, w.phi, u, v, p);
+  check_kernel<<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, w.cell, u, v, w.blockpart);
+  finish_kernel<<<1, 256, 0, s>>>(nblocks, w.blockpart, w.sc, (hyp_result*)res);
+  return hipGetLastError();
+}
+
+}  // namespace hyp

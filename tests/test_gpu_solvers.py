@@ -1,0 +1,167 @@
+"""GPU parity of the stencil path (planner, divergence, Jacobi, PCG, gradient
+correction) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import grid as G
+from oracle import solve as SV
+from oracle import project as PR
+from tests.gpu_util import gpu_project, f32, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def plume_state(n, seed, n_obs, ny=None, kind="mixed"):
+    sc = scenes.plume_scene(n, seed=seed, n_obstacles=n_obs, ny=ny)
+    u, v = scenes.random_faces(sc.nx, sc.ny, seed, kind=kind)
+    return sc, f32(u), f32(v)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def pocket_mask(nx, ny, seed, p=0.33):
+    rng = np.random.default_rng(seed)
+    flags = (rng.random((ny, nx)) < p).astype(np.uint8)
+    flags[0, nx // 3: 2 * nx // 3] |= 2
+    return flags
+
+
+@pytest.mark.parametrize("nx,ny,seed", [(40, 30, 0), (64, 64, 1), (96, 33, 2), (130, 70, 3)])
+def test_plan_and_faces_bit_exact(nx, ny, seed):
+    # random masks with many enclosed pockets: face masking, fluid count and
+    # the zero pressure on solids pin the planner exactly
+    say("plan", nx, ny, seed)
+    flags = pocket_mask(nx, ny, seed)
+    u, v = scenes.random_faces(nx, ny, seed, kind="white")
+    u, v = f32(u), f32(v)
+    g = gpu_project(flags, u, v, 1.0 / nx, thr=0.0, method="jacobi", fixed_iters=3)
+    P = G.plan(flags)
+    assert g["res"].n_fluid == P.nF
+    ou, ov = G.enforce_bc(P, u, v)
+    # faces that are not corrected (closed or inflow) are bit-exact
+    assert np.array_equal(g["u"][~P.uopen], ou[~P.uopen])
+    assert np.array_equal(g["v"][0], ov[0])
+    assert np.all(g["p"][~P.fluid] == 0)
+    assert P.nF < nx * ny  # the masks do contain solids
+
+
+@pytest.mark.parametrize("n,seed,nobs", [(64, 0, 0), (256, 1, 3), (512, 2, 3)])
+def test_divergence_and_init_error(n, seed, nobs):
+    say("div", n, seed)
+    sc, u, v = plume_state(n, seed, nobs)
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="jacobi", fixed_iters=1)
+    P = G.plan(sc.flags)
+    ou, ov = G.enforce_bc(P, u, v)
+    d = G.divergence(P, ou, ov, sc.dx)
+    assert g["res"].e1_init == pytest.approx(G.e1(P, d), rel=2e-6)
+
+
+@pytest.mark.parametrize("nx,ny,k,omega,seed", [
+    (64, 64, 1, 1.0, 0), (64, 64, 9, 1.0, 1), (100, 70, 17, 0.8, 2), (256, 256, 50, 1.0, 3),
+    (512, 512, 64, 1.0, 4), (48, 200, 23, 0.9, 5)])
+def test_jacobi_fixed_sweeps_parity(nx, ny, k, omega, seed):
+    say("jacobi fixed", nx, ny, k, omega)
+    sc = scenes.plume_scene(nx, seed=seed, n_obstacles=2, ny=ny)
+    u, v = scenes.random_faces(nx, ny, seed, kind="mixed")
+    u, v = f32(u), f32(v)
+    dt = 0.01
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="jacobi", fixed_iters=k, omega=omega,
+                    dt=dt)
+    o = PR.project(sc.flags, u, v, sc.dx, dt=dt, method="jacobi", fixed_iters=k, omega=omega)
+    assert g["res"].iters == k
+    err = rel_l2(g["p"], o["p"], o["plan"].fluid)
+    say("  rel L2 p", err)
+    assert err <= 1e-5
+    assert rel_l2(g["u"], o["u"]) <= 1e-5 and rel_l2(g["v"], o["v"]) <= 1e-5
+    assert g["res"].e1_cnn == pytest.approx(o["e1_init"], rel=1e-5)  # zero guess
+
+
+@pytest.mark.parametrize("n,seed,thr_rel,ce", [(64, 0, 0.2, 1), (128, 1, 0.1, 8), (256, 2, 0.3, 4)])
+def test_jacobi_threshold_parity(n, seed, thr_rel, ce):
+    say("jacobi thr", n, seed, thr_rel, ce)
+    sc, u, v = plume_state(n, seed, 1)
+    P = G.plan(sc.flags)
+    d = G.divergence(P, *G.enforce_bc(P, u, v), sc.dx)
+    thr = thr_rel * G.e1(P, d)
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=thr, method="jacobi", check_every=ce)
+    o = PR.project(sc.flags, u, v, sc.dx, threshold=thr, method="jacobi", check_every=ce)
+    kg, ko = g["res"].iters, o["iters"]
+    say("  iters gpu", kg, "oracle", ko)
+    assert g["res"].status == 0
+    assert abs(kg - ko) <= max(ce, 0.01 * ko)
+    assert kg % ce == 0
+    # same-algorithm parity at the GPU's sweep count
+    of = PR.project(sc.flags, u, v, sc.dx, method="jacobi", fixed_iters=kg)
+    assert rel_l2(g["p"], of["p"], P.fluid) <= 1e-4
+    assert g["res"].e1_final <= thr * 1.01
+
+
+@pytest.mark.parametrize("n,seed,nobs", [(64, 0, 0), (128, 3, 2), (256, 4, 3)])
+def test_pcg_reaches_exact_solution(n, seed, nobs):
+    say("pcg", n, seed)
+    sc, u, v = plume_state(n, seed, nobs)
+    P = G.plan(sc.flags)
+    ou, ov = G.enforce_bc(P, u, v)
+    d = G.divergence(P, ou, ov, sc.dx)
+    thr = 0.03 * G.e1(P, d)
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=thr, method="pcg")
+    ex = SV.exact_solve(P, d, sc.dx)
+    err = rel_l2(g["p"], ex, P.fluid)
+    o = PR.project(sc.flags, u, v, sc.dx, threshold=thr, method="pcg")
+    say("  iters gpu", g["res"].iters, "oracle", o["iters"], "rel L2 vs exact", err)
+    assert g["res"].status == 0
+    assert err <= 1e-3
+    assert g["res"].e1_final < 1.05 * thr
+    assert abs(g["res"].iters - o["iters"]) <= max(3, 0.1 * o["iters"])
+
+
+def test_pcg_fixed_iterations_match_oracle():
+    sc, u, v = plume_state(64, 7, 1)
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="pcg", fixed_iters=20)
+    o = PR.project(sc.flags, u, v, sc.dx, method="pcg", fixed_iters=20)
+    assert g["res"].iters == 20
+    assert rel_l2(g["p"], o["p"], o["plan"].fluid) <= 1e-4
+
+
+def test_nonfinite_and_maxiter_statuses():
+    sc, u, v = plume_state(64, 3, 1)
+    u2 = u.copy()
+    u2[10, 10] = np.nan
+    g = gpu_project(sc.flags, u2, v, sc.dx, thr=1e-3, method="jacobi")
+    assert g["res"].status == 2 and g["res"].iters == 0
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="jacobi", max_iters=20, check_every=8)
+    assert g["res"].status == 1 and g["res"].iters == 20
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="pcg", max_iters=15)
+    assert g["res"].status == 1 and g["res"].iters == 15
+
+
+def test_zero_divergence_takes_no_sweeps():
+    n = 64
+    flags = np.zeros((n, n), dtype=np.uint8)
+    u = np.zeros((n, n + 1)); v = np.zeros((n + 1, n))
+    g = gpu_project(flags, u, v, 1.0 / n, thr=1e-6, method="jacobi")
+    assert g["res"].iters == 0 and g["res"].status == 0
+    assert np.all(g["p"] == 0) and g["res"].e1_final == 0.0
+
+
+def test_warm_start_is_used():
+    sc, u, v = plume_state(64, 5, 1)
+    P = G.plan(sc.flags)
+    d = G.divergence(P, *G.enforce_bc(P, u, v), sc.dx)
+    ex = SV.exact_solve(P, d, sc.dx)
+    dt = 0.02
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=1e-2 * G.e1(P, d), method="jacobi", dt=dt,
+                    p_init=f32(ex / dt))
+    assert g["res"].iters == 0
+
+
+def test_large_grid_1024_sampled():
+    # full size of the differentiation workload: sampled parity after 16 sweeps
+    n = 1024
+    sc, u, v = plume_state(n, 11, 2, kind="smooth")
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="jacobi", fixed_iters=16)
+    o = PR.project(sc.flags, u, v, sc.dx, method="jacobi", fixed_iters=16)
+    assert rel_l2(g["p"], o["p"], o["plan"].fluid) <= 1e-5
