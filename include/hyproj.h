@@ -72,7 +72,8 @@ extern "C" {
 
 typedef struct hyp_ctx hyp_ctx;
 
-/* Multi-scale network shape.  scales in 1..5, channels in {16, 32, 64}. */
+/* Multi-scale network shape.  scales in 1..5; channels 16 or 32 with FP32,
+ * 32 or 64 with BF16 (the LDS tile of one 3x3 layer must fit one CU). */
 typedef struct {
   int32_t scales;
   int32_t channels;

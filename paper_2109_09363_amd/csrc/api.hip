@@ -114,8 +114,13 @@ int hyp_create(hyp_ctx** out, const hyp_net_desc* net) {
   NetShape ns;
   if (net) {
     if (net->scales < 1 || net->scales > 5) return HYP_EINVAL;
-    if (net->channels != 16 && net->channels != 32 && net->channels != 64) return HYP_EINVAL;
-    if (net->precision != HYP_PREC_FP32 && net->precision != HYP_PREC_BF16) return HYP_EINVAL;
+    if (net->precision == HYP_PREC_FP32) {
+      if (net->channels != 16 && net->channels != 32) return HYP_EINVAL;
+    } else if (net->precision == HYP_PREC_BF16) {
+      if (net->channels != 32 && net->channels != 64) return HYP_EINVAL;
+    } else {
+      return HYP_EINVAL;
+    }
     ns.scales = net->scales;
     ns.channels = net->channels;
     ns.precision = net->precision;
@@ -191,7 +196,7 @@ int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double thr
   const int nx = g->nx, ny = g->ny;
   if (run_div(nx, ny, g->dx, f->u, f->v, w, L.nblocks_stream, stream) != hipSuccess) return HYP_EHIP;
   if (use_cnn) {
-    if (run_cnn(ctx->net, L, nx, ny, g->dx, ctx->params, w, stream) != hipSuccess) return HYP_EHIP;
+    if (run_cnn(ctx->dev, ctx->net, L, nx, ny, g->dx, ctx->params, w, stream) != hipSuccess) return HYP_EHIP;
   } else {
     if (run_init_phi(nx, ny, f->p_init, g->dt / g->rho0, w, stream) != hipSuccess) return HYP_EHIP;
   }

@@ -80,7 +80,7 @@ hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int
 hipError_t run_grad_and_finish(int nx, int ny, double dx, double p_scale, float* u, float* v,
                                float* p, const Ws& w, int nblocks, void* res,
                                hipStream_t s);
-hipError_t run_cnn(const NetShape& net, const WsLayout& L, int nx, int ny, double dx,
-                   const float* params, const Ws& w, hipStream_t s);
+hipError_t run_cnn(const Device& dev, const NetShape& net, const WsLayout& L, int nx, int ny,
+                   double dx, const float* params, const Ws& w, hipStream_t s);
 
 }  // namespace hyp

@@ -99,21 +99,25 @@ def test_jacobi_threshold_parity(n, seed, thr_rel, ce):
     assert g["res"].e1_final <= thr * 1.01
 
 
-@pytest.mark.parametrize("n,seed,nobs", [(64, 0, 0), (128, 3, 2), (256, 4, 3)])
-def test_pcg_reaches_exact_solution(n, seed, nobs):
+@pytest.mark.parametrize("n,seed,nobs,rel", [(64, 0, 0, 3e-3), (128, 3, 2, 1e-2), (256, 4, 3, 1e-2)])
+def test_pcg_threshold_vs_oracle_and_exact(n, seed, nobs, rel):
+    # A threshold-stopped CG iterate is as far from the exact solution as the
+    # threshold allows; the GPU must stop where the FP64 oracle stops and be
+    # as close to the exact solution as the oracle's iterate is.
     say("pcg", n, seed)
     sc, u, v = plume_state(n, seed, nobs)
     P = G.plan(sc.flags)
     ou, ov = G.enforce_bc(P, u, v)
     d = G.divergence(P, ou, ov, sc.dx)
-    thr = 0.03 * G.e1(P, d)
+    thr = rel * G.e1(P, d)
     g = gpu_project(sc.flags, u, v, sc.dx, thr=thr, method="pcg")
     ex = SV.exact_solve(P, d, sc.dx)
-    err = rel_l2(g["p"], ex, P.fluid)
     o = PR.project(sc.flags, u, v, sc.dx, threshold=thr, method="pcg")
-    say("  iters gpu", g["res"].iters, "oracle", o["iters"], "rel L2 vs exact", err)
+    err_g = rel_l2(g["p"], ex, P.fluid)
+    err_o = rel_l2(o["p"], ex, P.fluid)
+    say("  iters gpu", g["res"].iters, "oracle", o["iters"], "rel L2 vs exact gpu", err_g, "oracle", err_o)
     assert g["res"].status == 0
-    assert err <= 1e-3
+    assert err_g <= 1.5 * err_o + 1e-4
     assert g["res"].e1_final < 1.05 * thr
     assert abs(g["res"].iters - o["iters"]) <= max(3, 0.1 * o["iters"])
 
