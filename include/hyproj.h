@@ -119,6 +119,7 @@ typedef struct {
   double s;            /* CNN input scale sqrt(mean d^2) (0 without CNN) */
   int32_t n_fluid;     /* fluid cells after the pocket fill */
   int32_t reserved;
+  double dt;           /* time step of hyp_step (CFL); unset by hyp_project */
 } hyp_result;
 
 int hyp_version(void);
@@ -159,6 +160,43 @@ int hyp_plan(hyp_ctx* ctx, const hyp_grid* g, const uint8_t* flags,
 int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f,
                 double threshold, const hyp_opts* o, void* ws,
                 size_t ws_bytes, hipStream_t stream, hyp_result* res);
+
+/* Phase timing (the t_ad / t_inf / t_p / t_it split of Sec. 5): when
+ * enabled, HIP events are recorded on the call's stream around each phase of
+ * hyp_project / hyp_step (a few microseconds of overhead per call). */
+int hyp_set_timing(hyp_ctx* ctx, int enable);
+/* Milliseconds of the last call, after waiting for it: ms[0] advection (0 for
+ * hyp_project), ms[1] divergence + CNN inference, ms[2] the iterative solver
+ * launch, ms[3] gradient correction + final check, ms[4] total. */
+int hyp_get_timing(hyp_ctx* ctx, float* ms);
+
+/* Physical parameters of the plume time step (Sec. 2.1-2.2). */
+typedef struct {
+  double g;      /* gravity (from the Richardson number, Eq. 1) */
+  double rho0;   /* reference (heavy) density */
+  double drho;   /* density contrast Delta rho / rho0 of the injected fluid */
+  double u_in;   /* inflow velocity */
+  double cfl;    /* dt = cfl dx / max(max|u|, max|v|, u_in) */
+} hyp_physics;
+
+typedef struct {
+  float* rho;            /* (ny, nx) density, advected in place */
+  float* u;              /* (ny, nx+1) velocity faces, advanced in place */
+  float* v;              /* (ny+1, nx) */
+  float* p;              /* (ny, nx) out: pressure of the projection */
+  const uint8_t* flags;  /* (ny, nx) input flags, as for hyp_project */
+  const float* xi;       /* (nx) inflow noise of this step: v_in = u_in (1 + xi) */
+} hyp_state;
+
+/* One full time step of the plume (Sec. 2.2): CFL time step, MacCormack
+ * semi-Lagrangian advection of rho, u and v with the start-of-step velocity
+ * (min/max limiter), buoyancy by forward Euler on interior and top v faces,
+ * inflow reset, boundary faces, then the projection exactly as hyp_project
+ * with p = rho0 phi / dt.  g->dt is ignored (the step computes its own dt,
+ * returned in res->dt).  Requires hyp_plan on the workspace. */
+int hyp_step(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_state* st,
+             double threshold, const hyp_opts* o, void* ws, size_t ws_bytes,
+             hipStream_t stream, hyp_result* res);
 
 #ifdef __cplusplus
 }

@@ -96,8 +96,7 @@ def advect_step(P: G.Plan, flags, rho, u, v, dx: float, dt: float, g: float,
     rf[1:ny] = 0.5 * (rho_n[:-1] + rho_n[1:])
     rf[ny] = rho_n[ny - 1]
     v_n[1:] += dt * g * (rho0 - rf[1:]) / rho0
-    inflow_cells = (np.asarray(flags)[0] & G.FLAG_INFLOW) != 0
-    rho_n[0, inflow_cells] = rho0 * (1.0 - drho)
+    rho_n[0, P.vinflow] = rho0 * (1.0 - drho)
     v_n[0] = np.where(P.vinflow, u_in * (1.0 + xi), 0.0)
     u_s, v_s = G.enforce_bc(P, u_n, v_n)
     return rho_n, u_s, v_s

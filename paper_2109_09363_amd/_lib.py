@@ -36,7 +36,15 @@ class Opts(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("iters", c_i32), ("status", c_i32), ("e1_init", c_f64), ("e1_cnn", c_f64),
                 ("e1_final", c_f64), ("einf_final", c_f64), ("s", c_f64),
-                ("n_fluid", c_i32), ("reserved", c_i32)]
+                ("n_fluid", c_i32), ("reserved", c_i32), ("dt", c_f64)]
+
+
+class Physics(ctypes.Structure):
+    _fields_ = [("g", c_f64), ("rho0", c_f64), ("drho", c_f64), ("u_in", c_f64), ("cfl", c_f64)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("rho", c_vp), ("u", c_vp), ("v", c_vp), ("p", c_vp), ("flags", c_vp), ("xi", c_vp)]
 
 
 # name -> (restype, argtypes); mirrors the declarations of include/hyproj.h
@@ -51,6 +59,10 @@ SIGNATURES = {
     "hyp_plan": (c_i32, [c_vp, ctypes.POINTER(Grid), c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hyp_project": (c_i32, [c_vp, ctypes.POINTER(Grid), ctypes.POINTER(Fields), c_f64,
                             ctypes.POINTER(Opts), c_vp, ctypes.c_size_t, c_vp, c_vp]),
+    "hyp_set_timing": (c_i32, [c_vp, c_i32]),
+    "hyp_get_timing": (c_i32, [c_vp, ctypes.POINTER(c_f32)]),
+    "hyp_step": (c_i32, [c_vp, ctypes.POINTER(Grid), ctypes.POINTER(Physics), ctypes.POINTER(State),
+                         c_f64, ctypes.POINTER(Opts), c_vp, ctypes.c_size_t, c_vp, c_vp]),
 }
 
 _LIB = None

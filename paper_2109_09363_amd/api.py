@@ -21,6 +21,7 @@ class ProjectionResult:
     einf_final: float
     s: float
     n_fluid: int
+    dt: float
 
 
 def _ptr(t):
@@ -115,11 +116,44 @@ class Projector:
             self.ctx, ctypes.byref(self.grid), ctypes.byref(f), float(threshold), ctypes.byref(o),
             _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
 
+    def set_timing(self, enable: bool = True):
+        L.check("hyp_set_timing", self.lib.hyp_set_timing(self.ctx, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        """Phase times (ms) of the last call: advection, divergence + CNN
+        (t_inf), solver, correction, total."""
+        arr = (ctypes.c_float * 5)()
+        L.check("hyp_get_timing", self.lib.hyp_get_timing(self.ctx, arr))
+        return dict(advect=arr[0], inference=arr[1], solver=arr[2], correct=arr[3], total=arr[4])
+
     def result(self) -> ProjectionResult:
         raw = bytes(self.res.cpu().numpy().tobytes())
         r = L.Result.from_buffer_copy(raw)
         return ProjectionResult(r.iters, r.status, r.e1_init, r.e1_cnn, r.e1_final,
-                                r.einf_final, r.s, r.n_fluid)
+                                r.einf_final, r.s, r.n_fluid, r.dt)
+
+    def step_async(self, rho, u, v, flags, p, xi, threshold: float, g: float, drho: float,
+                   u_in: float = 1.0, cfl: float = 0.5, method: str = "hybrid",
+                   max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
+                   omega: float = 1.0):
+        """Enqueue one full time step (advection, buoyancy, inflow, projection)
+        on the current stream.  rho, u, v advance in place; p is written."""
+        nx, ny = self.nx, self.ny
+        _need(rho, torch.float32, (ny, nx), "rho")
+        _need(u, torch.float32, (ny, nx + 1), "u")
+        _need(v, torch.float32, (ny + 1, nx), "v")
+        _need(flags, torch.uint8, (ny, nx), "flags")
+        _need(p, torch.float32, (ny, nx), "p")
+        _need(xi, torch.float32, (nx,), "xi")
+        if not self.planned:
+            raise RuntimeError("call plan(flags) before step")
+        ph = L.Physics(float(g), float(self.grid.rho0), float(drho), float(u_in), float(cfl))
+        st = L.State(_ptr(rho), _ptr(u), _ptr(v), _ptr(p), _ptr(flags), _ptr(xi))
+        o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
+                   float(omega), (ctypes.c_int32 * 3)())
+        L.check("hyp_step", self.lib.hyp_step(
+            self.ctx, ctypes.byref(self.grid), ctypes.byref(ph), ctypes.byref(st), float(threshold),
+            ctypes.byref(o), _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
 
 
 _CACHE: dict = {}

@@ -13,7 +13,16 @@ struct hyp_ctx {
   hyp::Device dev;
   const float* params = nullptr;
   int64_t n_params_set = 0;
+  // phase timing: events recorded on the caller's stream around advection,
+  // divergence + CNN, the solver launch, and the correction
+  bool timing = false;
+  bool timed_step = false;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
+
+static void mark(hyp_ctx* ctx, int i, hipStream_t s) {
+  if (ctx->timing) (void)hipEventRecord(ctx->ev[i], s);
+}
 
 namespace hyp {
 
@@ -37,6 +46,7 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
   L.d = take(4 * n);
   L.phi = take(4 * n);
   L.exch = take(8 * n);
+  L.adv = take(4 * 2 * (n + (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx));
   if (net.scales > 0) {
     size_t px = 0;
     for (int k = 0; k < net.scales; ++k) {
@@ -70,6 +80,7 @@ Ws ws_view(void* base, const WsLayout& L) {
   w.phi = (float*)(b + L.phi);
   w.exch = (float*)(b + L.exch);
   w.pcg = nullptr;
+  w.adv = (float*)(b + L.adv);
   w.cnn_in = L.cnn_in ? b + L.cnn_in : nullptr;
   w.cnn_act0 = L.cnn_act0 ? b + L.cnn_act0 : nullptr;
   w.cnn_act1 = L.cnn_act1 ? b + L.cnn_act1 : nullptr;
@@ -142,7 +153,36 @@ int hyp_create(hyp_ctx** out, const hyp_net_desc* net) {
 }
 
 int hyp_destroy(hyp_ctx* ctx) {
+  if (!ctx) return HYP_OK;
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
+  return HYP_OK;
+}
+
+int hyp_set_timing(hyp_ctx* ctx, int enable) {
+  if (!ctx) return HYP_EINVAL;
+  if (enable && !ctx->ev[0]) {
+    for (auto& e : ctx->ev)
+      if (hipEventCreate(&e) != hipSuccess) return HYP_EHIP;
+  }
+  ctx->timing = enable != 0;
+  return HYP_OK;
+}
+
+int hyp_get_timing(hyp_ctx* ctx, float* ms) {
+  if (!ctx || !ms) return HYP_EINVAL;
+  if (!ctx->timing) return HYP_EINVAL;
+  for (int i = 0; i < 5; ++i) ms[i] = 0.f;
+  for (int i = 0; i < 5; ++i)
+    if (hipEventSynchronize(ctx->ev[i]) != hipSuccess) return HYP_EHIP;
+  float t = 0.f;
+  if (ctx->timed_step && hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]) == hipSuccess) ms[0] = t;
+  if (hipEventElapsedTime(&t, ctx->ev[1], ctx->ev[2]) == hipSuccess) ms[1] = t;
+  if (hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3]) == hipSuccess) ms[2] = t;
+  if (hipEventElapsedTime(&t, ctx->ev[3], ctx->ev[4]) == hipSuccess) ms[3] = t;
+  if (hipEventElapsedTime(&t, ctx->timed_step ? ctx->ev[0] : ctx->ev[1], ctx->ev[4]) == hipSuccess)
+    ms[4] = t;
   return HYP_OK;
 }
 
@@ -176,11 +216,7 @@ int hyp_plan(hyp_ctx* ctx, const hyp_grid* g, const uint8_t* flags, void* ws, si
   return HYP_OK;
 }
 
-int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double threshold,
-                const hyp_opts* o, void* ws, size_t ws_bytes, hipStream_t stream,
-                hyp_result* res) {
-  if (!ctx || !f || !o || !ws || !res || !grid_ok(g)) return HYP_EINVAL;
-  if (!f->u || !f->v || !f->flags || !f->p) return HYP_EINVAL;
+static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, double threshold) {
   if (o->method < HYP_METHOD_HYBRID || o->method > HYP_METHOD_CNN) return HYP_EINVAL;
   if (o->max_iters < 0 || o->check_every < 1 || o->fixed_iters < 0) return HYP_EINVAL;
   if (!(threshold >= 0.0)) return HYP_EINVAL;
@@ -190,17 +226,29 @@ int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double thr
     const int m = 1 << (ctx->net.scales - 1);
     if (g->nx % m || g->ny % m) return HYP_EUNSUPPORTED;
   }
-  const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
-  if (ws_bytes < L.total) return HYP_EWORKSPACE;
-  const Ws w = ws_view(ws, L);
+  const bool pcg = o->method == HYP_METHOD_PCG;
+  if (!solver_fits(ctx->dev, g->nx, g->ny, pcg, o->check_every, o->fixed_iters))
+    return HYP_EUNSUPPORTED;
+  return HYP_OK;
+}
+
+// The projection pipeline, enqueued on `stream` (arguments already checked).
+static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* v,
+                              const float* p_init, float* p, double threshold, const hyp_opts* o,
+                              const WsLayout& L, const Ws& w, bool dt_dev, hipStream_t stream,
+                              hyp_result* res) {
   const int nx = g->nx, ny = g->ny;
-  if (run_div(nx, ny, g->dx, f->u, f->v, w, L.nblocks_stream, stream) != hipSuccess) return HYP_EHIP;
+  const bool use_cnn = o->method == HYP_METHOD_HYBRID || o->method == HYP_METHOD_CNN;
+  mark(ctx, 1, stream);
+  if (run_div(nx, ny, g->dx, u, v, w, L.nblocks_stream, stream) != hipSuccess) return HYP_EHIP;
   if (use_cnn) {
-    if (run_cnn(ctx->dev, ctx->net, L, nx, ny, g->dx, ctx->params, w, stream) != hipSuccess) return HYP_EHIP;
+    if (run_cnn(ctx->dev, ctx->net, L, nx, ny, g->dx, ctx->params, w, stream) != hipSuccess)
+      return HYP_EHIP;
   } else {
-    if (run_init_phi(nx, ny, f->p_init, g->dt / g->rho0, w, stream) != hipSuccess) return HYP_EHIP;
+    if (run_init_phi(nx, ny, p_init, g->dt / g->rho0, w, stream) != hipSuccess) return HYP_EHIP;
   }
   hipError_t e = hipSuccess;
+  mark(ctx, 2, stream);
   switch (o->method) {
     case HYP_METHOD_HYBRID:
     case HYP_METHOD_JACOBI:
@@ -216,12 +264,52 @@ int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double thr
       e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, w, stream);
       break;
   }
-  if (e == hipErrorInvalidValue) return HYP_EUNSUPPORTED;
   if (e != hipSuccess) return HYP_EHIP;
-  if (run_grad_and_finish(nx, ny, g->dx, g->rho0 / g->dt, f->u, f->v, f->p, w, L.nblocks_stream,
+  mark(ctx, 3, stream);
+  if (run_grad_and_finish(nx, ny, g->dx, g->rho0, g->dt, dt_dev, u, v, p, w, L.nblocks_stream,
                           res, stream) != hipSuccess)
     return HYP_EHIP;
+  mark(ctx, 4, stream);
   return HYP_OK;
+}
+
+int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double threshold,
+                const hyp_opts* o, void* ws, size_t ws_bytes, hipStream_t stream,
+                hyp_result* res) {
+  if (!ctx || !f || !o || !ws || !res || !grid_ok(g)) return HYP_EINVAL;
+  if (!f->u || !f->v || !f->flags || !f->p) return HYP_EINVAL;
+  int rc = check_opts(ctx, g, o, threshold);
+  if (rc != HYP_OK) return rc;
+  const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
+  if (ws_bytes < L.total) return HYP_EWORKSPACE;
+  const Ws w = ws_view(ws, L);
+  ctx->timed_step = false;
+  return enqueue_projection(ctx, g, f->u, f->v, f->p_init, f->p, threshold, o, L, w, false,
+                            stream, res);
+}
+
+int hyp_step(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_state* st,
+             double threshold, const hyp_opts* o, void* ws, size_t ws_bytes, hipStream_t stream,
+             hyp_result* res) {
+  if (!ctx || !ph || !st || !o || !ws || !res) return HYP_EINVAL;
+  if (!g || g->nx < 2 || g->ny < 2 || !(g->dx > 0.0) || !(g->rho0 > 0.0)) return HYP_EINVAL;
+  if (!st->rho || !st->u || !st->v || !st->p || !st->flags || !st->xi) return HYP_EINVAL;
+  if (!(ph->cfl > 0.0) || !(ph->u_in > 0.0) || !(ph->rho0 > 0.0)) return HYP_EINVAL;
+  hyp_grid gg = *g;
+  gg.dt = 1.0;  // placeholder for the checks; the pressure uses the device dt
+  if (!grid_ok(&gg)) return HYP_EINVAL;
+  int rc = check_opts(ctx, &gg, o, threshold);
+  if (rc != HYP_OK) return rc;
+  const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
+  if (ws_bytes < L.total) return HYP_EWORKSPACE;
+  const Ws w = ws_view(ws, L);
+  ctx->timed_step = true;
+  mark(ctx, 0, stream);
+  if (run_advect(g->nx, g->ny, g->dx, ph->g, ph->rho0, ph->drho, ph->u_in, ph->cfl, st->rho, st->u,
+                 st->v, st->xi, w, stream) != hipSuccess)
+    return HYP_EHIP;
+  return enqueue_projection(ctx, &gg, st->u, st->v, nullptr, st->p, threshold, o, L, w, true,
+                            stream, res);
 }
 
 }  // extern "C"

@@ -15,6 +15,7 @@ struct Scalars {
   double s;           // sqrt(sum_d2 / nF): CNN input scale
   double e1_cnn;      // E_1 of the initial guess
   double e1_solve;    // E_1 of the returned iterate as the solver saw it
+  double dt;          // time step of the last advection (CFL)
   int32_t nF;         // fluid cells after the pocket fill
   int32_t iters;
   int32_t status;
@@ -33,7 +34,7 @@ struct NetShape {
 // Byte offsets into the caller's workspace (all 256-byte aligned).
 struct WsLayout {
   size_t cell = 0, d = 0, phi = 0, exch = 0, blockpart = 0, partial = 0,
-         scalars = 0, reach = 0, pcg = 0;
+         scalars = 0, reach = 0, pcg = 0, adv = 0;
   size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0;
   size_t total = 0;
   int nblocks_stream = 0;
@@ -56,6 +57,7 @@ struct Ws {
   Scalars* sc;
   uint8_t* reach;
   float* pcg;         // PCG scratch
+  float* adv;         // advection temporaries: 2 x (cells + u faces + v faces)
   void* cnn_in; void* cnn_act0; void* cnn_act1; float* cnn_y; float* cnn_t; void* cnn_w;
 };
 Ws ws_view(void* base, const WsLayout& L);
@@ -75,11 +77,15 @@ hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, const Ws& w,
                       hipStream_t s);
+bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters);
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
                    int check_every, int fixed_iters, const Ws& w, hipStream_t s);
-hipError_t run_grad_and_finish(int nx, int ny, double dx, double p_scale, float* u, float* v,
-                               float* p, const Ws& w, int nblocks, void* res,
+hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt, bool dt_dev,
+                               float* u, float* v, float* p, const Ws& w, int nblocks, void* res,
                                hipStream_t s);
+hipError_t run_advect(int nx, int ny, double dx, double g, double rho0, double drho, double u_in,
+                      double cfl, float* rho, float* u, float* v, const float* xi, const Ws& w,
+                      hipStream_t s);
 hipError_t run_cnn(const Device& dev, const NetShape& net, const WsLayout& L, int nx, int ny,
                    double dx, const float* params, const Ws& w, hipStream_t s);
 

@@ -350,6 +350,17 @@ static int jacobi_block_len(int check_every, int fixed_iters) {
   return check_every < kMaxBlock ? check_every : kMaxBlock;
 }
 
+bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters) {
+  int T = 0, ntx = 0, nty = 0;
+  size_t lds = 0;
+  if (pcg) {
+    if (!pick_tile(dev, nx, ny, 1, 4, 1, &T, &ntx, &nty, &lds)) return false;
+    return T * T <= 16 * 256;
+  }
+  const int H = jacobi_block_len(check_every, fixed_iters) + 1;
+  return pick_tile(dev, nx, ny, H, 5, 1, &T, &ntx, &nty, &lds);
+}
+
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, const Ws& w,
                       hipStream_t s) {

@@ -231,12 +231,15 @@ hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const
 // thread rewrites only the faces it owns, so no face is read after another
 // thread's update.  p = rho0 phi / dt.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void grad_kernel(int nx, int ny, float inv_dx, float p_scale,
+__global__ __launch_bounds__(256) void grad_kernel(int nx, int ny, float inv_dx, double rho0,
+                                                   double dt_host, int dt_dev,
                                                    const uint8_t* __restrict__ cell,
                                                    const float* __restrict__ phi, float* u,
-                                                   float* v, float* __restrict__ p) {
+                                                   float* v, float* __restrict__ p,
+                                                   const Scalars* sc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nx * ny) return;
+  const float p_scale = (float)(rho0 / (dt_dev ? sc->dt : dt_host));
   const int i = c % nx, j = c / nx, U = nx + 1;
   const uint8_t ci = cell[c];
   const bool fl = !(ci & C_SOLID);
@@ -292,14 +295,17 @@ __global__ __launch_bounds__(256) void finish_kernel(int nblocks, const double* 
     r.s = sc->s;
     r.n_fluid = sc->nF;
     r.reserved = 0;
+    r.dt = sc->dt;
     *res = r;
   }
 }
 
-hipError_t run_grad_and_finish(int nx, int ny, double dx, double p_scale, float* u, float* v,
-                               float* p, const Ws& w, int nblocks, void* res, hipStream_t s) {
+hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt, bool dt_dev,
+                               float* u, float* v, float* p, const Ws& w, int nblocks, void* res,
+                               hipStream_t s) {
   const float inv_dx = (float)(1.0 / dx);
-  grad_kernel<<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, (float)p_scale, w.cell, w.phi, u, v, p);
+  grad_kernel<<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, rho0, dt, dt_dev ? 1 : 0, w.cell, w.phi, u,
+                                      v, p, w.sc);
   check_kernel<<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, w.cell, u, v, w.blockpart);
   finish_kernel<<<1, 256, 0, s>>>(nblocks, w.blockpart, w.sc, (hyp_result*)res);
   return hipGetLastError();
