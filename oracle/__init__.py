@@ -14,3 +14,4 @@ Modules: ``grid`` (planner, D, L, G, E_1), ``solve`` (exact, Jacobi, PCG),
 divergence loss).
 """
 from . import grid, solve, cnn, project, advect  # noqa: F401
+from . import adjoint  # noqa: F401,E402

@@ -178,6 +178,7 @@ hipError_t run_advect(int nx, int ny, double dx, double g, double rho0, double d
                       hipStream_t s) {
   const int n = nx * ny, nu = ny * (nx + 1), nv = (ny + 1) * nx;
   const int nbf = (nu + nv + 255) / 256;
+  if ((size_t)nbf > w.blockpart_n) return hipErrorInvalidValue;
   cfl_kernel<<<nbf, 256, 0, s>>>(nu, nv, u, v, w.blockpart);
   cfl_finish<<<1, 256, 0, s>>>(nbf, w.blockpart, dx, cfl, u_in, w.sc);
   AdvPtrs A{};

@@ -40,7 +40,12 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
   L.nblocks_stream = (int)((n + kStreamBlock - 1) / kStreamBlock);
   L.scalars = take(sizeof(Scalars));
   L.partial = take(sizeof(double) * 4 * kMaxCoopBlocks);
-  L.blockpart = take(sizeof(double) * 2 * (size_t)L.nblocks_stream);
+  // block partials: two per cell-grid block, or one per face-grid block (CFL)
+  const size_t nfaces = (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx;
+  const size_t nb_faces = (nfaces + kStreamBlock - 1) / kStreamBlock;
+  const size_t nbp = 2 * (size_t)L.nblocks_stream > nb_faces ? 2 * (size_t)L.nblocks_stream : nb_faces;
+  L.blockpart = take(sizeof(double) * nbp);
+  L.blockpart_n = nbp;
   L.cell = take(n);
   L.reach = take(n);
   L.d = take(4 * n);
@@ -74,6 +79,7 @@ Ws ws_view(void* base, const WsLayout& L) {
   w.sc = (Scalars*)(b + L.scalars);
   w.partial = (double*)(b + L.partial);
   w.blockpart = (double*)(b + L.blockpart);
+  w.blockpart_n = L.blockpart_n;
   w.cell = (uint8_t*)(b + L.cell);
   w.reach = (uint8_t*)(b + L.reach);
   w.d = (float*)(b + L.d);

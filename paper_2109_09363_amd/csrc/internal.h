@@ -37,6 +37,7 @@ struct WsLayout {
          scalars = 0, reach = 0, pcg = 0, adv = 0;
   size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0;
   size_t total = 0;
+  size_t blockpart_n = 0;
   int nblocks_stream = 0;
   // per-scale offsets (elements) into the CNN buffers
   int sc_h[6] = {0}, sc_w[6] = {0};
@@ -53,6 +54,7 @@ struct Ws {
   float* phi;
   float* exch;        // 2 x nx*ny (halo exchange ping-pong)
   double* blockpart;  // streaming-kernel block partials
+  size_t blockpart_n; // capacity of blockpart in doubles
   double* partial;    // 2 x kMaxCoopBlocks x 4 cooperative partials
   Scalars* sc;
   uint8_t* reach;

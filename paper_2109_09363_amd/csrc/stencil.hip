@@ -202,6 +202,7 @@ __global__ __launch_bounds__(256) void div_finish(int nblocks, const double* __r
 
 hipError_t run_div(int nx, int ny, double dx, float* u, float* v, const Ws& w, int nblocks,
                    hipStream_t s) {
+  if ((size_t)2 * nblocks > w.blockpart_n) return hipErrorInvalidValue;
   div_kernel<<<nblocks, 256, 0, s>>>(nx, ny, (float)(1.0 / dx), w.cell, u, v, w.d, w.blockpart,
                                      w.sc);
   div_finish<<<1, 256, 0, s>>>(nblocks, w.blockpart, w.sc);
@@ -303,6 +304,7 @@ __global__ __launch_bounds__(256) void finish_kernel(int nblocks, const double* 
 hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt, bool dt_dev,
                                float* u, float* v, float* p, const Ws& w, int nblocks, void* res,
                                hipStream_t s) {
+  if ((size_t)2 * nblocks > w.blockpart_n) return hipErrorInvalidValue;
   const float inv_dx = (float)(1.0 / dx);
   grad_kernel<<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, rho0, dt, dt_dev ? 1 : 0, w.cell, w.phi, u,
                                       v, p, w.sc);
