@@ -233,9 +233,58 @@ __global__ __launch_bounds__(256) void pcg_persist(PcgParams p) {
   double E = nF > 0 ? sum_partials(part_ra, G, red) / nF * p.inv_dx2 : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
   int k = 0;
+  float* xex = p.exch + (size_t)p.nx * p.ny;  // second plane: x halo exchange
   for (;;) {
     int st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
     if (st < 0 && !(rho > 0.0)) st = HYP_STATUS_OK;  // r = 0 exactly
+    if (st == HYP_STATUS_OK && p.fixed_iters <= 0) {
+      // The updated residual drifts from b - A x in FP32: confirm the stop on
+      // the true residual; if it fails, continue from it with p = z (restart).
+      REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
+        const int gx = ox + lx, gy = oy + ly;
+        if (gx < p.nx && gy < p.ny) xex[gy * p.nx + gx] = xl[ly * EX + lx];
+      }
+      ++nbar;
+      grid_barrier(&p.sc->bar, nbar * (unsigned)G);
+      REGION_LOOP(0, EY, 0, EX) {
+        if (ly >= 1 && ly < 1 + p.TH && lx >= 1 && lx < 1 + p.T) continue;
+        const int l = ly * EX + lx;
+        xl[l] = kl[l] > 0.f ? xex[(oy + ly) * p.nx + (ox + lx)] : 0.f;
+      }
+      __syncthreads();
+      double rzt = 0.0, rat = 0.0;
+      REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
+        const int l = ly * EX + lx;
+        if (kl[l] > 0.f) {
+          const int g = (oy + ly) * p.nx + (ox + lx);
+          const float b = -p.dx2 * p.d[g];
+          const float Ax = kl[l] * xl[l] - ((xl[l - 1] + xl[l + 1]) + (xl[l - EX] + xl[l + EX]));
+          const float r = b - Ax;
+          rl[l] = r;
+          rzt += (double)r * (double)(r / kl[l]);
+          rat += fabs((double)r);
+        }
+      }
+      rzt = block_sum(rzt, red);
+      rat = block_sum(rat, red);
+      if (threadIdx.x == 0) {
+        part_rz[blockIdx.x] = rzt;
+        part_ra[blockIdx.x] = rat;
+      }
+      ++nbar;
+      grid_barrier(&p.sc->bar, nbar * (unsigned)G);
+      rho = sum_partials(part_rz, G, red);
+      E = nF > 0 ? sum_partials(part_ra, G, red) / nF * p.inv_dx2 : 0.0;
+      st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
+      if (st < 0 && !(rho > 0.0)) st = HYP_STATUS_OK;
+      if (st < 0) {
+        REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
+          const int l = ly * EX + lx;
+          pl[l] = kl[l] > 0.f ? rl[l] / kl[l] : 0.f;
+        }
+        __syncthreads();
+      }
+    }
     if (st >= 0) {
       REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
         const int gx = ox + lx, gy = oy + ly;
