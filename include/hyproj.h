@@ -72,13 +72,17 @@ extern "C" {
 
 typedef struct hyp_ctx hyp_ctx;
 
+/* hyp_net_desc.flags */
+#define HYP_NET_TRAIN  1  /* keep every layer's activations (and the backward
+                             buffers) in the workspace for hyp_project_backward */
+
 /* Multi-scale network shape.  scales in 1..5; channels 16 or 32 with FP32,
  * 32 or 64 with BF16 (the LDS tile of one 3x3 layer must fit one CU). */
 typedef struct {
   int32_t scales;
   int32_t channels;
   int32_t precision;  /* HYP_PREC_* */
-  int32_t reserved;
+  int32_t flags;      /* HYP_NET_* */
 } hyp_net_desc;
 
 typedef struct {
@@ -161,6 +165,27 @@ int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f,
                 double threshold, const hyp_opts* o, void* ws,
                 size_t ws_bytes, hipStream_t stream, hyp_result* res);
 
+/* Adjoint of the projection (the gradient of the correction of Eq. 2 is
+ * known, Sec. 3.2): gradient of  loss = scale * sum_F r^2,  r = d - L phi_K,
+ * the divergence left after the CNN guess and exactly `sweeps` Jacobi sweeps
+ * of weight `omega`.  Must follow, on the same stream and workspace, the
+ * forward hyp_project of a context created with HYP_NET_TRAIN, run with
+ * method HYP_METHOD_HYBRID and fixed_iters = sweeps (or HYP_METHOD_CNN when
+ * sweeps = 0).  Writes (or adds to, when accumulate != 0) dL/du (ny, nx+1),
+ * dL/dv (ny+1, nx) and dL/dparams (packed layout); each pointer may be NULL.
+ * `loss` (device double, nullable) receives the loss.  Deterministic: every
+ * reduction has a fixed order. */
+int hyp_project_backward(hyp_ctx* ctx, const hyp_grid* g, int32_t sweeps, float omega,
+                         double scale, int32_t accumulate, float* du, float* dv,
+                         float* dparams, double* loss, void* ws, size_t ws_bytes,
+                         hipStream_t stream);
+
+/* One Adam update of n parameters (step >= 1 for the bias correction):
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).  All device FP32. */
+int hyp_adam(float* params, const float* grads, float* m, float* v, int64_t n, int32_t step,
+             float lr, float beta1, float beta2, float eps, hipStream_t stream);
+
 /* Phase timing (the t_ad / t_inf / t_p / t_it split of Sec. 5): when
  * enabled, HIP events are recorded on the call's stream around each phase of
  * hyp_project / hyp_step (a few microseconds of overhead per call). */
@@ -197,6 +222,12 @@ typedef struct {
 int hyp_step(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_state* st,
              double threshold, const hyp_opts* o, void* ws, size_t ws_bytes,
              hipStream_t stream, hyp_result* res);
+
+/* The advection + force half of hyp_step alone (produces u* in st->u,
+ * st->v and the advected density; st->p is not used).  For generating the
+ * intermediate velocities the projection receives, e.g. training data. */
+int hyp_advect(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_state* st,
+               void* ws, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

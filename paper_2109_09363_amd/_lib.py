@@ -12,12 +12,13 @@ HYP_OK = 0
 STATUS_OK, STATUS_MAXITER, STATUS_NONFINITE = 0, 1, 2
 METHODS = {"hybrid": 0, "jacobi": 1, "pcg": 2, "cnn": 3}
 PRECISIONS = {"fp32": 0, "bf16": 1}
+NET_TRAIN = 1
 
 c_i32, c_i64, c_f64, c_f32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float, ctypes.c_void_p
 
 
 class NetDesc(ctypes.Structure):
-    _fields_ = [("scales", c_i32), ("channels", c_i32), ("precision", c_i32), ("reserved", c_i32)]
+    _fields_ = [("scales", c_i32), ("channels", c_i32), ("precision", c_i32), ("flags", c_i32)]
 
 
 class Grid(ctypes.Structure):
@@ -63,6 +64,11 @@ SIGNATURES = {
     "hyp_get_timing": (c_i32, [c_vp, ctypes.POINTER(c_f32)]),
     "hyp_step": (c_i32, [c_vp, ctypes.POINTER(Grid), ctypes.POINTER(Physics), ctypes.POINTER(State),
                          c_f64, ctypes.POINTER(Opts), c_vp, ctypes.c_size_t, c_vp, c_vp]),
+    "hyp_advect": (c_i32, [c_vp, ctypes.POINTER(Grid), ctypes.POINTER(Physics), ctypes.POINTER(State),
+                           c_vp, ctypes.c_size_t, c_vp]),
+    "hyp_project_backward": (c_i32, [c_vp, ctypes.POINTER(Grid), c_i32, c_f32, c_f64, c_i32, c_vp,
+                                     c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "hyp_adam": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_f32, c_f32, c_f32, c_f32, c_vp]),
 }
 
 _LIB = None

@@ -47,7 +47,8 @@ class Projector:
     no device memory."""
 
     def __init__(self, nx: int, ny: int, dx: float, dt: float = 1.0, rho0: float = 1.0,
-                 scales: int = 0, channels: int = 0, precision: str = "fp32", device=None):
+                 scales: int = 0, channels: int = 0, precision: str = "fp32", device=None,
+                 train: bool = False):
         self.lib = L.lib()
         self.nx, self.ny = int(nx), int(ny)
         self.grid = L.Grid(self.nx, self.ny, float(dx), float(dt), float(rho0))
@@ -55,7 +56,8 @@ class Projector:
         ctx = ctypes.c_void_p()
         desc = None
         if scales > 0:
-            desc = L.NetDesc(int(scales), int(channels), L.PRECISIONS[precision], 0)
+            desc = L.NetDesc(int(scales), int(channels), L.PRECISIONS[precision],
+                             L.NET_TRAIN if train else 0)
         L.check("hyp_create", self.lib.hyp_create(ctypes.byref(ctx), ctypes.byref(desc) if desc else None))
         self.ctx = ctx
         self.scales, self.channels, self.precision = scales, channels, precision
@@ -116,6 +118,40 @@ class Projector:
             self.ctx, ctypes.byref(self.grid), ctypes.byref(f), float(threshold), ctypes.byref(o),
             _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
 
+    def advect_async(self, rho, u, v, xi, g: float, drho: float, u_in: float = 1.0,
+                     cfl: float = 0.5):
+        """Enqueue the advection + force half step: u, v become u*."""
+        nx, ny = self.nx, self.ny
+        _need(rho, torch.float32, (ny, nx), "rho")
+        _need(u, torch.float32, (ny, nx + 1), "u")
+        _need(v, torch.float32, (ny + 1, nx), "v")
+        _need(xi, torch.float32, (nx,), "xi")
+        if not self.planned:
+            raise RuntimeError("call plan(flags) before advect")
+        ph = L.Physics(float(g), float(self.grid.rho0), float(drho), float(u_in), float(cfl))
+        st = L.State(_ptr(rho), _ptr(u), _ptr(v), None, None, _ptr(xi))
+        L.check("hyp_advect", self.lib.hyp_advect(self.ctx, ctypes.byref(self.grid), ctypes.byref(ph),
+                                                  ctypes.byref(st), _ptr(self.ws), self.ws.numel(),
+                                                  _stream()))
+
+    def backward_async(self, sweeps: int, omega: float = 1.0, scale: float = 1.0, du=None, dv=None,
+                       dparams=None, loss=None, accumulate: bool = False):
+        """Gradient of scale * sum_F r^2 after the last forward (hybrid with
+        fixed_iters = sweeps, or method 'cnn' for sweeps = 0)."""
+        nx, ny = self.nx, self.ny
+        if du is not None:
+            _need(du, torch.float32, (ny, nx + 1), "du")
+        if dv is not None:
+            _need(dv, torch.float32, (ny + 1, nx), "dv")
+        if dparams is not None:
+            _need(dparams, torch.float32, (self.param_count,), "dparams")
+        if loss is not None:
+            _need(loss, torch.float64, (1,), "loss")
+        L.check("hyp_project_backward", self.lib.hyp_project_backward(
+            self.ctx, ctypes.byref(self.grid), int(sweeps), float(omega), float(scale),
+            1 if accumulate else 0, _ptr(du), _ptr(dv), _ptr(dparams), _ptr(loss), _ptr(self.ws),
+            self.ws.numel(), _stream()))
+
     def set_timing(self, enable: bool = True):
         L.check("hyp_set_timing", self.lib.hyp_set_timing(self.ctx, 1 if enable else 0))
 
@@ -154,6 +190,44 @@ class Projector:
         L.check("hyp_step", self.lib.hyp_step(
             self.ctx, ctypes.byref(self.grid), ctypes.byref(ph), ctypes.byref(st), float(threshold),
             ctypes.byref(o), _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
+
+
+def adam_async(params, grads, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9,
+               beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam update of FP32 device tensors on the current stream."""
+    for t, name in ((params, "params"), (grads, "grads"), (m, "m"), (v, "v")):
+        _need(t, torch.float32, tuple(params.shape), name)
+    L.check("hyp_adam", L.lib().hyp_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(),
+                                         int(step), float(lr), float(beta1), float(beta2), float(eps),
+                                         _stream()))
+
+
+class ProjectionLoss(torch.autograd.Function):
+    """loss = scale * sum_F r^2 of the hybrid projection with `sweeps` fixed
+    Jacobi sweeps, differentiable w.r.t. u, v and the network parameters
+    through the library's hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, u, v, params, projector, flags, sweeps, omega, scale):
+        pr = projector
+        pr.set_weights(params)
+        uu, vv = u.detach().clone(), v.detach().clone()
+        p = torch.empty((pr.ny, pr.nx), dtype=torch.float32, device=u.device)
+        method = "hybrid" if sweeps > 0 else "cnn"
+        pr.project_async(uu, vv, flags, p, 0.0, method=method, fixed_iters=sweeps, omega=omega)
+        loss = torch.zeros(1, dtype=torch.float64, device=u.device)
+        du = torch.empty_like(u)
+        dv = torch.empty_like(v)
+        dp = torch.empty_like(params)
+        pr.backward_async(sweeps, omega, scale, du=du, dv=dv, dparams=dp, loss=loss)
+        ctx.save_for_backward(du, dv, dp)
+        return loss[0].to(torch.float32)
+
+    @staticmethod
+    def backward(ctx, gout):
+        du, dv, dp = ctx.saved_tensors
+        g = gout.to(torch.float32)
+        return g * du, g * dv, g * dp, None, None, None, None, None
 
 
 _CACHE: dict = {}

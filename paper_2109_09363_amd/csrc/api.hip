@@ -68,6 +68,17 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
     L.cnn_y = take(px * 4);
     L.cnn_t = take(px * 4);
     L.cnn_w = take((size_t)cnn_param_count(net.scales, net.channels) * act_elt);
+    if (net.train) {
+      const size_t C = net.channels;
+      L.cnn_save = take(4 * px * C * act_elt);
+      L.bw_cells = take(3 * 4 * n);
+      L.bw_t = take(4 * px);
+      L.bw_x = take(4 * px);
+      L.bw_a = take(4 * px * C);
+      L.bw_b = take(4 * px * C);
+      L.bw_part_n = (size_t)kWgBlocks * (C * 9 * C + C);
+      L.bw_part = take(4 * L.bw_part_n);
+    }
   }
   L.total = o;
   return L;
@@ -93,6 +104,14 @@ Ws ws_view(void* base, const WsLayout& L) {
   w.cnn_y = L.cnn_y ? (float*)(b + L.cnn_y) : nullptr;
   w.cnn_t = L.cnn_t ? (float*)(b + L.cnn_t) : nullptr;
   w.cnn_w = L.cnn_w ? b + L.cnn_w : nullptr;
+  w.cnn_save = L.cnn_save ? b + L.cnn_save : nullptr;
+  w.bw_cells = L.bw_cells ? (float*)(b + L.bw_cells) : nullptr;
+  w.bw_t = L.bw_t ? (float*)(b + L.bw_t) : nullptr;
+  w.bw_x = L.bw_x ? (float*)(b + L.bw_x) : nullptr;
+  w.bw_a = L.bw_a ? (float*)(b + L.bw_a) : nullptr;
+  w.bw_b = L.bw_b ? (float*)(b + L.bw_b) : nullptr;
+  w.bw_part = L.bw_part ? (float*)(b + L.bw_part) : nullptr;
+  w.bw_part_n = L.bw_part_n;
   return w;
 }
 
@@ -138,9 +157,11 @@ int hyp_create(hyp_ctx** out, const hyp_net_desc* net) {
     } else {
       return HYP_EINVAL;
     }
+    if (net->flags & ~HYP_NET_TRAIN) return HYP_EINVAL;
     ns.scales = net->scales;
     ns.channels = net->channels;
     ns.precision = net->precision;
+    ns.train = (net->flags & HYP_NET_TRAIN) != 0;
   }
   hyp_ctx* c = new (std::nothrow) hyp_ctx;
   if (!c) return HYP_EINTERNAL;
@@ -292,6 +313,44 @@ int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double thr
   ctx->timed_step = false;
   return enqueue_projection(ctx, g, f->u, f->v, f->p_init, f->p, threshold, o, L, w, false,
                             stream, res);
+}
+
+int hyp_project_backward(hyp_ctx* ctx, const hyp_grid* g, int32_t sweeps, float omega,
+                         double scale, int32_t accumulate, float* du, float* dv, float* dparams,
+                         double* loss, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx || !ws || !grid_ok(g) || sweeps < 0) return HYP_EINVAL;
+  if (ctx->net.scales == 0 || !ctx->params) return HYP_ENOWEIGHTS;
+  if (!ctx->net.train) return HYP_EUNSUPPORTED;
+  const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
+  if (ws_bytes < L.total) return HYP_EWORKSPACE;
+  const Ws w = ws_view(ws, L);
+  if (run_backward(ctx->net, L, g->nx, g->ny, g->dx, sweeps, omega, scale, accumulate != 0,
+                   ctx->params, du, dv, dparams, loss, w, stream) != hipSuccess)
+    return HYP_EHIP;
+  return HYP_OK;
+}
+
+int hyp_adam(float* params, const float* grads, float* m, float* v, int64_t n, int32_t step,
+             float lr, float beta1, float beta2, float eps, hipStream_t stream) {
+  if (!params || !grads || !m || !v || n <= 0 || step < 1) return HYP_EINVAL;
+  if (run_adam(params, grads, m, v, n, step, lr, beta1, beta2, eps, stream) != hipSuccess)
+    return HYP_EHIP;
+  return HYP_OK;
+}
+
+int hyp_advect(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_state* st,
+               void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx || !ph || !st || !ws) return HYP_EINVAL;
+  if (!g || g->nx < 2 || g->ny < 2 || !(g->dx > 0.0) || !(g->rho0 > 0.0)) return HYP_EINVAL;
+  if (!st->rho || !st->u || !st->v || !st->xi) return HYP_EINVAL;
+  if (!(ph->cfl > 0.0) || !(ph->u_in > 0.0) || !(ph->rho0 > 0.0)) return HYP_EINVAL;
+  const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
+  if (ws_bytes < L.total) return HYP_EWORKSPACE;
+  const Ws w = ws_view(ws, L);
+  if (run_advect(g->nx, g->ny, g->dx, ph->g, ph->rho0, ph->drho, ph->u_in, ph->cfl, st->rho, st->u,
+                 st->v, st->xi, w, stream) != hipSuccess)
+    return HYP_EHIP;
+  return HYP_OK;
 }
 
 int hyp_step(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_state* st,

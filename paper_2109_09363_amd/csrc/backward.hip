@@ -1,0 +1,579 @@
+// Adjoint of the hybrid projection for training with the solver in the loop
+// (the gradient of the correction of Eq. 2 is known, Sec. 3.2):
+//
+//   loss = scale * sum_F r^2,   r = d - L phi_K,
+//   phi_K = K Jacobi sweeps from phi0 = dx^2 s CNN([d/s, solid]; theta).
+//
+// Reverse sweep (L symmetric on fluid cells, kinv = 1/k_c):
+//   lam_r = 2 scale r;  lam_phi = -L lam_r;  lam_d = lam_r
+//   K times: lam_d -= omega dx^2 kinv lam;  lam <- (1-omega) lam + omega sum_n kinv_n lam_n
+//   CNN: lam_t0 = dx^2 s lam_phi0, upsample-sum transpose, 1x1 head, four
+//   3x3 layers (ReLU masks, weight gradients, input gradients with the
+//   replicate-padding adjoint), 2x2-mean pyramid transpose, the d/s
+//   normalisation with ds/dd, then D^T onto the faces.
+// Every reduction (loss, lambda_s, weight and bias gradients) is two-stage
+// with a fixed order, so the result is bitwise reproducible.  Activations
+// may be stored as FP32 or BF16; the adjoint arithmetic is FP32.
+#include "../../include/hyproj.h"
+#include "common.h"
+#include "internal.h"
+
+namespace hyp {
+
+template <typename T> __device__ __forceinline__ float ld(const T* p);
+template <> __device__ __forceinline__ float ld<float>(const float* p) { return *p; }
+template <> __device__ __forceinline__ float ld<uint16_t>(const uint16_t* p) {
+  return __uint_as_float((uint32_t)(*p) << 16);
+}
+
+// ---- solver part ----------------------------------------------------------
+__global__ __launch_bounds__(256) void bw_init(int nx, int ny, float inv_dx2, float scale2,
+                                               const uint8_t* __restrict__ cell,
+                                               const float* __restrict__ d,
+                                               const float* __restrict__ phi,
+                                               float* __restrict__ lam_r, float* __restrict__ lam_d,
+                                               double* __restrict__ blockpart) {
+  __shared__ double red[4];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  double rr = 0.0;
+  if (c < nx * ny) {
+    const uint8_t ci = cell[c];
+    float lam = 0.f;
+    if (!(ci & C_SOLID)) {
+      const int j = c / nx;
+      const float pe = (ci & C_E) ? phi[c + 1] : 0.f;
+      const float pw = (ci & C_W) ? phi[c - 1] : 0.f;
+      const float pn = ((ci & C_N) && j + 1 < ny) ? phi[c + nx] : 0.f;
+      const float ps = (ci & C_S) ? phi[c - nx] : 0.f;
+      const float r = d[c] - (((pe + pw) + (pn + ps)) - (float)cell_k(ci) * phi[c]) * inv_dx2;
+      lam = scale2 * r;
+      rr = (double)r * (double)r;
+    }
+    lam_r[c] = lam;
+    lam_d[c] = lam;
+  }
+  rr = block_sum(rr, red);
+  if (threadIdx.x == 0) blockpart[blockIdx.x] = rr;
+}
+
+__global__ __launch_bounds__(256) void bw_loss_finish(int nblocks, const double* __restrict__ bp,
+                                                      double scale, Scalars* sc, double* loss_out) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) a += bp[b];
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) {
+    sc->loss = scale * a;
+    if (loss_out) *loss_out = scale * a;
+  }
+}
+
+// out = -L in on fluid cells
+__global__ __launch_bounds__(256) void bw_neglap(int nx, int ny, float inv_dx2,
+                                                 const uint8_t* __restrict__ cell,
+                                                 const float* __restrict__ in,
+                                                 float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nx * ny) return;
+  const uint8_t ci = cell[c];
+  float o = 0.f;
+  if (!(ci & C_SOLID)) {
+    const int j = c / nx;
+    const float e = (ci & C_E) ? in[c + 1] : 0.f;
+    const float w = (ci & C_W) ? in[c - 1] : 0.f;
+    const float n = ((ci & C_N) && j + 1 < ny) ? in[c + nx] : 0.f;
+    const float s = (ci & C_S) ? in[c - nx] : 0.f;
+    o = -(((e + w) + (n + s)) - (float)cell_k(ci) * in[c]) * inv_dx2;
+  }
+  out[c] = o;
+}
+
+__device__ __forceinline__ float kinv_of(uint8_t c) {
+  return (c & C_SOLID) ? 0.f : 1.f / (float)cell_k(c);
+}
+
+// one reversed Jacobi sweep
+__global__ __launch_bounds__(256) void bw_jacobi(int nx, int ny, float omega, float wdx2,
+                                                 const uint8_t* __restrict__ cell,
+                                                 const float* __restrict__ lam,
+                                                 float* __restrict__ lam_out,
+                                                 float* __restrict__ lam_d) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nx * ny) return;
+  const uint8_t ci = cell[c];
+  if (ci & C_SOLID) {
+    lam_out[c] = 0.f;
+    return;
+  }
+  const int j = c / nx;
+  float sum = 0.f;
+  if (ci & C_E) sum += kinv_of(cell[c + 1]) * lam[c + 1];
+  if (ci & C_W) sum += kinv_of(cell[c - 1]) * lam[c - 1];
+  if ((ci & C_N) && j + 1 < ny) sum += kinv_of(cell[c + nx]) * lam[c + nx];
+  if (ci & C_S) sum += kinv_of(cell[c - nx]) * lam[c - nx];
+  const float l = lam[c];
+  lam_out[c] = (1.f - omega) * l + omega * sum;
+  lam_d[c] -= wdx2 * kinv_of(ci) * l;
+}
+
+// lam_t0 = dx^2 s lam_phi0 (fluid); partial sums of lam_phi0 * t0 for lam_s
+__global__ __launch_bounds__(256) void bw_phi0(int n, float dx2, const uint8_t* __restrict__ cell,
+                                               const float* __restrict__ lam,
+                                               const float* __restrict__ t0,
+                                               float* __restrict__ lam_t0,
+                                               double* __restrict__ blockpart, const Scalars* sc) {
+  __shared__ double red[4];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  double a = 0.0;
+  const float s = (float)sc->s;
+  if (c < n) {
+    const bool fl = !(cell[c] & C_SOLID);
+    const float l = fl ? lam[c] : 0.f;
+    lam_t0[c] = dx2 * s * l;
+    a = (double)l * (double)t0[c];
+  }
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) blockpart[blockIdx.x] = a;
+}
+
+__global__ __launch_bounds__(256) void bw_lams_set(int nblocks, const double* __restrict__ bp,
+                                                   double dx2, Scalars* sc) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) a += bp[b];
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) sc->lam_s = dx2 * a;
+}
+
+// Adjoint of up2 (bilinear x2, half-pixel centres, clamp): a coarse pixel
+// gathers from the fine pixels whose interpolation stencil uses it.
+__device__ __forceinline__ void up_axis(int J, int nc, int* i0, int* i1, float* f) {
+  float c = fminf(fmaxf(0.5f * (float)J - 0.25f, 0.f), (float)(nc - 1));
+  int a = min((int)floorf(c), max(nc - 2, 0));
+  *i0 = a;
+  *i1 = min(a + 1, nc - 1);
+  *f = c - (float)a;
+}
+
+__global__ __launch_bounds__(256) void bw_up2T(int Hc, int Wc, const float* __restrict__ fine,
+                                               float* __restrict__ coarse) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= Hc * Wc) return;
+  const int X = gid % Wc, Y = gid / Wc;
+  const int Hf = 2 * Hc, Wf = 2 * Wc;
+  float acc = 0.f;
+  for (int J = max(2 * Y - 2, 0); J <= min(2 * Y + 3, Hf - 1); ++J) {
+    int y0, y1;
+    float fy;
+    up_axis(J, Hc, &y0, &y1, &fy);
+    const float wy = (y0 == Y ? 1.f - fy : 0.f) + (y1 == Y ? fy : 0.f);
+    if (wy == 0.f) continue;
+    for (int I = max(2 * X - 2, 0); I <= min(2 * X + 3, Wf - 1); ++I) {
+      int x0, x1;
+      float fx;
+      up_axis(I, Wc, &x0, &x1, &fx);
+      const float wx = (x0 == X ? 1.f - fx : 0.f) + (x1 == X ? fx : 0.f);
+      if (wx == 0.f) continue;
+      acc += wy * wx * fine[J * Wf + I];
+    }
+  }
+  coarse[gid] = acc;
+}
+
+// ---- CNN part ---------------------------------------------------------------
+// head: lam_pre3[px][c] = lam_y[px] wo[c] (h4 > 0); partial dwo, dbo
+template <typename T, int C>
+__global__ __launch_bounds__(256) void bw_head(int npx, const float* __restrict__ lam_y,
+                                               const T* __restrict__ h4,
+                                               const float* __restrict__ wo,
+                                               float* __restrict__ lam_pre,
+                                               float* __restrict__ part) {
+  const int p0 = blockIdx.x * 256;
+  const int px = p0 + threadIdx.x;
+  if (px < npx) {
+    const float ly = lam_y[px];
+    for (int c = 0; c < C; ++c) {
+      const float h = ld<T>(h4 + (size_t)px * C + c);
+      lam_pre[(size_t)px * C + c] = h > 0.f ? ly * wo[c] : 0.f;
+    }
+  }
+  if (threadIdx.x <= C) {
+    float acc = 0.f;
+    const int c = threadIdx.x;
+    for (int q = p0; q < min(p0 + 256, npx); ++q)
+      acc += lam_y[q] * (c < C ? ld<T>(h4 + (size_t)q * C + c) : 1.f);
+    part[(size_t)blockIdx.x * (C + 1) + c] = acc;
+  }
+}
+
+// fixed-order sum of per-block partials into the packed gradient
+__global__ __launch_bounds__(256) void bw_part_finish(int nblocks, int nout,
+                                                      const float* __restrict__ part,
+                                                      float* __restrict__ out, int accumulate) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nout) return;
+  float acc = 0.f;
+  for (int b = 0; b < nblocks; ++b) acc += part[(size_t)b * nout + e];
+  out[e] = accumulate ? out[e] + acc : acc;
+}
+
+constexpr int BT = 16;       // backward tile side
+constexpr int BE = BT + 2;
+
+// Weight and bias gradients of one 3x3 layer at one scale:
+//   dW[co][tap][ci] = sum_px lam_pre[px][co] in[clamp(px + tap - 1)][ci]
+//   db[co]          = sum_px lam_pre[px][co]
+// grid.x blocks take tiles bx, bx + gridDim.x, ...; grid.y splits the
+// outputs into chunks of 256 * NACC; partials go to part[bx][out].
+template <typename T, int CIN, int COUT, int NACC>
+__global__ __launch_bounds__(256) void bw_wgrad(int H, int W, const T* __restrict__ in,
+                                                const float* __restrict__ lam_pre,
+                                                float* __restrict__ part) {
+  extern __shared__ __attribute__((aligned(16))) float lds_w[];
+  float* lt = lds_w;                 // [BT*BT][COUT]
+  float* xt = lds_w + BT * BT * COUT; // [BE*BE][CIN]
+  constexpr int NOUT = COUT * 9 * CIN + COUT;
+  const int tiles_x = (W + BT - 1) / BT, tiles = tiles_x * ((H + BT - 1) / BT);
+  const int e0 = blockIdx.y * 256 * NACC;
+  float acc[NACC];
+#pragma unroll
+  for (int m = 0; m < NACC; ++m) acc[m] = 0.f;
+  for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int x0 = (t % tiles_x) * BT, y0 = (t / tiles_x) * BT;
+    __syncthreads();
+    for (int e = threadIdx.x; e < BT * BT * COUT; e += 256) {
+      const int q = e / COUT, co = e % COUT;
+      const int gy = y0 + q / BT, gx = x0 + q % BT;
+      lt[e] = (gy < H && gx < W) ? lam_pre[((size_t)gy * W + gx) * COUT + co] : 0.f;
+    }
+    for (int e = threadIdx.x; e < BE * BE * CIN; e += 256) {
+      const int q = e / CIN, ci = e % CIN;
+      const int gy = min(max(y0 - 1 + q / BE, 0), H - 1);
+      const int gx = min(max(x0 - 1 + q % BE, 0), W - 1);
+      xt[e] = ld<T>(in + ((size_t)gy * W + gx) * CIN + ci);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NACC; ++m) {
+      const int e = e0 + m * 256 + threadIdx.x;
+      if (e >= NOUT) break;
+      float a = 0.f;
+      if (e < COUT * 9 * CIN) {
+        const int co = e / (9 * CIN), rem = e % (9 * CIN), tap = rem / CIN, ci = rem % CIN;
+        const int ky = tap / 3, kx = tap % 3;
+        for (int q = 0; q < BT * BT; ++q)
+          a += lt[q * COUT + co] * xt[((q / BT + ky) * BE + (q % BT) + kx) * CIN + ci];
+      } else {
+        const int co = e - COUT * 9 * CIN;
+        for (int q = 0; q < BT * BT; ++q) a += lt[q * COUT + co];
+      }
+      acc[m] += a;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NACC; ++m) {
+    const int e = e0 + m * 256 + threadIdx.x;
+    if (e < NOUT) part[(size_t)blockIdx.x * NOUT + e] = acc[m];
+  }
+}
+
+// Input gradient of one 3x3 layer (transposed convolution with the
+// replicate-padding adjoint): lam_in[y][x][ci] = sum over taps and the
+// output pixels whose clamped stencil reads (y, x).  With MASK the result
+// is multiplied by (h_in > 0), the ReLU of the layer below; with ONLY_C0
+// only input channel 0 is produced (the normalised divergence).
+template <typename T, int CIN, int COUT, bool MASK, bool ONLY_C0>
+__global__ __launch_bounds__(256) void bw_dgrad(int H, int W, const float* __restrict__ lam_pre,
+                                                const float* __restrict__ Wt,
+                                                const T* __restrict__ h_in,
+                                                float* __restrict__ lam_in) {
+  extern __shared__ __attribute__((aligned(16))) float lds_d[];  // [BE*BE][COUT]
+  const int tiles_x = (W + BT - 1) / BT;
+  const int x0 = (blockIdx.x % tiles_x) * BT, y0 = (blockIdx.x / tiles_x) * BT;
+  for (int e = threadIdx.x; e < BE * BE * COUT; e += 256) {
+    const int q = e / COUT, co = e % COUT;
+    const int gy = y0 - 1 + q / BE, gx = x0 - 1 + q % BE;
+    lds_d[e] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? lam_pre[((size_t)gy * W + gx) * COUT + co] : 0.f;
+  }
+  __syncthreads();
+  const int ty = threadIdx.x / BT, tx = threadIdx.x % BT;
+  const int y = y0 + ty, x = x0 + tx;
+  if (y >= H || x >= W) return;
+  constexpr int NC = ONLY_C0 ? 1 : CIN;
+  float acc[NC];
+#pragma unroll
+  for (int ci = 0; ci < NC; ++ci) acc[ci] = 0.f;
+  for (int ky = 0; ky < 3; ++ky) {
+    int cy[2], ny_ = 0;
+    { const int p = y - ky + 1; if (p >= 0 && p < H) cy[ny_++] = p; }
+    if (y == 0 && ky == 0) cy[ny_++] = 0;
+    if (y == H - 1 && ky == 2) cy[ny_++] = H - 1;
+    for (int kx = 0; kx < 3; ++kx) {
+      int cx[2], nx_ = 0;
+      { const int p = x - kx + 1; if (p >= 0 && p < W) cx[nx_++] = p; }
+      if (x == 0 && kx == 0) cx[nx_++] = 0;
+      if (x == W - 1 && kx == 2) cx[nx_++] = W - 1;
+      const float* wk = Wt + (ky * 3 + kx) * CIN;
+      for (int a = 0; a < ny_; ++a)
+        for (int b = 0; b < nx_; ++b) {
+          const float* lp = lds_d + ((cy[a] - y0 + 1) * BE + (cx[b] - x0 + 1)) * COUT;
+          for (int co = 0; co < COUT; ++co) {
+            const float l = lp[co];
+            const float* wr = wk + (size_t)co * 9 * CIN;
+#pragma unroll
+            for (int ci = 0; ci < NC; ++ci) acc[ci] += wr[ci] * l;
+          }
+        }
+    }
+  }
+  const size_t px = (size_t)y * W + x;
+  if constexpr (ONLY_C0) {
+    lam_in[px] = acc[0];
+  } else {
+#pragma unroll
+    for (int ci = 0; ci < NC; ++ci) {
+      float v = acc[ci];
+      if (MASK) v = ld<T>(h_in + px * CIN + ci) > 0.f ? v : 0.f;
+      lam_in[px * CIN + ci] = v;
+    }
+  }
+}
+
+// pyramid transpose: lam_x(c) = sum_k lam_xk[parent] / 4^k on fluid cells;
+// partial sums of lam_x * d for lam_s.
+struct PyrT {
+  const float* lx[5];
+  int nscales;
+};
+
+__device__ __forceinline__ float pyr_lam(const PyrT& P, int i, int j, int nx) {
+  float a = 0.f;
+  for (int k = 0; k < P.nscales; ++k) {
+    const int Wk = nx >> k;
+    a += P.lx[k][(j >> k) * Wk + (i >> k)] * (1.f / (float)(1 << (2 * k)));
+  }
+  return a;
+}
+
+__global__ __launch_bounds__(256) void bw_pyr_sum(int nx, int ny, PyrT P,
+                                                  const uint8_t* __restrict__ cell,
+                                                  const float* __restrict__ d,
+                                                  double* __restrict__ blockpart) {
+  __shared__ double red[4];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  double a = 0.0;
+  if (c < nx * ny && !(cell[c] & C_SOLID)) a = (double)pyr_lam(P, c % nx, c / nx, nx) * (double)d[c];
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) blockpart[blockIdx.x] = a;
+}
+
+__global__ __launch_bounds__(256) void bw_lams_add(int nblocks, const double* __restrict__ bp,
+                                                   Scalars* sc) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) a += bp[b];
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) {
+    const double s = sc->s;
+    if (s > 0.0) sc->lam_s -= a / (s * s);
+  }
+}
+
+__global__ __launch_bounds__(256) void bw_dnorm(int nx, int ny, PyrT P,
+                                                const uint8_t* __restrict__ cell,
+                                                const float* __restrict__ d,
+                                                float* __restrict__ lam_d, const Scalars* sc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nx * ny || (cell[c] & C_SOLID)) return;
+  const double s = sc->s;
+  if (!(s > 0.0)) return;
+  const float inv_s = (float)(1.0 / s);
+  const float ks = (float)(sc->lam_s / ((double)sc->nF * s));
+  lam_d[c] += pyr_lam(P, c % nx, c / nx, nx) * inv_s + ks * d[c];
+}
+
+// D^T: face gradients from lam_d (open interior faces, open top faces,
+// inflow faces; closed faces get 0)
+__global__ __launch_bounds__(256) void bw_faces(int nx, int ny, float inv_dx,
+                                                const uint8_t* __restrict__ cell,
+                                                const float* __restrict__ lam_d,
+                                                float* __restrict__ du, float* __restrict__ dv,
+                                                int accumulate) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nx * ny) return;
+  const int i = c % nx, j = c / nx, U = nx + 1;
+  const uint8_t ci = cell[c];
+  const bool fl = !(ci & C_SOLID);
+  const float l = fl ? lam_d[c] : 0.f;
+  float gw = 0.f, gs = 0.f, gn = 0.f;
+  if (fl && (ci & C_W)) gw = (lam_d[c - 1] - l) * inv_dx;
+  if (j == 0) gs = (fl && (ci & C_INFLOW)) ? -l * inv_dx : 0.f;
+  else if (fl && (ci & C_S)) gs = (lam_d[c - nx] - l) * inv_dx;
+  if (j == ny - 1 && fl && (ci & C_N)) gn = l * inv_dx;
+  if (du) {
+    du[j * U + i] = accumulate ? du[j * U + i] + gw : gw;
+    if (i == nx - 1 && !accumulate) du[j * U + nx] = 0.f;
+  }
+  if (dv) {
+    dv[j * nx + i] = accumulate ? dv[j * nx + i] + gs : gs;
+    if (j == ny - 1) dv[ny * nx + i] = accumulate ? dv[ny * nx + i] + gn : gn;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int CIN, int COUT>
+static hipError_t wgrad_layer(int H, int W, const T* in, const float* lam_pre, float* part,
+                              size_t part_n, float* dst, int accumulate, hipStream_t s) {
+  constexpr int NACC = 36;
+  constexpr int NOUT = COUT * 9 * CIN + COUT;
+  const int tiles = ((W + BT - 1) / BT) * ((H + BT - 1) / BT);
+  const int gx = min(tiles, kWgBlocks);
+  if ((size_t)gx * NOUT > part_n) return hipErrorInvalidValue;
+  const int gy = (NOUT + 256 * NACC - 1) / (256 * NACC);
+  const size_t lds = sizeof(float) * (BT * BT * COUT + BE * BE * CIN);
+  auto k = bw_wgrad<T, CIN, COUT, NACC>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(gx, gy), dim3(256), lds, s, H, W, in, lam_pre, part);
+  hipLaunchKernelGGL(bw_part_finish, dim3((NOUT + 255) / 256), dim3(256), 0, s, gx, NOUT, part,
+                     dst, accumulate);
+  return hipGetLastError();
+}
+
+template <typename T, int CIN, int COUT, bool MASK, bool ONLY_C0>
+static hipError_t dgrad_layer(int H, int W, const float* lam_pre, const float* Wt, const T* h_in,
+                              float* lam_in, hipStream_t s) {
+  const int tiles = ((W + BT - 1) / BT) * ((H + BT - 1) / BT);
+  const size_t lds = sizeof(float) * BE * BE * COUT;
+  auto k = bw_dgrad<T, CIN, COUT, MASK, ONLY_C0>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(tiles), dim3(256), lds, s, H, W, lam_pre, Wt, h_in, lam_in);
+  return hipGetLastError();
+}
+
+template <typename T, int C>
+static hipError_t backward_cnn(const NetShape& net, const WsLayout& Ly, int nx, int ny,
+                               const float* params, float* dparams, int acc, const Ws& w,
+                               hipStream_t s) {
+  const int S = net.scales;
+  const size_t per_scale = (size_t)C * 18 + C + 3 * ((size_t)C * 9 * C + C) + C + 1;
+  const size_t hoff = (size_t)C * 18 + C + 3 * ((size_t)C * 9 * C + C);
+  const T* save = reinterpret_cast<const T*>(w.cnn_save);
+  const T* in = reinterpret_cast<const T*>(w.cnn_in);
+  auto act = [&](int l) { return save + (size_t)l * Ly.total_px * C; };  // output of layer l
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < S; ++k) {
+    const int H = Ly.sc_h[k], W = Ly.sc_w[k], npx = H * W;
+    const size_t off = Ly.sc_off_px[k];
+    const float* pk = params + k * per_scale;
+    float* gk = dparams ? dparams + k * per_scale : nullptr;
+    float* la = w.bw_a + off * C;  // lambda_pre of the current layer
+    float* lb = w.bw_b + off * C;
+    // head
+    const int nbh = (npx + 255) / 256;
+    if ((size_t)nbh * (C + 1) > w.bw_part_n) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((bw_head<T, C>), dim3(nbh), dim3(256), 0, s, npx, w.bw_t + off,
+                       act(3) + off * C, pk + hoff, la, w.bw_part);
+    if (gk) hipLaunchKernelGGL(bw_part_finish, dim3(1), dim3(256), 0, s, nbh, C + 1, w.bw_part,
+                               gk + hoff, acc);
+    for (int l = 3; l >= 0; --l) {
+      const size_t woff = l == 0 ? 0 : (size_t)C * 18 + C + (size_t)(l - 1) * ((size_t)C * 9 * C + C);
+      const float* Wt = pk + woff;
+      if (l == 0) {
+        if (gk) e = wgrad_layer<T, 2, C>(H, W, in + off * 2, la, w.bw_part, w.bw_part_n, gk + woff, acc, s);
+        if (e != hipSuccess) return e;
+        e = dgrad_layer<T, 2, C, false, true>(H, W, la, Wt, nullptr, w.bw_x + off, s);
+      } else {
+        if (gk) e = wgrad_layer<T, C, C>(H, W, act(l - 1) + off * C, la, w.bw_part, w.bw_part_n, gk + woff, acc, s);
+        if (e != hipSuccess) return e;
+        e = dgrad_layer<T, C, C, true, false>(H, W, la, Wt, act(l - 1) + off * C, lb, s);
+        float* t = la; la = lb; lb = t;
+      }
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_backward(const NetShape& net, const WsLayout& Ly, int nx, int ny, double dx,
+                        int sweeps, float omega, double scale, bool accumulate,
+                        const float* params, float* du, float* dv, float* dparams,
+                        double* loss_out, const Ws& w, hipStream_t s) {
+  const int n = nx * ny, nb = (n + 255) / 256;
+  if ((size_t)nb > w.blockpart_n) return hipErrorInvalidValue;
+  float* lamA = w.bw_cells;
+  float* lamB = w.bw_cells + n;
+  float* lamD = w.bw_cells + 2 * (size_t)n;
+  const float inv_dx2 = (float)(1.0 / (dx * dx));
+  bw_init<<<nb, 256, 0, s>>>(nx, ny, inv_dx2, (float)(2.0 * scale), w.cell, w.d, w.phi, lamA, lamD,
+                             w.blockpart);
+  bw_loss_finish<<<1, 256, 0, s>>>(nb, w.blockpart, scale, w.sc, loss_out);
+  bw_neglap<<<nb, 256, 0, s>>>(nx, ny, inv_dx2, w.cell, lamA, lamB);
+  float* cur = lamB;
+  float* nxt = lamA;
+  const float wdx2 = (float)(omega * dx * dx);
+  for (int k = 0; k < sweeps; ++k) {
+    bw_jacobi<<<nb, 256, 0, s>>>(nx, ny, omega, wdx2, w.cell, cur, nxt, lamD);
+    float* t = cur; cur = nxt; nxt = t;
+  }
+  // CNN
+  bw_phi0<<<nb, 256, 0, s>>>(n, (float)(dx * dx), w.cell, cur, w.cnn_t, w.bw_t, w.blockpart, w.sc);
+  bw_lams_set<<<1, 256, 0, s>>>(nb, w.blockpart, dx * dx, w.sc);
+  for (int k = 0; k + 1 < net.scales; ++k) {
+    const int Hc = Ly.sc_h[k + 1], Wc = Ly.sc_w[k + 1];
+    bw_up2T<<<(Hc * Wc + 255) / 256, 256, 0, s>>>(Hc, Wc, w.bw_t + Ly.sc_off_px[k],
+                                                  w.bw_t + Ly.sc_off_px[k + 1]);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int acc = accumulate ? 1 : 0;
+  if (net.precision == HYP_PREC_BF16) {
+    switch (net.channels) {
+      case 32: e = backward_cnn<uint16_t, 32>(net, Ly, nx, ny, params, dparams, acc, w, s); break;
+      case 64: e = backward_cnn<uint16_t, 64>(net, Ly, nx, ny, params, dparams, acc, w, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (net.channels) {
+      case 16: e = backward_cnn<float, 16>(net, Ly, nx, ny, params, dparams, acc, w, s); break;
+      case 32: e = backward_cnn<float, 32>(net, Ly, nx, ny, params, dparams, acc, w, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (e != hipSuccess) return e;
+  PyrT P{};
+  P.nscales = net.scales;
+  for (int k = 0; k < net.scales; ++k) P.lx[k] = w.bw_x + Ly.sc_off_px[k];
+  bw_pyr_sum<<<nb, 256, 0, s>>>(nx, ny, P, w.cell, w.d, w.blockpart);
+  bw_lams_add<<<1, 256, 0, s>>>(nb, w.blockpart, w.sc);
+  bw_dnorm<<<nb, 256, 0, s>>>(nx, ny, P, w.cell, w.d, lamD, w.sc);
+  if (du || dv)
+    bw_faces<<<nb, 256, 0, s>>>(nx, ny, (float)(1.0 / dx), w.cell, lamD, du, dv, acc);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v,
+                                                   int64_t n, float lr, float b1, float b2,
+                                                   float eps, float bc1, float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+hipError_t run_adam(float* params, const float* grads, float* m, float* v, int64_t n, int step,
+                    float lr, float b1, float b2, float eps, hipStream_t s) {
+  const float bc1 = (float)(1.0 - pow((double)b1, step));
+  const float bc2 = (float)(1.0 - pow((double)b2, step));
+  adam_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(params, grads, m, v, n, lr, b1, b2, eps,
+                                                         bc1, bc2);
+  return hipGetLastError();
+}
+
+}  // namespace hyp

@@ -374,7 +374,9 @@ static hipError_t run_cnn_t(const Device& dev, const NetShape& net, const WsLayo
   // four 3x3 layers, all scales per launch
   const T* src = in;
   T* bufs[2] = {a0, a1};
+  T* save = reinterpret_cast<T*>(w.cnn_save);
   for (int l = 0; l < 4; ++l) {
+    T* dst = net.train ? save + (size_t)l * Ly.total_px * C : bufs[l & 1];
     ConvLaunch L{};
     L.nscales = S;
     int tiles = 0;
@@ -383,7 +385,7 @@ static hipError_t run_cnn_t(const Device& dev, const NetShape& net, const WsLayo
     for (int k = 0; k < S; ++k) {
       ScaleDesc& D = L.sc[k];
       D.in = src + Ly.sc_off_px[k] * cin;
-      D.out = bufs[l & 1] + Ly.sc_off_px[k] * C;
+      D.out = dst + Ly.sc_off_px[k] * C;
       D.w = params + k * per_scale + woff;
       D.b = D.w + (size_t)C * 9 * cin;
       D.H = Ly.sc_h[k];
@@ -415,7 +417,7 @@ static hipError_t run_cnn_t(const Device& dev, const NetShape& net, const WsLayo
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    src = bufs[l & 1];
+    src = dst;
   }
   // 1x1 head for every scale
   HeadLaunch Hd{};

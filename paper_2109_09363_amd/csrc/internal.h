@@ -22,6 +22,8 @@ struct Scalars {
   int32_t plan_rounds;
   unsigned bar;       // grid-barrier counter (zeroed before each launch)
   unsigned pad[3];
+  double lam_s;       // adjoint of the CNN input scale s
+  double loss;        // last backward's loss
 };
 
 constexpr int kMaxCoopBlocks = 1024;   // partial-sum slots per parity
@@ -29,13 +31,18 @@ constexpr int kStreamBlock = 256;      // threads of the streaming kernels
 
 struct NetShape {
   int scales = 0, channels = 0, precision = 0;
+  bool train = false;  // keep every layer's activations for the backward pass
 };
+
+constexpr int kWgBlocks = 128;  // pixel-chunk blocks of the weight-gradient reduction
 
 // Byte offsets into the caller's workspace (all 256-byte aligned).
 struct WsLayout {
   size_t cell = 0, d = 0, phi = 0, exch = 0, blockpart = 0, partial = 0,
          scalars = 0, reach = 0, pcg = 0, adv = 0;
   size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0;
+  size_t cnn_save = 0, bw_cells = 0, bw_t = 0, bw_x = 0, bw_a = 0, bw_b = 0, bw_part = 0;
+  size_t bw_part_n = 0;
   size_t total = 0;
   size_t blockpart_n = 0;
   int nblocks_stream = 0;
@@ -61,6 +68,14 @@ struct Ws {
   float* pcg;         // PCG scratch
   float* adv;         // advection temporaries: 2 x (cells + u faces + v faces)
   void* cnn_in; void* cnn_act0; void* cnn_act1; float* cnn_y; float* cnn_t; void* cnn_w;
+  void* cnn_save;     // training: 4 layers x total_px x C activations
+  float* bw_cells;    // backward: 3 x cells (lambda ping-pong, lambda_d)
+  float* bw_t;        // backward: lambda of t / y, all scales
+  float* bw_x;        // backward: lambda of input channel 0, all scales
+  float* bw_a;        // backward: activation lambdas (total_px x C) x 2
+  float* bw_b;
+  float* bw_part;     // backward: weight-gradient partials
+  size_t bw_part_n;
 };
 Ws ws_view(void* base, const WsLayout& L);
 
@@ -88,6 +103,12 @@ hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt
 hipError_t run_advect(int nx, int ny, double dx, double g, double rho0, double drho, double u_in,
                       double cfl, float* rho, float* u, float* v, const float* xi, const Ws& w,
                       hipStream_t s);
+hipError_t run_backward(const NetShape& net, const WsLayout& L, int nx, int ny, double dx,
+                        int sweeps, float omega, double scale, bool accumulate,
+                        const float* params, float* du, float* dv, float* dparams,
+                        double* loss_out, const Ws& w, hipStream_t s);
+hipError_t run_adam(float* params, const float* grads, float* m, float* v, int64_t n, int step,
+                    float lr, float b1, float b2, float eps, hipStream_t s);
 hipError_t run_cnn(const Device& dev, const NetShape& net, const WsLayout& L, int nx, int ny,
                    double dx, const float* params, const Ws& w, hipStream_t s);
 

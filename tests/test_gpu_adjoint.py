@@ -1,0 +1,160 @@
+"""GPU adjoint of the hybrid projection against the FP64 oracle gradient and
+against finite differences of the GPU's own loss."""
+import numpy as np
+import pytest
+import torch
+
+import scenes
+import paper_2109_09363_amd as hp
+from oracle import adjoint as AJ
+from oracle import cnn as CN
+from tests.gpu_util import to_dev, f32, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+class Run:
+    """Forward + backward on the GPU through the C ABI."""
+
+    def __init__(self, sc, S, C, prec="fp32"):
+        self.sc = sc
+        self.pr = hp.Projector(sc.nx, sc.ny, sc.dx, 1.0, 1.0, S, C, prec, train=True)
+        self.tf = to_dev(sc.flags, torch.uint8)
+        self.pr.plan(self.tf)
+        self.S, self.C = S, C
+
+    def __call__(self, u, v, w, K, omega=1.0, scale=1.0, grads=True):
+        pr = self.pr
+        tw = to_dev(w)
+        pr.set_weights(tw)
+        tu, tv = to_dev(u), to_dev(v)
+        p = torch.empty((pr.ny, pr.nx), dtype=torch.float32, device="cuda")
+        pr.project_async(tu, tv, self.tf, p, 0.0, method="hybrid" if K > 0 else "cnn",
+                         fixed_iters=K, omega=omega)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        du = torch.empty((pr.ny, pr.nx + 1), dtype=torch.float32, device="cuda") if grads else None
+        dv = torch.empty((pr.ny + 1, pr.nx), dtype=torch.float32, device="cuda") if grads else None
+        dp = torch.empty(pr.param_count, dtype=torch.float32, device="cuda") if grads else None
+        pr.backward_async(K, omega, scale, du=du, dv=dv, dparams=dp, loss=loss)
+        torch.cuda.synchronize()
+        out = dict(loss=float(loss.item()))
+        if grads:
+            out.update(du=du.cpu().numpy().astype(np.float64), dv=dv.cpu().numpy().astype(np.float64),
+                       dp=dp.cpu().numpy().astype(np.float64))
+        return out
+
+
+def state(n, seed, nobs, ny=None):
+    sc = scenes.plume_scene(n, seed=seed, n_obstacles=nobs, ny=ny)
+    u, v = scenes.random_faces(sc.nx, sc.ny, seed, kind="mixed")
+    return sc, f32(u), f32(v)
+
+
+@pytest.mark.parametrize("n,ny,S,C,K,omega,seed", [
+    (32, None, 2, 16, 0, 1.0, 0), (32, None, 2, 16, 5, 1.0, 1), (48, 32, 3, 16, 7, 0.8, 2),
+    (64, None, 3, 32, 20, 1.0, 3)])
+def test_backward_matches_oracle(n, ny, S, C, K, omega, seed):
+    say("adjoint", n, ny, S, C, K)
+    sc, u, v = state(n, seed, 2, ny)
+    w = f32(scenes.random_weights(S, C, seed))
+    g = Run(sc, S, C)(u, v, w, K, omega)
+    loss, gu, gv, gp = AJ.loss_and_grad(sc.flags, u, v, sc.dx, w, S, C, K, omega)
+    say("  loss", g["loss"], loss)
+    say("  rel L2 dparams", rel_l2(g["dp"], gp), "du", rel_l2(g["du"], gu), "dv", rel_l2(g["dv"], gv))
+    assert g["loss"] == pytest.approx(loss, rel=1e-5)
+    assert rel_l2(g["dp"], gp) <= 1e-4
+    assert rel_l2(g["du"], gu) <= 1e-4
+    assert rel_l2(g["dv"], gv) <= 1e-4
+
+
+def test_backward_bf16_close_to_fp64():
+    sc, u, v = state(64, 4, 1)
+    w = f32(scenes.random_weights(3, 32, 4))
+    g = Run(sc, 3, 32, "bf16")(u, v, w, 4)
+    loss, gu, gv, gp = AJ.loss_and_grad(sc.flags, u, v, sc.dx, w, 3, 32, 4)
+    say("  bf16 rel L2 dparams", rel_l2(g["dp"], gp), "du", rel_l2(g["du"], gu))
+    assert rel_l2(g["dp"], gp) <= 5e-2 and rel_l2(g["du"], gu) <= 5e-2
+
+
+def test_backward_deterministic_and_accumulate():
+    sc, u, v = state(64, 5, 2)
+    w = f32(scenes.random_weights(3, 16, 5))
+    r = Run(sc, 3, 16)
+    a = r(u, v, w, 6)
+    b = r(u, v, w, 6)
+    assert np.array_equal(a["dp"], b["dp"]) and np.array_equal(a["du"], b["du"])
+    # accumulate adds onto the existing gradient
+    pr = r.pr
+    dp = torch.from_numpy(a["dp"].astype(np.float32)).cuda()
+    pr.backward_async(6, 1.0, 1.0, dparams=dp, accumulate=True)
+    torch.cuda.synchronize()
+    assert np.allclose(dp.cpu().numpy(), 2 * a["dp"], rtol=1e-6, atol=0)
+
+
+def snap(x, bits=20):
+    return np.round(np.asarray(x, np.float64) * 2.0 ** bits) / 2.0 ** bits
+
+
+def test_fd_head_parameters_exact_quadratic():
+    # the loss is exactly quadratic in the 1x1 head (no ReLU after it): the
+    # central difference has no truncation error, only FP32 rounding
+    S, C, K = 3, 16, 10
+    sc, u, v = state(64, 6, 1)
+    w = snap(scenes.random_weights(S, C, 6))
+    run = Run(sc, S, C)
+    g = run(u, v, w, K)
+    rng = np.random.default_rng(0)
+    dirn = np.zeros_like(w)
+    per = CN.param_count(1, C)
+    for k in range(S):
+        o = k * per + per - (C + 1)
+        dirn[o:o + C + 1] = rng.choice([-1.0, 1.0], C + 1)
+    gd = float(g["dp"] @ dirn)
+    for h, tol in ((2.0 ** -10, 1e-3), (2.0 ** -3, 1e-5)):
+        lp = run(u, v, w + h * dirn, K, grads=False)["loss"]
+        lm = run(u, v, w - h * dirn, K, grads=False)["loss"]
+        fd = (lp - lm) / (2 * h)
+        say("  head FD h", h, fd, "adjoint", gd)
+        assert fd == pytest.approx(gd, rel=tol)
+
+
+def test_fd_velocity_with_zero_network_exact_quadratic():
+    # zero weights: phi0 = 0 and the loss is a quadratic form of u, v
+    S, C, K = 3, 16, 12
+    sc, u, v = state(64, 7, 2)
+    u, v = snap(u), snap(v)
+    w = np.zeros(CN.param_count(S, C))
+    run = Run(sc, S, C)
+    g = run(u, v, w, K)
+    rng = np.random.default_rng(1)
+    du = rng.choice([-1.0, 1.0], u.shape)
+    dv = rng.choice([-1.0, 1.0], v.shape)
+    gd = float(np.sum(g["du"] * du) + np.sum(g["dv"] * dv))
+    for h, tol in ((2.0 ** -10, 1e-3), (2.0 ** -4, 1e-5)):
+        lp = run(u + h * du, v + h * dv, w, K, grads=False)["loss"]
+        lm = run(u - h * du, v - h * dv, w, K, grads=False)["loss"]
+        fd = (lp - lm) / (2 * h)
+        say("  velocity FD h", h, fd, "adjoint", gd)
+        assert fd == pytest.approx(gd, rel=tol)
+
+
+def test_autograd_function():
+    S, C, K = 2, 16, 3
+    sc, u, v = state(32, 8, 1)
+    w = f32(scenes.random_weights(S, C, 8))
+    pr = hp.Projector(32, 32, sc.dx, 1.0, 1.0, S, C, "fp32", train=True)
+    tf = to_dev(sc.flags, torch.uint8)
+    pr.plan(tf)
+    tu = to_dev(u).requires_grad_(True)
+    tv = to_dev(v).requires_grad_(True)
+    tw = to_dev(w).requires_grad_(True)
+    loss = hp.ProjectionLoss.apply(tu, tv, tw, pr, tf, K, 1.0, 0.5)
+    (3.0 * loss).backward()
+    l0, gu, gv, gp = AJ.loss_and_grad(sc.flags, u, v, sc.dx, w, S, C, K, 1.0, 0.5)
+    assert float(loss) == pytest.approx(l0, rel=1e-5)
+    assert rel_l2(tw.grad.cpu().numpy(), 3 * gp) <= 1e-4
+    assert rel_l2(tu.grad.cpu().numpy(), 3 * gu) <= 1e-4
