@@ -39,6 +39,7 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
   L.nblocks_stream = (int)((n + kStreamBlock - 1) / kStreamBlock);
   L.scalars = take(sizeof(Scalars));
+  L.sync = take(256);
   L.partial = take(sizeof(double) * 4 * kMaxCoopBlocks);
   // block partials: two per cell-grid block, or one per face-grid block (CFL)
   const size_t nfaces = (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx;
@@ -88,6 +89,7 @@ Ws ws_view(void* base, const WsLayout& L) {
   char* b = (char*)base;
   Ws w;
   w.sc = (Scalars*)(b + L.scalars);
+  w.sync = (unsigned*)(b + L.sync);
   w.partial = (double*)(b + L.partial);
   w.blockpart = (double*)(b + L.blockpart);
   w.blockpart_n = L.blockpart_n;

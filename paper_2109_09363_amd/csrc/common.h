@@ -57,21 +57,59 @@ __device__ __forceinline__ double block_max(double v, double* scratch) {
 }
 
 // ---- grid-wide barrier for cooperative (co-resident) launches ------------
-// `counter` is zeroed before the launch; barrier number `n` (1, 2, ...) is
-// passed when all `nblocks` work-groups have arrived `n` times.  Release and
-// acquire fences at agent scope make every global write issued before the
-// barrier visible to every work-group after it (across XCD L2s).
-__device__ __forceinline__ void grid_barrier(unsigned* counter, unsigned target) {
-  __threadfence();
+// Data that crosses work-groups is written and read with agent-scope atomic
+// stores/loads (coherent across the XCD L2 caches), so the barrier needs no
+// L2 write-back/invalidate fences: every wave waits for its own stores
+// (workgroup-scope release fence), the work-group arrives on a counter, the
+// last arriver raises a generation flag on its own cache line, and everyone
+// polls the flag.  `sync[0]` (counter) and `sync[32]` (flag) are zeroed
+// before the launch; barrier number n (1, 2, ...) passes when all `nblocks`
+// work-groups have arrived n times.
+__device__ __forceinline__ void grid_barrier(unsigned* sync, unsigned n, unsigned nblocks) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-    }
-    __threadfence();
+    const unsigned old = __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == n * nblocks - 1)
+      __hip_atomic_store(sync + 32, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (__hip_atomic_load(sync + 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n)
+      __builtin_amdgcn_s_sleep(2);
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void st_agent(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_agent(const float* p) {
+  return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint8_t* p, uint8_t v) {
+  // byte stores: go through a 32-bit atomic OR/AND pair on the containing word
+  unsigned* w = reinterpret_cast<unsigned*>(reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3);
+  const unsigned sh = (unsigned)(reinterpret_cast<uintptr_t>(p) & 3) * 8;
+  __hip_atomic_fetch_and(w, ~(0xFFu << sh), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_or(w, (unsigned)v << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint8_t ld_agent(const uint8_t* p) {
+  const unsigned* w = reinterpret_cast<const unsigned*>(reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3);
+  const unsigned sh = (unsigned)(reinterpret_cast<uintptr_t>(p) & 3) * 8;
+  return (uint8_t)(__hip_atomic_load(const_cast<unsigned*>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> sh);
+}
+
+// lane l receives x from lane l-1 (lane 0 receives 0): DPP wave_shr:1
+__device__ __forceinline__ float from_left(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xF, 0xF, false));
+}
+// lane l receives x from lane l+1 (lane 63 receives 0): DPP wave_shl:1
+__device__ __forceinline__ float from_right(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xF, 0xF, false));
 }
 
 // Sum of `n` doubles in global memory written by other work-groups, in a

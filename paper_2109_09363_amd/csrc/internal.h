@@ -39,7 +39,7 @@ constexpr int kWgBlocks = 128;  // pixel-chunk blocks of the weight-gradient red
 // Byte offsets into the caller's workspace (all 256-byte aligned).
 struct WsLayout {
   size_t cell = 0, d = 0, phi = 0, exch = 0, blockpart = 0, partial = 0,
-         scalars = 0, reach = 0, pcg = 0, adv = 0;
+         scalars = 0, reach = 0, pcg = 0, adv = 0, sync = 0;
   size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0;
   size_t cnn_save = 0, bw_cells = 0, bw_t = 0, bw_x = 0, bw_a = 0, bw_b = 0, bw_part = 0;
   size_t bw_part_n = 0;
@@ -64,6 +64,7 @@ struct Ws {
   size_t blockpart_n; // capacity of blockpart in doubles
   double* partial;    // 2 x kMaxCoopBlocks x 4 cooperative partials
   Scalars* sc;
+  unsigned* sync;     // grid barrier: counter at [0], generation flag at [32]
   uint8_t* reach;
   float* pcg;         // PCG scratch
   float* adv;         // advection temporaries: 2 x (cells + u faces + v faces)

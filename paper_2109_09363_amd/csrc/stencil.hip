@@ -17,8 +17,10 @@ constexpr int PT = 32;
 constexpr int PE = PT + 2;
 
 __global__ __launch_bounds__(256) void plan_init(int nx, int ny, const uint8_t* __restrict__ flags,
-                                                 uint8_t* __restrict__ reach, Scalars* sc) {
+                                                 uint8_t* __restrict__ reach, Scalars* sc,
+                                                 unsigned* sync) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < 64) sync[c] = 0;
   if (c == 0) {
     sc->bar = 0;
     sc->nF = 0;
@@ -31,7 +33,7 @@ __global__ __launch_bounds__(256) void plan_init(int nx, int ny, const uint8_t* 
 }
 
 __global__ __launch_bounds__(256) void plan_flood(int nx, int ny, uint8_t* reach, double* partial,
-                                                  Scalars* sc, int ntx, int nty,
+                                                  Scalars* sc, unsigned* sync, int ntx, int nty,
                                                   unsigned max_rounds) {
   __shared__ uint8_t s[PE * PE];
   __shared__ int changed;
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(256) void plan_flood(int nx, int ny, uint8_t* reach
       for (int c = threadIdx.x; c < PE * PE; c += blockDim.x) {
         const int gx = x0 - 1 + c % PE, gy = y0 - 1 + c / PE;
         uint8_t st = 0;
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) st = reach[gy * nx + gx];
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) st = ld_agent(reach + gy * nx + gx);
         s[c] = st;
       }
       __syncthreads();
@@ -69,15 +71,18 @@ __global__ __launch_bounds__(256) void plan_flood(int nx, int ny, uint8_t* reach
       }
       for (int c = threadIdx.x; c < PT * PT; c += blockDim.x) {
         const int gx = x0 + c % PT, gy = y0 + c / PT;
-        if (gx < nx && gy < ny) reach[gy * nx + gx] = s[(1 + c / PT) * PE + 1 + c % PT];
+        if (gx < nx && gy < ny) {
+          const uint8_t nv = s[(1 + c / PT) * PE + 1 + c % PT];
+          if (nv != ld_agent(reach + gy * nx + gx)) st_agent(reach + gy * nx + gx, nv);
+        }
       }
       __syncthreads();
     }
     const double tot_local = block_sum(my_changes, red);
     double* part = partial + (round & 1) * kMaxCoopBlocks;
-    if (threadIdx.x == 0) part[blockIdx.x] = tot_local;
+    if (threadIdx.x == 0) st_agent(part + blockIdx.x, tot_local);
     ++round;
-    grid_barrier(&sc->bar, round * (unsigned)G);
+    grid_barrier(sync, round, (unsigned)G);
     const double tot = sum_partials(part, G, red);
     if (tot == 0.0 || round >= max_rounds) break;
   }
@@ -112,7 +117,7 @@ hipError_t run_plan(const Device& dev, int nx, int ny, const uint8_t* flags, con
                     hipStream_t s) {
   const int n = nx * ny;
   const int nb = (n + 255) / 256;
-  plan_init<<<nb, 256, 0, s>>>(nx, ny, flags, w.reach, w.sc);
+  plan_init<<<nb, 256, 0, s>>>(nx, ny, flags, w.reach, w.sc, w.sync);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int ntx = (nx + PT - 1) / PT, nty = (ny + PT - 1) / PT;
@@ -128,8 +133,9 @@ hipError_t run_plan(const Device& dev, int nx, int ny, const uint8_t* flags, con
   uint8_t* reach = w.reach;
   double* partial = w.partial;
   Scalars* sc = w.sc;
+  unsigned* sync = w.sync;
   int ntx_ = ntx, nty_ = nty;
-  void* args[] = {&nx_, &ny_, &reach, &partial, &sc, &ntx_, &nty_, &max_rounds};
+  void* args[] = {&nx_, &ny_, &reach, &partial, &sc, &sync, &ntx_, &nty_, &max_rounds};
   e = hipLaunchCooperativeKernel((const void*)plan_flood, dim3(G), dim3(256), args, 0, s);
   if (e != hipSuccess) return e;
   plan_finalize<<<nb, 256, 0, s>>>(nx, ny, flags, w.reach, w.cell, w.sc);
@@ -146,9 +152,11 @@ hipError_t run_plan(const Device& dev, int nx, int ny, const uint8_t* flags, con
 __global__ __launch_bounds__(256) void div_kernel(int nx, int ny, float inv_dx,
                                                   const uint8_t* __restrict__ cell, float* u,
                                                   float* v, float* __restrict__ d,
-                                                  double* __restrict__ blockpart, Scalars* sc) {
+                                                  double* __restrict__ blockpart, Scalars* sc,
+                                                  unsigned* sync) {
   __shared__ double red[4];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < 64) sync[c] = 0;
   if (c == 0) sc->bar = 0;
   double a = 0.0, q = 0.0;
   if (c < nx * ny) {
@@ -204,7 +212,7 @@ hipError_t run_div(int nx, int ny, double dx, float* u, float* v, const Ws& w, i
                    hipStream_t s) {
   if ((size_t)2 * nblocks > w.blockpart_n) return hipErrorInvalidValue;
   div_kernel<<<nblocks, 256, 0, s>>>(nx, ny, (float)(1.0 / dx), w.cell, u, v, w.d, w.blockpart,
-                                     w.sc);
+                                     w.sc, w.sync);
   div_finish<<<1, 256, 0, s>>>(nblocks, w.blockpart, w.sc);
   return hipGetLastError();
 }

@@ -1,0 +1,139 @@
+"""Solver-in-the-loop training of the multi-scale CNN on the GPU.
+
+The physics-driven loss of Sec. 3.2: the divergence left in the corrected
+velocity, here after the CNN guess and K Jacobi sweeps (the hybrid's own
+iteration), with the gradient of the correction (Eq. 2) and of the sweeps
+taken by the library's adjoint.  Each sample's loss is normalised by its
+initial divergence energy, so  loss = sum_F r^2 / sum_F d^2.
+
+Training data (the paper's Mantaflow set is not available): intermediate
+velocities u* of plume runs that the plain solver (PCG) projects, on random
+obstacle layouts with Ri in {0, 0.1}, plus random smooth and noisy
+divergence fields on random obstacle layouts (the "divergence sources" of
+the paper's training set).  Everything runs through the C ABI: advection,
+projection, CNN forward/backward and Adam.
+
+python -m paper_2109_09363_amd.train --n 128 --scales 4 --channels 64 \
+    --precision bf16 --steps 400 --out weights.npy
+"""
+from __future__ import annotations
+
+import argparse
+import time
+
+import numpy as np
+import torch
+
+import scenes
+from . import api
+
+
+def _dev(a, dtype=torch.float32, device="cuda"):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(device)
+
+
+def generate_dataset(n: int, n_scenes: int = 12, steps: int = 32, keep_every: int = 2,
+                     n_random: int = 64, seed: int = 0, device="cuda", log=print):
+    """List of samples (flags, u*, v*, sum_F d^2) on the device."""
+    samples = []
+    t0 = time.time()
+    for i in range(n_scenes):
+        sc = scenes.plume_scene(n, seed=seed * 1000 + i, n_obstacles=(0, 3),
+                                ri=0.1 if i % 2 == 0 else 0.0)
+        pr = api.Projector(n, n, sc.dx, 1.0, sc.rho0, device=device)
+        tf = _dev(sc.flags, torch.uint8, device)
+        pr.plan(tf)
+        rho = torch.full((n, n), sc.rho0, dtype=torch.float32, device=device)
+        u = torch.zeros((n, n + 1), dtype=torch.float32, device=device)
+        v = torch.zeros((n + 1, n), dtype=torch.float32, device=device)
+        p = torch.zeros((n, n), dtype=torch.float32, device=device)
+        g = sc.g if sc.ri > 0 else 0.0
+        for s in range(steps):
+            xi = _dev(scenes.inflow_noise(seed * 1000 + i, s, n), device=device)
+            pr.advect_async(rho, u, v, xi, g=g, drho=sc.drho, u_in=sc.u_in)
+            if s >= 1 and s % keep_every == 0:
+                samples.append([tf, u.clone(), v.clone()])
+            pr.project_async(u, v, tf, p, 1e-3, method="pcg", max_iters=20000)
+    rng = np.random.default_rng(seed + 7)
+    for i in range(n_random):
+        sc = scenes.plume_scene(n, seed=seed * 1000 + 500 + i, n_obstacles=(0, 3))
+        kind = ("smooth", "mixed", "white")[i % 3]
+        uu, vv = scenes.random_faces(n, n, int(rng.integers(1 << 30)), kind=kind)
+        samples.append([_dev(sc.flags, torch.uint8, device), _dev(uu, device=device),
+                        _dev(vv, device=device)])
+    torch.cuda.synchronize()
+    log(f"dataset: {len(samples)} samples at {n}x{n} in {time.time() - t0:.1f} s")
+    return samples
+
+
+def train(samples, n: int, scales: int, channels: int, precision: str = "fp32",
+          steps: int = 200, batch: int = 4, lr: float = 1e-3, sweeps: int = 4,
+          params0=None, seed: int = 0, device="cuda", log=print, log_every: int = 20):
+    """Adam on the normalised divergence loss; returns (params, loss history)."""
+    dx = 1.0 / n
+    pr = api.Projector(n, n, dx, 1.0, 1.0, scales, channels, precision, device=device, train=True)
+    if params0 is None:
+        params0 = scenes.random_weights(scales, channels, seed, out_scale=0.1)
+    params = _dev(params0, device=device)
+    m = torch.zeros_like(params)
+    v2 = torch.zeros_like(params)
+    grads = torch.zeros_like(params)
+    pr.set_weights(params)
+    # per-sample normalisation from the library's CNN input scale s: sum d^2 = s^2 nF
+    norms = []
+    pz = torch.empty((n, n), dtype=torch.float32, device=device)
+    for (tf, u, v) in samples:
+        pr.plan(tf)
+        uu, vv = u.clone(), v.clone()
+        pr.project_async(uu, vv, tf, pz, 0.0, method="cnn")
+        r = pr.result()
+        norms.append(1.0 / max(r.s * r.s * r.n_fluid, 1e-30))
+    rng = np.random.default_rng(seed)
+    loss_dev = torch.zeros(1, dtype=torch.float64, device=device)
+    hist = []
+    method = "hybrid" if sweeps > 0 else "cnn"
+    t0 = time.time()
+    for it in range(1, steps + 1):
+        idx = rng.choice(len(samples), batch, replace=False)
+        acc_loss = 0.0
+        for b, i in enumerate(idx):
+            tf, u, v = samples[i]
+            pr.plan(tf)
+            uu, vv = u.clone(), v.clone()
+            pr.project_async(uu, vv, tf, pz, 0.0, method=method, fixed_iters=sweeps)
+            pr.backward_async(sweeps, 1.0, norms[i] / batch, dparams=grads, loss=loss_dev,
+                              accumulate=b > 0)
+            if it % log_every == 0 or it == 1 or it == steps:
+                acc_loss += float(loss_dev.item())
+        api.adam_async(params, grads, m, v2, it, lr=lr)
+        if it % log_every == 0 or it == 1 or it == steps:
+            hist.append((it, acc_loss))
+            log(f"step {it:5d}  loss {acc_loss:.5f}  ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return params.cpu().numpy(), hist
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--scales", type=int, default=4)
+    ap.add_argument("--channels", type=int, default=64)
+    ap.add_argument("--precision", default="bf16")
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--sweeps", type=int, default=4)
+    ap.add_argument("--scenes", type=int, default=12)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    data = generate_dataset(a.n, n_scenes=a.scenes, seed=a.seed)
+    w, hist = train(data, a.n, a.scales, a.channels, a.precision, steps=a.steps, batch=a.batch,
+                    lr=a.lr, sweeps=a.sweeps, seed=a.seed)
+    if a.out:
+        np.save(a.out, w.astype(np.float32), allow_pickle=False)
+        print(f"saved {a.out}")
+
+
+if __name__ == "__main__":
+    main()
