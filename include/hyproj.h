@@ -58,6 +58,9 @@ extern "C" {
 #define HYP_STATUS_OK         0  /* threshold reached (or fixed_iters done) */
 #define HYP_STATUS_MAXITER    1  /* max_iters reached; last iterate returned */
 #define HYP_STATUS_NONFINITE  2  /* NaN/Inf in the residual; iterate returned */
+#define HYP_STATUS_FLOOR      3  /* the threshold lies below what FP32 reached
+                                    after every defect-correction round; the
+                                    best iterate is returned */
 
 /* methods */
 #define HYP_METHOD_HYBRID  0  /* CNN initial guess, then Jacobi (Sec. 3.3) */
@@ -109,7 +112,13 @@ typedef struct {
   int32_t check_every;  /* test E_1 every k updates (>= 1) and at max_iters */
   int32_t fixed_iters;  /* > 0: ignore the threshold, do exactly this many */
   float omega;          /* Jacobi weight, 1 = the paper's undamped form */
-  int32_t reserved[3];
+  int32_t fold_window;  /* defect correction (FP32 residual floor): Jacobi
+                           folds its pressure into the faces and restarts on
+                           the recomputed divergence when E_1 fell by less
+                           than 1 % over this many sweeps (0: 1024); PCG folds
+                           when its true residual disagrees with the updated
+                           one at a stop.  At most 3 folds per projection. */
+  int32_t reserved[2];
 } hyp_opts;
 
 /* Written by the device when the projection's last kernel completes. */

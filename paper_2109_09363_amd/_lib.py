@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhyproj.so")
 
 HYP_OK = 0
-STATUS_OK, STATUS_MAXITER, STATUS_NONFINITE = 0, 1, 2
+STATUS_OK, STATUS_MAXITER, STATUS_NONFINITE, STATUS_FLOOR = 0, 1, 2, 3
 METHODS = {"hybrid": 0, "jacobi": 1, "pcg": 2, "cnn": 3}
 PRECISIONS = {"fp32": 0, "bf16": 1}
 NET_TRAIN = 1
@@ -31,7 +31,8 @@ class Fields(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("method", c_i32), ("max_iters", c_i32), ("check_every", c_i32),
-                ("fixed_iters", c_i32), ("omega", c_f32), ("reserved", c_i32 * 3)]
+                ("fixed_iters", c_i32), ("omega", c_f32), ("fold_window", c_i32),
+                ("reserved", c_i32 * 2)]
 
 
 class Result(ctypes.Structure):

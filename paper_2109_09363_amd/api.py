@@ -97,7 +97,7 @@ class Projector:
 
     def project_async(self, u, v, flags, p, threshold: float, method: str = "hybrid",
                       max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
-                      omega: float = 1.0, rho=None, p_init=None):
+                      omega: float = 1.0, rho=None, p_init=None, fold_window: int = 0):
         """Enqueue one projection on the current stream; u, v corrected in
         place, p written.  Read the result with `result()` after a sync."""
         nx, ny = self.nx, self.ny
@@ -113,7 +113,7 @@ class Projector:
             raise RuntimeError("call plan(flags) before project")
         f = L.Fields(_ptr(u), _ptr(v), _ptr(rho), _ptr(flags), _ptr(p), _ptr(p_init))
         o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
-                   float(omega), (ctypes.c_int32 * 3)())
+                   float(omega), int(fold_window), (ctypes.c_int32 * 2)())
         L.check("hyp_project", self.lib.hyp_project(
             self.ctx, ctypes.byref(self.grid), ctypes.byref(f), float(threshold), ctypes.byref(o),
             _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
@@ -171,7 +171,7 @@ class Projector:
     def step_async(self, rho, u, v, flags, p, xi, threshold: float, g: float, drho: float,
                    u_in: float = 1.0, cfl: float = 0.5, method: str = "hybrid",
                    max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
-                   omega: float = 1.0):
+                   omega: float = 1.0, fold_window: int = 0):
         """Enqueue one full time step (advection, buoyancy, inflow, projection)
         on the current stream.  rho, u, v advance in place; p is written."""
         nx, ny = self.nx, self.ny
@@ -186,7 +186,7 @@ class Projector:
         ph = L.Physics(float(g), float(self.grid.rho0), float(drho), float(u_in), float(cfl))
         st = L.State(_ptr(rho), _ptr(u), _ptr(v), _ptr(p), _ptr(flags), _ptr(xi))
         o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
-                   float(omega), (ctypes.c_int32 * 3)())
+                   float(omega), int(fold_window), (ctypes.c_int32 * 2)())
         L.check("hyp_step", self.lib.hyp_step(
             self.ctx, ctypes.byref(self.grid), ctypes.byref(ph), ctypes.byref(st), float(threshold),
             ctypes.byref(o), _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))

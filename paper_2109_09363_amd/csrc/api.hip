@@ -51,6 +51,7 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
   L.reach = take(n);
   L.d = take(4 * n);
   L.phi = take(4 * n);
+  L.phi_acc = take(4 * n);
   L.exch = take(8 * n);
   L.adv = take(4 * 2 * (n + (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx));
   if (net.scales > 0) {
@@ -97,6 +98,7 @@ Ws ws_view(void* base, const WsLayout& L) {
   w.reach = (uint8_t*)(b + L.reach);
   w.d = (float*)(b + L.d);
   w.phi = (float*)(b + L.phi);
+  w.phi_acc = (float*)(b + L.phi_acc);
   w.exch = (float*)(b + L.exch);
   w.pcg = nullptr;
   w.adv = (float*)(b + L.adv);
@@ -248,6 +250,7 @@ int hyp_plan(hyp_ctx* ctx, const hyp_grid* g, const uint8_t* flags, void* ws, si
 static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, double threshold) {
   if (o->method < HYP_METHOD_HYBRID || o->method > HYP_METHOD_CNN) return HYP_EINVAL;
   if (o->max_iters < 0 || o->check_every < 1 || o->fixed_iters < 0) return HYP_EINVAL;
+  if (o->fold_window < 0) return HYP_EINVAL;
   if (!(threshold >= 0.0)) return HYP_EINVAL;
   const bool use_cnn = o->method == HYP_METHOD_HYBRID || o->method == HYP_METHOD_CNN;
   if (use_cnn) {
@@ -278,20 +281,21 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
   }
   hipError_t e = hipSuccess;
   mark(ctx, 2, stream);
-  switch (o->method) {
-    case HYP_METHOD_HYBRID:
-    case HYP_METHOD_JACOBI:
-      e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,
-                     o->fixed_iters, w, stream);
-      break;
-    case HYP_METHOD_PCG:
-      e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
-                  o->fixed_iters, w, stream);
-      break;
-    case HYP_METHOD_CNN:
-      // no sweeps: a zero-length Jacobi pass records E_1 of the prediction
-      e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, w, stream);
-      break;
+  if (o->method == HYP_METHOD_CNN) {
+    // no sweeps: a zero-length Jacobi pass records E_1 of the prediction
+    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, kSolveRounds - 1, w, stream);
+  } else {
+    // rounds separated by defect-correction folds; a round after the solve
+    // has finished returns at once
+    for (int r = 0; r < kSolveRounds && e == hipSuccess; ++r) {
+      if (o->method == HYP_METHOD_PCG)
+        e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
+                    o->fixed_iters, r, w, stream);
+      else
+        e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,
+                       o->fixed_iters, o->fold_window, r, w, stream);
+      if (e == hipSuccess && r + 1 < kSolveRounds) e = run_fold(nx, ny, g->dx, u, v, w, stream);
+    }
   }
   if (e != hipSuccess) return HYP_EHIP;
   mark(ctx, 3, stream);

@@ -27,6 +27,9 @@ struct Scalars {
 };
 
 constexpr int kMaxCoopBlocks = 1024;   // partial-sum slots per parity
+constexpr int kSolveRounds = 4;        // solver rounds (up to 3 defect-correction folds)
+constexpr int kStatusRunning = -1;     // Scalars::status while a solve is in progress
+constexpr int kStatusFold = -2;        // a round asks for a fold before the next one
 constexpr int kStreamBlock = 256;      // threads of the streaming kernels
 
 struct NetShape {
@@ -38,7 +41,7 @@ constexpr int kWgBlocks = 128;  // pixel-chunk blocks of the weight-gradient red
 
 // Byte offsets into the caller's workspace (all 256-byte aligned).
 struct WsLayout {
-  size_t cell = 0, d = 0, phi = 0, exch = 0, blockpart = 0, partial = 0,
+  size_t cell = 0, d = 0, phi = 0, phi_acc = 0, exch = 0, blockpart = 0, partial = 0,
          scalars = 0, reach = 0, pcg = 0, adv = 0, sync = 0;
   size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0;
   size_t cnn_save = 0, bw_cells = 0, bw_t = 0, bw_x = 0, bw_a = 0, bw_b = 0, bw_part = 0;
@@ -59,6 +62,7 @@ struct Ws {
   uint8_t* cell;
   float* d;
   float* phi;
+  float* phi_acc;     // pressure folded into the faces by earlier rounds
   float* exch;        // 2 x nx*ny (halo exchange ping-pong)
   double* blockpart;  // streaming-kernel block partials
   size_t blockpart_n; // capacity of blockpart in doubles
@@ -93,11 +97,12 @@ hipError_t run_div(int nx, int ny, double dx, float* u, float* v, const Ws& w,
 hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const Ws& w,
                         hipStream_t s);
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
-                      int max_iters, int check_every, int fixed_iters, const Ws& w,
-                      hipStream_t s);
+                      int max_iters, int check_every, int fixed_iters, int fold_window,
+                      int round, const Ws& w, hipStream_t s);
+hipError_t run_fold(int nx, int ny, double dx, float* u, float* v, const Ws& w, hipStream_t s);
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters);
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
-                   int check_every, int fixed_iters, const Ws& w, hipStream_t s);
+                   int check_every, int fixed_iters, int round, const Ws& w, hipStream_t s);
 hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt, bool dt_dev,
                                float* u, float* v, float* p, const Ws& w, int nblocks, void* res,
                                hipStream_t s);

@@ -40,6 +40,8 @@ struct JacParams {
   float inv_dx2, wfac;  // wfac = omega * dx^2
   double thr;
   int max_iters, check_every, fixed_iters;
+  int fold_window;      // sweeps per stagnation window (0: no folds)
+  int last_round;       // 1: this round may not end with a fold
   const uint8_t* cell;
   const float* d;
   float* phi;    // in: initial guess, out: returned iterate
@@ -87,17 +89,14 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
   const bool col_in = gx >= 0 && gx < p.nx;
   const bool lane_int = lane >= H && lane < H + TW && col_in;
   const int nF = p.sc->nF;
-  // rows of this thread inside the tile interior (and the domain)
-  unsigned rmask = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int er = wave * R + r, gy = gy0 + r;
-    if (lane_int && er >= H && er < H + TH && gy < p.ny) rmask |= 1u << r;
-  }
+  if (p.sc->status >= 0) return;  // an earlier round finished the solve
+  // rows of this thread inside the tile interior (and the domain): imask;
+  // the fluid ones among them, which enter E_1: fmask
+  unsigned imask = 0, fmask = 0;
   float ph[R], dd[R], kk[R], ww[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int gy = gy0 + r;
+    const int er = wave * R + r, gy = gy0 + r;
     float d_ = 0.f, k_ = 0.f, w_ = 0.f, p_ = 0.f;
     if (col_in && gy >= 0 && gy < p.ny) {
       const int g = gy * p.nx + gx;
@@ -109,13 +108,20 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
         w_ = p.wfac / (float)k;
         p_ = p.phi[g];
       }
+      if (lane_int && er >= H && er < H + TH) {
+        imask |= 1u << r;
+        if (!(ci & C_SOLID)) fmask |= 1u << r;
+      }
     }
     ph[r] = p_; dd[r] = d_; kk[r] = k_; ww[r] = w_;
   }
-  int k = 0, par = 0, q = 0;
+  int k = p.sc->iters, par = 0, q = 0;
   unsigned nbar = 0;
   const int end = p.fixed_iters > 0 ? p.fixed_iters : p.max_iters;
   const size_t plane = (size_t)p.nx * p.ny;
+  const int k_start = k;
+  int k_ref = k;
+  double E_ref = 0.0;
   auto edges = [&](float* below, float* above) {
     edge[q][0][wave][lane] = ph[0];
     edge[q][1][wave][lane] = ph[R - 1];
@@ -127,11 +133,11 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
   for (;;) {
     float below, above;
     edges(&below, &above);
-    const double loc = jac_rows<R, false>(ph, dd, kk, ww, below, above, p.inv_dx2, rmask);
+    const double loc = jac_rows<R, false>(ph, dd, kk, ww, below, above, p.inv_dx2, fmask);
     float* ex = p.exch + par * plane;
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if ((rmask >> r) & 1u) st_agent(ex + (size_t)(gy0 + r) * p.nx + gx, ph[r]);
+      if ((imask >> r) & 1u) st_agent(ex + (size_t)(gy0 + r) * p.nx + gx, ph[r]);
     const double tot_local = block_sum(loc, red);
     double* part = p.partial + par * kMaxCoopBlocks;
     if (threadIdx.x == 0) st_agent(part + blockIdx.x, tot_local);
@@ -140,11 +146,19 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     const double tot = sum_partials(part, G, red);
     const double E = nF > 0 ? tot / nF : 0.0;
     if (k == 0 && blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
-    const int st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
-    if (st >= 0) {
+    int st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
+    if (k == k_start) E_ref = E;
+    if (st < 0 && !p.last_round && p.fold_window > 0 && k - k_ref >= p.fold_window) {
+      // stagnation window: fold when E_1 fell by less than 1 % (always in
+      // fixed-sweep mode, where folds only re-base the same iteration)
+      if (p.fixed_iters > 0 || !(E < 0.99 * E_ref)) st = kStatusFold;
+      k_ref = k;
+      E_ref = E;
+    }
+    if (st != -1) {
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if ((rmask >> r) & 1u) p.phi[(size_t)(gy0 + r) * p.nx + gx] = ph[r];
+        if ((imask >> r) & 1u) p.phi[(size_t)(gy0 + r) * p.nx + gx] = ph[r];
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         p.sc->iters = k;
         p.sc->status = st;
@@ -157,7 +171,7 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     // refresh every non-interior cell from the neighbours' interiors
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if ((rmask >> r) & 1u) continue;
+      if ((imask >> r) & 1u) continue;
       if (kk[r] > 0.f) ph[r] = ld_agent(ex + (size_t)(gy0 + r) * p.nx + gx);
     }
     for (int s = 0; s < B; ++s) {
@@ -179,6 +193,7 @@ struct PcgParams {
   float dx2;
   double thr, inv_dx2;
   int max_iters, check_every, fixed_iters;
+  int last_round;
   const uint8_t* cell;
   const float* d;
   float* phi;
@@ -206,6 +221,8 @@ __global__ __launch_bounds__(256) void pcg_persist(PcgParams p) {
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   unsigned nbar = 0;
   const int nF = p.sc->nF;
+  if (p.sc->status >= 0) return;  // an earlier round finished the solve
+  const int round0 = p.sc->iters == 0;
   double* part_rz = p.partial;
   double* part_ra = p.partial + kMaxCoopBlocks;
   double* part_pq = p.partial + 2 * kMaxCoopBlocks;
@@ -256,8 +273,8 @@ __global__ __launch_bounds__(256) void pcg_persist(PcgParams p) {
   grid_barrier(p.sync, nbar, (unsigned)G);
   double rho = sum_partials(part_rz, G, red);
   double E = nF > 0 ? sum_partials(part_ra, G, red) / nF * p.inv_dx2 : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
-  int k = 0;
+  if (round0 && blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
+  int k = p.sc->iters;
   auto finish = [&](int st) {
     REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
       const int gx = ox + lx, gy = oy + ly;
@@ -312,6 +329,7 @@ __global__ __launch_bounds__(256) void pcg_persist(PcgParams p) {
       E = nF > 0 ? sum_partials(part_ra, G, red) / nF * p.inv_dx2 : 0.0;
       st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
       if (st < 0 && !(rho > 0.0)) st = HYP_STATUS_OK;
+      if (st < 0 && !p.last_round) st = kStatusFold;  // fold, then CG on the new residual
       if (st < 0) {
         REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
           const int l = ly * EX + lx;
@@ -320,7 +338,7 @@ __global__ __launch_bounds__(256) void pcg_persist(PcgParams p) {
         __syncthreads();
       }
     }
-    if (st >= 0) {
+    if (st != -1) {
       finish(st);
       return;
     }
@@ -456,8 +474,8 @@ static hipError_t launch_jacobi(JacParams& p, int G, hipStream_t s) {
 }
 
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
-                      int max_iters, int check_every, int fixed_iters, const Ws& w,
-                      hipStream_t s) {
+                      int max_iters, int check_every, int fixed_iters, int fold_window,
+                      int round, const Ws& w, hipStream_t s) {
   JacParams p{};
   int R = 0, H = 0, ntx = 0, nty = 0;
   if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, &R, &H, &ntx, &nty))
@@ -467,6 +485,8 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
   p.wfac = (float)(omega * dx * dx);
   p.thr = thr;
   p.max_iters = max_iters; p.check_every = check_every; p.fixed_iters = fixed_iters;
+  p.fold_window = fold_window > 0 ? fold_window : (fixed_iters > 0 ? 0 : 1024);
+  p.last_round = round + 1 >= kSolveRounds;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.exch = w.exch; p.partial = w.partial; p.sc = w.sc;
   p.sync = w.sync;
   const int G = ntx * nty;
@@ -482,7 +502,7 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
 }
 
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
-                   int check_every, int fixed_iters, const Ws& w, hipStream_t s) {
+                   int check_every, int fixed_iters, int round, const Ws& w, hipStream_t s) {
   PcgParams p{};
   p.nx = nx; p.ny = ny;
   int T = 0, ntx = 0, nty = 0;
@@ -493,6 +513,7 @@ hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int
   p.inv_dx2 = 1.0 / (dx * dx);
   p.thr = thr;
   p.max_iters = max_iters; p.check_every = check_every; p.fixed_iters = fixed_iters;
+  p.last_round = round + 1 >= kSolveRounds;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.exch = w.exch; p.partial = w.partial; p.sc = w.sc;
   p.sync = w.sync;
   hipError_t e = hipFuncSetAttribute((const void*)pcg_persist,

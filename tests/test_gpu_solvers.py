@@ -169,3 +169,39 @@ def test_large_grid_1024_sampled():
     g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="jacobi", fixed_iters=16)
     o = PR.project(sc.flags, u, v, sc.dx, method="jacobi", fixed_iters=16)
     assert rel_l2(g["p"], o["p"], o["plan"].fluid) <= 1e-5
+
+
+@pytest.mark.parametrize("n,k,window", [(64, 40, 16), (256, 100, 24)])
+def test_jacobi_folds_preserve_the_iteration(n, k, window):
+    # a fold moves the pressure into the faces and restarts on the
+    # recomputed divergence; in exact arithmetic the sweep sequence is the
+    # same, so the result must match the oracle's unfolded iterate
+    say("jacobi folds", n, k, window)
+    sc, u, v = plume_state(n, 12, 2)
+    dt = 0.02
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="jacobi", fixed_iters=k, dt=dt,
+                    fold_window=window)
+    o = PR.project(sc.flags, u, v, sc.dx, dt=dt, method="jacobi", fixed_iters=k)
+    assert g["res"].iters == k
+    err = rel_l2(g["p"], o["p"], o["plan"].fluid)
+    say("  rel L2 p", err, "u", rel_l2(g["u"], o["u"]))
+    assert err <= 1e-5
+    assert rel_l2(g["u"], o["u"]) <= 1e-5 and rel_l2(g["v"], o["v"]) <= 1e-5
+
+
+@pytest.mark.parametrize("n,rel", [(256, 1e-5), (512, 1e-5)])
+def test_pcg_reaches_threshold_below_fp32_floor(n, rel):
+    # without the folds an FP32 CG stalls well above this threshold
+    say("pcg floor", n, rel)
+    sc, u, v = plume_state(n, 13, 3, kind="smooth")
+    P = G.plan(sc.flags)
+    d = G.divergence(P, *G.enforce_bc(P, u, v), sc.dx)
+    thr = rel * G.e1(P, d)
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=thr, method="pcg", max_iters=20000)
+    ex = SV.exact_solve(P, d, sc.dx)
+    err = rel_l2(g["p"], ex, P.fluid)
+    say("  status", g["res"].status, "iters", g["res"].iters, "e1_final", g["res"].e1_final,
+        "thr", thr, "rel L2 vs exact", err)
+    assert g["res"].status == 0
+    assert g["res"].e1_final < 1.05 * thr
+    assert err <= 1e-3
