@@ -40,7 +40,7 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
   L.nblocks_stream = (int)((n + kStreamBlock - 1) / kStreamBlock);
   L.scalars = take(sizeof(Scalars));
   L.sync = take(256);
-  L.partial = take(sizeof(double) * 4 * kMaxCoopBlocks);
+  L.partial = take(sizeof(double) * 6 * kMaxCoopBlocks);
   // block partials: two per cell-grid block, or one per face-grid block (CFL)
   const size_t nfaces = (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx;
   const size_t nb_faces = (nfaces + kStreamBlock - 1) / kStreamBlock;

@@ -66,7 +66,7 @@ struct Ws {
   float* exch;        // 2 x nx*ny (halo exchange ping-pong)
   double* blockpart;  // streaming-kernel block partials
   size_t blockpart_n; // capacity of blockpart in doubles
-  double* partial;    // 2 x kMaxCoopBlocks x 4 cooperative partials
+  double* partial;    // 6 x kMaxCoopBlocks cooperative partials
   Scalars* sc;
   unsigned* sync;     // grid barrier: counter at [0], generation flag at [32]
   uint8_t* reach;

@@ -185,11 +185,16 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
 
 // ---------------------------------------------------------------------------
 // Jacobi-preconditioned CG on A x = b, A = -dx^2 L (diagonal k_c, -1 per
-// non-solid neighbour), b = -dx^2 d, M = diag(k_c).  LDS holds x, r, p (with
-// a 1-wide halo for p) and k per tile; vectors are FP32, dot products FP64.
+// non-solid neighbour), b = -dx^2 d, M = diag(k_c), in the single-reduction
+// form of Chronopoulos and Gear: per iteration one halo exchange of the
+// preconditioned residual u and one merged FP64 reduction of (r.u, w.u,
+// sum|r|), w = A u.  Same tile layout as the Jacobi kernel with a one-cell
+// halo; x, r, u, w, p, s live in registers.  A stop is confirmed on the true
+// residual b - A x (FP32 drift of the updated residual); when it fails the
+// round ends with a fold (or, in the last round, CG restarts from it).
 // ---------------------------------------------------------------------------
 struct PcgParams {
-  int nx, ny, T, TH, ntx;
+  int nx, ny, ntx;
   float dx2;
   double thr, inv_dx2;
   int max_iters, check_every, fixed_iters;
@@ -203,212 +208,189 @@ struct PcgParams {
   unsigned* sync;
 };
 
-#define REGION_LOOP(Y0, Y1, X0, X1)                              \
-  for (int ly = (Y0) + ty; ly < (Y1); ly += 4)                  \
-    for (int lx = (X0) + tx; lx < (X1); lx += 64)
+template <int R>
+__device__ __forceinline__ void band_edges(float (&a)[R], float (*edge)[2][4][64], int& q, int wave,
+                                           int lane, float* below, float* above) {
+  edge[q][0][wave][lane] = a[0];
+  edge[q][1][wave][lane] = a[R - 1];
+  __syncthreads();
+  *below = wave > 0 ? edge[q][1][wave - 1][lane] : 0.f;
+  *above = wave < 3 ? edge[q][0][wave + 1][lane] : 0.f;
+  q ^= 1;
+}
 
-__global__ __launch_bounds__(256) void pcg_persist(PcgParams p) {
-  extern __shared__ float smem[];
+// y = A v on the rows of a lane (k v - sum of the four neighbours; 0 where k = 0)
+template <int R>
+__device__ __forceinline__ void apply_A(const float (&v)[R], const float (&kk)[R], float below,
+                                        float above, float (&y)[R]) {
+  float prev = below;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float c = v[r];
+    const float n = (r + 1 < R) ? v[r + 1] : above;
+    const float e = from_right(c);
+    const float w = from_left(c);
+    y[r] = kk[r] > 0.f ? kk[r] * c - ((e + w) + (n + prev)) : 0.f;
+    prev = c;
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
+  __shared__ float edge[2][2][4][64];
   __shared__ double red[4];
-  const int EX = p.T + 2, EY = p.TH + 2, NE = EX * EY;
-  float* xl = smem;
-  float* rl = xl + NE;
-  float* pl = rl + NE;
-  float* kl = pl + NE;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int TW = 62, TH = 4 * R - 2;
   const int G = gridDim.x;
-  const int ox = (blockIdx.x % p.ntx) * p.T - 1;
-  const int oy = (blockIdx.x / p.ntx) * p.TH - 1;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  unsigned nbar = 0;
+  const int bx = blockIdx.x % p.ntx, by = blockIdx.x / p.ntx;
+  const int gx = bx * TW - 1 + lane;
+  const int gy0 = by * TH - 1 + wave * R;
+  const bool col_in = gx >= 0 && gx < p.nx;
+  const bool lane_int = lane >= 1 && lane < 1 + TW && col_in;
   const int nF = p.sc->nF;
   if (p.sc->status >= 0) return;  // an earlier round finished the solve
-  const int round0 = p.sc->iters == 0;
-  double* part_rz = p.partial;
-  double* part_ra = p.partial + kMaxCoopBlocks;
-  double* part_pq = p.partial + 2 * kMaxCoopBlocks;
-  const size_t plane = (size_t)p.nx * p.ny;
-  float* pex = p.exch;          // search-direction halo exchange
-  float* xex = p.exch + plane;  // iterate halo exchange (true-residual check)
-
-  REGION_LOOP(0, EY, 0, EX) {
-    const int gx = ox + lx, gy = oy + ly, l = ly * EX + lx;
-    float kk = 0.f, xx = 0.f;
-    if (gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny) {
+  const bool round0 = p.sc->iters == 0;
+  unsigned imask = 0;
+  float x[R], r[R], u[R], w[R], pp[R], ss[R], kk[R], bb[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int er = wave * R + i, gy = gy0 + i;
+    float k_ = 0.f, b_ = 0.f, x_ = 0.f;
+    if (col_in && gy >= 0 && gy < p.ny) {
       const int g = gy * p.nx + gx;
       const uint8_t ci = p.cell[g];
       if (!(ci & C_SOLID)) {
-        kk = (float)cell_k(ci);
-        xx = p.phi[g];
+        k_ = (float)cell_k(ci);
+        b_ = -p.dx2 * p.d[g];
+        x_ = p.phi[g];
       }
+      if (lane_int && er >= 1 && er < 1 + TH) imask |= 1u << i;
     }
-    xl[l] = xx;
-    kl[l] = kk;
-    pl[l] = 0.f;
-    rl[l] = 0.f;
+    kk[i] = k_; bb[i] = b_; x[i] = x_;
+    r[i] = 0.f; u[i] = 0.f; w[i] = 0.f; pp[i] = 0.f; ss[i] = 0.f;
   }
-  __syncthreads();
-  // r = b - A x, p = z = r / k
-  double rz = 0.0, ra = 0.0;
-  REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
-    const int l = ly * EX + lx;
-    if (kl[l] > 0.f) {
-      const int g = (oy + ly) * p.nx + (ox + lx);
-      const float b = -p.dx2 * p.d[g];
-      const float Ax = kl[l] * xl[l] - ((xl[l - 1] + xl[l + 1]) + (xl[l - EX] + xl[l + EX]));
-      const float r = b - Ax;
-      const float z = r / kl[l];
-      rl[l] = r;
-      pl[l] = z;
-      rz += (double)r * (double)z;
-      ra += fabs((double)r);
+  int q = 0, k = p.sc->iters;
+  unsigned nbar = 0;
+  const size_t plane = (size_t)p.nx * p.ny;
+  float* uex = p.exch;
+  float* xex = p.exch + plane;
+  double* part = p.partial;  // [3][kMaxCoopBlocks], parity-doubled below
+  int par = 0;
+  float below, above;
+
+  // refresh the halo of v from the neighbours' interiors (after a barrier)
+  auto exchange = [&](float (&v)[R], float* ex) {
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if ((imask >> i) & 1u) st_agent(ex + (size_t)(gy0 + i) * p.nx + gx, v[i]);
+    ++nbar;
+    grid_barrier(p.sync, nbar, (unsigned)G);
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (!((imask >> i) & 1u) && kk[i] > 0.f) v[i] = ld_agent(ex + (size_t)(gy0 + i) * p.nx + gx);
+  };
+  // merged reduction of (r.u, w.u, sum|r|) over the interior
+  double gam = 0.0, del = 0.0, E = 0.0;
+  auto reduce3 = [&]() {
+    double a = 0.0, c = 0.0, e = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if ((imask >> i) & 1u) {
+        a += (double)r[i] * (double)u[i];
+        c += (double)w[i] * (double)u[i];
+        e += fabs((double)r[i]);
+      }
+    a = block_sum(a, red);
+    c = block_sum(c, red);
+    e = block_sum(e, red);
+    double* pa = part + par * 3 * kMaxCoopBlocks;
+    if (threadIdx.x == 0) {
+      st_agent(pa + blockIdx.x, a);
+      st_agent(pa + kMaxCoopBlocks + blockIdx.x, c);
+      st_agent(pa + 2 * kMaxCoopBlocks + blockIdx.x, e);
     }
-  }
-  rz = block_sum(rz, red);
-  ra = block_sum(ra, red);
-  if (threadIdx.x == 0) {
-    st_agent(part_rz + blockIdx.x, rz);
-    st_agent(part_ra + blockIdx.x, ra);
-  }
-  ++nbar;
-  grid_barrier(p.sync, nbar, (unsigned)G);
-  double rho = sum_partials(part_rz, G, red);
-  double E = nF > 0 ? sum_partials(part_ra, G, red) / nF * p.inv_dx2 : 0.0;
-  if (round0 && blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
-  int k = p.sc->iters;
+    ++nbar;
+    grid_barrier(p.sync, nbar, (unsigned)G);
+    gam = sum_partials(pa, G, red);
+    del = sum_partials(pa + kMaxCoopBlocks, G, red);
+    E = nF > 0 ? sum_partials(pa + 2 * kMaxCoopBlocks, G, red) / nF * p.inv_dx2 : 0.0;
+    par ^= 1;
+  };
+  // (re)start the recurrence from the current r: u = M^-1 r, w = A u, p = s = 0
+  double alpha = 0.0, beta = 0.0;
+  auto restart = [&]() {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      u[i] = kk[i] > 0.f ? r[i] / kk[i] : 0.f;
+      pp[i] = 0.f;
+      ss[i] = 0.f;
+    }
+    exchange(u, uex);
+    band_edges<R>(u, edge, q, wave, lane, &below, &above);
+    apply_A<R>(u, kk, below, above, w);
+    reduce3();
+    alpha = del > 0.0 ? gam / del : 0.0;
+    beta = 0.0;
+  };
+  // true residual r = b - A x (needs the halo of x)
+  auto true_residual = [&]() {
+    exchange(x, xex);
+    float ax[R];
+    band_edges<R>(x, edge, q, wave, lane, &below, &above);
+    apply_A<R>(x, kk, below, above, ax);
+#pragma unroll
+    for (int i = 0; i < R; ++i) r[i] = kk[i] > 0.f ? bb[i] - ax[i] : 0.f;
+  };
   auto finish = [&](int st) {
-    REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
-      const int gx = ox + lx, gy = oy + ly;
-      if (gx < p.nx && gy < p.ny) p.phi[gy * p.nx + gx] = xl[ly * EX + lx];
-    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if ((imask >> i) & 1u) p.phi[(size_t)(gy0 + i) * p.nx + gx] = x[i];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       p.sc->iters = k;
       p.sc->status = st;
       p.sc->e1_solve = E;
     }
   };
+
+  true_residual();
+  restart();
+  if (round0 && blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
   for (;;) {
     int st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
-    if (st < 0 && !(rho > 0.0)) st = HYP_STATUS_OK;  // r = 0 exactly
+    if (st < 0 && !(gam > 0.0)) st = HYP_STATUS_OK;  // r = 0 exactly
     if (st == HYP_STATUS_OK && p.fixed_iters <= 0) {
-      // The updated residual drifts from b - A x in FP32: confirm the stop on
-      // the true residual; if it fails, continue from it with p = z (restart).
-      REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
-        const int gx = ox + lx, gy = oy + ly;
-        if (gx < p.nx && gy < p.ny) st_agent(xex + gy * p.nx + gx, xl[ly * EX + lx]);
-      }
-      ++nbar;
-      grid_barrier(p.sync, nbar, (unsigned)G);
-      REGION_LOOP(0, EY, 0, EX) {
-        if (ly >= 1 && ly < 1 + p.TH && lx >= 1 && lx < 1 + p.T) continue;
-        const int l = ly * EX + lx;
-        xl[l] = kl[l] > 0.f ? ld_agent(xex + (oy + ly) * p.nx + (ox + lx)) : 0.f;
-      }
-      __syncthreads();
-      double rzt = 0.0, rat = 0.0;
-      REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
-        const int l = ly * EX + lx;
-        if (kl[l] > 0.f) {
-          const int g = (oy + ly) * p.nx + (ox + lx);
-          const float b = -p.dx2 * p.d[g];
-          const float Ax = kl[l] * xl[l] - ((xl[l - 1] + xl[l + 1]) + (xl[l - EX] + xl[l + EX]));
-          const float r = b - Ax;
-          rl[l] = r;
-          rzt += (double)r * (double)(r / kl[l]);
-          rat += fabs((double)r);
-        }
-      }
-      rzt = block_sum(rzt, red);
-      rat = block_sum(rat, red);
-      if (threadIdx.x == 0) {
-        st_agent(part_rz + blockIdx.x, rzt);
-        st_agent(part_ra + blockIdx.x, rat);
-      }
-      ++nbar;
-      grid_barrier(p.sync, nbar, (unsigned)G);
-      rho = sum_partials(part_rz, G, red);
-      E = nF > 0 ? sum_partials(part_ra, G, red) / nF * p.inv_dx2 : 0.0;
+      // confirm on the true residual
+      true_residual();
+      restart();
       st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
-      if (st < 0 && !(rho > 0.0)) st = HYP_STATUS_OK;
-      if (st < 0 && !p.last_round) st = kStatusFold;  // fold, then CG on the new residual
-      if (st < 0) {
-        REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
-          const int l = ly * EX + lx;
-          pl[l] = kl[l] > 0.f ? rl[l] / kl[l] : 0.f;
-        }
-        __syncthreads();
-      }
+      if (st < 0 && !(gam > 0.0)) st = HYP_STATUS_OK;
+      if (st < 0 && !p.last_round) st = kStatusFold;
     }
     if (st != -1) {
       finish(st);
       return;
     }
-    // exchange p
-    REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
-      const int gx = ox + lx, gy = oy + ly;
-      if (gx < p.nx && gy < p.ny) st_agent(pex + gy * p.nx + gx, pl[ly * EX + lx]);
-    }
-    ++nbar;
-    grid_barrier(p.sync, nbar, (unsigned)G);
-    REGION_LOOP(0, EY, 0, EX) {
-      if (ly >= 1 && ly < 1 + p.TH && lx >= 1 && lx < 1 + p.T) continue;
-      const int l = ly * EX + lx;
-      pl[l] = kl[l] > 0.f ? ld_agent(pex + (oy + ly) * p.nx + (ox + lx)) : 0.f;
-    }
-    __syncthreads();
-    // q = A p kept in registers (each thread revisits the same cells)
-    float qv[16];
-    double pq = 0.0;
-    int n = 0;
-    REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
-      const int l = ly * EX + lx;
-      float q = 0.f;
-      if (kl[l] > 0.f) {
-        q = kl[l] * pl[l] - ((pl[l - 1] + pl[l + 1]) + (pl[l - EX] + pl[l + EX]));
-        pq += (double)pl[l] * (double)q;
-      }
-      qv[n++ & 15] = q;
-    }
-    pq = block_sum(pq, red);
-    if (threadIdx.x == 0) st_agent(part_pq + blockIdx.x, pq);
-    ++nbar;
-    grid_barrier(p.sync, nbar, (unsigned)G);
-    const double pqt = sum_partials(part_pq, G, red);
-    if (!(pqt > 0.0)) {  // breakdown or p = 0: return the current iterate
-      finish(isfinite(pqt) ? HYP_STATUS_OK : HYP_STATUS_NONFINITE);
+    if (!(alpha == alpha) || !isfinite(alpha)) {
+      finish(HYP_STATUS_NONFINITE);
       return;
     }
-    const float alpha = (float)(rho / pqt);
-    double rz2 = 0.0, ra2 = 0.0;
-    n = 0;
-    REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
-      const int l = ly * EX + lx;
-      const float q = qv[n++ & 15];
-      if (kl[l] > 0.f) {
-        xl[l] += alpha * pl[l];
-        const float r = rl[l] - alpha * q;
-        rl[l] = r;
-        const float z = r / kl[l];
-        rz2 += (double)r * (double)z;
-        ra2 += fabs((double)r);
-      }
+    const float a = (float)alpha, bt = (float)beta;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      pp[i] = u[i] + bt * pp[i];
+      ss[i] = w[i] + bt * ss[i];
+      x[i] += a * pp[i];
+      r[i] -= a * ss[i];
+      u[i] = kk[i] > 0.f ? r[i] / kk[i] : 0.f;
     }
-    rz2 = block_sum(rz2, red);
-    ra2 = block_sum(ra2, red);
-    if (threadIdx.x == 0) {
-      st_agent(part_rz + blockIdx.x, rz2);
-      st_agent(part_ra + blockIdx.x, ra2);
-    }
-    ++nbar;
-    grid_barrier(p.sync, nbar, (unsigned)G);
-    const double rho_new = sum_partials(part_rz, G, red);
-    E = nF > 0 ? sum_partials(part_ra, G, red) / nF * p.inv_dx2 : 0.0;
-    const float beta = (float)(rho != 0.0 ? rho_new / rho : 0.0);
-    REGION_LOOP(1, 1 + p.TH, 1, 1 + p.T) {
-      const int l = ly * EX + lx;
-      if (kl[l] > 0.f) pl[l] = rl[l] / kl[l] + beta * pl[l];
-    }
-    __syncthreads();
-    rho = rho_new;
+    exchange(u, uex);
+    band_edges<R>(u, edge, q, wave, lane, &below, &above);
+    apply_A<R>(u, kk, below, above, w);
+    const double gam_old = gam;
+    reduce3();
+    beta = gam_old != 0.0 ? gam / gam_old : 0.0;
+    const double den = del - beta * gam / alpha;
+    alpha = den != 0.0 ? gam / den : 0.0;
     ++k;
   }
 }
@@ -443,14 +425,14 @@ static bool jacobi_geom(const Device& dev, int nx, int ny, int check_every, int 
   return false;
 }
 
-// PCG: the smallest square tile side (>= 16) whose tile count fits.
-static bool pcg_geom(const Device& dev, int nx, int ny, int* T, int* ntx, int* nty, size_t* lds) {
-  for (int t = 16; t <= 64; t *= 2) {
-    const int tx = (nx + t - 1) / t, ty = (ny + t - 1) / t;
-    const size_t bytes = (size_t)4 * (t + 2) * (t + 2) * sizeof(float);
-    if (bytes + 1024 > (size_t)dev.max_lds) return false;
-    if (tx * ty <= dev.cu && tx * ty <= kMaxCoopBlocks) {
-      *T = t; *ntx = tx; *nty = ty; *lds = bytes;
+// PCG: halo 1, tile interior 62 x (4R - 2), the smallest R that fits.
+static bool pcg_geom(const Device& dev, int nx, int ny, int* R, int* ntx, int* nty) {
+  const int tx = (nx + 61) / 62;
+  const int cap = dev.cu < kMaxCoopBlocks ? dev.cu : kMaxCoopBlocks;
+  for (int r : kRows) {
+    const int ty = (ny + 4 * r - 3) / (4 * r - 2);
+    if (tx * ty <= cap) {
+      *R = r; *ntx = tx; *nty = ty;
       return true;
     }
   }
@@ -459,9 +441,8 @@ static bool pcg_geom(const Device& dev, int nx, int ny, int* T, int* ntx, int* n
 
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters) {
   if (pcg) {
-    int T, ntx, nty;
-    size_t lds;
-    return pcg_geom(dev, nx, ny, &T, &ntx, &nty, &lds);
+    int R, ntx, nty;
+    return pcg_geom(dev, nx, ny, &R, &ntx, &nty);
   }
   int R, H, ntx, nty;
   return jacobi_geom(dev, nx, ny, check_every, fixed_iters, &R, &H, &ntx, &nty);
@@ -501,14 +482,18 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
   return hipErrorInvalidValue;
 }
 
+template <int R>
+static hipError_t launch_pcg(PcgParams& p, int G, hipStream_t s) {
+  void* args[] = {&p};
+  return hipLaunchCooperativeKernel((const void*)pcg_reg<R>, dim3(G), dim3(256), args, 0, s);
+}
+
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
                    int check_every, int fixed_iters, int round, const Ws& w, hipStream_t s) {
   PcgParams p{};
-  p.nx = nx; p.ny = ny;
-  int T = 0, ntx = 0, nty = 0;
-  size_t lds = 0;
-  if (!pcg_geom(dev, nx, ny, &T, &ntx, &nty, &lds)) return hipErrorInvalidValue;
-  p.T = p.TH = T; p.ntx = ntx;
+  int R = 0, ntx = 0, nty = 0;
+  if (!pcg_geom(dev, nx, ny, &R, &ntx, &nty)) return hipErrorInvalidValue;
+  p.nx = nx; p.ny = ny; p.ntx = ntx;
   p.dx2 = (float)(dx * dx);
   p.inv_dx2 = 1.0 / (dx * dx);
   p.thr = thr;
@@ -516,12 +501,16 @@ hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int
   p.last_round = round + 1 >= kSolveRounds;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.exch = w.exch; p.partial = w.partial; p.sc = w.sc;
   p.sync = w.sync;
-  hipError_t e = hipFuncSetAttribute((const void*)pcg_persist,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  void* args[] = {&p};
-  return hipLaunchCooperativeKernel((const void*)pcg_persist, dim3(ntx * nty), dim3(256), args,
-                                    (unsigned)lds, s);
+  const int G = ntx * nty;
+  switch (R) {
+    case 4: return launch_pcg<4>(p, G, s);
+    case 8: return launch_pcg<8>(p, G, s);
+    case 12: return launch_pcg<12>(p, G, s);
+    case 16: return launch_pcg<16>(p, G, s);
+    case 24: return launch_pcg<24>(p, G, s);
+    case 32: return launch_pcg<32>(p, G, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace hyp
