@@ -238,6 +238,34 @@ int hyp_step(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_s
 int hyp_advect(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_state* st,
                void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- batched form: many plumes of uneven sizes ---------------------------
+ * A batch fixes the instances (grids, state pointers, thresholds, options)
+ * once.  Per step, every instance gets its own advection, divergence and CNN
+ * launches, then ONE persistent Jacobi launch sweeps the tiles of all
+ * instances (per-instance stop tests; finished instances drop out), then
+ * the per-instance corrections.  Methods HYBRID and JACOBI; check_every and
+ * fold_window are not used (the batch tests E_1 every 8 sweeps).  The
+ * workspace holds the batch tables followed by one projection workspace per
+ * instance. */
+typedef struct hyp_batch hyp_batch;
+
+int hyp_batch_workspace_size(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, size_t* bytes);
+/* Validates, uploads the tables and plans every instance (synchronous).
+ * states[i].rho and .xi may be NULL when only hyp_batch_project is used. */
+int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_state* states,
+                     const double* thresholds, const hyp_opts* o, void* ws, size_t ws_bytes,
+                     hyp_batch** out);
+/* Projection of the current faces of every instance; res: n results
+ * (device or host-pinned). */
+int hyp_batch_project(hyp_batch* b, hipStream_t stream, hyp_result* res);
+/* One time step (advection, buoyancy, inflow, projection) of every instance. */
+int hyp_batch_step(hyp_batch* b, const hyp_physics* ph, hipStream_t stream, hyp_result* res);
+/* Record hyp_batch_step into a hipGraph (replayed by hyp_batch_launch on any
+ * stream).  The inflow noise arrays are read at replay time. */
+int hyp_batch_capture(hyp_batch* b, const hyp_physics* ph, hipStream_t stream, hyp_result* res);
+int hyp_batch_launch(hyp_batch* b, hipStream_t stream);
+int hyp_batch_destroy(hyp_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

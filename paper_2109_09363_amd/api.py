@@ -192,6 +192,98 @@ class Projector:
             ctypes.byref(o), _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
 
 
+class Batch:
+    """Many plumes of uneven sizes projected (or stepped) together: per
+    instance advection / divergence / CNN launches and one persistent Jacobi
+    launch for all instances.  `instances` is a list of dicts with keys
+    nx, ny, dx, flags, u, v, p and optionally rho, xi, dt, rho0, threshold."""
+
+    def __init__(self, instances, threshold: float = 1e-3, method: str = "hybrid",
+                 params=None, scales: int = 0, channels: int = 0, precision: str = "fp32",
+                 max_iters: int = 200000, omega: float = 1.0, device=None):
+        self.lib = L.lib()
+        self.device = torch.device("cuda" if device is None else device)
+        ctx = ctypes.c_void_p()
+        desc = L.NetDesc(int(scales), int(channels), L.PRECISIONS[precision], 0) if scales > 0 else None
+        L.check("hyp_create", self.lib.hyp_create(ctypes.byref(ctx), ctypes.byref(desc) if desc else None))
+        self.ctx = ctx
+        self.n = len(instances)
+        self.inst = instances
+        if params is not None:
+            L.check("hyp_set_weights", self.lib.hyp_set_weights(self.ctx, _ptr(params), params.numel()))
+            self.params = params
+        G = (L.Grid * self.n)()
+        S = (L.State * self.n)()
+        T = (ctypes.c_double * self.n)()
+        for i, d in enumerate(instances):
+            nx, ny = int(d["nx"]), int(d["ny"])
+            G[i] = L.Grid(nx, ny, float(d["dx"]), float(d.get("dt", 1.0)), float(d.get("rho0", 1.0)))
+            _need(d["u"], torch.float32, (ny, nx + 1), "u")
+            _need(d["v"], torch.float32, (ny + 1, nx), "v")
+            _need(d["p"], torch.float32, (ny, nx), "p")
+            _need(d["flags"], torch.uint8, (ny, nx), "flags")
+            S[i] = L.State(_ptr(d.get("rho")), _ptr(d["u"]), _ptr(d["v"]), _ptr(d["p"]),
+                           _ptr(d["flags"]), _ptr(d.get("xi")))
+            T[i] = float(d.get("threshold", threshold))
+        self._grids, self._states, self._thr = G, S, T
+        nbytes = ctypes.c_size_t()
+        L.check("hyp_batch_workspace_size",
+                self.lib.hyp_batch_workspace_size(self.ctx, self.n, G, ctypes.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.res = torch.zeros(self.n * ctypes.sizeof(L.Result), dtype=torch.uint8, device=self.device)
+        o = L.Opts(L.METHODS[method], int(max_iters), 8, 0, float(omega), 0, (ctypes.c_int32 * 2)())
+        b = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        L.check("hyp_batch_create", self.lib.hyp_batch_create(self.ctx, self.n, G, S, T, ctypes.byref(o),
+                                                              _ptr(self.ws), self.ws.numel(), ctypes.byref(b)))
+        self.batch = b
+
+    def __del__(self):
+        try:
+            if getattr(self, "batch", None):
+                self.lib.hyp_batch_destroy(self.batch)
+                self.batch = None
+            if getattr(self, "ctx", None):
+                self.lib.hyp_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    def project_async(self):
+        L.check("hyp_batch_project", self.lib.hyp_batch_project(self.batch, _stream(), _ptr(self.res)))
+
+    def _phys(self, g, drho, u_in, cfl, rho0):
+        return L.Physics(float(g), float(rho0), float(drho), float(u_in), float(cfl))
+
+    def step_async(self, g: float, drho: float, u_in: float = 1.0, cfl: float = 0.5, rho0: float = 1.0):
+        ph = self._phys(g, drho, u_in, cfl, rho0)
+        L.check("hyp_batch_step", self.lib.hyp_batch_step(self.batch, ctypes.byref(ph), _stream(),
+                                                          _ptr(self.res)))
+
+    def capture(self, g: float, drho: float, u_in: float = 1.0, cfl: float = 0.5, rho0: float = 1.0):
+        """Record one batched time step as a hipGraph (on a side stream)."""
+        ph = self._phys(g, drho, u_in, cfl, rho0)
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            L.check("hyp_batch_capture", self.lib.hyp_batch_capture(self.batch, ctypes.byref(ph), _stream(),
+                                                                    _ptr(self.res)))
+        torch.cuda.synchronize()
+
+    def launch_async(self):
+        L.check("hyp_batch_launch", self.lib.hyp_batch_launch(self.batch, _stream()))
+
+    def results(self):
+        raw = bytes(self.res.cpu().numpy().tobytes())
+        sz = ctypes.sizeof(L.Result)
+        out = []
+        for i in range(self.n):
+            r = L.Result.from_buffer_copy(raw[i * sz:(i + 1) * sz])
+            out.append(ProjectionResult(r.iters, r.status, r.e1_init, r.e1_cnn, r.e1_final,
+                                        r.einf_final, r.s, r.n_fluid, r.dt))
+        return out
+
+
 def adam_async(params, grads, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9,
                beta2: float = 0.999, eps: float = 1e-8):
     """One Adam update of FP32 device tensors on the current stream."""

@@ -4,6 +4,7 @@
 // in the kernels of stencil.hip, solvers.hip and cnn.hip.
 #include <new>
 #include <string.h>
+#include <vector>
 
 #include "../../include/hyproj.h"
 #include "internal.h"
@@ -381,6 +382,184 @@ int hyp_step(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_s
     return HYP_EHIP;
   return enqueue_projection(ctx, &gg, st->u, st->v, nullptr, st->p, threshold, o, L, w, true,
                             stream, res);
+}
+
+// ---------------------------------------------------------------------------
+// Batched projection of many plumes of uneven sizes.
+struct hyp_batch {
+  hyp_ctx* ctx = nullptr;
+  int n = 0, ntiles = 0;
+  std::vector<hyp_grid> grids;
+  std::vector<hyp_state> states;
+  std::vector<WsLayout> layouts;
+  std::vector<Ws> ws;
+  std::vector<double> thr;
+  hyp_opts opts{};
+  void* area = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static size_t batch_layout(hyp_ctx* ctx, int n, const hyp_grid* grids, std::vector<size_t>* offs,
+                           int* ntiles_out) {
+  int ntiles = 0;
+  for (int i = 0; i < n; ++i) ntiles += batch_tiles_of(grids[i].nx, grids[i].ny);
+  size_t o = align256(batch_area_bytes(n, ntiles));
+  for (int i = 0; i < n; ++i) {
+    if (offs) offs->push_back(o);
+    o = align256(o + make_layout(grids[i].nx, grids[i].ny, ctx->net).total);
+  }
+  if (ntiles_out) *ntiles_out = ntiles;
+  return o;
+}
+
+int hyp_batch_workspace_size(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, size_t* bytes) {
+  if (!ctx || n < 1 || !grids || !bytes) return HYP_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    hyp_grid g = grids[i];
+    g.dt = g.dt > 0.0 ? g.dt : 1.0;
+    if (!grid_ok(&g)) return HYP_EINVAL;
+  }
+  *bytes = batch_layout(ctx, n, grids, nullptr, nullptr);
+  return HYP_OK;
+}
+
+int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_state* states,
+                     const double* thresholds, const hyp_opts* o, void* ws, size_t ws_bytes,
+                     hyp_batch** out) {
+  if (!ctx || n < 1 || !grids || !states || !thresholds || !o || !ws || !out) return HYP_EINVAL;
+  *out = nullptr;
+  if (o->method != HYP_METHOD_HYBRID && o->method != HYP_METHOD_JACOBI) return HYP_EUNSUPPORTED;
+  if (o->max_iters < 0 || !(o->omega > 0.f)) return HYP_EINVAL;
+  if (o->method == HYP_METHOD_HYBRID && (ctx->net.scales == 0 || !ctx->params)) return HYP_ENOWEIGHTS;
+  for (int i = 0; i < n; ++i) {
+    hyp_grid g = grids[i];
+    g.dt = g.dt > 0.0 ? g.dt : 1.0;
+    if (!grid_ok(&g) || !(thresholds[i] >= 0.0)) return HYP_EINVAL;
+    const hyp_state& s = states[i];
+    if (!s.u || !s.v || !s.p || !s.flags) return HYP_EINVAL;
+    if (o->method == HYP_METHOD_HYBRID) {
+      const int m = 1 << (ctx->net.scales - 1);
+      if (g.nx % m || g.ny % m) return HYP_EUNSUPPORTED;
+    }
+  }
+  std::vector<size_t> offs;
+  int ntiles = 0;
+  const size_t need = batch_layout(ctx, n, grids, &offs, &ntiles);
+  if (ws_bytes < need) return HYP_EWORKSPACE;
+  hyp_batch* b = new (std::nothrow) hyp_batch;
+  if (!b) return HYP_EINTERNAL;
+  b->ctx = ctx;
+  b->n = n;
+  b->ntiles = ntiles;
+  b->opts = *o;
+  b->area = ws;
+  std::vector<int> nx(n), ny(n);
+  std::vector<double> dx(n);
+  for (int i = 0; i < n; ++i) {
+    b->grids.push_back(grids[i]);
+    b->states.push_back(states[i]);
+    b->thr.push_back(thresholds[i]);
+    b->layouts.push_back(make_layout(grids[i].nx, grids[i].ny, ctx->net));
+    b->ws.push_back(ws_view((char*)ws + offs[i], b->layouts.back()));
+    nx[i] = grids[i].nx; ny[i] = grids[i].ny; dx[i] = grids[i].dx;
+  }
+  if (batch_setup(ws, n, nx.data(), ny.data(), dx.data(), b->thr.data(), o->max_iters, o->omega,
+                  b->ws.data()) != hipSuccess) {
+    delete b;
+    return HYP_EHIP;
+  }
+  for (int i = 0; i < n; ++i)
+    if (run_plan(ctx->dev, nx[i], ny[i], states[i].flags, b->ws[i], nullptr) != hipSuccess) {
+      delete b;
+      return HYP_EHIP;
+    }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    delete b;
+    return HYP_EHIP;
+  }
+  *out = b;
+  return HYP_OK;
+}
+
+static int batch_enqueue(hyp_batch* b, const hyp_physics* ph, hipStream_t s, hyp_result* res,
+                         bool cooperative) {
+  hyp_ctx* ctx = b->ctx;
+  const bool cnn = b->opts.method == HYP_METHOD_HYBRID;
+  for (int i = 0; i < b->n; ++i) {
+    const hyp_grid& g = b->grids[i];
+    const hyp_state& st = b->states[i];
+    const Ws& w = b->ws[i];
+    if (ph && run_advect(g.nx, g.ny, g.dx, ph->g, ph->rho0, ph->drho, ph->u_in, ph->cfl, st.rho,
+                         st.u, st.v, st.xi, w, s) != hipSuccess)
+      return HYP_EHIP;
+    if (run_div(g.nx, g.ny, g.dx, st.u, st.v, w, b->layouts[i].nblocks_stream, s) != hipSuccess)
+      return HYP_EHIP;
+    if (cnn) {
+      if (run_cnn(ctx->dev, ctx->net, b->layouts[i], g.nx, g.ny, g.dx, ctx->params, w, s) != hipSuccess)
+        return HYP_EHIP;
+    } else if (run_init_phi(g.nx, g.ny, nullptr, 1.0, w, s) != hipSuccess) {
+      return HYP_EHIP;
+    }
+  }
+  if (run_jacobi_batch(ctx->dev, b->area, b->n, b->ntiles, cooperative, s) != hipSuccess)
+    return HYP_EHIP;
+  for (int i = 0; i < b->n; ++i) {
+    const hyp_grid& g = b->grids[i];
+    const hyp_state& st = b->states[i];
+    if (run_grad_and_finish(g.nx, g.ny, g.dx, g.rho0, g.dt > 0.0 ? g.dt : 1.0, ph != nullptr, st.u,
+                            st.v, st.p, b->ws[i], b->layouts[i].nblocks_stream, res + i, s) != hipSuccess)
+      return HYP_EHIP;
+  }
+  return HYP_OK;
+}
+
+int hyp_batch_project(hyp_batch* b, hipStream_t stream, hyp_result* res) {
+  if (!b || !res) return HYP_EINVAL;
+  return batch_enqueue(b, nullptr, stream, res, true);
+}
+
+int hyp_batch_step(hyp_batch* b, const hyp_physics* ph, hipStream_t stream, hyp_result* res) {
+  if (!b || !ph || !res) return HYP_EINVAL;
+  for (const auto& s : b->states)
+    if (!s.rho || !s.xi) return HYP_EINVAL;
+  return batch_enqueue(b, ph, stream, res, true);
+}
+
+int hyp_batch_capture(hyp_batch* b, const hyp_physics* ph, hipStream_t stream, hyp_result* res) {
+  if (!b || !res || !stream) return HYP_EINVAL;
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return HYP_EHIP;
+  const int rc = batch_enqueue(b, ph, stream, res, false);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(stream, &g);
+  if (rc != HYP_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != HYP_OK ? rc : HYP_EHIP;
+  }
+  b->graph = g;
+  if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) return HYP_EHIP;
+  return HYP_OK;
+}
+
+int hyp_batch_launch(hyp_batch* b, hipStream_t stream) {
+  if (!b || !b->exec) return HYP_EINVAL;
+  return hipGraphLaunch(b->exec, stream) == hipSuccess ? HYP_OK : HYP_EHIP;
+}
+
+int hyp_batch_destroy(hyp_batch* b) {
+  if (!b) return HYP_OK;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+  return HYP_OK;
 }
 
 }  // extern "C"
