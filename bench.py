@@ -35,6 +35,20 @@ MAX_ITERS = 1000000
 BYTES_PER_CELL_SWEEP = 13   # phi read + write (8), d (4), flags (1)
 HBM_PEAK_GBS = 8000.0
 WEIGHTS = os.path.join(ROOT, "paper_2109_09363_amd", "weights", "plume_s4c64.npy")
+# HBM traffic of the Jacobi kernel per dispatch of this benchmark, from two
+# rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a copy kernel's
+# reading; used only while the kernel's sources are unchanged since then
+TRAFFIC = os.path.join(ROOT, "profiles", "jacobi_reg_plume512_traffic.txt")
+
+
+def measured_traffic():
+    from paper_2109_09363_amd import profsummary as PS
+    if not os.path.exists(TRAFFIC):
+        return None, "no counter summary"
+    t = PS.read_traffic(TRAFFIC)
+    if t.get("source_sha") != PS.source_hash("jacobi_reg"):
+        return None, "kernel changed since the counters were taken"
+    return float(t["traffic_bytes_per_dispatch"]), os.path.relpath(TRAFFIC, ROOT)
 
 
 def load_weights(scenes):
@@ -165,18 +179,20 @@ def main():
     tot_ms = np.array([t["total"] for _, t in rows_h])
     e1f = max(r.e1_final for r, _ in rows_h)
 
-    # roofline of the dominant kernel: the persistent Jacobi launch
+    # roofline of the dominant kernel: the persistent Jacobi launch (one per
+    # projection; the solver phase's HIP events bracket exactly that launch)
     cells = N * N
-    bytes_per_launch = BYTES_PER_CELL_SWEEP * cells * it_h
-    mask = it_h > 0
-    if mask.any():
-        achieved = float(bytes_per_launch[mask].sum() / (solver_ms[mask].sum() * 1e-3) / 1e9)
-    else:
-        achieved = 0.0
+    bytes_per_launch = float(BYTES_PER_CELL_SWEEP * cells * it_h.mean())
+    avg_ms = float(solver_ms.mean())
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic, traffic_src = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "jacobi_persist", "avg_launch_ms": round(float(solver_ms[mask].mean()), 4) if mask.any() else None,
-                "algorithmic_bytes_per_launch": int(bytes_per_launch[mask].mean()) if mask.any() else 0}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "traffic_source": traffic_src,
+                "kernel": "jacobi_reg", "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                "bytes_per_cell_sweep": BYTES_PER_CELL_SWEEP}
 
     cpu = None
     if not args.no_cpu:

@@ -61,6 +61,10 @@ extern "C" {
 #define HYP_STATUS_FLOOR      3  /* the threshold lies below what FP32 reached
                                     after every defect-correction round; the
                                     best iterate is returned */
+#define HYP_STATUS_ABORTED    4  /* a persistent solver stopped waiting for
+                                    data from another work-group (a 2 s limit
+                                    per wait; an internal error): the outputs
+                                    are not valid */
 
 /* methods */
 #define HYP_METHOD_HYBRID  0  /* CNN initial guess, then Jacobi (Sec. 3.3) */

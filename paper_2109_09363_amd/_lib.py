@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhyproj.so")
 
 HYP_OK = 0
-STATUS_OK, STATUS_MAXITER, STATUS_NONFINITE, STATUS_FLOOR = 0, 1, 2, 3
+STATUS_OK, STATUS_MAXITER, STATUS_NONFINITE, STATUS_FLOOR, STATUS_ABORTED = 0, 1, 2, 3, 4
 METHODS = {"hybrid": 0, "jacobi": 1, "pcg": 2, "cnn": 3}
 PRECISIONS = {"fp32": 0, "bf16": 1}
 NET_TRAIN = 1

@@ -40,7 +40,7 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
   L.nblocks_stream = (int)((n + kStreamBlock - 1) / kStreamBlock);
   L.scalars = take(sizeof(Scalars));
-  L.sync = take(256);
+  L.sync = take(kSyncBytes);
   L.partial = take(sizeof(double) * 6 * kMaxCoopBlocks);
   // block partials: two per cell-grid block, or one per face-grid block (CFL)
   const size_t nfaces = (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx;
@@ -284,19 +284,19 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
   mark(ctx, 2, stream);
   if (o->method == HYP_METHOD_CNN) {
     // no sweeps: a zero-length Jacobi pass records E_1 of the prediction
-    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, kSolveRounds - 1, w, stream);
-  } else {
+    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, u, v, w, stream);
+  } else if (o->method == HYP_METHOD_PCG) {
     // rounds separated by defect-correction folds; a round after the solve
     // has finished returns at once
     for (int r = 0; r < kSolveRounds && e == hipSuccess; ++r) {
-      if (o->method == HYP_METHOD_PCG)
-        e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
-                    o->fixed_iters, r, w, stream);
-      else
-        e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,
-                       o->fixed_iters, o->fold_window, r, w, stream);
+      e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
+                  o->fixed_iters, r, w, stream);
       if (e == hipSuccess && r + 1 < kSolveRounds) e = run_fold(nx, ny, g->dx, u, v, w, stream);
     }
+  } else {
+    // one persistent launch, defect-correction folds included
+    e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,
+                   o->fixed_iters, o->fold_window, u, v, w, stream);
   }
   if (e != hipSuccess) return HYP_EHIP;
   mark(ctx, 3, stream);

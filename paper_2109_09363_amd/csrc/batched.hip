@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void jacobi_batch(BatchParams P) {
 
 __global__ void batch_reset(BatchState* st, int n, unsigned* sync) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 64) sync[i] = 0;
+  sync_clear(sync, i);
   if (i < n) {
     st[i].status = kStatusRunning;
     st[i].iters = 0;
@@ -206,11 +206,6 @@ __global__ void batch_reset(BatchState* st, int n, unsigned* sync) {
 
 int batch_rows() { return 16; }
 
-size_t batch_area_bytes(int ninst, int ntiles) {
-  return 256 + sizeof(BatchInstDev) * (size_t)ninst + 256 + sizeof(int) * (size_t)ntiles + 256 +
-         sizeof(double) * 2 * (size_t)ntiles + 256 + sizeof(BatchState) * (size_t)ninst + 512;
-}
-
 // Host view of the batch area and the launch.
 struct BatchArea {
   BatchInstDev* inst;
@@ -220,17 +215,30 @@ struct BatchArea {
   unsigned* sync;
 };
 
-static BatchArea carve(void* base, int ninst, int ntiles) {
-  char* b = (char*)base;
+// The one layout of the batch area: carve() places every table, and the
+// area size is what carve() takes from a null base.
+static BatchArea carve(void* base, int ninst, int ntiles, size_t* bytes = nullptr) {
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
   size_t o = 0;
-  auto take = [&](size_t bytes) { char* p = b + o; o = (o + bytes + 255) & ~(size_t)255; return p; };
+  auto take = [&](size_t n) {
+    const size_t at = o;
+    o = (o + n + 255) & ~(size_t)255;
+    return reinterpret_cast<char*>(b + at);
+  };
   BatchArea A;
-  A.sync = (unsigned*)take(256);
+  A.sync = (unsigned*)take(kSyncBytes);
   A.inst = (BatchInstDev*)take(sizeof(BatchInstDev) * ninst);
   A.tile_inst = (int*)take(sizeof(int) * ntiles);
   A.tile_part = (double*)take(sizeof(double) * 2 * ntiles);
   A.st = (BatchState*)take(sizeof(BatchState) * ninst);
+  if (bytes) *bytes = o;
   return A;
+}
+
+size_t batch_area_bytes(int ninst, int ntiles) {
+  size_t n = 0;
+  (void)carve(nullptr, ninst, ntiles, &n);
+  return n;
 }
 
 int batch_tiles_of(int nx, int ny) {

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "internal.h"
+
 namespace hyp {
 
 constexpr int kWave = 64;
@@ -19,12 +21,31 @@ __device__ __forceinline__ int cell_k(uint8_t c) { return __popc((c >> 2) & 15u)
 __device__ __forceinline__ bool cell_fluid(uint8_t c) { return !(c & C_SOLID); }
 
 // ---- wave / block reductions (fixed order, deterministic) ----------------
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
-  return v;
+// Sums use DPP row shifts and row broadcasts (VALU rate; no LDS permutes).
+// 64-bit DPP move of a double, lanes without a source (or in a disabled row)
+// receive 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+// Sum over the 64 lanes of a wave with row shifts and row broadcasts (no LDS
+// permutes); the result is valid in every lane.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_f64<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_f64<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_f64<0x118, 0xF>(v);  // row_shr:8  -> lane 15 of each row: the row sum
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3 -> lane 63: total
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, kWave));
@@ -36,7 +57,7 @@ __device__ __forceinline__ double wave_max(double v) {
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
-  v = wave_sum(v);
+  v = wave_sum_dpp(v);
   __syncthreads();
   if (lane == 0) scratch[w] = v;
   __syncthreads();
@@ -59,23 +80,53 @@ __device__ __forceinline__ double block_max(double v, double* scratch) {
 // ---- grid-wide barrier for cooperative (co-resident) launches ------------
 // Data that crosses work-groups is written and read with agent-scope atomic
 // stores/loads (coherent across the XCD L2 caches), so the barrier needs no
-// L2 write-back/invalidate fences: every wave waits for its own stores
-// (workgroup-scope release fence), the work-group arrives on a counter, the
-// last arriver raises a generation flag on its own cache line, and everyone
-// polls the flag.  `sync[0]` (counter) and `sync[32]` (flag) are zeroed
-// before the launch; barrier number n (1, 2, ...) passes when all `nblocks`
-// work-groups have arrived n times.
-__device__ __forceinline__ void grid_barrier(unsigned* sync, unsigned n, unsigned nblocks) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+// L2 write-back/invalidate fences.  Every wave first waits until its own
+// memory operations have completed (s_waitcnt 0: a workgroup-scope fence does
+// not wait for stores on this target, and an arrival could otherwise overtake
+// the data it announces).  Arrival is two-level: work-groups count on the
+// counter of their group of kSyncGroup consecutive blocks (each counter on its
+// own 128-byte line), the last of a group counts on the top counter, and the
+// last of all raises the generation flag.  One thread per work-group polls
+// that flag: agent-scope polling bypasses the L2, and more pollers (one per
+// group counter, say) measurably slow every work-group's stores.  Barrier
+// number n (1, 2, ...) passes when all `nblocks` work-groups have arrived n
+// times.  Slot i of the sync area is the word sync[32 i]: 0 top counter,
+// 1 flag, 2 + g group g; all are zeroed before a launch (sync_clear).
+__device__ __forceinline__ void sync_clear(unsigned* sync, int i) {
+  if (i >= 0 && i < kSyncSlots) sync[32 * i] = 0;
+}
+
+// Every wait is bounded (kSpinTicks of the constant 100 MHz wall clock):
+// returns false in every thread of a work-group that gave up, so that a
+// persistent kernel can end instead of hanging on a lost arrival.
+constexpr uint64_t kSpinTicks = 200000000ull;  // 2 s
+
+__device__ __forceinline__ bool grid_barrier_bounded(unsigned* sync, unsigned n, unsigned nblocks) {
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  int ok = 1;
   if (threadIdx.x == 0) {
-    const unsigned old = __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == n * nblocks - 1)
-      __hip_atomic_store(sync + 32, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (__hip_atomic_load(sync + 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n)
+    const unsigned ng = (nblocks + kSyncGroup - 1) / kSyncGroup, g = blockIdx.x / kSyncGroup;
+    const unsigned gs = (g == ng - 1) ? nblocks - kSyncGroup * (ng - 1) : kSyncGroup;
+    const unsigned old = __hip_atomic_fetch_add(sync + 32 * (2 + g), 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (old == n * gs - 1) {
+      const unsigned top = __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (top == n * ng - 1) __hip_atomic_store(sync + 32, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint64_t t0 = (uint64_t)wall_clock64();
+    while (__hip_atomic_load(sync + 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n) {
+      if ((uint64_t)wall_clock64() - t0 > kSpinTicks) { ok = 0; break; }
       __builtin_amdgcn_s_sleep(2);
+    }
   }
-  __syncthreads();
+  return __syncthreads_and(ok) != 0;
+}
+
+// The same barrier for kernels without an abort path (the bounded wait can
+// only give up on a lost arrival, which a correct launch never has).
+__device__ __forceinline__ void grid_barrier(unsigned* sync, unsigned n, unsigned nblocks) {
+  (void)grid_barrier_bounded(sync, n, nblocks);
 }
 
 __device__ __forceinline__ void st_agent(float* p, float v) {
@@ -89,6 +140,11 @@ __device__ __forceinline__ void st_agent(double* p, double v) {
                      static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __longlong_as_double(static_cast<long long>(__hip_atomic_load(
+      reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED,
+      __HIP_MEMORY_SCOPE_AGENT)));
+}
 __device__ __forceinline__ void st_agent(uint8_t* p, uint8_t v) {
   // byte stores: go through a 32-bit atomic OR/AND pair on the containing word
   unsigned* w = reinterpret_cast<unsigned*>(reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3);
@@ -101,6 +157,19 @@ __device__ __forceinline__ uint8_t ld_agent(const uint8_t* p) {
   const unsigned* w = reinterpret_cast<const unsigned*>(reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3);
   const unsigned sh = (unsigned)(reinterpret_cast<uintptr_t>(p) & 3) * 8;
   return (uint8_t)(__hip_atomic_load(const_cast<unsigned*>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> sh);
+}
+
+__device__ __forceinline__ void st_agent(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_agent(const unsigned* p) {
+  return __hip_atomic_load(const_cast<unsigned*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // lane l receives x from lane l-1 (lane 0 receives 0): DPP wave_shr:1

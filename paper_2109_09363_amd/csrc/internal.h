@@ -27,7 +27,12 @@ struct Scalars {
 };
 
 constexpr int kMaxCoopBlocks = 1024;   // partial-sum slots per parity
-constexpr int kSolveRounds = 4;        // solver rounds (up to 3 defect-correction folds)
+// grid-barrier area: top counter, flag and one counter per group of
+// kSyncGroup blocks, each on its own 128-byte line (common.h)
+constexpr int kSyncGroup = 16;
+constexpr int kSyncSlots = 2 + kMaxCoopBlocks / kSyncGroup;
+constexpr int kSyncBytes = kSyncSlots * 128;
+constexpr int kSolveRounds = 4;        // PCG rounds (up to 3 defect-correction folds)
 constexpr int kStatusRunning = -1;     // Scalars::status while a solve is in progress
 constexpr int kStatusFold = -2;        // a round asks for a fold before the next one
 constexpr int kStreamBlock = 256;      // threads of the streaming kernels
@@ -98,7 +103,7 @@ hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const
                         hipStream_t s);
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      int round, const Ws& w, hipStream_t s);
+                      float* u, float* v, const Ws& w, hipStream_t s);
 hipError_t run_fold(int nx, int ny, double dx, float* u, float* v, const Ws& w, hipStream_t s);
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters);
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,

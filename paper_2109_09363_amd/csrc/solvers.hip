@@ -1,23 +1,24 @@
 // Persistent iterative solvers of L phi = d (Eq. 3), one cooperative launch
-// each (all work-groups co-resident, grid barrier of common.h):
+// each (all work-groups co-resident):
 //
 //  * Jacobi (Sec. 2.2) in correction form phi <- phi - omega dx^2 r / k_c,
 //    r = d - L phi.  Register-resident with temporal blocking: a work-group
 //    owns a 64-column extended tile (interior + halo of width H on every
 //    side), one lane per column; each of the 4 waves keeps R consecutive
 //    rows of its lane's column in registers, together with d, k and the
-//    update weight.  East/west neighbours move between lanes with DPP
-//    wave shifts, north/south come from the same lane's registers (band
-//    edges through LDS).  Every block of B <= H - 1 sweeps ends with the
-//    FP64 sum of |r| over the interior, an exchange of the interior through
-//    global memory and one grid barrier; the halo is then refreshed.
-//    E_1 is tested at the block boundaries (every check_every sweeps and at
-//    max_iters).
+//    update weight.  East/west neighbours move between lanes with DPP wave
+//    shifts, north/south come from the same lane's registers (band edges
+//    through LDS).  A step of B <= H - 1 sweeps ends with the interior and,
+//    at a test, the FP64 partial of sum|r| written with agent-scope stores,
+//    one grid barrier, and one round trip that brings back the halo and all
+//    partials together.  E_1 is tested at the steps that end on a multiple
+//    of check_every (and at max_iters); every work-group sums the partials
+//    in the same order, so all take the same decision at the same sweep.
+//    Defect-correction folds (the velocity takes the increment, d is
+//    recomputed from the faces, phi restarts at 0) run inside the launch.
 //  * Jacobi-preconditioned conjugate gradient with FP64 dot products: LDS
-//    tiles with a one-cell halo for the search direction, three grid-wide
-//    reductions per iteration, and a stop confirmed on the true residual.
-// Every work-group sums the same partials in the same order, so all take
-// the same stop decision at the same iteration.
+//    tiles with a one-cell halo for the search direction, one merged grid
+//    reduction per iteration, and a stop confirmed on the true residual.
 #include "../../include/hyproj.h"
 #include "common.h"
 #include "internal.h"
@@ -36,19 +37,21 @@ __device__ __forceinline__ int decide(int k, double E, double thr, int max_iters
 }
 
 struct JacParams {
-  int nx, ny, H, ntx;
-  float inv_dx2, wfac;  // wfac = omega * dx^2
+  int nx, ny, H, ntx, nty;
+  float inv_dx2, wfac, inv_dx;  // wfac = omega * dx^2
   double thr;
   int max_iters, check_every, fixed_iters;
   int fold_window;      // sweeps per stagnation window (0: no folds)
-  int last_round;       // 1: this round may not end with a fold
   const uint8_t* cell;
-  const float* d;
-  float* phi;    // in: initial guess, out: returned iterate
-  float* exch;   // 2 x nx*ny
-  double* partial;
+  float* d;             // recomputed on the interior at a fold
+  float* phi;           // in: initial guess, out: returned iterate
+  float* phi_acc;       // pressure folded into the faces
+  float* u;             // faces, corrected at a fold
+  float* v;
+  float* exch;          // 2 x nx*ny halo exchange planes
+  double* partial;      // 2 x kMaxCoopBlocks partial sums
   Scalars* sc;
-  unsigned* sync;
+  unsigned* sync;       // grid barrier
 };
 
 // One pass over the R rows of a lane: new value (or residual) of every cell.
@@ -76,6 +79,11 @@ __device__ __forceinline__ double jac_rows(float (&ph)[R], const float (&dd)[R],
   return acc;
 }
 
+__device__ __forceinline__ void abort_solve(Scalars* sc) {
+  __hip_atomic_fetch_max(&sc->status, (int32_t)HYP_STATUS_ABORTED, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
   __shared__ float edge[2][2][4][64];  // [parity][low row / high row][wave][lane]
@@ -89,16 +97,17 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
   const bool col_in = gx >= 0 && gx < p.nx;
   const bool lane_int = lane >= H && lane < H + TW && col_in;
   const int nF = p.sc->nF;
-  if (p.sc->status >= 0) return;  // an earlier round finished the solve
-  // rows of this thread inside the tile interior (and the domain): imask;
-  // the fluid ones among them, which enter E_1: fmask
-  unsigned imask = 0, fmask = 0;
+  if (p.sc->status >= 0) return;  // nothing to do (status already final)
+  // rows of this thread inside the domain (dmask), inside the tile interior
+  // (imask), and the fluid ones among the latter, which enter E_1 (fmask)
+  unsigned dmask = 0, imask = 0, fmask = 0;
   float ph[R], dd[R], kk[R], ww[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int er = wave * R + r, gy = gy0 + r;
     float d_ = 0.f, k_ = 0.f, w_ = 0.f, p_ = 0.f;
     if (col_in && gy >= 0 && gy < p.ny) {
+      dmask |= 1u << r;
       const int g = gy * p.nx + gx;
       const uint8_t ci = p.cell[g];
       if (!(ci & C_SOLID)) {
@@ -115,13 +124,13 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     }
     ph[r] = p_; dd[r] = d_; kk[r] = k_; ww[r] = w_;
   }
-  int k = p.sc->iters, par = 0, q = 0;
-  unsigned nbar = 0;
+  const int k0 = p.sc->iters;
   const int end = p.fixed_iters > 0 ? p.fixed_iters : p.max_iters;
   const size_t plane = (size_t)p.nx * p.ny;
-  const int k_start = k;
-  int k_ref = k;
+  int k = k0, q = 0, k_ref = k0;
+  unsigned j = 0, t = 0, nbar = 0;
   double E_ref = 0.0;
+  bool ref_set = false;
   auto edges = [&](float* below, float* above) {
     edge[q][0][wave][lane] = ph[0];
     edge[q][1][wave][lane] = ph[R - 1];
@@ -130,56 +139,129 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     *above = wave < 3 ? edge[q][0][wave + 1][lane] : 0.f;
     q ^= 1;
   };
-  for (;;) {
-    float below, above;
-    edges(&below, &above);
-    const double loc = jac_rows<R, false>(ph, dd, kk, ww, below, above, p.inv_dx2, fmask);
-    float* ex = p.exch + par * plane;
+  auto finish = [&](int st, double E) {
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if ((imask >> r) & 1u) st_agent(ex + (size_t)(gy0 + r) * p.nx + gx, ph[r]);
-    const double tot_local = block_sum(loc, red);
-    double* part = p.partial + par * kMaxCoopBlocks;
-    if (threadIdx.x == 0) st_agent(part + blockIdx.x, tot_local);
-    ++nbar;
-    grid_barrier(p.sync, nbar, (unsigned)G);
-    const double tot = sum_partials(part, G, red);
-    const double E = nF > 0 ? tot / nF : 0.0;
-    if (k == 0 && blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
-    int st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
-    if (k == k_start) E_ref = E;
-    if (st < 0 && !p.last_round && p.fold_window > 0 && k - k_ref >= p.fold_window) {
-      // stagnation window: fold when E_1 fell by less than 1 % (always in
-      // fixed-sweep mode, where folds only re-base the same iteration)
-      if (p.fixed_iters > 0 || !(E < 0.99 * E_ref)) st = kStatusFold;
+      if ((imask >> r) & 1u) p.phi[(size_t)(gy0 + r) * p.nx + gx] = ph[r];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      p.sc->iters = k;
+      p.sc->e1_solve = E;
+      __hip_atomic_fetch_max(&p.sc->status, (int32_t)st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+  auto barrier = [&]() -> bool {
+    if (grid_barrier_bounded(p.sync, ++nbar, (unsigned)G)) return true;
+    if (threadIdx.x == 0) abort_solve(p.sc);
+    return false;
+  };
+  for (;;) {
+    // publish the interior of the state after j steps (read by the
+    // neighbours after the barrier)
+    float* ex = p.exch + (size_t)(j & 1u) * plane;
+    if (j > 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (((imask >> r) & 1u) && kk[r] > 0.f) st_agent(ex + (size_t)(gy0 + r) * p.nx + gx, ph[r]);
+    }
+    const bool test = k == k0 || (p.fixed_iters > 0 ? k >= end : (k % p.check_every == 0 || k >= end));
+    // E_1 of the current state: the interior and the ring around it are
+    // valid, so the residual needs no fresh halo
+    double* part = p.partial + (size_t)((t + 1) & 1u) * kMaxCoopBlocks;
+    if (test) {
+      float below, above;
+      edges(&below, &above);
+      const double loc = block_sum(jac_rows<R, false>(ph, dd, kk, ww, below, above, p.inv_dx2, fmask), red);
+      ++t;
+      if (threadIdx.x == 0) st_agent(part + blockIdx.x, loc);
+    }
+    if (!barrier()) return;
+    // one round trip: the halo (every non-interior fluid cell) and the partials
+    if (j > 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (!((imask >> r) & 1u) && kk[r] > 0.f) ph[r] = ld_agent(ex + (size_t)(gy0 + r) * p.nx + gx);
+    }
+    int st = -1;
+    double E = 0.0;
+    if (test) {
+      double a = 0.0;
+      for (int i = threadIdx.x; i < G; i += 256) a += ld_agent(part + i);
+      const double tot = block_sum(a, red);
+      E = nF > 0 ? tot / nF : 0.0;
+      if (k == 0 && blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
+      st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
+      if (!ref_set) { E_ref = E; ref_set = true; }
+    }
+    // stagnation window: fold when E_1 fell by less than 1 % over the window
+    // (always in fixed-sweep mode, where folds only re-base the iteration)
+    bool fold = false;
+    if (st < 0 && p.fold_window > 0 && k - k_ref >= p.fold_window && (p.fixed_iters > 0 || test)) {
+      fold = p.fixed_iters > 0 || !(E < 0.99 * E_ref);
       k_ref = k;
       E_ref = E;
     }
     if (st != -1) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if ((imask >> r) & 1u) p.phi[(size_t)(gy0 + r) * p.nx + gx] = ph[r];
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        p.sc->iters = k;
-        p.sc->status = st;
-        p.sc->e1_solve = E;
-      }
+      finish(st, E);
       return;
+    }
+    if (fold) {
+      // (1) the faces this tile owns (west and south of each interior cell,
+      //     plus the open top face) take the increment; phi_acc keeps it.
+      //     The refreshed halo holds the owners' values, bit-identical to
+      //     the ring this tile computed itself.
+      float below, above;
+      edges(&below, &above);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float west = from_left(ph[r]);
+        const float south = r > 0 ? ph[r - 1] : below;
+        if (((imask >> r) & 1u) && kk[r] > 0.f) {
+          const int gy = gy0 + r;
+          const size_t c = (size_t)gy * p.nx + gx;
+          const uint8_t ci = p.cell[c];
+          const float pc = ph[r];
+          if (ci & C_W) {
+            float* f = p.u + (size_t)gy * (p.nx + 1) + gx;
+            st_agent(f, ld_agent(f) - (pc - west) * p.inv_dx);
+          }
+          if (ci & C_S) {
+            float* f = p.v + c;
+            st_agent(f, ld_agent(f) - (pc - south) * p.inv_dx);
+          }
+          if (gy == p.ny - 1 && (ci & C_N)) {
+            float* f = p.v + plane + gx;
+            st_agent(f, ld_agent(f) - (0.f - pc) * p.inv_dx);
+          }
+          p.phi_acc[c] += pc;
+        }
+      }
+      (void)above;
+      // (2) every tile's faces are in place
+      if (!barrier()) return;
+      // (3) d from the corrected faces on the whole extended tile; phi = 0
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (((dmask >> r) & 1u) && kk[r] > 0.f) {
+          const int gy = gy0 + r;
+          const size_t U = (size_t)p.nx + 1;
+          const float uw = ld_agent(p.u + gy * U + gx), ue = ld_agent(p.u + gy * U + gx + 1);
+          const float vs = ld_agent(p.v + (size_t)gy * p.nx + gx);
+          const float vn = ld_agent(p.v + (size_t)(gy + 1) * p.nx + gx);
+          dd[r] = ((ue - uw) + (vn - vs)) * p.inv_dx;
+          if ((imask >> r) & 1u) p.d[(size_t)gy * p.nx + gx] = dd[r];
+        }
+        ph[r] = 0.f;
+      }
     }
     int B = min(H - 1, end - k);
     if (p.fixed_iters <= 0) B = min(B, p.check_every - k % p.check_every);
-    // refresh every non-interior cell from the neighbours' interiors
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if ((imask >> r) & 1u) continue;
-      if (kk[r] > 0.f) ph[r] = ld_agent(ex + (size_t)(gy0 + r) * p.nx + gx);
-    }
     for (int s = 0; s < B; ++s) {
+      float below, above;
       edges(&below, &above);
       jac_rows<R, true>(ph, dd, kk, ww, below, above, p.inv_dx2, 0u);
     }
     k += B;
-    par ^= 1;
+    ++j;
   }
 }
 
@@ -397,7 +479,7 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
 
 // ---------------------------------------------------------------------------
 // Launch geometry.  Jacobi: halo H = B + 1 with B = min(check_every, 8)
-// sweeps per block (8 for fixed_iters), tile interior (64 - 2H) x (4R - 2H),
+// sweeps per step (8 for fixed_iters), tile interior (64 - 2H) x (4R - 2H),
 // the smallest R whose tile count fits one work-group per CU.
 static int jacobi_block_len(int check_every, int fixed_iters) {
   const int kMaxBlock = 8;
@@ -456,20 +538,20 @@ static hipError_t launch_jacobi(JacParams& p, int G, hipStream_t s) {
 
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      int round, const Ws& w, hipStream_t s) {
+                      float* u, float* v, const Ws& w, hipStream_t s) {
   JacParams p{};
   int R = 0, H = 0, ntx = 0, nty = 0;
   if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, &R, &H, &ntx, &nty))
     return hipErrorInvalidValue;
-  p.nx = nx; p.ny = ny; p.H = H; p.ntx = ntx;
+  p.nx = nx; p.ny = ny; p.H = H; p.ntx = ntx; p.nty = nty;
   p.inv_dx2 = (float)(1.0 / (dx * dx));
+  p.inv_dx = (float)(1.0 / dx);
   p.wfac = (float)(omega * dx * dx);
   p.thr = thr;
   p.max_iters = max_iters; p.check_every = check_every; p.fixed_iters = fixed_iters;
   p.fold_window = fold_window > 0 ? fold_window : (fixed_iters > 0 ? 0 : 1024);
-  p.last_round = round + 1 >= kSolveRounds;
-  p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.exch = w.exch; p.partial = w.partial; p.sc = w.sc;
-  p.sync = w.sync;
+  p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.phi_acc = w.phi_acc; p.u = u; p.v = v;
+  p.exch = w.exch; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
   const int G = ntx * nty;
   switch (R) {
     case 4: return launch_jacobi<4>(p, G, s);

@@ -20,7 +20,7 @@ __global__ __launch_bounds__(256) void plan_init(int nx, int ny, const uint8_t* 
                                                  uint8_t* __restrict__ reach, Scalars* sc,
                                                  unsigned* sync) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < 64) sync[c] = 0;
+  sync_clear(sync, c);
   if (c == 0) {
     sc->bar = 0;
     sc->nF = 0;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void div_kernel(int nx, int ny, float inv_dx,
                                                   unsigned* sync, float* __restrict__ phi_acc) {
   __shared__ double red[4];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < 64) sync[c] = 0;
+  sync_clear(sync, c);
   if (c == 0) sc->bar = 0;
   double a = 0.0, q = 0.0;
   if (c < nx * ny) {
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void fold_div(int nx, int ny, float inv_dx,
                                                 unsigned* sync) {
   if (sc->status != kStatusFold) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < 64) sync[c] = 0;  // the next round's grid barrier starts afresh
+  sync_clear(sync, c);  // the next round's grid barrier starts afresh
   if (c >= nx * ny) return;
   const int i = c % nx, j = c / nx, U = nx + 1;
   const bool fl = !(cell[c] & C_SOLID);
