@@ -58,9 +58,10 @@ extern "C" {
 #define HYP_STATUS_OK         0  /* threshold reached (or fixed_iters done) */
 #define HYP_STATUS_MAXITER    1  /* max_iters reached; last iterate returned */
 #define HYP_STATUS_NONFINITE  2  /* NaN/Inf in the residual; iterate returned */
-#define HYP_STATUS_FLOOR      3  /* the threshold lies below what FP32 reached
-                                    after every defect-correction round; the
-                                    best iterate is returned */
+#define HYP_STATUS_FLOOR      3  /* PCG: the true residual stayed above the
+                                    threshold after 3 defect-correction folds
+                                    (the threshold lies below what FP32
+                                    reaches); the last iterate is returned */
 #define HYP_STATUS_ABORTED    4  /* a persistent solver stopped waiting for
                                     data from another work-group (a 2 s limit
                                     per wait; an internal error): the outputs

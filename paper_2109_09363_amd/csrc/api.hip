@@ -286,13 +286,9 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
     // no sweeps: a zero-length Jacobi pass records E_1 of the prediction
     e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, u, v, w, stream);
   } else if (o->method == HYP_METHOD_PCG) {
-    // rounds separated by defect-correction folds; a round after the solve
-    // has finished returns at once
-    for (int r = 0; r < kSolveRounds && e == hipSuccess; ++r) {
-      e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
-                  o->fixed_iters, r, w, stream);
-      if (e == hipSuccess && r + 1 < kSolveRounds) e = run_fold(nx, ny, g->dx, u, v, w, stream);
-    }
+    // one persistent launch, defect-correction folds included
+    e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
+                o->fixed_iters, u, v, w, stream);
   } else {
     // one persistent launch, defect-correction folds included
     e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,

@@ -32,9 +32,7 @@ constexpr int kMaxCoopBlocks = 1024;   // partial-sum slots per parity
 constexpr int kSyncGroup = 16;
 constexpr int kSyncSlots = 2 + kMaxCoopBlocks / kSyncGroup;
 constexpr int kSyncBytes = kSyncSlots * 128;
-constexpr int kSolveRounds = 4;        // PCG rounds (up to 3 defect-correction folds)
 constexpr int kStatusRunning = -1;     // Scalars::status while a solve is in progress
-constexpr int kStatusFold = -2;        // a round asks for a fold before the next one
 constexpr int kStreamBlock = 256;      // threads of the streaming kernels
 
 struct NetShape {
@@ -67,7 +65,7 @@ struct Ws {
   uint8_t* cell;
   float* d;
   float* phi;
-  float* phi_acc;     // pressure folded into the faces by earlier rounds
+  float* phi_acc;     // pressure folded into the faces by defect-correction folds
   float* exch;        // 2 x nx*ny (halo exchange ping-pong)
   double* blockpart;  // streaming-kernel block partials
   size_t blockpart_n; // capacity of blockpart in doubles
@@ -104,10 +102,9 @@ hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
                       float* u, float* v, const Ws& w, hipStream_t s);
-hipError_t run_fold(int nx, int ny, double dx, float* u, float* v, const Ws& w, hipStream_t s);
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters);
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
-                   int check_every, int fixed_iters, int round, const Ws& w, hipStream_t s);
+                   int check_every, int fixed_iters, float* u, float* v, const Ws& w, hipStream_t s);
 hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt, bool dt_dev,
                                float* u, float* v, float* p, const Ws& w, int nblocks, void* res,
                                hipStream_t s);

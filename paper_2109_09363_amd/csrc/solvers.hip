@@ -272,20 +272,26 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
 // preconditioned residual u and one merged FP64 reduction of (r.u, w.u,
 // sum|r|), w = A u.  Same tile layout as the Jacobi kernel with a one-cell
 // halo; x, r, u, w, p, s live in registers.  A stop is confirmed on the true
-// residual b - A x (FP32 drift of the updated residual); when it fails the
-// round ends with a fold (or, in the last round, CG restarts from it).
+// residual b - A x (FP32 drift of the updated residual).  When it fails, the
+// velocity takes the increment (defect-correction fold: faces corrected, d
+// recomputed from them, x restarts at 0) and CG restarts; after kMaxFolds
+// folds a failed confirmation ends the solve with HYP_STATUS_FLOOR.
 // ---------------------------------------------------------------------------
+constexpr int kMaxFolds = 3;
+
 struct PcgParams {
   int nx, ny, ntx;
-  float dx2;
+  float dx2, inv_dx;
   double thr, inv_dx2;
   int max_iters, check_every, fixed_iters;
-  int last_round;
   const uint8_t* cell;
-  const float* d;
-  float* phi;
-  float* exch;
-  double* partial;
+  float* d;             // recomputed on the interior at a fold
+  float* phi;           // in: initial guess, out: returned iterate
+  float* phi_acc;       // pressure folded into the faces
+  float* u;             // faces, corrected at a fold
+  float* v;
+  float* exch;          // 2 x nx*ny
+  double* partial;      // 2 x 3 x kMaxCoopBlocks
   Scalars* sc;
   unsigned* sync;
 };
@@ -330,15 +336,15 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
   const bool col_in = gx >= 0 && gx < p.nx;
   const bool lane_int = lane >= 1 && lane < 1 + TW && col_in;
   const int nF = p.sc->nF;
-  if (p.sc->status >= 0) return;  // an earlier round finished the solve
-  const bool round0 = p.sc->iters == 0;
-  unsigned imask = 0;
+  if (p.sc->status >= 0) return;
+  unsigned dmask = 0, imask = 0;
   float x[R], r[R], u[R], w[R], pp[R], ss[R], kk[R], bb[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int er = wave * R + i, gy = gy0 + i;
     float k_ = 0.f, b_ = 0.f, x_ = 0.f;
     if (col_in && gy >= 0 && gy < p.ny) {
+      dmask |= 1u << i;
       const int g = gy * p.nx + gx;
       const uint8_t ci = p.cell[g];
       if (!(ci & C_SOLID)) {
@@ -351,29 +357,34 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
     kk[i] = k_; bb[i] = b_; x[i] = x_;
     r[i] = 0.f; u[i] = 0.f; w[i] = 0.f; pp[i] = 0.f; ss[i] = 0.f;
   }
-  int q = 0, k = p.sc->iters;
+  int q = 0, k = p.sc->iters, nfold = 0;
+  const bool first = k == 0;
   unsigned nbar = 0;
   const size_t plane = (size_t)p.nx * p.ny;
   float* uex = p.exch;
   float* xex = p.exch + plane;
-  double* part = p.partial;  // [3][kMaxCoopBlocks], parity-doubled below
   int par = 0;
   float below, above;
 
-  // refresh the halo of v from the neighbours' interiors (after a barrier)
-  auto exchange = [&](float (&v)[R], float* ex) {
+  auto barrier = [&]() -> bool {
+    if (grid_barrier_bounded(p.sync, ++nbar, (unsigned)G)) return true;
+    if (threadIdx.x == 0) abort_solve(p.sc);
+    return false;
+  };
+  // refresh the halo of v from the neighbours' interiors
+  auto exchange = [&](float (&v)[R], float* ex) -> bool {
 #pragma unroll
     for (int i = 0; i < R; ++i)
       if ((imask >> i) & 1u) st_agent(ex + (size_t)(gy0 + i) * p.nx + gx, v[i]);
-    ++nbar;
-    grid_barrier(p.sync, nbar, (unsigned)G);
+    if (!barrier()) return false;
 #pragma unroll
     for (int i = 0; i < R; ++i)
       if (!((imask >> i) & 1u) && kk[i] > 0.f) v[i] = ld_agent(ex + (size_t)(gy0 + i) * p.nx + gx);
+    return true;
   };
   // merged reduction of (r.u, w.u, sum|r|) over the interior
   double gam = 0.0, del = 0.0, E = 0.0;
-  auto reduce3 = [&]() {
+  auto reduce3 = [&]() -> bool {
     double a = 0.0, c = 0.0, e = 0.0;
 #pragma unroll
     for (int i = 0; i < R; ++i)
@@ -385,43 +396,52 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
     a = block_sum(a, red);
     c = block_sum(c, red);
     e = block_sum(e, red);
-    double* pa = part + par * 3 * kMaxCoopBlocks;
+    double* pa = p.partial + par * 3 * kMaxCoopBlocks;
     if (threadIdx.x == 0) {
       st_agent(pa + blockIdx.x, a);
       st_agent(pa + kMaxCoopBlocks + blockIdx.x, c);
       st_agent(pa + 2 * kMaxCoopBlocks + blockIdx.x, e);
     }
-    ++nbar;
-    grid_barrier(p.sync, nbar, (unsigned)G);
-    gam = sum_partials(pa, G, red);
-    del = sum_partials(pa + kMaxCoopBlocks, G, red);
-    E = nF > 0 ? sum_partials(pa + 2 * kMaxCoopBlocks, G, red) / nF * p.inv_dx2 : 0.0;
+    if (!barrier()) return false;
+    // the three partial arrays come back in one round trip
+    double sa = 0.0, sc_ = 0.0, se = 0.0;
+    for (int i = threadIdx.x; i < G; i += 256) {
+      sa += ld_agent(pa + i);
+      sc_ += ld_agent(pa + kMaxCoopBlocks + i);
+      se += ld_agent(pa + 2 * kMaxCoopBlocks + i);
+    }
+    gam = block_sum(sa, red);
+    del = block_sum(sc_, red);
+    E = nF > 0 ? block_sum(se, red) / nF * p.inv_dx2 : 0.0;
     par ^= 1;
+    return true;
   };
   // (re)start the recurrence from the current r: u = M^-1 r, w = A u, p = s = 0
   double alpha = 0.0, beta = 0.0;
-  auto restart = [&]() {
+  auto restart = [&]() -> bool {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       u[i] = kk[i] > 0.f ? r[i] / kk[i] : 0.f;
       pp[i] = 0.f;
       ss[i] = 0.f;
     }
-    exchange(u, uex);
+    if (!exchange(u, uex)) return false;
     band_edges<R>(u, edge, q, wave, lane, &below, &above);
     apply_A<R>(u, kk, below, above, w);
-    reduce3();
+    if (!reduce3()) return false;
     alpha = del > 0.0 ? gam / del : 0.0;
     beta = 0.0;
+    return true;
   };
   // true residual r = b - A x (needs the halo of x)
-  auto true_residual = [&]() {
-    exchange(x, xex);
+  auto true_residual = [&]() -> bool {
+    if (!exchange(x, xex)) return false;
     float ax[R];
     band_edges<R>(x, edge, q, wave, lane, &below, &above);
     apply_A<R>(x, kk, below, above, ax);
 #pragma unroll
     for (int i = 0; i < R; ++i) r[i] = kk[i] > 0.f ? bb[i] - ax[i] : 0.f;
+    return true;
   };
   auto finish = [&](int st) {
 #pragma unroll
@@ -429,24 +449,75 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
       if ((imask >> i) & 1u) p.phi[(size_t)(gy0 + i) * p.nx + gx] = x[i];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       p.sc->iters = k;
-      p.sc->status = st;
       p.sc->e1_solve = E;
+      __hip_atomic_fetch_max(&p.sc->status, (int32_t)st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
+  // defect-correction fold of the current x (its halo is fresh from the
+  // true-residual exchange): faces, phi_acc, d recomputed from the faces
+  auto fold = [&]() -> bool {
+    band_edges<R>(x, edge, q, wave, lane, &below, &above);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const float west = from_left(x[i]);
+      const float south = i > 0 ? x[i - 1] : below;
+      if (((imask >> i) & 1u) && kk[i] > 0.f) {
+        const int gy = gy0 + i;
+        const size_t c = (size_t)gy * p.nx + gx;
+        const uint8_t ci = p.cell[c];
+        const float pc = x[i];
+        if (ci & C_W) {
+          float* f = p.u + (size_t)gy * (p.nx + 1) + gx;
+          st_agent(f, ld_agent(f) - (pc - west) * p.inv_dx);
+        }
+        if (ci & C_S) {
+          float* f = p.v + c;
+          st_agent(f, ld_agent(f) - (pc - south) * p.inv_dx);
+        }
+        if (gy == p.ny - 1 && (ci & C_N)) {
+          float* f = p.v + plane + gx;
+          st_agent(f, ld_agent(f) - (0.f - pc) * p.inv_dx);
+        }
+        p.phi_acc[c] += pc;
+      }
+    }
+    if (!barrier()) return false;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (((dmask >> i) & 1u) && kk[i] > 0.f) {
+        const int gy = gy0 + i;
+        const size_t U = (size_t)p.nx + 1;
+        const float uw = ld_agent(p.u + gy * U + gx), ue = ld_agent(p.u + gy * U + gx + 1);
+        const float vs = ld_agent(p.v + (size_t)gy * p.nx + gx);
+        const float vn = ld_agent(p.v + (size_t)(gy + 1) * p.nx + gx);
+        const float dv = ((ue - uw) + (vn - vs)) * p.inv_dx;
+        bb[i] = -p.dx2 * dv;
+        if ((imask >> i) & 1u) p.d[(size_t)gy * p.nx + gx] = dv;
+      }
+      x[i] = 0.f;
+    }
+    return true;
+  };
 
-  true_residual();
-  restart();
-  if (round0 && blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
+  if (!true_residual() || !restart()) return;
+  if (first && blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
   for (;;) {
     int st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
     if (st < 0 && !(gam > 0.0)) st = HYP_STATUS_OK;  // r = 0 exactly
     if (st == HYP_STATUS_OK && p.fixed_iters <= 0) {
       // confirm on the true residual
-      true_residual();
-      restart();
+      if (!true_residual() || !restart()) return;
       st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
       if (st < 0 && !(gam > 0.0)) st = HYP_STATUS_OK;
-      if (st < 0 && !p.last_round) st = kStatusFold;
+      if (st < 0) {
+        if (nfold >= kMaxFolds) {
+          st = HYP_STATUS_FLOOR;
+        } else {
+          ++nfold;
+          if (!fold() || !true_residual() || !restart()) return;
+          continue;
+        }
+      }
     }
     if (st != -1) {
       finish(st);
@@ -465,11 +536,11 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
       r[i] -= a * ss[i];
       u[i] = kk[i] > 0.f ? r[i] / kk[i] : 0.f;
     }
-    exchange(u, uex);
+    if (!exchange(u, uex)) return;
     band_edges<R>(u, edge, q, wave, lane, &below, &above);
     apply_A<R>(u, kk, below, above, w);
     const double gam_old = gam;
-    reduce3();
+    if (!reduce3()) return;
     beta = gam_old != 0.0 ? gam / gam_old : 0.0;
     const double den = del - beta * gam / alpha;
     alpha = den != 0.0 ? gam / den : 0.0;
@@ -571,18 +642,18 @@ static hipError_t launch_pcg(PcgParams& p, int G, hipStream_t s) {
 }
 
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
-                   int check_every, int fixed_iters, int round, const Ws& w, hipStream_t s) {
+                   int check_every, int fixed_iters, float* u, float* v, const Ws& w, hipStream_t s) {
   PcgParams p{};
   int R = 0, ntx = 0, nty = 0;
   if (!pcg_geom(dev, nx, ny, &R, &ntx, &nty)) return hipErrorInvalidValue;
   p.nx = nx; p.ny = ny; p.ntx = ntx;
   p.dx2 = (float)(dx * dx);
+  p.inv_dx = (float)(1.0 / dx);
   p.inv_dx2 = 1.0 / (dx * dx);
   p.thr = thr;
   p.max_iters = max_iters; p.check_every = check_every; p.fixed_iters = fixed_iters;
-  p.last_round = round + 1 >= kSolveRounds;
-  p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.exch = w.exch; p.partial = w.partial; p.sc = w.sc;
-  p.sync = w.sync;
+  p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.phi_acc = w.phi_acc; p.u = u; p.v = v;
+  p.exch = w.exch; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
   const int G = ntx * nty;
   switch (R) {
     case 4: return launch_pcg<4>(p, G, s);

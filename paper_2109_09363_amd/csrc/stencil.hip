@@ -261,54 +261,6 @@ __global__ __launch_bounds__(256) void grad_kernel(int nx, int ny, float inv_dx,
   p[c] = fl ? (phi_acc[c] + pc) * p_scale : 0.f;
 }
 
-// Defect correction ("fold") between solver rounds, when the last round
-// asked for it: the faces lose grad phi (Eq. 2), phi is accumulated into the
-// pressure, then the divergence is recomputed from the corrected faces and
-// the next round starts from phi = 0.  The FP32 residual of a stored phi has
-// a floor proportional to max|phi|/dx^2; after the fold the remaining
-// correction is small, and so is its floor.
-__global__ __launch_bounds__(256) void fold_faces(int nx, int ny, float inv_dx,
-                                                  const uint8_t* __restrict__ cell,
-                                                  const float* __restrict__ phi,
-                                                  float* __restrict__ phi_acc, float* u, float* v,
-                                                  const Scalars* sc) {
-  if (sc->status != kStatusFold) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nx * ny) return;
-  const int i = c % nx, j = c / nx, U = nx + 1;
-  const uint8_t ci = cell[c];
-  const bool fl = !(ci & C_SOLID);
-  const float pc = phi[c];
-  if (fl && (ci & C_W)) u[j * U + i] -= (pc - phi[c - 1]) * inv_dx;
-  if (fl && (ci & C_S)) v[j * nx + i] -= (pc - phi[c - nx]) * inv_dx;
-  if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= (0.f - pc) * inv_dx;
-  if (fl) phi_acc[c] += pc;
-}
-
-__global__ __launch_bounds__(256) void fold_div(int nx, int ny, float inv_dx,
-                                                const uint8_t* __restrict__ cell,
-                                                const float* __restrict__ u,
-                                                const float* __restrict__ v, float* __restrict__ d,
-                                                float* __restrict__ phi, const Scalars* sc,
-                                                unsigned* sync) {
-  if (sc->status != kStatusFold) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  sync_clear(sync, c);  // the next round's grid barrier starts afresh
-  if (c >= nx * ny) return;
-  const int i = c % nx, j = c / nx, U = nx + 1;
-  const bool fl = !(cell[c] & C_SOLID);
-  d[c] = fl ? ((u[j * U + i + 1] - u[j * U + i]) + (v[(j + 1) * nx + i] - v[j * nx + i])) * inv_dx : 0.f;
-  phi[c] = 0.f;
-}
-
-hipError_t run_fold(int nx, int ny, double dx, float* u, float* v, const Ws& w, hipStream_t s) {
-  const int n = nx * ny, nb = (n + 255) / 256;
-  const float inv_dx = (float)(1.0 / dx);
-  fold_faces<<<nb, 256, 0, s>>>(nx, ny, inv_dx, w.cell, w.phi, w.phi_acc, u, v, w.sc);
-  fold_div<<<nb, 256, 0, s>>>(nx, ny, inv_dx, w.cell, u, v, w.d, w.phi, w.sc, w.sync);
-  return hipGetLastError();
-}
-
 // Divergence of the returned faces: FP64 sum of |div| and max |div|.
 __global__ __launch_bounds__(256) void check_kernel(int nx, int ny, float inv_dx,
                                                     const uint8_t* __restrict__ cell,

@@ -140,6 +140,12 @@ def test_nonfinite_and_maxiter_statuses():
     assert g["res"].status == 1 and g["res"].iters == 20
     g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="pcg", max_iters=15)
     assert g["res"].status == 1 and g["res"].iters == 15
+    # a threshold far below what FP32 reaches: PCG folds three times, then
+    # reports FLOOR instead of running to max_iters
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=1e-12, method="pcg", max_iters=100000)
+    print("  floor case: status", g["res"].status, "iters", g["res"].iters, "e1_final", g["res"].e1_final)
+    assert g["res"].status == 3 and g["res"].iters < 100000
+    assert g["res"].e1_final < 1e-3 * g["res"].e1_init
 
 
 def test_zero_divergence_takes_no_sweeps():
