@@ -109,6 +109,10 @@ typedef struct {
   float* p;              /* (ny, nx) out: pressure p = rho0 * phi / dt */
   const float* p_init;   /* nullable: warm start (as p, same scaling) for
                             the JACOBI / PCG methods */
+  float* phi_ckpt;       /* nullable: Jacobi checkpoints (see
+                            hyp_opts.checkpoint_every): n_ckpt planes of
+                            (ny, nx) phi = (dt / rho0) p after every
+                            checkpoint_every sweeps, caller-owned */
 } hyp_fields;
 
 typedef struct {
@@ -120,10 +124,18 @@ typedef struct {
   int32_t fold_window;  /* defect correction (FP32 residual floor): Jacobi
                            folds its pressure into the faces and restarts on
                            the recomputed divergence when E_1 fell by less
-                           than 1 % over this many sweeps (0: 1024); PCG folds
-                           when its true residual disagrees with the updated
-                           one at a stop.  At most 3 folds per projection. */
-  int32_t reserved[2];
+                           than 1 % over this many sweeps (0: 1024 when a
+                           threshold decides, no folds with fixed_iters);
+                           PCG folds when its true residual does not confirm
+                           a stop (at most 3 folds, then HYP_STATUS_FLOOR). */
+  int32_t checkpoint_every;  /* HYBRID/JACOBI with fixed_iters > 0 and
+                           fields.phi_ckpt set: after sweep c, 2c, ... <=
+                           fixed_iters (c = checkpoint_every) the iterate phi
+                           of the interior is written to plane k/c - 1 of
+                           phi_ckpt (at most 64 planes); without folds it
+                           restarts the iteration bit-exactly as a warm
+                           start.  0: none.  EINVAL otherwise. */
+  int32_t reserved;
 } hyp_opts;
 
 /* Written by the device when the projection's last kernel completes. */

@@ -26,13 +26,14 @@ class Grid(ctypes.Structure):
 
 
 class Fields(ctypes.Structure):
-    _fields_ = [("u", c_vp), ("v", c_vp), ("rho", c_vp), ("flags", c_vp), ("p", c_vp), ("p_init", c_vp)]
+    _fields_ = [("u", c_vp), ("v", c_vp), ("rho", c_vp), ("flags", c_vp), ("p", c_vp), ("p_init", c_vp),
+                ("phi_ckpt", c_vp)]
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("method", c_i32), ("max_iters", c_i32), ("check_every", c_i32),
                 ("fixed_iters", c_i32), ("omega", c_f32), ("fold_window", c_i32),
-                ("reserved", c_i32 * 2)]
+                ("checkpoint_every", c_i32), ("reserved", c_i32)]
 
 
 class Result(ctypes.Structure):

@@ -97,9 +97,12 @@ class Projector:
 
     def project_async(self, u, v, flags, p, threshold: float, method: str = "hybrid",
                       max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
-                      omega: float = 1.0, rho=None, p_init=None, fold_window: int = 0):
+                      omega: float = 1.0, rho=None, p_init=None, fold_window: int = 0,
+                      checkpoint_every: int = 0, phi_ckpt=None):
         """Enqueue one projection on the current stream; u, v corrected in
-        place, p written.  Read the result with `result()` after a sync."""
+        place, p written.  Read the result with `result()` after a sync.
+        With fixed_iters and checkpoint_every > 0, phi_ckpt (n, ny, nx) float32
+        receives the Jacobi iterate after every checkpoint_every sweeps."""
         nx, ny = self.nx, self.ny
         _need(u, torch.float32, (ny, nx + 1), "u")
         _need(v, torch.float32, (ny + 1, nx), "v")
@@ -109,11 +112,15 @@ class Projector:
             _need(rho, torch.float32, (ny, nx), "rho")
         if p_init is not None:
             _need(p_init, torch.float32, (ny, nx), "p_init")
+        if phi_ckpt is not None:
+            if checkpoint_every <= 0 or fixed_iters <= 0:
+                raise ValueError("phi_ckpt needs checkpoint_every > 0 and fixed_iters > 0")
+            _need(phi_ckpt, torch.float32, (fixed_iters // checkpoint_every, ny, nx), "phi_ckpt")
         if not self.planned:
             raise RuntimeError("call plan(flags) before project")
-        f = L.Fields(_ptr(u), _ptr(v), _ptr(rho), _ptr(flags), _ptr(p), _ptr(p_init))
+        f = L.Fields(_ptr(u), _ptr(v), _ptr(rho), _ptr(flags), _ptr(p), _ptr(p_init), _ptr(phi_ckpt))
         o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
-                   float(omega), int(fold_window), (ctypes.c_int32 * 2)())
+                   float(omega), int(fold_window), int(checkpoint_every), 0)
         L.check("hyp_project", self.lib.hyp_project(
             self.ctx, ctypes.byref(self.grid), ctypes.byref(f), float(threshold), ctypes.byref(o),
             _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
@@ -186,7 +193,7 @@ class Projector:
         ph = L.Physics(float(g), float(self.grid.rho0), float(drho), float(u_in), float(cfl))
         st = L.State(_ptr(rho), _ptr(u), _ptr(v), _ptr(p), _ptr(flags), _ptr(xi))
         o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
-                   float(omega), int(fold_window), (ctypes.c_int32 * 2)())
+                   float(omega), int(fold_window), 0, 0)
         L.check("hyp_step", self.lib.hyp_step(
             self.ctx, ctypes.byref(self.grid), ctypes.byref(ph), ctypes.byref(st), float(threshold),
             ctypes.byref(o), _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
@@ -231,7 +238,7 @@ class Batch:
                 self.lib.hyp_batch_workspace_size(self.ctx, self.n, G, ctypes.byref(nbytes)))
         self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         self.res = torch.zeros(self.n * ctypes.sizeof(L.Result), dtype=torch.uint8, device=self.device)
-        o = L.Opts(L.METHODS[method], int(max_iters), 8, 0, float(omega), 0, (ctypes.c_int32 * 2)())
+        o = L.Opts(L.METHODS[method], int(max_iters), 8, 0, float(omega), 0, 0, 0)
         b = ctypes.c_void_p()
         torch.cuda.synchronize()
         L.check("hyp_batch_create", self.lib.hyp_batch_create(self.ctx, self.n, G, S, T, ctypes.byref(o),

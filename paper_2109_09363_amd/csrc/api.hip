@@ -251,7 +251,7 @@ int hyp_plan(hyp_ctx* ctx, const hyp_grid* g, const uint8_t* flags, void* ws, si
 static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, double threshold) {
   if (o->method < HYP_METHOD_HYBRID || o->method > HYP_METHOD_CNN) return HYP_EINVAL;
   if (o->max_iters < 0 || o->check_every < 1 || o->fixed_iters < 0) return HYP_EINVAL;
-  if (o->fold_window < 0) return HYP_EINVAL;
+  if (o->fold_window < 0 || o->checkpoint_every < 0) return HYP_EINVAL;
   if (!(threshold >= 0.0)) return HYP_EINVAL;
   const bool use_cnn = o->method == HYP_METHOD_HYBRID || o->method == HYP_METHOD_CNN;
   if (use_cnn) {
@@ -267,7 +267,8 @@ static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, 
 
 // The projection pipeline, enqueued on `stream` (arguments already checked).
 static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* v,
-                              const float* p_init, float* p, double threshold, const hyp_opts* o,
+                              const float* p_init, float* p, float* phi_ckpt, double threshold,
+                              const hyp_opts* o,
                               const WsLayout& L, const Ws& w, bool dt_dev, hipStream_t stream,
                               hyp_result* res) {
   const int nx = g->nx, ny = g->ny;
@@ -284,7 +285,7 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
   mark(ctx, 2, stream);
   if (o->method == HYP_METHOD_CNN) {
     // no sweeps: a zero-length Jacobi pass records E_1 of the prediction
-    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, u, v, w, stream);
+    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, 0, nullptr, u, v, w, stream);
   } else if (o->method == HYP_METHOD_PCG) {
     // one persistent launch, defect-correction folds included
     e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
@@ -292,7 +293,8 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
   } else {
     // one persistent launch, defect-correction folds included
     e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,
-                   o->fixed_iters, o->fold_window, u, v, w, stream);
+                   o->fixed_iters, o->fold_window, phi_ckpt ? o->checkpoint_every : 0, phi_ckpt,
+                   u, v, w, stream);
   }
   if (e != hipSuccess) return HYP_EHIP;
   mark(ctx, 3, stream);
@@ -310,12 +312,18 @@ int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double thr
   if (!f->u || !f->v || !f->flags || !f->p) return HYP_EINVAL;
   int rc = check_opts(ctx, g, o, threshold);
   if (rc != HYP_OK) return rc;
+  if (o->checkpoint_every > 0) {
+    if (o->fixed_iters <= 0 || !f->phi_ckpt) return HYP_EINVAL;
+    if (o->method != HYP_METHOD_HYBRID && o->method != HYP_METHOD_JACOBI) return HYP_EINVAL;
+    if (o->fixed_iters / o->checkpoint_every > kMaxCheckpoints) return HYP_EINVAL;
+  }
   const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
   if (ws_bytes < L.total) return HYP_EWORKSPACE;
   const Ws w = ws_view(ws, L);
   ctx->timed_step = false;
-  return enqueue_projection(ctx, g, f->u, f->v, f->p_init, f->p, threshold, o, L, w, false,
-                            stream, res);
+  return enqueue_projection(ctx, g, f->u, f->v, f->p_init, f->p,
+                            o->checkpoint_every > 0 ? f->phi_ckpt : nullptr, threshold, o, L, w,
+                            false, stream, res);
 }
 
 int hyp_project_backward(hyp_ctx* ctx, const hyp_grid* g, int32_t sweeps, float omega,
@@ -368,6 +376,7 @@ int hyp_step(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_s
   if (!grid_ok(&gg)) return HYP_EINVAL;
   int rc = check_opts(ctx, &gg, o, threshold);
   if (rc != HYP_OK) return rc;
+  if (o->checkpoint_every != 0) return HYP_EINVAL;
   const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
   if (ws_bytes < L.total) return HYP_EWORKSPACE;
   const Ws w = ws_view(ws, L);
@@ -376,7 +385,7 @@ int hyp_step(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_s
   if (run_advect(g->nx, g->ny, g->dx, ph->g, ph->rho0, ph->drho, ph->u_in, ph->cfl, st->rho, st->u,
                  st->v, st->xi, w, stream) != hipSuccess)
     return HYP_EHIP;
-  return enqueue_projection(ctx, &gg, st->u, st->v, nullptr, st->p, threshold, o, L, w, true,
+  return enqueue_projection(ctx, &gg, st->u, st->v, nullptr, st->p, nullptr, threshold, o, L, w, true,
                             stream, res);
 }
 
@@ -426,7 +435,7 @@ int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_s
   if (!ctx || n < 1 || !grids || !states || !thresholds || !o || !ws || !out) return HYP_EINVAL;
   *out = nullptr;
   if (o->method != HYP_METHOD_HYBRID && o->method != HYP_METHOD_JACOBI) return HYP_EUNSUPPORTED;
-  if (o->max_iters < 0 || !(o->omega > 0.f)) return HYP_EINVAL;
+  if (o->max_iters < 0 || !(o->omega > 0.f) || o->checkpoint_every != 0) return HYP_EINVAL;
   if (o->method == HYP_METHOD_HYBRID && (ctx->net.scales == 0 || !ctx->params)) return HYP_ENOWEIGHTS;
   for (int i = 0; i < n; ++i) {
     hyp_grid g = grids[i];

@@ -172,13 +172,14 @@ __device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
   return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// lane l receives x from lane l-1 (lane 0 receives 0): DPP wave_shr:1
+// lane l receives x from lane l-1 (lane 0 receives 0): DPP wave_shr:1 with
+// bound_ctrl, so the lane without a source reads 0 and no old value is needed
 __device__ __forceinline__ float from_left(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xF, 0xF, true));
 }
 // lane l receives x from lane l+1 (lane 63 receives 0): DPP wave_shl:1
 __device__ __forceinline__ float from_right(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xF, 0xF, true));
 }
 
 // Sum of `n` doubles in global memory written by other work-groups, in a

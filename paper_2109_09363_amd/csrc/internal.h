@@ -27,6 +27,7 @@ struct Scalars {
 };
 
 constexpr int kMaxCoopBlocks = 1024;   // partial-sum slots per parity
+constexpr int kMaxCheckpoints = 64;    // Jacobi checkpoint planes per projection
 // grid-barrier area: top counter, flag and one counter per group of
 // kSyncGroup blocks, each on its own 128-byte line (common.h)
 constexpr int kSyncGroup = 16;
@@ -101,7 +102,8 @@ hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const
                         hipStream_t s);
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      float* u, float* v, const Ws& w, hipStream_t s);
+                      int checkpoint_every, float* phi_ckpt, float* u, float* v, const Ws& w,
+                      hipStream_t s);
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters);
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
                    int check_every, int fixed_iters, float* u, float* v, const Ws& w, hipStream_t s);

@@ -42,6 +42,8 @@ struct JacParams {
   double thr;
   int max_iters, check_every, fixed_iters;
   int fold_window;      // sweeps per stagnation window (0: no folds)
+  int ckpt_every;       // > 0: write the interior iterate after every ckpt_every sweeps
+  float* ckpt;          // ... into plane k / ckpt_every - 1 of this buffer
   const uint8_t* cell;
   float* d;             // recomputed on the interior at a fold
   float* phi;           // in: initial guess, out: returned iterate
@@ -55,11 +57,33 @@ struct JacParams {
 };
 
 // One pass over the R rows of a lane: new value (or residual) of every cell.
-// `below`/`above` are the rows just outside the band (from LDS).
+// `below`/`above` are the rows just outside the band (from LDS).  The update
+// computes the rows that need no band edge first, so that the LDS reads of
+// the edges are in flight meanwhile.
+template <int R>
+__device__ __forceinline__ float jac_cell(float c, float s, float n, float d, float k, float w,
+                                          float inv_dx2) {
+  const float e = from_right(c);
+  const float wv = from_left(c);
+  const float res = d - (((e + wv) + (n + s)) - k * c) * inv_dx2;
+  return c - w * res;
+}
+
 template <int R, bool UPDATE>
 __device__ __forceinline__ double jac_rows(float (&ph)[R], const float (&dd)[R], const float (&kk)[R],
                                            const float (&ww)[R], float below, float above,
                                            float inv_dx2, unsigned rmask) {
+  if (UPDATE) {
+    float nv[R];
+#pragma unroll
+    for (int r = 1; r + 1 < R; ++r)
+      nv[r] = jac_cell<R>(ph[r], ph[r - 1], ph[r + 1], dd[r], kk[r], ww[r], inv_dx2);
+    nv[0] = jac_cell<R>(ph[0], below, ph[1], dd[0], kk[0], ww[0], inv_dx2);
+    nv[R - 1] = jac_cell<R>(ph[R - 1], ph[R - 2], above, dd[R - 1], kk[R - 1], ww[R - 1], inv_dx2);
+#pragma unroll
+    for (int r = 0; r < R; ++r) ph[r] = nv[r];
+    return 0.0;
+  }
   float prev = below;
   double acc = 0.0;
 #pragma unroll
@@ -70,11 +94,7 @@ __device__ __forceinline__ double jac_rows(float (&ph)[R], const float (&dd)[R],
     const float w = from_left(c);
     const float res = dd[r] - (((e + w) + (n + prev)) - kk[r] * c) * inv_dx2;
     prev = c;
-    if (UPDATE) {
-      ph[r] = c - ww[r] * res;
-    } else if ((rmask >> r) & 1u) {
-      acc += fabs((double)res);
-    }
+    if ((rmask >> r) & 1u) acc += fabs((double)res);
   }
   return acc;
 }
@@ -255,6 +275,7 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     }
     int B = min(H - 1, end - k);
     if (p.fixed_iters <= 0) B = min(B, p.check_every - k % p.check_every);
+    if (p.ckpt_every > 0) B = min(B, p.ckpt_every - k % p.ckpt_every);
     for (int s = 0; s < B; ++s) {
       float below, above;
       edges(&below, &above);
@@ -262,6 +283,12 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     }
     k += B;
     ++j;
+    if (p.ckpt_every > 0 && k % p.ckpt_every == 0) {
+      float* cp = p.ckpt + (size_t)(k / p.ckpt_every - 1) * plane;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if ((imask >> r) & 1u) cp[(size_t)(gy0 + r) * p.nx + gx] = ph[r];
+    }
   }
 }
 
@@ -609,7 +636,8 @@ static hipError_t launch_jacobi(JacParams& p, int G, hipStream_t s) {
 
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      float* u, float* v, const Ws& w, hipStream_t s) {
+                      int checkpoint_every, float* phi_ckpt, float* u, float* v, const Ws& w,
+                      hipStream_t s) {
   JacParams p{};
   int R = 0, H = 0, ntx = 0, nty = 0;
   if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, &R, &H, &ntx, &nty))
@@ -621,6 +649,8 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
   p.thr = thr;
   p.max_iters = max_iters; p.check_every = check_every; p.fixed_iters = fixed_iters;
   p.fold_window = fold_window > 0 ? fold_window : (fixed_iters > 0 ? 0 : 1024);
+  p.ckpt_every = phi_ckpt ? checkpoint_every : 0;
+  p.ckpt = phi_ckpt;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.phi_acc = w.phi_acc; p.u = u; p.v = v;
   p.exch = w.exch; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
   const int G = ntx * nty;

@@ -1,0 +1,279 @@
+"""Measurements beside the headline benchmark (one JSON object per line).
+
+python -m paper_2109_09363_amd.experiments WHAT [options]
+
+WHAT:
+  thresholds  512^2 plumes (seeds 0-4, 0-3 disks): after `warmup` PCG-projected
+              steps, `steps` time steps from the same state with the hybrid
+              (4-scale 64-channel BF16 net, and the same weights in FP32) and
+              with PCG, for each threshold 1e-2, 1e-3, 1e-4; sweeps/iterations
+              per step, ms per step, statuses, and the BF16-vs-FP32 distance
+              of the CNN guess and of the returned pressure.
+  gain        the same 512^2 states: trained net vs zero net (= plain
+              Jacobi) vs seeded random net vs PCG, at 1e-3.
+  batch       128 plumes, sides from {128, 192, 256, 384, 512}, 0-3 disks,
+              density ratio ~ U[0.01, 0.5] (seed 0): one batched step (per
+              instance advection, divergence, CNN, then one persistent
+              Jacobi launch for all instances) to 1e-3, eager and as a
+              captured graph; per-instance sweeps.
+  dram        the streaming (batched) Jacobi kernel on one large grid
+              (default 8192^2, 268 MB per FP32 field) for a fixed number of
+              sweeps: algorithmic bytes per second against the HBM peak.
+All inputs are seeded and synthetic; timings use the stream's HIP events
+(through torch.cuda.Event on the current stream, which the library uses).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import scenes  # noqa: E402
+import paper_2109_09363_amd as hp  # noqa: E402
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "plume_s4c64.npy")
+S4, C64 = 4, 64
+
+
+def emit(obj):
+    print(json.dumps(obj), flush=True)
+
+
+class Plume:
+    """One 512^2 plume developed by PCG-projected steps; snapshot/restore."""
+
+    def __init__(self, n, seed, warmup, dev, weights, precision="bf16"):
+        self.sc = scenes.plume_scene(n, seed=seed, n_obstacles=(0, 3))
+        self.n, self.seed = n, seed
+        self.flags = torch.from_numpy(self.sc.flags).to(dev)
+        self.pr = hp.Projector(n, n, self.sc.dx, 1.0, self.sc.rho0, S4, C64, precision, device=dev)
+        self.pr.set_weights(weights)
+        self.pr.plan(self.flags)
+        self.rho = torch.full((n, n), self.sc.rho0, dtype=torch.float32, device=dev)
+        self.u = torch.zeros((n, n + 1), dtype=torch.float32, device=dev)
+        self.v = torch.zeros((n + 1, n), dtype=torch.float32, device=dev)
+        self.p = torch.zeros((n, n), dtype=torch.float32, device=dev)
+        self.xi = [torch.from_numpy(scenes.inflow_noise(seed, s, n).astype(np.float32)).to(dev)
+                   for s in range(warmup + 400)]
+        self.warmup = warmup
+        for s in range(warmup):
+            self.step("pcg", 1e-3, s)
+        torch.cuda.synchronize()
+        self.snap = [t.clone() for t in (self.rho, self.u, self.v, self.p)]
+
+    def restore(self):
+        for dst, src in zip((self.rho, self.u, self.v, self.p), self.snap):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    def step(self, method, thr, s, pr=None):
+        (pr or self.pr).step_async(self.rho, self.u, self.v, self.flags, self.p, self.xi[s], thr,
+                                   g=self.sc.g, drho=self.sc.drho, u_in=self.sc.u_in, cfl=0.5,
+                                   method=method, max_iters=1000000, check_every=8)
+
+    def run(self, method, thr, steps, pr=None):
+        """`steps` time steps from the snapshot; per-step results and the
+        event-timed total."""
+        self.restore()
+        pr = pr or self.pr
+        rows = []
+        t_ms = 0.0
+        for s in range(self.warmup, self.warmup + steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            self.step(method, thr, s, pr)
+            b.record()
+            torch.cuda.synchronize()
+            t_ms += a.elapsed_time(b)
+            rows.append(pr.result())
+        return rows, t_ms
+
+
+def summarize(rows, t_ms, steps):
+    it = np.array([r.iters for r in rows], dtype=np.float64)
+    return {"timesteps_per_s": round(steps / (t_ms * 1e-3), 3), "ms_per_step": round(t_ms / steps, 4),
+            "mean_iters": round(float(it.mean()), 1), "max_iters": int(it.max()),
+            "statuses": sorted(set(int(r.status) for r in rows)),
+            "max_e1_final": max(r.e1_final for r in rows)}
+
+
+def load_trained(dev):
+    w = np.load(WEIGHTS, allow_pickle=False).astype(np.float32)
+    return torch.from_numpy(w).to(dev)
+
+
+def cmd_thresholds(a, dev):
+    w = load_trained(dev)
+    for seed in a.seeds:
+        pl = Plume(512, seed, a.warmup, dev, w)
+        pr32 = hp.Projector(512, 512, pl.sc.dx, 1.0, pl.sc.rho0, S4, C64, "fp32", device=dev)
+        pr32.set_weights(w)
+        pr32.plan(pl.flags)
+        # BF16 vs FP32 network on the snapshot's advected state (guess only)
+        pl.restore()
+        pl.pr.advect_async(pl.rho, pl.u, pl.v, pl.xi[pl.warmup], g=pl.sc.g, drho=pl.sc.drho)
+        u0, v0 = pl.u.clone(), pl.v.clone()
+        guesses = []
+        for pr in (pl.pr, pr32):
+            uu, vv = u0.clone(), v0.clone()
+            p = torch.zeros_like(pl.p)
+            pr.project_async(uu, vv, pl.flags, p, 0.0, method="cnn")
+            torch.cuda.synchronize()
+            guesses.append(p.clone())
+        d_guess = float(torch.linalg.norm(guesses[0] - guesses[1]) / torch.linalg.norm(guesses[1]))
+        for thr in a.thresholds:
+            out = {"what": "thresholds", "seed": seed, "threshold": thr, "n_obstacles": len(pl.sc.disks),
+                   "steps": a.steps, "cnn_guess_bf16_vs_fp32_rel_l2": d_guess}
+            rows, t = pl.run("hybrid", thr, a.steps)
+            out["hybrid_bf16"] = summarize(rows, t, a.steps)
+            p_bf = pl.p.clone()
+            rows, t = pl.run("hybrid", thr, a.steps, pr32)
+            out["hybrid_fp32"] = summarize(rows, t, a.steps)
+            out["final_p_bf16_vs_fp32_rel_l2"] = float(torch.linalg.norm(p_bf - pl.p) / torch.linalg.norm(pl.p))
+            rows, t = pl.run("pcg", thr, a.steps)
+            out["pcg"] = summarize(rows, t, a.steps)
+            out["hybrid_over_pcg"] = round(out["pcg"]["ms_per_step"] / out["hybrid_bf16"]["ms_per_step"], 4)
+            emit(out)
+
+
+def cmd_gain(a, dev):
+    nets = {"trained": load_trained(dev),
+            "zero": torch.zeros(scenes.cnn_param_count(S4, C64), dtype=torch.float32, device=dev),
+            "random": torch.from_numpy(scenes.random_weights(S4, C64, 7).astype(np.float32)).to(dev)}
+    for seed in a.seeds:
+        pl = Plume(512, seed, a.warmup, dev, nets["trained"])
+        out = {"what": "gain", "seed": seed, "threshold": 1e-3, "steps": a.steps, "n_obstacles": len(pl.sc.disks)}
+        for name, w in nets.items():
+            pl.pr.set_weights(w)
+            rows, t = pl.run("hybrid", 1e-3, a.steps)
+            out["hybrid_" + name] = summarize(rows, t, a.steps)
+        pl.pr.set_weights(nets["trained"])
+        rows, t = pl.run("pcg", 1e-3, a.steps)
+        out["pcg"] = summarize(rows, t, a.steps)
+        emit(out)
+
+
+def batch_instances(dev, n_inst=128, seed=0):
+    rng = np.random.default_rng(seed)
+    sides = [128, 192, 256, 384, 512]
+    inst = []
+    for i in range(n_inst):
+        s = int(rng.choice(sides))
+        drho = float(rng.uniform(0.01, 0.5))
+        sc = scenes.plume_scene(s, seed=1000 + i, n_obstacles=(0, 3), drho=drho)
+        inst.append(dict(nx=s, ny=s, dx=sc.dx, dt=1.0, rho0=sc.rho0, scene=sc,
+                         flags=torch.from_numpy(sc.flags).to(dev),
+                         rho=torch.full((s, s), sc.rho0, dtype=torch.float32, device=dev),
+                         u=torch.zeros((s, s + 1), dtype=torch.float32, device=dev),
+                         v=torch.zeros((s + 1, s), dtype=torch.float32, device=dev),
+                         p=torch.zeros((s, s), dtype=torch.float32, device=dev),
+                         xi=torch.from_numpy(scenes.inflow_noise(1000 + i, 0, s).astype(np.float32)).to(dev)))
+    return inst
+
+
+def cmd_batch(a, dev):
+    inst = batch_instances(dev)
+    cells = sum(d["nx"] * d["ny"] for d in inst)
+    w = load_trained(dev)
+    # every instance has its own g (Ri 0.1) and drho; the batched step takes
+    # one g/drho, so instances are developed individually first with PCG
+    for d in inst:
+        sc = d["scene"]
+        pr = hp.Projector(d["nx"], d["ny"], sc.dx, 1.0, sc.rho0, S4, C64, "bf16", device=dev)
+        pr.set_weights(w)
+        pr.plan(d["flags"])
+        for s in range(a.warmup):
+            xi = torch.from_numpy(scenes.inflow_noise(1000, s, d["nx"]).astype(np.float32)).to(dev)
+            pr.step_async(d["rho"], d["u"], d["v"], d["flags"], d["p"], xi, 1e-3, g=sc.g, drho=sc.drho,
+                          method="pcg", max_iters=200000)
+        # the batch projects the next advected state
+        xi = torch.from_numpy(scenes.inflow_noise(1000, a.warmup, d["nx"]).astype(np.float32)).to(dev)
+        pr.advect_async(d["rho"], d["u"], d["v"], xi, g=sc.g, drho=sc.drho)
+    torch.cuda.synchronize()
+    snap = [(d["u"].clone(), d["v"].clone(), d["p"].clone()) for d in inst]
+
+    def restore():
+        for d, (u, v, p) in zip(inst, snap):
+            d["u"].copy_(u); d["v"].copy_(v); d["p"].copy_(p)
+        torch.cuda.synchronize()
+
+    out = {"what": "batch", "instances": len(inst), "cells": cells, "threshold": 1e-3,
+           "sides": sorted(set(d["nx"] for d in inst))}
+    for method in ("hybrid", "jacobi"):
+        b = hp.Batch(inst, threshold=1e-3, method=method, params=w, scales=S4, channels=C64,
+                     precision="bf16", max_iters=400000)
+        restore()
+        b.project_async()          # warm
+        torch.cuda.synchronize()
+        restore()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.project_async()
+        e1.record()
+        torch.cuda.synchronize()
+        res = b.results()
+        it = np.array([r.iters for r in res], dtype=np.float64)
+        out[method] = {"ms_per_projection_of_all": round(e0.elapsed_time(e1), 3),
+                       "mean_sweeps": round(float(it.mean()), 1), "max_sweeps": int(it.max()),
+                       "min_sweeps": int(it.min()), "statuses": sorted(set(int(r.status) for r in res)),
+                       "max_e1_final": max(r.e1_final for r in res)}
+        del b
+    emit(out)
+
+
+def cmd_dram(a, dev):
+    n = a.n
+    sc = scenes.plume_scene(n, seed=0, n_obstacles=2)
+    u, v = scenes.random_faces(n, n, 0, kind="white")
+    inst = [dict(nx=n, ny=n, dx=sc.dx, flags=torch.from_numpy(sc.flags).to(dev),
+                 u=torch.from_numpy(u.astype(np.float32)).to(dev),
+                 v=torch.from_numpy(v.astype(np.float32)).to(dev),
+                 p=torch.zeros((n, n), dtype=torch.float32, device=dev))]
+    b = hp.Batch(inst, threshold=0.0, method="jacobi", max_iters=a.sweeps)
+    b.project_async()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(a.reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.project_async()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    r = b.results()[0]
+    ms = float(np.median(times))
+    algo = 13.0 * n * n * r.iters
+    emit({"what": "dram", "n": n, "sweeps": int(r.iters), "status": int(r.status),
+          "ms_per_projection": round(ms, 3), "us_per_sweep": round(1e3 * ms / max(r.iters, 1), 3),
+          "algorithmic_GBps": round(algo / (ms * 1e-3) / 1e9, 1), "hbm_peak_GBps": 8000.0,
+          "note": "the projection also runs the divergence, gradient and check passes"})
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["thresholds", "gain", "batch", "dram"])
+    ap.add_argument("--seeds", type=int, nargs="*", default=[0, 1, 2, 3, 4])
+    ap.add_argument("--thresholds", type=float, nargs="*", default=[1e-2, 1e-3, 1e-4])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--sweeps", type=int, default=800)
+    ap.add_argument("--reps", type=int, default=3)
+    a = ap.parse_args()
+    dev = torch.device("cuda")
+    t0 = time.time()
+    {"thresholds": cmd_thresholds, "gain": cmd_gain, "batch": cmd_batch, "dram": cmd_dram}[a.what](a, dev)
+    print(f"# {a.what} done in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+
+if __name__ == "__main__":
+    main()

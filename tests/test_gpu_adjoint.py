@@ -159,3 +159,34 @@ def test_autograd_function():
     assert float(loss) == pytest.approx(l0, rel=1e-5)
     assert rel_l2(tw.grad.cpu().numpy(), 3 * gp) <= 1e-4
     assert rel_l2(tu.grad.cpu().numpy(), 3 * gu) <= 1e-4
+
+
+def test_checkpoints_replay_bitwise():
+    # phi after every 5 of the K = 20 forward sweeps.  The sweep is affine in
+    # phi, so the adjoint needs none of these iterates; restarting from a
+    # checkpoint as a warm start reproduces the later ones bit for bit.
+    from oracle import grid as G
+    from oracle import solve as SV
+    n, K, c = 256, 20, 5
+    sc, u, v = state(n, 9, 2)
+    pr = hp.Projector(n, n, sc.dx, 1.0, 1.0, 0, 0, "fp32")
+    tf = to_dev(sc.flags, torch.uint8)
+    pr.plan(tf)
+    ck = torch.empty((K // c, n, n), dtype=torch.float32, device="cuda")
+    p = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    pr.project_async(to_dev(u), to_dev(v), tf, p, 0.0, method="jacobi", fixed_iters=K,
+                     checkpoint_every=c, phi_ckpt=ck)
+    torch.cuda.synchronize()
+    assert torch.equal(ck[-1], p)  # dt = rho0 = 1 and no folds: p is the last iterate
+    for i in range(K // c - 1):
+        p2 = torch.empty_like(p)
+        pr.project_async(to_dev(u), to_dev(v), tf, p2, 0.0, method="jacobi", fixed_iters=c,
+                         p_init=ck[i].clone())
+        torch.cuda.synchronize()
+        assert torch.equal(p2, ck[i + 1]), i
+    P = G.plan(sc.flags)
+    d = G.divergence(P, *G.enforce_bc(P, u, v), sc.dx)
+    phi5 = SV.jacobi(P, d, sc.dx, np.zeros(P.shape), fixed_iters=c)[0]
+    err = rel_l2(ck[0].cpu().numpy().astype(np.float64), phi5, P.fluid)
+    say("  checkpoint 0 vs oracle 5 sweeps", err)
+    assert err <= 1e-5

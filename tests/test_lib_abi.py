@@ -63,8 +63,8 @@ def test_host_side_rejections():
     assert lib.hyp_workspace_size(ctx, ctypes.byref(gbad), ctypes.byref(nbytes)) == -1
     # a projection with a too-small workspace is rejected before any launch
     dummy = ctypes.c_void_p(0x1000)
-    f = L.Fields(dummy, dummy, None, dummy, dummy, None)
-    o = L.Opts(1, 100, 1, 0, 1.0, 0, (ctypes.c_int32 * 2)())
+    f = L.Fields(dummy, dummy, None, dummy, dummy, None, None)
+    o = L.Opts(1, 100, 1, 0, 1.0, 0, 0, 0)
     assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
                            16, None, dummy) == -3
     # hybrid without weights
@@ -78,6 +78,25 @@ def test_host_side_rejections():
                            nbytes.value, None, dummy) == -1
     o.check_every = 1
     assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), -1.0, ctypes.byref(o), dummy,
+                           nbytes.value, None, dummy) == -1
+    # checkpoints: need fixed_iters, a buffer, a Jacobi method, at most 64 planes
+    o.checkpoint_every = 5
+    assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
+                           nbytes.value, None, dummy) == -1
+    o.fixed_iters = 20
+    assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
+                           nbytes.value, None, dummy) == -1
+    f.phi_ckpt = dummy
+    o.fixed_iters = 5 * 65
+    assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
+                           nbytes.value, None, dummy) == -1
+    o.method = 2
+    o.fixed_iters = 20
+    assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
+                           nbytes.value, None, dummy) == -1
+    o.method, o.checkpoint_every, o.fixed_iters, f.phi_ckpt = 1, 0, 0, None
+    o.checkpoint_every = -1
+    assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
                            nbytes.value, None, dummy) == -1
     assert lib.hyp_set_weights(ctx, dummy, 5) == -1
     assert lib.hyp_destroy(ctx) == 0
