@@ -84,8 +84,9 @@ typedef struct hyp_ctx hyp_ctx;
 #define HYP_NET_TRAIN  1  /* keep every layer's activations (and the backward
                              buffers) in the workspace for hyp_project_backward */
 
-/* Multi-scale network shape.  scales in 1..5; channels 16 or 32 with FP32,
- * 32 or 64 with BF16 (the LDS tile of one 3x3 layer must fit one CU). */
+/* Multi-scale network shape.  scales in 1..5; channels 16, 32 or 64 with
+ * FP32 (64: inference only, HYP_EUNSUPPORTED with HYP_NET_TRAIN), 32 or 64
+ * with BF16. */
 typedef struct {
   int32_t scales;
   int32_t channels;

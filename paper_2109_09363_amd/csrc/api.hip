@@ -70,7 +70,7 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
     L.cnn_act1 = take(px * net.channels * act_elt);
     L.cnn_y = take(px * 4);
     L.cnn_t = take(px * 4);
-    L.cnn_w = take((size_t)cnn_param_count(net.scales, net.channels) * act_elt);
+    L.cnn_w = take(cnn_weight_image_bytes(net));
     if (net.train) {
       const size_t C = net.channels;
       L.cnn_save = take(4 * px * C * act_elt);
@@ -156,7 +156,9 @@ int hyp_create(hyp_ctx** out, const hyp_net_desc* net) {
   if (net) {
     if (net->scales < 1 || net->scales > 5) return HYP_EINVAL;
     if (net->precision == HYP_PREC_FP32) {
-      if (net->channels != 16 && net->channels != 32) return HYP_EINVAL;
+      if (net->channels != 16 && net->channels != 32 && net->channels != 64) return HYP_EINVAL;
+      // the FP32 64-channel network is inference only
+      if (net->channels == 64 && (net->flags & HYP_NET_TRAIN)) return HYP_EUNSUPPORTED;
     } else if (net->precision == HYP_PREC_BF16) {
       if (net->channels != 32 && net->channels != 64) return HYP_EINVAL;
     } else {

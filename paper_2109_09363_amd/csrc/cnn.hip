@@ -49,7 +49,7 @@ constexpr int EW = TW + 2, EH = TH + 2;
 struct ScaleDesc {
   const void* in;     // NHWC input activations (storage type)
   void* out;          // NHWC output activations
-  const float* w;     // FP32 weights [Cout][3][3][Cin]
+  const void* wimg;   // weights as the LDS image: [Cout][WSTR] storage type, zero-padded K
   const float* b;     // FP32 bias [Cout]
   int H, W;
   int tiles_x, tile0; // tile columns, first global tile index of this scale
@@ -68,8 +68,13 @@ struct ConvGeom {
   static constexpr int KPAD = ((KTOT + KSTEP - 1) / KSTEP) * KSTEP;
   static constexpr int WSTR = KPAD + 16 / ELT;                // LDS weight row stride (elts)
   static constexpr int PSTR = (CIN == 2 ? 2 : CIN + 16 / ELT); // LDS pixel stride (elts)
-  static constexpr int MB = COUT / 16;                        // cout blocks
-  static constexpr size_t LDS = (size_t)COUT * WSTR * ELT + (size_t)EH * EW * PSTR * ELT;
+  static constexpr size_t TILE_LDS = (size_t)EH * EW * PSTR * ELT;
+  // output channels per pass: all of them unless their weights and the
+  // input tile overflow the 160 KB of LDS (FP32 64 -> 64: 16 per pass)
+  static constexpr int CT = ((size_t)COUT * WSTR * ELT + TILE_LDS <= 160 * 1024) ? COUT : 16;
+  static constexpr int PASSES = COUT / CT;
+  static constexpr int MB = CT / 16;                          // cout blocks per pass
+  static constexpr size_t LDS = (size_t)CT * WSTR * ELT + TILE_LDS;
 };
 
 // Fragment loads.  FP32: a lane holds 4 consecutive K values (one float4) and
@@ -178,22 +183,27 @@ __global__ __launch_bounds__(256) void conv3x3_relu(ConvLaunch L) {
   using Gm = ConvGeom<T, CIN, COUT>;
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
   T* wl = reinterpret_cast<T*>(lds_raw);
-  T* xl = wl + COUT * Gm::WSTR;
+  T* xl = wl + Gm::CT * Gm::WSTR;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t_begin = blockIdx.x * L.tiles_per_wg;
   const int t_end = min(t_begin + L.tiles_per_wg, L.total_tiles);
   int cur = -1;
+  // copy cout rows [co0, co0 + CT) of the layer's weight image into LDS with
+  // 16-byte loads, several in flight per thread
+  auto load_weights = [&](const void* img, int co0) {
+    __syncthreads();
+    constexpr int N16 = Gm::CT * Gm::WSTR * Gm::ELT / 16;
+    const uint4* src = reinterpret_cast<const uint4*>(img) + (size_t)co0 * Gm::WSTR * Gm::ELT / 16;
+    uint4* dstl = reinterpret_cast<uint4*>(wl);
+#pragma unroll 8
+    for (int e = threadIdx.x; e < N16; e += 256) dstl[e] = src[e];
+  };
   for (int t = t_begin; t < t_end; ++t) {
     int k = 0;
     while (k + 1 < L.nscales && t >= L.sc[k + 1].tile0) ++k;
     const ScaleDesc& S = L.sc[k];
-    if (k != cur) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < COUT * Gm::KPAD; e += blockDim.x) {
-        const int co = e / Gm::KPAD, kk = e % Gm::KPAD;
-        const float wv = kk < Gm::KTOT ? S.w[co * Gm::KTOT + kk] : 0.f;
-        wl[co * Gm::WSTR + kk] = St<T>::from(wv);
-      }
+    if (Gm::PASSES == 1 && k != cur) {
+      load_weights(S.wimg, 0);
       cur = k;
     }
     const int lt = t - S.tile0;
@@ -210,6 +220,7 @@ __global__ __launch_bounds__(256) void conv3x3_relu(ConvLaunch L) {
       }
     } else {
       constexpr int CH = CIN * sizeof(T) / 16;  // 16-byte chunks per pixel
+#pragma unroll 4
       for (int e = threadIdx.x; e < EH * EW * CH; e += blockDim.x) {
         const int pix = e / CH, ch = e % CH;
         const int gy = min(max(y0 - 1 + pix / EW, 0), S.H - 1);
@@ -219,35 +230,38 @@ __global__ __launch_bounds__(256) void conv3x3_relu(ConvLaunch L) {
         *reinterpret_cast<uint4*>(reinterpret_cast<char*>(xl + pix * Gm::PSTR) + ch * 16) = v;
       }
     }
-    __syncthreads();
-    floatx4 acc[Gm::MB][4];
-#pragma unroll
-    for (int mb = 0; mb < Gm::MB; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    conv_tile<T, CIN, COUT>(wl, xl, acc, wave, lane);
-    // epilogue: bias + ReLU; lane holds couts 4g..4g+3 of block mb for pixel col
     const int col = lane & 15, g = lane >> 4;
     T* out = reinterpret_cast<T*>(S.out);
+    for (int pass = 0; pass < Gm::PASSES; ++pass) {
+      if (Gm::PASSES > 1) load_weights(S.wimg, pass * Gm::CT);
+      __syncthreads();
+      floatx4 acc[Gm::MB][4];
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const int gy = y0 + wave * 4 + nb, gx = x0 + col;
-      if (gy >= S.H || gx >= S.W) continue;
-      T* dst = out + ((size_t)gy * S.W + gx) * COUT;
+      for (int mb = 0; mb < Gm::MB; ++mb)
 #pragma unroll
-      for (int mb = 0; mb < Gm::MB; ++mb) {
-        const int co = mb * 16 + g * 4;
-        float v0 = fmaxf(acc[mb][nb][0] + S.b[co + 0], 0.f);
-        float v1 = fmaxf(acc[mb][nb][1] + S.b[co + 1], 0.f);
-        float v2 = fmaxf(acc[mb][nb][2] + S.b[co + 2], 0.f);
-        float v3 = fmaxf(acc[mb][nb][3] + S.b[co + 3], 0.f);
-        if constexpr (sizeof(T) == 4) {
-          *reinterpret_cast<float4*>(dst + co) = make_float4(v0, v1, v2, v3);
-        } else {
-          uint2 pk;
-          pk.x = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
-          pk.y = (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16);
-          *reinterpret_cast<uint2*>(dst + co) = pk;
+        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+      conv_tile<T, CIN, COUT>(wl, xl, acc, wave, lane);
+      // epilogue: bias + ReLU; lane holds couts 4g..4g+3 of block mb for pixel col
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int gy = y0 + wave * 4 + nb, gx = x0 + col;
+        if (gy >= S.H || gx >= S.W) continue;
+        T* dst = out + ((size_t)gy * S.W + gx) * COUT;
+#pragma unroll
+        for (int mb = 0; mb < Gm::MB; ++mb) {
+          const int co = pass * Gm::CT + mb * 16 + g * 4;
+          float v0 = fmaxf(acc[mb][nb][0] + S.b[co + 0], 0.f);
+          float v1 = fmaxf(acc[mb][nb][1] + S.b[co + 1], 0.f);
+          float v2 = fmaxf(acc[mb][nb][2] + S.b[co + 2], 0.f);
+          float v3 = fmaxf(acc[mb][nb][3] + S.b[co + 3], 0.f);
+          if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4*>(dst + co) = make_float4(v0, v1, v2, v3);
+          } else {
+            uint2 pk;
+            pk.x = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+            pk.y = (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16);
+            *reinterpret_cast<uint2*>(dst + co) = pk;
+          }
         }
       }
     }
@@ -347,6 +361,58 @@ __global__ __launch_bounds__(256) void cnn_upsum(int H, int W, const float* __re
   }
 }
 
+// ---- weight images: every 3x3 layer's weights in the LDS layout of the conv
+// kernel ([Cout][WSTR], storage type, K zero-padded), written once per
+// inference so that a work-group copies them with wide loads.
+template <typename T, int CIN, int COUT>
+__device__ __forceinline__ void write_wimg(const float* __restrict__ w, T* __restrict__ img, int e) {
+  using Gm = ConvGeom<T, CIN, COUT>;
+  const int co = e / Gm::WSTR, kk = e % Gm::WSTR;
+  const float v = kk < Gm::KTOT ? w[co * Gm::KTOT + kk] : 0.f;
+  img[e] = St<T>::from(v);
+}
+
+template <typename T, int C>
+struct WImg {
+  static constexpr size_t L0 = (size_t)C * ConvGeom<T, 2, C>::WSTR;   // elements, layer 0
+  static constexpr size_t L1 = (size_t)C * ConvGeom<T, C, C>::WSTR;   // elements, layers 1..3
+  static constexpr size_t PER_SCALE = L0 + 3 * L1;
+};
+
+template <typename T, int C>
+__global__ __launch_bounds__(256) void cnn_wimg(const float* __restrict__ params, size_t per_scale,
+                                                int nscales, T* __restrict__ img) {
+  using WI = WImg<T, C>;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= WI::PER_SCALE * nscales) return;
+  const int k = (int)(gid / WI::PER_SCALE);
+  size_t e = gid % WI::PER_SCALE;
+  const float* wk = params + k * per_scale;
+  T* ik = img + k * WI::PER_SCALE;
+  if (e < WI::L0) {
+    write_wimg<T, 2, C>(wk, ik, (int)e);
+    return;
+  }
+  e -= WI::L0;
+  const int l = 1 + (int)(e / WI::L1);
+  const int el = (int)(e % WI::L1);
+  const size_t woff = (size_t)C * 18 + C + (size_t)(l - 1) * ((size_t)C * 9 * C + C);
+  write_wimg<T, C, C>(wk + woff, ik + WI::L0 + (size_t)(l - 1) * WI::L1, el);
+}
+
+size_t cnn_weight_image_bytes(const NetShape& net) {
+  if (net.scales <= 0) return 0;
+  if (net.precision == HYP_PREC_BF16) {
+    if (net.channels == 32) return WImg<uint16_t, 32>::PER_SCALE * net.scales * 2;
+    if (net.channels == 64) return WImg<uint16_t, 64>::PER_SCALE * net.scales * 2;
+  } else {
+    if (net.channels == 16) return WImg<float, 16>::PER_SCALE * net.scales * 4;
+    if (net.channels == 32) return WImg<float, 32>::PER_SCALE * net.scales * 4;
+    if (net.channels == 64) return WImg<float, 64>::PER_SCALE * net.scales * 4;
+  }
+  return 0;
+}
+
 // ---------------------------------------------------------------------------
 template <typename T, int C>
 static hipError_t run_cnn_t(const Device& dev, const NetShape& net, const WsLayout& Ly, int nx,
@@ -371,6 +437,13 @@ static hipError_t run_cnn_t(const Device& dev, const NetShape& net, const WsLayo
   hipLaunchKernelGGL(cnn_input<T>, dim3(nb_px), dim3(256), 0, s, P, w.d, w.cell, w.sc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  using WI = WImg<T, C>;
+  T* img = reinterpret_cast<T*>(w.cnn_w);
+  const size_t nimg = WI::PER_SCALE * S;
+  hipLaunchKernelGGL((cnn_wimg<T, C>), dim3((unsigned)((nimg + 255) / 256)), dim3(256), 0, s, params,
+                     per_scale, S, img);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   // four 3x3 layers, all scales per launch
   const T* src = in;
   T* bufs[2] = {a0, a1};
@@ -386,8 +459,8 @@ static hipError_t run_cnn_t(const Device& dev, const NetShape& net, const WsLayo
       ScaleDesc& D = L.sc[k];
       D.in = src + Ly.sc_off_px[k] * cin;
       D.out = dst + Ly.sc_off_px[k] * C;
-      D.w = params + k * per_scale + woff;
-      D.b = D.w + (size_t)C * 9 * cin;
+      D.wimg = img + k * WI::PER_SCALE + (l == 0 ? 0 : WI::L0 + (size_t)(l - 1) * WI::L1);
+      D.b = params + k * per_scale + woff + (size_t)C * 9 * cin;
       D.H = Ly.sc_h[k];
       D.W = Ly.sc_w[k];
       D.tiles_x = (D.W + TW - 1) / TW;
@@ -459,6 +532,7 @@ hipError_t run_cnn(const Device& dev, const NetShape& net, const WsLayout& L, in
   switch (net.channels) {
     case 16: return run_cnn_t<float, 16>(dev, net, L, nx, ny, dx, params, w, s);
     case 32: return run_cnn_t<float, 32>(dev, net, L, nx, ny, dx, params, w, s);
+    case 64: return run_cnn_t<float, 64>(dev, net, L, nx, ny, dx, params, w, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -125,6 +125,7 @@ hipError_t batch_setup(void* area, int ninst, const int* nx, const int* ny, cons
                        const double* thr, int max_iters, float omega, const Ws* ws);
 hipError_t run_jacobi_batch(const Device& dev, void* area, int ninst, int ntiles, bool cooperative,
                             hipStream_t s);
+size_t cnn_weight_image_bytes(const NetShape& net);
 hipError_t run_cnn(const Device& dev, const NetShape& net, const WsLayout& L, int nx, int ny,
                    double dx, const float* params, const Ws& w, hipStream_t s);
 

@@ -31,6 +31,8 @@ def state(nx, ny, seed, nobs):
     (64, 48, 2, 32, "bf16", 4),
     (128, 128, 4, 64, "bf16", 5),
     (80, 40, 1, 16, "fp32", 6),     # single scale, ragged
+    (64, 64, 2, 64, "fp32", 8),     # FP32 64 channels: 16 output channels per pass
+    (96, 64, 4, 64, "fp32", 9),
 ])
 def test_cnn_prediction_parity(nx, ny, S, C, prec, seed):
     say("cnn", nx, ny, S, C, prec)
