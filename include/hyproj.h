@@ -136,7 +136,11 @@ typedef struct {
                            phi_ckpt (at most 64 planes); without folds it
                            restarts the iteration bit-exactly as a warm
                            start.  0: none.  EINVAL otherwise. */
-  int32_t reserved;
+  int32_t tile_rows;    /* Jacobi tile: rows per wave in registers (4, 8,
+                           12, 16, 24 or 32); 0: the tuned table for this
+                           grid (csrc/tile_table.h), else the smallest that
+                           fits one work-group per CU.  EUNSUPPORTED when the
+                           tiles do not fit. */
 } hyp_opts;
 
 /* Written by the device when the projection's last kernel completes. */

@@ -98,7 +98,7 @@ class Projector:
     def project_async(self, u, v, flags, p, threshold: float, method: str = "hybrid",
                       max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
                       omega: float = 1.0, rho=None, p_init=None, fold_window: int = 0,
-                      checkpoint_every: int = 0, phi_ckpt=None):
+                      checkpoint_every: int = 0, phi_ckpt=None, tile_rows: int = 0):
         """Enqueue one projection on the current stream; u, v corrected in
         place, p written.  Read the result with `result()` after a sync.
         With fixed_iters and checkpoint_every > 0, phi_ckpt (n, ny, nx) float32
@@ -120,7 +120,7 @@ class Projector:
             raise RuntimeError("call plan(flags) before project")
         f = L.Fields(_ptr(u), _ptr(v), _ptr(rho), _ptr(flags), _ptr(p), _ptr(p_init), _ptr(phi_ckpt))
         o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
-                   float(omega), int(fold_window), int(checkpoint_every), 0)
+                   float(omega), int(fold_window), int(checkpoint_every), int(tile_rows))
         L.check("hyp_project", self.lib.hyp_project(
             self.ctx, ctypes.byref(self.grid), ctypes.byref(f), float(threshold), ctypes.byref(o),
             _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))

@@ -1,0 +1,116 @@
+"""Tile autotuner of the persistent Jacobi kernel.
+
+For each grid size, time a fixed number of sweeps (check every 8, halo 9)
+with every tile height R that fits the GPU (one work-group per CU) and keep
+the fastest.  The result is the C header the library compiles
+(csrc/tile_table.h); grids without an entry use the smallest R that fits.
+
+python -m paper_2109_09363_amd.autotune [--sizes 128 192 256 384 512 768 1024]
+        [--sweeps 512] [--reps 3] [--out paper_2109_09363_amd/csrc/tile_table.h]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import scenes  # noqa: E402
+import paper_2109_09363_amd as hp  # noqa: E402
+from paper_2109_09363_amd import _lib as L  # noqa: E402
+
+ROWS = (4, 8, 12, 16, 24, 32)
+HALO = 9  # check_every 8 (and fixed-sweep runs): 8 sweeps per step
+
+
+def time_rows(n, rows, sweeps, reps, dev):
+    sc = scenes.plume_scene(n, seed=0, n_obstacles=2)
+    u, v = scenes.random_faces(n, n, 0, kind="mixed")
+    pr = hp.Projector(n, n, sc.dx, 1.0, 1.0, 0, 0, "fp32", device=dev)
+    flags = torch.from_numpy(sc.flags).to(dev)
+    pr.plan(flags)
+    u0 = torch.from_numpy(u.astype(np.float32)).to(dev)
+    v0 = torch.from_numpy(v.astype(np.float32)).to(dev)
+    p = torch.empty((n, n), dtype=torch.float32, device=dev)
+    out = {}
+    for r in rows:
+        ts = []
+        try:
+            for rep in range(reps + 1):
+                uu, vv = u0.clone(), v0.clone()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                pr.project_async(uu, vv, flags, p, 0.0, method="jacobi", fixed_iters=sweeps,
+                                 check_every=8, tile_rows=r)
+                b.record()
+                torch.cuda.synchronize()
+                if rep > 0:
+                    ts.append(a.elapsed_time(b))
+        except L.HypError:
+            continue  # these tiles do not fit
+        out[r] = float(np.median(ts))
+    return out
+
+
+def write_header(path, entries):
+    lines = [
+        "// Tuned tile heights of the persistent Jacobi kernel: for a grid of",
+        "// nx x ny cells and halo H, the rows per wave R that ran fastest on MI355X.",
+        "// Written by paper_2109_09363_amd/autotune.py (do not edit by hand); a grid",
+        "// without an entry uses the smallest R whose tiles fit one work-group per CU.",
+        "#pragma once",
+        "",
+        "namespace hyp {",
+        "",
+        "struct TileEntry {",
+        "  int nx, ny, H, R;",
+        "};",
+        "",
+    ]
+    if entries:
+        lines.append("constexpr TileEntry kTileTable[] = {")
+        for (n, r, ms) in entries:
+            lines.append(f"    {{{n}, {n}, {HALO}, {r}}},  // {ms:.3f} ms")
+        lines.append("};")
+        lines.append(f"constexpr int kTileTableSize = {len(entries)};")
+    else:
+        lines.append("// (no measured entries yet)")
+        lines.append("constexpr TileEntry kTileTable[] = {{0, 0, 0, 0}};")
+        lines.append("constexpr int kTileTableSize = 0;")
+    lines += ["", "}  // namespace hyp", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", type=int, nargs="*", default=[128, 192, 256, 384, 512, 768, 1024])
+    ap.add_argument("--sweeps", type=int, default=512)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                   "csrc", "tile_table.h"))
+    a = ap.parse_args()
+    dev = torch.device("cuda")
+    entries = []
+    for n in a.sizes:
+        t = time_rows(n, ROWS, a.sweeps, a.reps, dev)
+        if not t:
+            print(json.dumps({"n": n, "fits": False}), flush=True)
+            continue
+        best = min(t, key=t.get)
+        entries.append((n, best, t[best]))
+        print(json.dumps({"n": n, "sweeps": a.sweeps, "ms_by_rows": t, "best_rows": best,
+                          "us_per_sweep": round(1e3 * t[best] / a.sweeps, 3)}), flush=True)
+    write_header(a.out, entries)
+    print(f"# wrote {a.out}", file=sys.stderr, flush=True)
+
+
+if __name__ == "__main__":
+    main()

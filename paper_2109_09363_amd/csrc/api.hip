@@ -262,7 +262,8 @@ static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, 
     if (g->nx % m || g->ny % m) return HYP_EUNSUPPORTED;
   }
   const bool pcg = o->method == HYP_METHOD_PCG;
-  if (!solver_fits(ctx->dev, g->nx, g->ny, pcg, o->check_every, o->fixed_iters))
+  if (o->tile_rows < 0 || (pcg && o->tile_rows != 0)) return HYP_EINVAL;
+  if (!solver_fits(ctx->dev, g->nx, g->ny, pcg, o->check_every, o->fixed_iters, o->tile_rows))
     return HYP_EUNSUPPORTED;
   return HYP_OK;
 }
@@ -287,7 +288,7 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
   mark(ctx, 2, stream);
   if (o->method == HYP_METHOD_CNN) {
     // no sweeps: a zero-length Jacobi pass records E_1 of the prediction
-    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, 0, nullptr, u, v, w, stream);
+    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, 0, nullptr, 0, u, v, w, stream);
   } else if (o->method == HYP_METHOD_PCG) {
     // one persistent launch, defect-correction folds included
     e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
@@ -296,7 +297,7 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
     // one persistent launch, defect-correction folds included
     e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,
                    o->fixed_iters, o->fold_window, phi_ckpt ? o->checkpoint_every : 0, phi_ckpt,
-                   u, v, w, stream);
+                   o->tile_rows, u, v, w, stream);
   }
   if (e != hipSuccess) return HYP_EHIP;
   mark(ctx, 3, stream);

@@ -12,6 +12,7 @@
 #include "../../include/hyproj.h"
 #include "common.h"
 #include "internal.h"
+#include "jacobi_rows.h"
 
 namespace hyp {
 
@@ -58,14 +59,17 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
     const int er = wave * R + r, gy = gy0 + r;
     float d_ = 0.f, k_ = 0.f, w_ = 0.f, p_ = 0.f;
     if (col_in && gy >= 0 && gy < I.ny) {
+      // the three loads are independent (masked afterwards): one round trip
       const int g = gy * I.nx + gx;
       const uint8_t ci = I.cell[g];
+      const float dv = I.d[g];
+      const float pv = from_phi ? I.phi[g] : ld_agent(src + g);
       if (!(ci & C_SOLID)) {
         const int k = cell_k(ci);
         k_ = (float)k;
-        d_ = I.d[g];
+        d_ = dv;
         w_ = I.wfac / (float)k;
-        p_ = from_phi ? I.phi[g] : ld_agent(src + g);
+        p_ = pv;
       }
       if (lane_int && er >= H && er < H + TH) {
         imask |= 1u << r;
@@ -86,31 +90,10 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
   };
   for (int s = 0; s < B; ++s) {
     edges();
-    float prev = below;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const float c = ph[r];
-      const float n = (r + 1 < R) ? ph[r + 1] : above;
-      const float e = from_right(c), w = from_left(c);
-      const float res = dd[r] - (((e + w) + (n + prev)) - kk[r] * c) * I.inv_dx2;
-      prev = c;
-      ph[r] = c - ww[r] * res;
-    }
+    jac_rows<R, true>(ph, dd, kk, ww, below, above, I.inv_dx2, 0u);
   }
   edges();
-  double acc = 0.0;
-  {
-    float prev = below;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const float c = ph[r];
-      const float n = (r + 1 < R) ? ph[r + 1] : above;
-      const float e = from_right(c), w = from_left(c);
-      const float res = dd[r] - (((e + w) + (n + prev)) - kk[r] * c) * I.inv_dx2;
-      prev = c;
-      acc += ((fmask >> r) & 1u) ? fabs((double)res) : 0.0;
-    }
-  }
+  const double acc = jac_rows<R, false>(ph, dd, kk, ww, below, above, I.inv_dx2, fmask);
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if ((imask >> r) & 1u) st_agent(dst + (size_t)(gy0 + r) * I.nx + gx, ph[r]);
@@ -288,12 +271,20 @@ hipError_t run_jacobi_batch(const Device& dev, void* area, int ninst, int ntiles
   BatchParams P{};
   P.inst = A.inst; P.tile_inst = A.tile_inst; P.ninst = ninst; P.ntiles = ntiles; P.H = 9;
   P.tile_part = A.tile_part; P.st = A.st; P.sync = A.sync;
-  const int G = dev.cu < kMaxCoopBlocks ? dev.cu : kMaxCoopBlocks;
+  // as many work-groups per CU as fit (up to 4), so that one work-group's
+  // loads overlap another's sweeps; every one of them is resident (the
+  // occupancy query accounts for registers and LDS), which the grid barrier
+  // needs, also for the plain launch used inside stream capture
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)jacobi_batch<16>, 256, 0) !=
+          hipSuccess || per_cu < 1)
+    per_cu = 1;
+  per_cu = per_cu > 4 ? 4 : per_cu;
+  int G = dev.cu * per_cu;
+  G = G < kMaxCoopBlocks ? G : kMaxCoopBlocks;
   void* args[] = {&P};
   if (cooperative)
     return hipLaunchCooperativeKernel((const void*)jacobi_batch<16>, dim3(G), dim3(256), args, 0, s);
-  // inside stream capture: a plain launch of one work-group per CU (the
-  // kernel's 167 VGPRs leave room for it on every CU, so all are resident)
   hipLaunchKernelGGL(jacobi_batch<16>, dim3(G), dim3(256), 0, s, P);
   return hipGetLastError();
 }

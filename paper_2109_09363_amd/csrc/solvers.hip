@@ -22,6 +22,8 @@
 #include "../../include/hyproj.h"
 #include "common.h"
 #include "internal.h"
+#include "jacobi_rows.h"
+#include "tile_table.h"
 
 namespace hyp {
 
@@ -55,49 +57,6 @@ struct JacParams {
   Scalars* sc;
   unsigned* sync;       // grid barrier
 };
-
-// One pass over the R rows of a lane: new value (or residual) of every cell.
-// `below`/`above` are the rows just outside the band (from LDS).  The update
-// computes the rows that need no band edge first, so that the LDS reads of
-// the edges are in flight meanwhile.
-template <int R>
-__device__ __forceinline__ float jac_cell(float c, float s, float n, float d, float k, float w,
-                                          float inv_dx2) {
-  const float e = from_right(c);
-  const float wv = from_left(c);
-  const float res = d - (((e + wv) + (n + s)) - k * c) * inv_dx2;
-  return c - w * res;
-}
-
-template <int R, bool UPDATE>
-__device__ __forceinline__ double jac_rows(float (&ph)[R], const float (&dd)[R], const float (&kk)[R],
-                                           const float (&ww)[R], float below, float above,
-                                           float inv_dx2, unsigned rmask) {
-  if (UPDATE) {
-    float nv[R];
-#pragma unroll
-    for (int r = 1; r + 1 < R; ++r)
-      nv[r] = jac_cell<R>(ph[r], ph[r - 1], ph[r + 1], dd[r], kk[r], ww[r], inv_dx2);
-    nv[0] = jac_cell<R>(ph[0], below, ph[1], dd[0], kk[0], ww[0], inv_dx2);
-    nv[R - 1] = jac_cell<R>(ph[R - 1], ph[R - 2], above, dd[R - 1], kk[R - 1], ww[R - 1], inv_dx2);
-#pragma unroll
-    for (int r = 0; r < R; ++r) ph[r] = nv[r];
-    return 0.0;
-  }
-  float prev = below;
-  double acc = 0.0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const float c = ph[r];
-    const float n = (r + 1 < R) ? ph[r + 1] : above;
-    const float e = from_right(c);
-    const float w = from_left(c);
-    const float res = dd[r] - (((e + w) + (n + prev)) - kk[r] * c) * inv_dx2;
-    prev = c;
-    if ((rmask >> r) & 1u) acc += fabs((double)res);
-  }
-  return acc;
-}
 
 __device__ __forceinline__ void abort_solve(Scalars* sc) {
   __hip_atomic_fetch_max(&sc->status, (int32_t)HYP_STATUS_ABORTED, __ATOMIC_RELAXED,
@@ -587,18 +546,39 @@ static int jacobi_block_len(int check_every, int fixed_iters) {
 
 static const int kRows[] = {4, 8, 12, 16, 24, 32};
 
-static bool jacobi_geom(const Device& dev, int nx, int ny, int check_every, int fixed_iters,
-                        int* R, int* H, int* ntx, int* nty) {
-  const int h = jacobi_block_len(check_every, fixed_iters) + 1;
-  const int tw = 64 - 2 * h;
-  const int tx = (nx + tw - 1) / tw;
+static bool jacobi_fit(const Device& dev, int nx, int ny, int r, int h, int* ntx, int* nty) {
+  const int tw = 64 - 2 * h, th = 4 * r - 2 * h;
+  if (tw < 1 || th < 1) return false;
   const int cap = dev.cu < kMaxCoopBlocks ? dev.cu : kMaxCoopBlocks;
+  const int tx = (nx + tw - 1) / tw, ty = (ny + th - 1) / th;
+  if (tx * ty > cap) return false;
+  *ntx = tx;
+  *nty = ty;
+  return true;
+}
+
+// rows = 0: the tuned table, else the smallest R that fits; rows > 0: that R
+static bool jacobi_geom(const Device& dev, int nx, int ny, int check_every, int fixed_iters,
+                        int rows, int* R, int* H, int* ntx, int* nty) {
+  const int h = jacobi_block_len(check_every, fixed_iters) + 1;
+  *H = h;
+  if (rows > 0) {
+    bool known = false;
+    for (int r : kRows) known = known || r == rows;
+    if (!known || !jacobi_fit(dev, nx, ny, rows, h, ntx, nty)) return false;
+    *R = rows;
+    return true;
+  }
+  for (int i = 0; i < kTileTableSize; ++i) {
+    const TileEntry& t = kTileTable[i];
+    if (t.nx == nx && t.ny == ny && t.H == h && jacobi_fit(dev, nx, ny, t.R, h, ntx, nty)) {
+      *R = t.R;
+      return true;
+    }
+  }
   for (int r : kRows) {
-    const int th = 4 * r - 2 * h;
-    if (th < 1) continue;
-    const int ty = (ny + th - 1) / th;
-    if (tx * ty <= cap) {
-      *R = r; *H = h; *ntx = tx; *nty = ty;
+    if (jacobi_fit(dev, nx, ny, r, h, ntx, nty)) {
+      *R = r;
       return true;
     }
   }
@@ -619,13 +599,14 @@ static bool pcg_geom(const Device& dev, int nx, int ny, int* R, int* ntx, int* n
   return false;
 }
 
-bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters) {
+bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters,
+                 int tile_rows) {
   if (pcg) {
     int R, ntx, nty;
     return pcg_geom(dev, nx, ny, &R, &ntx, &nty);
   }
   int R, H, ntx, nty;
-  return jacobi_geom(dev, nx, ny, check_every, fixed_iters, &R, &H, &ntx, &nty);
+  return jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, &R, &H, &ntx, &nty);
 }
 
 template <int R>
@@ -636,11 +617,11 @@ static hipError_t launch_jacobi(JacParams& p, int G, hipStream_t s) {
 
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      int checkpoint_every, float* phi_ckpt, float* u, float* v, const Ws& w,
-                      hipStream_t s) {
+                      int checkpoint_every, float* phi_ckpt, int tile_rows, float* u, float* v,
+                      const Ws& w, hipStream_t s) {
   JacParams p{};
   int R = 0, H = 0, ntx = 0, nty = 0;
-  if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, &R, &H, &ntx, &nty))
+  if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, &R, &H, &ntx, &nty))
     return hipErrorInvalidValue;
   p.nx = nx; p.ny = ny; p.H = H; p.ntx = ntx; p.nty = nty;
   p.inv_dx2 = (float)(1.0 / (dx * dx));

@@ -15,6 +15,10 @@ projection, CNN forward/backward and Adam.
 
 python -m paper_2109_09363_amd.train --n 128 --scales 4 --channels 64 \
     --precision bf16 --steps 400 --out weights.npy
+Fine-tuning at the benchmark resolution from existing weights, judged by the
+Jacobi sweeps the hybrid needs to reach a threshold on held-out plume states:
+python -m paper_2109_09363_amd.train --n 512 --init w.npy --random 0 \
+    --sweeps 64 --eval 6 --out w512.npy
 """
 from __future__ import annotations
 
@@ -113,6 +117,45 @@ def train(samples, n: int, scales: int, channels: int, precision: str = "fp32",
     return params.cpu().numpy(), hist
 
 
+def plume_states(n: int, n_scenes: int, steps: int, seed: int, device="cuda"):
+    """Held-out evaluation states: u* of plume runs after `steps` PCG-projected
+    steps (the state the hybrid would project next)."""
+    out = []
+    for i in range(n_scenes):
+        sc = scenes.plume_scene(n, seed=seed + i, n_obstacles=(0, 3))
+        pr = api.Projector(n, n, sc.dx, 1.0, sc.rho0, device=device)
+        tf = _dev(sc.flags, torch.uint8, device)
+        pr.plan(tf)
+        rho = torch.full((n, n), sc.rho0, dtype=torch.float32, device=device)
+        u = torch.zeros((n, n + 1), dtype=torch.float32, device=device)
+        v = torch.zeros((n + 1, n), dtype=torch.float32, device=device)
+        p = torch.zeros((n, n), dtype=torch.float32, device=device)
+        for s in range(steps + 1):
+            xi = _dev(scenes.inflow_noise(seed + i, s, n), device=device)
+            pr.advect_async(rho, u, v, xi, g=sc.g, drho=sc.drho, u_in=sc.u_in)
+            if s == steps:
+                out.append([tf, u.clone(), v.clone()])
+                break
+            pr.project_async(u, v, tf, p, 1e-3, method="pcg", max_iters=20000)
+    torch.cuda.synchronize()
+    return out
+
+
+def evaluate(states, n: int, scales: int, channels: int, precision: str, params, thr: float = 1e-3,
+             device="cuda"):
+    """Mean and max Jacobi sweeps the hybrid needs to reach mean|div| < thr."""
+    pr = api.Projector(n, n, 1.0 / n, 1.0, 1.0, scales, channels, precision, device=device)
+    pr.set_weights(_dev(params, device=device))
+    p = torch.empty((n, n), dtype=torch.float32, device=device)
+    its = []
+    for (tf, u, v) in states:
+        pr.plan(tf)
+        uu, vv = u.clone(), v.clone()
+        pr.project_async(uu, vv, tf, p, thr, method="hybrid", max_iters=1000000, check_every=8)
+        its.append(pr.result().iters)
+    return float(np.mean(its)), int(np.max(its))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=128)
@@ -125,11 +168,28 @@ def main():
     ap.add_argument("--sweeps", type=int, default=4)
     ap.add_argument("--scenes", type=int, default=12)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--init", default=None, help="start from these weights (.npy)")
+    ap.add_argument("--random", type=int, default=64, help="random divergence samples")
+    ap.add_argument("--sim-steps", type=int, default=32, help="plume steps per scene")
+    ap.add_argument("--eval", type=int, default=0, help="held-out plume states to evaluate")
+    ap.add_argument("--eval-steps", type=int, default=40)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
-    data = generate_dataset(a.n, n_scenes=a.scenes, seed=a.seed)
+    params0 = None
+    if a.init:
+        params0 = np.load(a.init, allow_pickle=False).astype(np.float32)
+    held = plume_states(a.n, a.eval, a.eval_steps, seed=900000 + a.seed) if a.eval > 0 else []
+    if held and params0 is not None:
+        m, mx = evaluate(held, a.n, a.scales, a.channels, a.precision, params0)
+        print(f"eval before: mean sweeps to 1e-3 {m:.1f} (max {mx}) on {len(held)} held-out states",
+              flush=True)
+    data = generate_dataset(a.n, n_scenes=a.scenes, steps=a.sim_steps, n_random=a.random, seed=a.seed)
     w, hist = train(data, a.n, a.scales, a.channels, a.precision, steps=a.steps, batch=a.batch,
-                    lr=a.lr, sweeps=a.sweeps, seed=a.seed)
+                    lr=a.lr, sweeps=a.sweeps, seed=a.seed, params0=params0)
+    if held:
+        m, mx = evaluate(held, a.n, a.scales, a.channels, a.precision, w)
+        print(f"eval after: mean sweeps to 1e-3 {m:.1f} (max {mx}) on {len(held)} held-out states",
+              flush=True)
     if a.out:
         np.save(a.out, w.astype(np.float32), allow_pickle=False)
         print(f"saved {a.out}")

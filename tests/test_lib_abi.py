@@ -98,6 +98,18 @@ def test_host_side_rejections():
     o.checkpoint_every = -1
     assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
                            nbytes.value, None, dummy) == -1
+    # tile rows: one of the instantiated heights, Jacobi/hybrid only
+    o.checkpoint_every = 0
+    o.tile_rows = -4
+    assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
+                           nbytes.value, None, dummy) == -1
+    o.tile_rows = 5
+    assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
+                           nbytes.value, None, dummy) == -2
+    o.method, o.tile_rows = 2, 8
+    assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
+                           nbytes.value, None, dummy) == -1
+    o.method, o.tile_rows = 1, 0
     assert lib.hyp_set_weights(ctx, dummy, 5) == -1
     assert lib.hyp_destroy(ctx) == 0
     assert lib.hyp_status_str(-4) == b"HIP error"
