@@ -8,6 +8,7 @@ WHAT:
   cnn      CNN inference only (4 scales, 64 channels, BF16)
   copy     a device-to-device copy of 256 MiB (calibration of FETCH/WRITE_SIZE)
   batch    one batched projection of many uneven plumes (streaming Jacobi)
+  dram     the streaming Jacobi on one --n x --n grid (default 8192^2), fixed sweeps
 Each workload runs once untimed, then `reps` times; the launch count and the
 algorithmic bytes of one launch are printed so that per-dispatch counters can
 be compared with them.
@@ -58,7 +59,7 @@ def plume_state(n, dev, steps=10):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["jacobi", "pcg", "cnn", "copy", "batch"])
+    ap.add_argument("what", choices=["jacobi", "pcg", "cnn", "copy", "batch", "dram"])
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--sweeps", type=int, default=4096)
     ap.add_argument("--reps", type=int, default=3)
@@ -93,6 +94,20 @@ def main():
         torch.cuda.synchronize()
         print(f"batch: {len(inst)} instances, {cells} cells, {a.sweeps} sweeps per launch, "
               f"algorithmic bytes per launch {13 * cells * a.sweeps}")
+        return
+    if a.what == "dram":
+        sc = scenes.plume_scene(n, seed=0, n_obstacles=2)
+        u, v = scenes.random_faces(n, n, 0, kind="white")
+        inst = [dict(nx=n, ny=n, dx=sc.dx, flags=torch.from_numpy(sc.flags).to(dev),
+                     u=torch.from_numpy(u.astype(np.float32)).to(dev),
+                     v=torch.from_numpy(v.astype(np.float32)).to(dev),
+                     p=torch.zeros((n, n), dtype=torch.float32, device=dev))]
+        b = hp.Batch(inst, threshold=0.0, method="jacobi", max_iters=a.sweeps)
+        for _ in range(a.reps + 1):
+            b.project_async()
+        torch.cuda.synchronize()
+        print(f"dram: {a.reps + 1} projections of {a.sweeps} sweeps at {n}^2; algorithmic bytes "
+              f"per jacobi_batch launch {13 * n * n * a.sweeps}")
         return
     pr, flags, u, v, p, tw = plume_state(n, dev)
     uu, vv = u.clone(), v.clone()
