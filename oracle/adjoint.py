@@ -20,6 +20,9 @@ Reverse sweep, with L symmetric on fluid cells and M = diag(1/k_c):
     (ReLU masks, replicate-padding adjoint folds ghost pixels onto the edge),
     2x2-mean pyramid transpose, the d/s normalisation incl. ds/dd
     faces: lam_u = D^T lam_d on open and inflow faces, 0 on closed faces.
+
+long_term() adds the paper's long-term term: the same loss after n unrolled
+time steps, with the advection not differentiated (Sec. 3.2, Fig. 5, Eq. 4).
 """
 from __future__ import annotations
 
@@ -27,6 +30,7 @@ import numpy as np
 
 from . import grid as G
 from . import cnn as CN
+from . import advect as AD
 
 
 def _axis_matrix(n_coarse: int) -> np.ndarray:
@@ -165,3 +169,48 @@ def loss_and_grad(flags, u, v, dx, params, S, C, K, omega=1.0, scale=1.0):
     gv[1:] = np.where(P.vopen[1:], gv[1:], 0.0)
     gv[0] = np.where(P.vinflow, gv[0], 0.0)
     return loss, gu, gv, dparams
+
+
+def hybrid_corrected(P: G.Plan, u, v, dx, params, S, C, K, omega=1.0):
+    """u - grad(phi) after the CNN guess and K Jacobi sweeps (Eq. 2)."""
+    _, F = forward(P, u, v, dx, params, S, C, K, omega)
+    ub, vb = G.enforce_bc(P, u, v)
+    return G.correct(P, ub, vb, F["phi"], dx)
+
+
+def long_term(flags, rho, u, v, dx, params, S, C, K, n, alpha, beta, g, rho0, drho, u_in,
+              xis, omega=1.0, cfl=0.5):
+    """The short-term plus long-term physics-driven loss (Sec. 3.2, Fig. 5,
+    Eq. 4) and its gradient with respect to the network parameters.
+
+    Short term: the divergence left after the network's correction of the
+    sample u*_t.  Long term: that corrected velocity is advanced n time steps
+    (advection and forces, then the same CNN + K sweeps projection) and the
+    divergence left after the correction of u*_{t+n} is taken.  Advection is
+    not differentiated and the network is frozen inside the unrolled steps,
+    so the long-term gradient is the gradient of the last projection's loss
+    at the state the rollout reached.  Each term is the sum of squared
+    residuals over fluid cells divided by the sum of squared divergences of
+    its own input state, weighted by alpha and beta.  xis[j] is the inflow
+    perturbation of unrolled step j (j = 0 .. n-1); dt follows the CFL rule.
+
+    Returns dict(loss, loss_short, loss_long, dparams, u_star, v_star, rho).
+    """
+    assert n >= 1
+    P = G.plan(flags)
+
+    def norm(uu, vv):
+        d = G.divergence(P, *G.enforce_bc(P, uu, vv), dx)
+        return 1.0 / float(np.sum(d[P.fluid] ** 2))
+
+    ls, _, _, gs = loss_and_grad(flags, u, v, dx, params, S, C, K, omega, alpha * norm(u, v))
+    uc, vc = hybrid_corrected(P, u, v, dx, params, S, C, K, omega)
+    r = np.asarray(rho, np.float64)
+    for j in range(n):
+        dt = AD.cfl_dt(uc, vc, dx, u_in, cfl)
+        r, us, vs = AD.advect_step(P, flags, r, uc, vc, dx, dt, g, rho0, drho, u_in, xis[j])
+        if j < n - 1:
+            uc, vc = hybrid_corrected(P, us, vs, dx, params, S, C, K, omega)
+    ll, _, _, gl = loss_and_grad(flags, us, vs, dx, params, S, C, K, omega, beta * norm(us, vs))
+    return dict(loss=ls + ll, loss_short=ls, loss_long=ll, dparams=gs + gl, u_star=us, v_star=vs,
+                rho=r)

@@ -144,6 +144,19 @@ def random_faces(nx: int, ny: int, seed: int, kind: str = "smooth", modes: int =
     return u, v
 
 
+def random_density(nx: int, ny: int, seed: int, rho0: float, drho: float, blobs: int = 4):
+    """A smooth random density field (ny, nx), float64, between rho0 (1 - drho)
+    and rho0: a few Gaussian blobs of lighter fluid (the plume's own density
+    range) at random positions and widths."""
+    rng = np.random.Generator(np.random.PCG64([seed, 104729]))
+    X, Y = np.meshgrid((np.arange(nx) + 0.5) / nx, (np.arange(ny) + 0.5) / nx)
+    light = np.zeros((ny, nx))
+    for _ in range(blobs):
+        cx, cy = rng.uniform(0.1, 0.9), rng.uniform(0.1, 0.9) * ny / nx
+        w = rng.uniform(0.05, 0.2)
+        light = np.maximum(light, rng.uniform(0.3, 1.0) * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (w * w)))
+    return rho0 * (1.0 - drho * light)
+
 # ---- network parameters -------------------------------------------------------
 
 def cnn_param_count(scales: int, channels: int) -> int:
@@ -181,3 +194,28 @@ def random_weights(scales: int, channels: int, seed: int, out_scale: float = 1.0
 
 def zero_weights(scales: int, channels: int) -> np.ndarray:
     return np.zeros(cnn_param_count(scales, channels), dtype=np.float32)
+
+
+# Layer shapes of the cascaded MultiScale / SmallScale networks, (k, cin, cout)
+# per layer, branches from the coarsest to the finest (used only to size the
+# random initialisation below).
+def paper_net_layers(arch: str):
+    a, mid = {"multiscale": (64, 32), "smallscale": (32, 32)}[arch]
+    coarse = [(5, 2, a), (3, a, a), (3, a, a), (3, a, a), (1, a, 1)]
+    finer = [(5, 3, a), (3, a, a), (3, a, mid), (3, mid, a), (3, a, a), (3, a, a), (1, a, 1)]
+    return [coarse, finer, finer]
+
+
+def random_paper_weights(arch: str, seed: int, out_scale: float = 1.0) -> np.ndarray:
+    """He-uniform random init of a cascaded network in its packed float32
+    layout: per layer W[Cout][k][k][Cin] then b[Cout], branches coarse to
+    fine.  The output layers are scaled by ``out_scale``."""
+    rng = np.random.Generator(np.random.PCG64([seed, 31337]))
+    parts = []
+    for br in paper_net_layers(arch):
+        for i, (k, ci, co) in enumerate(br):
+            fan_in = k * k * ci
+            bw = np.sqrt(6.0 / fan_in) * (out_scale if i == len(br) - 1 else 1.0)
+            parts.append(rng.uniform(-bw, bw, co * k * k * ci))
+            parts.append(rng.uniform(-1, 1, co) / np.sqrt(fan_in))
+    return np.concatenate(parts).astype(np.float32)

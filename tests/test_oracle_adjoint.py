@@ -10,6 +10,7 @@ import pytest
 
 import scenes
 from oracle import adjoint as AJ
+from oracle import advect as AD
 from oracle import cnn as CN
 from oracle import grid as G
 
@@ -119,3 +120,88 @@ def test_dot_product_conv_input():
     lx, dW, db = AJ.conv3x3_backward(x, W, lam)
     assert np.sum(CN.conv3x3_replicate(x, W, b) * lam) == pytest.approx(np.sum(x * lx), rel=1e-12)
     assert np.sum(CN.conv3x3_replicate(x, W, b) * lam) == pytest.approx(np.sum(W * dW), rel=1e-12)
+
+
+def lt_setup(n=16, S=2, C=4, seed=3):
+    sc = scenes.plume_scene(n, seed=seed, n_obstacles=1, ri=0.1)
+    u, v = scenes.random_faces(n, n, seed, kind="smooth")
+    rho = scenes.random_density(n, n, seed, sc.rho0, sc.drho)
+    w = scenes.random_weights(S, C, seed).astype(np.float64)
+    xis = [scenes.inflow_noise(seed, j, n) for j in range(4)]
+    return sc, rho, u, v, w, xis
+
+
+def lt(sc, rho, u, v, w, xis, n, alpha, beta, K=2):
+    return AJ.long_term(sc.flags, rho, u, v, sc.dx, w, 2, 4, K, n, alpha, beta, sc.g, sc.rho0,
+                        sc.drho, sc.u_in, xis)
+
+
+def test_long_term_weights_are_linear():
+    sc, rho, u, v, w, xis = lt_setup()
+    a = lt(sc, rho, u, v, w, xis, 3, 1.0, 0.0)
+    b = lt(sc, rho, u, v, w, xis, 3, 0.0, 1.0)
+    c = lt(sc, rho, u, v, w, xis, 3, 2.0, 3.0)
+    assert a["loss_long"] == 0.0 and b["loss_short"] == 0.0
+    assert c["loss"] == pytest.approx(2 * a["loss"] + 3 * b["loss"], rel=1e-12)
+    assert np.allclose(c["dparams"], 2 * a["dparams"] + 3 * b["dparams"], rtol=1e-12, atol=1e-15)
+    # the short term alone is the single-projection loss, normalised by sum_F d^2
+    P = G.plan(sc.flags)
+    d = G.divergence(P, *G.enforce_bc(P, u, v), sc.dx)
+    l0, _, _, g0 = AJ.loss_and_grad(sc.flags, u, v, sc.dx, w, 2, 4, 2)
+    nrm = float(np.sum(d[P.fluid] ** 2))
+    assert a["loss"] == pytest.approx(l0 / nrm, rel=1e-12)
+    assert np.allclose(a["dparams"], g0 / nrm, rtol=1e-12, atol=1e-15)
+
+
+def test_long_term_rollout_starts_from_corrected_velocity():
+    # The loss of the short term is the divergence energy of the corrected
+    # velocity (computed here from the faces), which is what the first
+    # unrolled advection must receive.
+    sc, rho, u, v, w, xis = lt_setup(seed=4)
+    P = G.plan(sc.flags)
+    uc, vc = AJ.hybrid_corrected(P, u, v, sc.dx, w, 2, 4, 2)
+    dc = G.divergence(P, uc, vc, sc.dx)
+    l0 = AJ.loss_and_grad(sc.flags, u, v, sc.dx, w, 2, 4, 2)[0]
+    assert float(np.sum(dc[P.fluid] ** 2)) == pytest.approx(l0, rel=1e-9)
+    one = lt(sc, rho, u, v, w, xis, 1, 1.0, 1.0)
+    dt = AD.cfl_dt(uc, vc, sc.dx, sc.u_in)
+    r1, us, vs = AD.advect_step(P, sc.flags, rho, uc, vc, sc.dx, dt, sc.g, sc.rho0, sc.drho,
+                                sc.u_in, xis[0])
+    assert np.array_equal(one["u_star"], us) and np.array_equal(one["v_star"], vs)
+    assert np.array_equal(one["rho"], r1)
+
+
+def test_long_term_two_steps_compose():
+    # n = 2 is n = 1, the frozen network's correction of u*_{t+1}, and one
+    # more step with the second inflow perturbation.
+    sc, rho, u, v, w, xis = lt_setup(seed=5)
+    P = G.plan(sc.flags)
+    one = lt(sc, rho, u, v, w, xis, 1, 1.0, 1.0)
+    two = lt(sc, rho, u, v, w, xis, 2, 1.0, 1.0)
+    uc, vc = AJ.hybrid_corrected(P, one["u_star"], one["v_star"], sc.dx, w, 2, 4, 2)
+    dt = AD.cfl_dt(uc, vc, sc.dx, sc.u_in)
+    r2, us, vs = AD.advect_step(P, sc.flags, one["rho"], uc, vc, sc.dx, dt, sc.g, sc.rho0,
+                                sc.drho, sc.u_in, xis[1])
+    assert np.array_equal(two["u_star"], us) and np.array_equal(two["v_star"], vs)
+    assert np.array_equal(two["rho"], r2)
+    assert two["loss_short"] == one["loss_short"]
+    assert not np.array_equal(two["u_star"], one["u_star"])
+
+
+def test_long_term_gradient_is_frozen_state_derivative():
+    # Advection is not differentiated: the long-term gradient is the
+    # derivative of the last projection's loss with the unrolled state held
+    # fixed (central differences in FP64 along random directions).
+    sc, rho, u, v, w, xis = lt_setup(seed=6)
+    b = lt(sc, rho, u, v, w, xis, 3, 0.0, 1.0)
+    P = G.plan(sc.flags)
+    us, vs = b["u_star"], b["v_star"]
+    d = G.divergence(P, *G.enforce_bc(P, us, vs), sc.dx)
+    scale = 1.0 / float(np.sum(d[P.fluid] ** 2))
+    f = lambda ww: AJ.forward(P, us, vs, sc.dx, ww, 2, 4, 2, 1.0, scale)[0]
+    assert f(w) == pytest.approx(b["loss"], rel=1e-12)
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        dirn = rng.standard_normal(w.size)
+        dd = (f(w + 1e-6 * dirn) - f(w - 1e-6 * dirn)) / 2e-6
+        assert dd == pytest.approx(float(b["dparams"] @ dirn), rel=1e-5)
