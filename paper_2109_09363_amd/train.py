@@ -4,7 +4,10 @@ The physics-driven loss of Sec. 3.2: the divergence left in the corrected
 velocity, here after the CNN guess and K Jacobi sweeps (the hybrid's own
 iteration), with the gradient of the correction (Eq. 2) and of the sweeps
 taken by the library's adjoint.  Each sample's loss is normalised by its
-initial divergence energy, so  loss = sum_F r^2 / sum_F d^2.
+initial divergence energy, so  loss = sum_F r^2 / sum_F d^2.  With --beta the
+long-term term is added: the same loss after 4 (or, one time in ten, 16)
+unrolled time steps of the plume with the network in the loop, the advection
+not differentiated (Sec. 3.2, Fig. 5, Eq. 4).
 
 Training data (the paper's Mantaflow set is not available): intermediate
 velocities u* of plume runs that the plain solver (PCG) projects, on random
@@ -36,14 +39,25 @@ def _dev(a, dtype=torch.float32, device="cuda"):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(device)
 
 
+class Sample:
+    """One training state on the device: the intermediate velocity u*, v*,
+    the density and the plume's physics (for the unrolled steps of the
+    long-term loss)."""
+    __slots__ = ("flags", "u", "v", "rho", "g", "drho", "u_in", "seed")
+
+    def __init__(self, flags, u, v, rho, g, drho, u_in, seed):
+        self.flags, self.u, self.v, self.rho = flags, u, v, rho
+        self.g, self.drho, self.u_in, self.seed = g, drho, u_in, seed
+
+
 def generate_dataset(n: int, n_scenes: int = 12, steps: int = 32, keep_every: int = 2,
                      n_random: int = 64, seed: int = 0, device="cuda", log=print):
-    """List of samples (flags, u*, v*, sum_F d^2) on the device."""
+    """List of Samples on the device."""
     samples = []
     t0 = time.time()
     for i in range(n_scenes):
-        sc = scenes.plume_scene(n, seed=seed * 1000 + i, n_obstacles=(0, 3),
-                                ri=0.1 if i % 2 == 0 else 0.0)
+        sid = seed * 1000 + i
+        sc = scenes.plume_scene(n, seed=sid, n_obstacles=(0, 3), ri=0.1 if i % 2 == 0 else 0.0)
         pr = api.Projector(n, n, sc.dx, 1.0, sc.rho0, device=device)
         tf = _dev(sc.flags, torch.uint8, device)
         pr.plan(tf)
@@ -53,27 +67,75 @@ def generate_dataset(n: int, n_scenes: int = 12, steps: int = 32, keep_every: in
         p = torch.zeros((n, n), dtype=torch.float32, device=device)
         g = sc.g if sc.ri > 0 else 0.0
         for s in range(steps):
-            xi = _dev(scenes.inflow_noise(seed * 1000 + i, s, n), device=device)
+            xi = _dev(scenes.inflow_noise(sid, s, n), device=device)
             pr.advect_async(rho, u, v, xi, g=g, drho=sc.drho, u_in=sc.u_in)
             if s >= 1 and s % keep_every == 0:
-                samples.append([tf, u.clone(), v.clone()])
+                samples.append(Sample(tf, u.clone(), v.clone(), rho.clone(), g, sc.drho, sc.u_in,
+                                      sid * 100 + s))
             pr.project_async(u, v, tf, p, 1e-3, method="pcg", max_iters=20000)
     rng = np.random.default_rng(seed + 7)
     for i in range(n_random):
-        sc = scenes.plume_scene(n, seed=seed * 1000 + 500 + i, n_obstacles=(0, 3))
+        sid = seed * 1000 + 500 + i
+        sc = scenes.plume_scene(n, seed=sid, n_obstacles=(0, 3))
         kind = ("smooth", "mixed", "white")[i % 3]
         uu, vv = scenes.random_faces(n, n, int(rng.integers(1 << 30)), kind=kind)
-        samples.append([_dev(sc.flags, torch.uint8, device), _dev(uu, device=device),
-                        _dev(vv, device=device)])
+        rho = torch.full((n, n), sc.rho0, dtype=torch.float32, device=device)
+        # the divergence sources have no density variation (Ri = 0)
+        samples.append(Sample(_dev(sc.flags, torch.uint8, device), _dev(uu, device=device),
+                              _dev(vv, device=device), rho, 0.0, sc.drho, sc.u_in, sid * 100))
     torch.cuda.synchronize()
     log(f"dataset: {len(samples)} samples at {n}x{n} in {time.time() - t0:.1f} s")
     return samples
 
 
+def draw_unroll(rng, long_frac: float = 0.1, short: int = 4, long: int = 16) -> int:
+    """Number of unrolled steps of the long-term loss: 16 one time in ten,
+    else 4 (Sec. 3.2)."""
+    return long if rng.random() < long_frac else short
+
+
+def unrolled_backward(pr, smp: Sample, sweeps: int, n_unroll: int, alpha: float, beta: float,
+                      norm_short: float, grads, xis, weight: float = 1.0, accumulate: bool = False,
+                      loss_short=None, loss_long=None, p=None):
+    """Enqueue the gradient of  alpha * short + beta * long  for one sample
+    (Sec. 3.2, Fig. 5, Eq. 4) into `grads` (added when `accumulate`).
+
+    short: sum_F r^2 / sum_F d^2 after the network's projection (CNN guess and
+    `sweeps` Jacobi sweeps) of u*_t;  long: the same after n_unroll more time
+    steps (advection and forces, then the same projection with the network
+    frozen), with the advection not differentiated: only the last projection
+    is back-propagated.  xis[j] is the inflow perturbation (device, nx) of
+    unrolled step j.  Returns the long-term normalisation (host sync)."""
+    method = "hybrid" if sweeps > 0 else "cnn"
+    n = pr.nx
+    if p is None:
+        p = torch.empty((pr.ny, n), dtype=torch.float32, device=smp.u.device)
+    pr.plan(smp.flags)
+    uu, vv = smp.u.clone(), smp.v.clone()
+    pr.project_async(uu, vv, smp.flags, p, 0.0, method=method, fixed_iters=sweeps)
+    if alpha != 0.0:
+        pr.backward_async(sweeps, 1.0, weight * alpha * norm_short, dparams=grads, loss=loss_short,
+                          accumulate=accumulate)
+        accumulate = True
+    if beta == 0.0 or n_unroll == 0:
+        return 0.0
+    rr = smp.rho.clone()
+    for j in range(n_unroll):
+        pr.advect_async(rr, uu, vv, xis[j], g=smp.g, drho=smp.drho, u_in=smp.u_in)
+        pr.project_async(uu, vv, smp.flags, p, 0.0, method=method, fixed_iters=sweeps)
+    r = pr.result()
+    norm_long = 1.0 / max(r.s * r.s * r.n_fluid, 1e-30)
+    pr.backward_async(sweeps, 1.0, weight * beta * norm_long, dparams=grads, loss=loss_long,
+                      accumulate=accumulate)
+    return norm_long
+
+
 def train(samples, n: int, scales: int, channels: int, precision: str = "fp32",
           steps: int = 200, batch: int = 4, lr: float = 1e-3, sweeps: int = 4,
-          params0=None, seed: int = 0, device="cuda", log=print, log_every: int = 20):
-    """Adam on the normalised divergence loss; returns (params, loss history)."""
+          params0=None, seed: int = 0, device="cuda", log=print, log_every: int = 20,
+          alpha: float = 1.0, beta: float = 0.0):
+    """Adam on  alpha * short-term + beta * long-term  normalised divergence
+    losses (beta = 0: the single-step loss); returns (params, loss history)."""
     dx = 1.0 / n
     pr = api.Projector(n, n, dx, 1.0, 1.0, scales, channels, precision, device=device, train=True)
     if params0 is None:
@@ -86,31 +148,37 @@ def train(samples, n: int, scales: int, channels: int, precision: str = "fp32",
     # per-sample normalisation from the library's CNN input scale s: sum d^2 = s^2 nF
     norms = []
     pz = torch.empty((n, n), dtype=torch.float32, device=device)
-    for (tf, u, v) in samples:
-        pr.plan(tf)
-        uu, vv = u.clone(), v.clone()
-        pr.project_async(uu, vv, tf, pz, 0.0, method="cnn")
+    for smp in samples:
+        pr.plan(smp.flags)
+        uu, vv = smp.u.clone(), smp.v.clone()
+        pr.project_async(uu, vv, smp.flags, pz, 0.0, method="cnn")
         r = pr.result()
         norms.append(1.0 / max(r.s * r.s * r.n_fluid, 1e-30))
     rng = np.random.default_rng(seed)
-    loss_dev = torch.zeros(1, dtype=torch.float64, device=device)
+    ls_dev = torch.zeros(1, dtype=torch.float64, device=device)
+    ll_dev = torch.zeros(1, dtype=torch.float64, device=device)
     hist = []
-    method = "hybrid" if sweeps > 0 else "cnn"
     t0 = time.time()
     for it in range(1, steps + 1):
         idx = rng.choice(len(samples), batch, replace=False)
+        logging = it % log_every == 0 or it == 1 or it == steps
         acc_loss = 0.0
         for b, i in enumerate(idx):
-            tf, u, v = samples[i]
-            pr.plan(tf)
-            uu, vv = u.clone(), v.clone()
-            pr.project_async(uu, vv, tf, pz, 0.0, method=method, fixed_iters=sweeps)
-            pr.backward_async(sweeps, 1.0, norms[i] / batch, dparams=grads, loss=loss_dev,
-                              accumulate=b > 0)
-            if it % log_every == 0 or it == 1 or it == steps:
-                acc_loss += float(loss_dev.item())
+            smp = samples[i]
+            xis = []
+            n_unroll = 0
+            if beta != 0.0:
+                n_unroll = draw_unroll(rng)
+                xis = [_dev(scenes.inflow_noise(smp.seed, 1 + 1000 * it + j, n), device=device)
+                       for j in range(n_unroll)]
+            unrolled_backward(pr, smp, sweeps, n_unroll, alpha, beta, norms[i], grads, xis,
+                              weight=1.0 / batch, accumulate=b > 0, loss_short=ls_dev,
+                              loss_long=ll_dev, p=pz)
+            if logging:
+                acc_loss += (float(ls_dev.item()) if alpha != 0.0 else 0.0) + \
+                            (float(ll_dev.item()) if beta != 0.0 else 0.0)
         api.adam_async(params, grads, m, v2, it, lr=lr)
-        if it % log_every == 0 or it == 1 or it == steps:
+        if logging:
             hist.append((it, acc_loss))
             log(f"step {it:5d}  loss {acc_loss:.5f}  ({time.time() - t0:.1f} s)")
     torch.cuda.synchronize()
@@ -173,6 +241,9 @@ def main():
     ap.add_argument("--sim-steps", type=int, default=32, help="plume steps per scene")
     ap.add_argument("--eval", type=int, default=0, help="held-out plume states to evaluate")
     ap.add_argument("--eval-steps", type=int, default=40)
+    ap.add_argument("--alpha", type=float, default=1.0, help="weight of the short-term loss")
+    ap.add_argument("--beta", type=float, default=0.0,
+                    help="weight of the long-term loss (4 or 16 unrolled steps)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     params0 = None
@@ -185,7 +256,8 @@ def main():
               flush=True)
     data = generate_dataset(a.n, n_scenes=a.scenes, steps=a.sim_steps, n_random=a.random, seed=a.seed)
     w, hist = train(data, a.n, a.scales, a.channels, a.precision, steps=a.steps, batch=a.batch,
-                    lr=a.lr, sweeps=a.sweeps, seed=a.seed, params0=params0)
+                    lr=a.lr, sweeps=a.sweeps, seed=a.seed, params0=params0, alpha=a.alpha,
+                    beta=a.beta)
     if held:
         m, mx = evaluate(held, a.n, a.scales, a.channels, a.precision, w)
         print(f"eval after: mean sweeps to 1e-3 {m:.1f} (max {mx}) on {len(held)} held-out states",

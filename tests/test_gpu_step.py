@@ -1,6 +1,7 @@
 """GPU parity of the full time step (CFL dt, MacCormack advection, buoyancy,
-inflow, boundary faces, projection) against the FP64 oracle.  The plume is
-chaotic, so parity is per step: the oracle re-steps from the GPU's state."""
+inflow, boundary faces, projection) against the FP64 oracle: one step from
+seeded states, and eight-step rollouts in which each side advances its own
+state from the same seeded scene."""
 import numpy as np
 import pytest
 import torch
@@ -10,7 +11,7 @@ import paper_2109_09363_amd as hp
 from oracle import advect as AD
 from oracle import grid as G
 from oracle import project as PR
-from tests.gpu_util import to_dev, rel_l2
+from tests.gpu_util import to_dev, f32
 
 pytestmark = pytest.mark.gpu
 
@@ -28,10 +29,59 @@ def close_mostly(a, b, tol, frac=0.999):
     return ok.mean() >= frac
 
 
+def frac_within(a, b, tol):
+    return float((np.abs(a - b) <= tol * max(np.abs(b).max(), 1e-30)).mean())
+
+
+def gpu_state(rho, u, v):
+    return (to_dev(rho), to_dev(u), to_dev(v))
+
+
+@pytest.mark.parametrize("n,nobs,seed,method", [(64, 1, 10, "jacobi"), (96, 2, 11, "pcg")])
+def test_single_step_from_seeded_state(n, nobs, seed, method):
+    """One step from a developed-looking seeded state (light blobs, smooth
+    velocities), each side from the same FP32-rounded inputs."""
+    say("single step", n, nobs, method)
+    sc = scenes.plume_scene(n, seed=seed, n_obstacles=nobs)
+    P = G.plan(sc.flags)
+    r0 = f32(scenes.random_density(n, n, seed, sc.rho0, 0.2))
+    u0, v0 = (f32(0.5 * a) for a in scenes.random_faces(n, n, seed, kind="smooth"))
+    xi = f32(scenes.inflow_noise(seed, 0, n))
+    pr = hp.Projector(n, n, sc.dx, 1.0, sc.rho0)
+    tf = to_dev(sc.flags, torch.uint8)
+    pr.plan(tf)
+    rho, u, v = gpu_state(r0, u0, v0)
+    p = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    fixed = 30 if method == "jacobi" else 0
+    pr.step_async(rho, u, v, tf, p, to_dev(xi), threshold=1e-3, g=sc.g, drho=0.2, u_in=sc.u_in,
+                  method=method, fixed_iters=fixed, max_iters=20000)
+    torch.cuda.synchronize()
+    res = pr.result()
+    dt_o = AD.cfl_dt(u0, v0, sc.dx, sc.u_in)
+    assert res.dt == pytest.approx(dt_o, rel=1e-7)
+    ro, us, vs = AD.advect_step(P, sc.flags, r0, u0, v0, sc.dx, res.dt, sc.g, sc.rho0, 0.2, sc.u_in, xi)
+    assert close_mostly(rho.cpu().numpy(), ro, 1e-5)
+    if method == "jacobi":
+        o = PR.project(sc.flags, us, vs, sc.dx, dt=res.dt, method="jacobi", fixed_iters=fixed)
+        assert res.iters == fixed
+    else:
+        o = PR.project(sc.flags, us, vs, sc.dx, dt=res.dt, method="pcg", threshold=1e-3)
+        assert abs(res.iters - o["iters"]) <= max(3, 0.1 * o["iters"])
+        assert res.e1_final < 1.05e-3
+    say("  fraction within 1e-4: u", frac_within(u.cpu().numpy(), o["u"], 1e-4),
+        "v", frac_within(v.cpu().numpy(), o["v"], 1e-4), "iters", res.iters, o["iters"])
+    assert close_mostly(u.cpu().numpy(), o["u"], 1e-4)
+    assert close_mostly(v.cpu().numpy(), o["v"], 1e-4)
+    assert res.e1_init == pytest.approx(o["e1_init"], rel=1e-2)
+
+
 @pytest.mark.parametrize("n,nobs,seed,method", [(64, 0, 0, "jacobi"), (128, 2, 1, "pcg"),
                                                  (96, 1, 2, "jacobi")])
-def test_step_parity_per_step(n, nobs, seed, method):
-    say("step", n, nobs, method)
+def test_rollout_parity(n, nobs, seed, method):
+    """Eight steps of the plume from rest, GPU and oracle each running its own
+    rollout from the same seeded scene and inflow perturbations; compared
+    after every step."""
+    say("rollout", n, nobs, method)
     sc = scenes.plume_scene(n, seed=seed, n_obstacles=nobs)
     P = G.plan(sc.flags)
     pr = hp.Projector(n, n, sc.dx, 1.0, sc.rho0)
@@ -41,33 +91,39 @@ def test_step_parity_per_step(n, nobs, seed, method):
     u = torch.zeros((n, n + 1), dtype=torch.float32, device="cuda")
     v = torch.zeros((n + 1, n), dtype=torch.float32, device="cuda")
     p = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    ro = np.full((n, n), sc.rho0)
+    uo = np.zeros((n, n + 1))
+    vo = np.zeros((n + 1, n))
     fixed = 30 if method == "jacobi" else 0
+    # the PCG stop decision may fall one iteration apart, which shifts the
+    # state by about the last update; over eight steps allow 1e-3
+    tol = 1e-4 if method == "jacobi" else 1e-3
     for step in range(8):
-        xi = scenes.inflow_noise(seed, step, n)
-        r0 = rho.cpu().numpy().astype(np.float64)
-        u0 = u.cpu().numpy().astype(np.float64)
-        v0 = v.cpu().numpy().astype(np.float64)
+        xi = f32(scenes.inflow_noise(seed, step, n))
         pr.step_async(rho, u, v, tf, p, to_dev(xi), threshold=1e-3, g=sc.g, drho=sc.drho,
                       u_in=sc.u_in, method=method, fixed_iters=fixed, max_iters=20000)
         torch.cuda.synchronize()
         res = pr.result()
-        dt_o = AD.cfl_dt(u0, v0, sc.dx, sc.u_in)
-        assert res.dt == pytest.approx(dt_o, rel=1e-12)
-        xi32 = np.float32(xi).astype(np.float64)
-        ro, us, vs = AD.advect_step(P, sc.flags, r0, u0, v0, sc.dx, res.dt, sc.g, sc.rho0,
-                                    sc.drho, sc.u_in, xi32)
-        assert close_mostly(rho.cpu().numpy(), ro, 1e-5)
+        dt_o = AD.cfl_dt(uo, vo, sc.dx, sc.u_in)
+        assert res.dt == pytest.approx(dt_o, rel=tol)  # dt follows max|u|, a field value
+        ro, us, vs = AD.advect_step(P, sc.flags, ro, uo, vo, sc.dx, dt_o, sc.g, sc.rho0,
+                                    sc.drho, sc.u_in, xi)
         if method == "jacobi":
-            o = PR.project(sc.flags, us, vs, sc.dx, dt=res.dt, method="jacobi", fixed_iters=fixed)
+            o = PR.project(sc.flags, us, vs, sc.dx, dt=dt_o, method="jacobi", fixed_iters=fixed)
             assert res.iters == fixed
         else:
-            o = PR.project(sc.flags, us, vs, sc.dx, dt=res.dt, method="pcg", threshold=1e-3)
+            o = PR.project(sc.flags, us, vs, sc.dx, dt=dt_o, method="pcg", threshold=1e-3)
             assert abs(res.iters - o["iters"]) <= max(3, 0.1 * o["iters"])
             assert res.e1_final < 1.05e-3
-        assert close_mostly(u.cpu().numpy(), o["u"], 1e-4)
-        assert close_mostly(v.cpu().numpy(), o["v"], 1e-4)
+        uo, vo = o["u"], o["v"]
+        ug, vg = u.cpu().numpy(), v.cpu().numpy()
+        say("  step", step, "dt", res.dt, "iters", res.iters, o["iters"], "within 1e-4: rho",
+            frac_within(rho.cpu().numpy(), ro, 1e-4), "u", frac_within(ug, uo, 1e-4),
+            "v", frac_within(vg, vo, 1e-4), "within 1e-5: u", frac_within(ug, uo, 1e-5))
+        assert close_mostly(rho.cpu().numpy(), ro, 1e-5, frac=0.99)
+        assert close_mostly(ug, uo, tol, frac=0.99)
+        assert close_mostly(vg, vo, tol, frac=0.99)
         assert res.e1_init == pytest.approx(o["e1_init"], rel=1e-2)
-        say("  step", step, "dt", res.dt, "iters", res.iters, "e1_init", res.e1_init)
 
 
 def test_step_bad_arguments():
