@@ -84,14 +84,29 @@ typedef struct hyp_ctx hyp_ctx;
 #define HYP_NET_TRAIN  1  /* keep every layer's activations (and the backward
                              buffers) in the workspace for hyp_project_backward */
 
-/* Multi-scale network shape.  scales in 1..5; channels 16, 32 or 64 with
- * FP32 (64: inference only, HYP_EUNSUPPORTED with HYP_NET_TRAIN), 32 or 64
- * with BF16. */
+/* hyp_net_desc.arch: the network that predicts the initial pressure. */
+#define HYP_ARCH_PARALLEL    0  /* S parallel branches (one per 2x2-mean pyramid
+                                   level) of four 3x3 + ReLU layers and a 1x1
+                                   output, summed coarse to fine after bilinear
+                                   x2 upsampling (Sec. 3.1's multi-scale idea) */
+#define HYP_ARCH_MULTISCALE  1  /* the paper's cascaded MultiScale (Sec. 3.1,
+                                   Fig. 3): branches at n/4, n/2, n of 5, 7, 7
+                                   layers; each coarser output is upsampled x2
+                                   and concatenated to the next branch's input */
+#define HYP_ARCH_SMALLSCALE  2  /* the same cascade with 32 channels (Sec. 3.1's
+                                   SmallScale) */
+
+/* Network shape.  HYP_ARCH_PARALLEL: scales in 1..5; channels 16, 32 or 64
+ * with FP32 (64: inference only, HYP_EUNSUPPORTED with HYP_NET_TRAIN), 32 or
+ * 64 with BF16.  HYP_ARCH_MULTISCALE / SMALLSCALE: scales 3 (or 0), channels
+ * 64 / 32 (or 0), FP32 or BF16, inference only (HYP_NET_TRAIN gives
+ * HYP_EUNSUPPORTED); the grid sides must be multiples of 4. */
 typedef struct {
   int32_t scales;
   int32_t channels;
   int32_t precision;  /* HYP_PREC_* */
   int32_t flags;      /* HYP_NET_* */
+  int32_t arch;       /* HYP_ARCH_* */
 } hyp_net_desc;
 
 typedef struct {
@@ -169,11 +184,20 @@ int hyp_destroy(hyp_ctx* ctx);
 int64_t hyp_param_count(const hyp_ctx* ctx);
 
 /* Point the context at caller-owned FP32 parameters on the device, in the
- * packed layout: for each scale k = 0 (finest) .. S-1, four 3x3 layers as
- * W[Cout][3][3][Cin] then bias[Cout] (Cin = 2 for the first layer: the
- * normalised divergence and the solid mask; C after), then the 1x1 output
- * as w[C] then bias[1].  The buffer is read at every projection and must
- * stay valid; it is never copied.  n_params must equal hyp_param_count. */
+ * packed layout of its architecture.  HYP_ARCH_PARALLEL: for each scale
+ * k = 0 (finest) .. S-1, four 3x3 layers as W[Cout][3][3][Cin] then
+ * bias[Cout] (Cin = 2 for the first layer: the normalised divergence and the
+ * solid mask; C after), then the 1x1 output as w[C] then bias[1].
+ * HYP_ARCH_MULTISCALE / SMALLSCALE (C = 64 / 32): branches from the coarsest
+ * (n/4) to the finest (n), each layer as W[Cout][k][k][Cin] then b[Cout]:
+ *   n/4:      5x5 2->C, 3x3 C->C, 3x3 C->C, 3x3 C->C (linear), 1x1 C->1
+ *   n/2 and n: 5x5 3->C, 3x3 C->C, 3x3 C->32, 3x3 32->C, 3x3 C->C,
+ *             3x3 C->C (linear), 1x1 C->1
+ * with ReLU after every layer but the last two of a branch, and input
+ * channels (normalised divergence, solid mask, upsampled coarser output)
+ * (419,459 and 126,819 parameters).  The buffer is read at every projection
+ * and must stay valid; it is never copied.  n_params must equal
+ * hyp_param_count. */
 int hyp_set_weights(hyp_ctx* ctx, const float* dev_params, int64_t n_params);
 
 /* Workspace bytes for a grid (and the context's network).  The workspace

@@ -48,19 +48,24 @@ class Projector:
 
     def __init__(self, nx: int, ny: int, dx: float, dt: float = 1.0, rho0: float = 1.0,
                  scales: int = 0, channels: int = 0, precision: str = "fp32", device=None,
-                 train: bool = False):
+                 train: bool = False, arch: str = "parallel"):
         self.lib = L.lib()
         self.nx, self.ny = int(nx), int(ny)
         self.grid = L.Grid(self.nx, self.ny, float(dx), float(dt), float(rho0))
         self.device = torch.device("cuda" if device is None else device)
         ctx = ctypes.c_void_p()
         desc = None
+        if arch not in L.ARCHS:
+            raise ValueError(f"arch must be one of {sorted(L.ARCHS)}")
+        if arch != "parallel":
+            scales = 3  # the cascaded networks have three branches
         if scales > 0:
             desc = L.NetDesc(int(scales), int(channels), L.PRECISIONS[precision],
-                             L.NET_TRAIN if train else 0)
+                             L.NET_TRAIN if train else 0, L.ARCHS[arch])
         L.check("hyp_create", self.lib.hyp_create(ctypes.byref(ctx), ctypes.byref(desc) if desc else None))
         self.ctx = ctx
         self.scales, self.channels, self.precision = scales, channels, precision
+        self.arch = arch
         nbytes = ctypes.c_size_t()
         L.check("hyp_workspace_size",
                 self.lib.hyp_workspace_size(self.ctx, ctypes.byref(self.grid), ctypes.byref(nbytes)))

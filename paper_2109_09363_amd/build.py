@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhyproj.so")
-SOURCES = ["api.hip", "stencil.hip", "solvers.hip", "cnn.hip", "advect.hip", "backward.hip", "batched.hip"]
+SOURCES = ["api.hip", "stencil.hip", "solvers.hip", "cnn.hip", "advect.hip", "backward.hip", "batched.hip",
+           "papernets.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

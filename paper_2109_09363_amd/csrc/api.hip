@@ -65,7 +65,8 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
     }
     L.total_px = px;
     const size_t act_elt = net.precision == HYP_PREC_BF16 ? 2 : 4;
-    L.cnn_in = take(px * 2 * act_elt);
+    // the cascaded networks feed 3 input channels to the finest branch
+    L.cnn_in = take((net.arch == HYP_ARCH_PARALLEL ? px * 2 : n * 3) * act_elt);
     L.cnn_act0 = take(px * net.channels * act_elt);
     L.cnn_act1 = take(px * net.channels * act_elt);
     L.cnn_y = take(px * 4);
@@ -153,7 +154,20 @@ int hyp_create(hyp_ctx** out, const hyp_net_desc* net) {
   if (!out) return HYP_EINVAL;
   *out = nullptr;
   NetShape ns;
-  if (net) {
+  if (net && (net->arch == HYP_ARCH_MULTISCALE || net->arch == HYP_ARCH_SMALLSCALE)) {
+    // the paper's cascaded networks: 3 scales, fixed widths, inference only
+    const int C = net->arch == HYP_ARCH_MULTISCALE ? 64 : 32;
+    if ((net->scales != 0 && net->scales != 3) || (net->channels != 0 && net->channels != C))
+      return HYP_EINVAL;
+    if (net->precision != HYP_PREC_FP32 && net->precision != HYP_PREC_BF16) return HYP_EINVAL;
+    if (net->flags & ~HYP_NET_TRAIN) return HYP_EINVAL;
+    if (net->flags & HYP_NET_TRAIN) return HYP_EUNSUPPORTED;
+    ns.scales = 3;
+    ns.channels = C;
+    ns.precision = net->precision;
+    ns.arch = net->arch;
+  } else if (net) {
+    if (net->arch != HYP_ARCH_PARALLEL) return HYP_EINVAL;
     if (net->scales < 1 || net->scales > 5) return HYP_EINVAL;
     if (net->precision == HYP_PREC_FP32) {
       if (net->channels != 16 && net->channels != 32 && net->channels != 64) return HYP_EINVAL;
@@ -222,6 +236,7 @@ int hyp_get_timing(hyp_ctx* ctx, float* ms) {
 
 int64_t hyp_param_count(const hyp_ctx* ctx) {
   if (!ctx || ctx->net.scales == 0) return 0;
+  if (ctx->net.arch != HYP_ARCH_PARALLEL) return pn_param_count(ctx->net.arch);
   return cnn_param_count(ctx->net.scales, ctx->net.channels);
 }
 

@@ -1,0 +1,317 @@
+// k x k convolution with replicated edges, bias and optional ReLU as an
+// implicit GEMM on MFMA (the convolution layers of Sec. 3.1's networks):
+//   D[cout][px] = b[cout] + sum_k W[cout][k] X[k][px],  k = (tap, cin).
+// One template serves both precisions: FP32 storage with
+// v_mfma_f32_16x16x4f32, and BF16 storage with the gfx950
+// v_mfma_f32_16x16x32_bf16 (FP32 accumulation).  Activations are NHWC so a
+// lane's K-fragment is 16 contiguous bytes in LDS; inputs of 2 or 3
+// channels (the network inputs) are gathered element by element instead.
+// A work-group of 4 waves computes 16x16-pixel tiles; every scale of a
+// layer can run in one launch over a concatenated tile list.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace hyp {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  // round to nearest even (finite inputs)
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <typename T> struct St;
+template <> struct St<float> {
+  static __device__ __forceinline__ float from(float f) { return f; }
+  static __device__ __forceinline__ float to_f(float x) { return x; }
+};
+template <> struct St<uint16_t> {
+  static __device__ __forceinline__ uint16_t from(float f) { return f2bf(f); }
+  static __device__ __forceinline__ float to_f(uint16_t x) { return bf2f(x); }
+};
+
+constexpr int kMaxScales = 5;
+constexpr int TW = 16;  // tile width (pixels)
+constexpr int TH = 16;  // tile height: 4 waves x 4 rows
+
+struct ScaleDesc {
+  const void* in;     // NHWC input activations (storage type)
+  void* out;          // NHWC output activations
+  const void* wimg;   // weights as the LDS image: [Cout][WSTR] storage type, zero-padded K
+  const float* b;     // FP32 bias [Cout]
+  int H, W;
+  int tiles_x, tile0; // tile columns, first global tile index of this scale
+};
+
+struct ConvLaunch {
+  ScaleDesc sc[kMaxScales];
+  int nscales, total_tiles, tiles_per_wg;
+};
+
+// K step of one MFMA fragment and the padded weight row, shared by the
+// kernels and the host code that writes weight images.
+__host__ __device__ constexpr int conv_kstep(int elt) { return elt == 4 ? 16 : 32; }
+__host__ __device__ constexpr int conv_wstr(int elt, int ks, int cin) {
+  return ((ks * ks * cin + conv_kstep(elt) - 1) / conv_kstep(elt)) * conv_kstep(elt) + 16 / elt;
+}
+
+template <typename T, int KS, int CIN, int COUT>
+struct ConvGeom {
+  static constexpr int ELT = sizeof(T);
+  static constexpr bool SMALL = CIN < 8;                      // gathered input channels
+  static constexpr int KSTEP = conv_kstep(ELT);               // K per fragment step
+  static constexpr int HALO = KS / 2;
+  static constexpr int EW = TW + KS - 1, EH = TH + KS - 1;    // input tile with halo
+  static constexpr int KTOT = KS * KS * CIN;
+  static constexpr int KPAD = ((KTOT + KSTEP - 1) / KSTEP) * KSTEP;
+  static constexpr int WSTR = conv_wstr(ELT, KS, CIN);        // LDS weight row stride (elts)
+  static constexpr int PSTR = SMALL ? CIN : CIN + 16 / ELT;   // LDS pixel stride (elts)
+  static constexpr size_t TILE_LDS = (((size_t)EH * EW * PSTR * ELT + 15) / 16) * 16;
+  // output channels per pass: all of them unless their weights and the
+  // input tile overflow the 160 KB of LDS (FP32 64 -> 64: 16 per pass)
+  static constexpr int CT = ((size_t)COUT * WSTR * ELT + TILE_LDS <= 160 * 1024) ? COUT : 16;
+  static constexpr int PASSES = COUT / CT;
+  static constexpr int MB = CT / 16;                          // cout blocks per pass
+  static constexpr size_t LDS = (size_t)CT * WSTR * ELT + TILE_LDS;
+  static_assert(COUT % 16 == 0, "output channels in blocks of 16");
+  static_assert(SMALL || CIN % KSTEP == 0, "input channels in whole K fragments");
+  static_assert(KS % 2 == 1, "odd kernel size");
+  static_assert(LDS <= 160 * 1024, "tile and weights fit the LDS of a CU");
+};
+
+// Fragment loads.  FP32: a lane holds 4 consecutive K values (one float4) and
+// feeds them to 4 MFMAs; BF16: 8 consecutive K values (16 bytes) for one MFMA.
+template <typename T, int KS, int CIN, int COUT>
+__device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __restrict__ xl,
+                                          floatx4 (&acc)[ConvGeom<T, KS, CIN, COUT>::MB][4],
+                                          int wave, int lane) {
+  using Gm = ConvGeom<T, KS, CIN, COUT>;
+  constexpr int EW = Gm::EW;
+  const int col = lane & 15, g = lane >> 4;
+  if constexpr (Gm::SMALL) {
+    // K = KS*KS*CIN (tap, cin) gathered per element, zero-padded to KPAD
+    for (int k0 = 0; k0 < Gm::KPAD; k0 += Gm::KSTEP) {
+      constexpr int PER = (sizeof(T) == 4) ? 4 : 8;
+      T bv[4][PER];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int row = wave * 4 + nb;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int k = k0 + g * PER + e;
+          T val = St<T>::from(0.f);
+          if (k < Gm::KTOT) {
+            const int tap = k / CIN, ci = k % CIN;
+            val = xl[((row + tap / KS) * EW + col + tap % KS) * Gm::PSTR + ci];
+          }
+          bv[nb][e] = val;
+        }
+      }
+#pragma unroll
+      for (int mb = 0; mb < Gm::MB; ++mb) {
+        const T* wrow = wl + (mb * 16 + col) * Gm::WSTR + k0 + g * PER;
+        if constexpr (sizeof(T) == 4) {
+          const float4 a = *reinterpret_cast<const float4*>(wrow);
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) {
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bv[nb][0], acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bv[nb][1], acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bv[nb][2], acc[mb][nb], 0, 0, 0);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bv[nb][3], acc[mb][nb], 0, 0, 0);
+          }
+        } else {
+          const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wrow));
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) {
+            uint4 raw;
+            uint16_t* r16 = reinterpret_cast<uint16_t*>(&raw);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) r16[e] = bv[nb][e];
+            const bf16x8 b = __builtin_bit_cast(bf16x8, raw);
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mb][nb], 0, 0, 0);
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int tap = 0; tap < KS * KS; ++tap) {
+      const int ky = tap / KS, kx = tap % KS;
+#pragma unroll
+      for (int c0 = 0; c0 < CIN; c0 += Gm::KSTEP) {
+        const int k0 = tap * CIN + c0;
+        if constexpr (sizeof(T) == 4) {
+          float4 bv[4];
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) {
+            const int row = wave * 4 + nb;
+            bv[nb] = *reinterpret_cast<const float4*>(
+                xl + ((row + ky) * EW + col + kx) * Gm::PSTR + c0 + g * 4);
+          }
+#pragma unroll
+          for (int mb = 0; mb < Gm::MB; ++mb) {
+            const float4 a = *reinterpret_cast<const float4*>(wl + (mb * 16 + col) * Gm::WSTR + k0 + g * 4);
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bv[nb].x, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bv[nb].y, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bv[nb].z, acc[mb][nb], 0, 0, 0);
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bv[nb].w, acc[mb][nb], 0, 0, 0);
+            }
+          }
+        } else {
+          bf16x8 bv[4];
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) {
+            const int row = wave * 4 + nb;
+            bv[nb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                xl + ((row + ky) * EW + col + kx) * Gm::PSTR + c0 + g * 8));
+          }
+#pragma unroll
+          for (int mb = 0; mb < Gm::MB; ++mb) {
+            const bf16x8 a = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const uint4*>(wl + (mb * 16 + col) * Gm::WSTR + k0 + g * 8));
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv[nb], acc[mb][nb], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int KS, int CIN, int COUT, bool RELU>
+__global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
+  using Gm = ConvGeom<T, KS, CIN, COUT>;
+  constexpr int EW = Gm::EW, EH = Gm::EH, HALO = Gm::HALO;
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  T* wl = reinterpret_cast<T*>(lds_raw);
+  T* xl = wl + Gm::CT * Gm::WSTR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t_begin = blockIdx.x * L.tiles_per_wg;
+  const int t_end = min(t_begin + L.tiles_per_wg, L.total_tiles);
+  int cur = -1;
+  // copy cout rows [co0, co0 + CT) of the layer's weight image into LDS with
+  // 16-byte loads, several in flight per thread
+  auto load_weights = [&](const void* img, int co0) {
+    __syncthreads();
+    constexpr int N16 = Gm::CT * Gm::WSTR * Gm::ELT / 16;
+    const uint4* src = reinterpret_cast<const uint4*>(img) + (size_t)co0 * Gm::WSTR * Gm::ELT / 16;
+    uint4* dstl = reinterpret_cast<uint4*>(wl);
+#pragma unroll 8
+    for (int e = threadIdx.x; e < N16; e += 256) dstl[e] = src[e];
+  };
+  for (int t = t_begin; t < t_end; ++t) {
+    int k = 0;
+    while (k + 1 < L.nscales && t >= L.sc[k + 1].tile0) ++k;
+    const ScaleDesc& S = L.sc[k];
+    if (Gm::PASSES == 1 && k != cur) {
+      load_weights(S.wimg, 0);
+      cur = k;
+    }
+    const int lt = t - S.tile0;
+    const int x0 = (lt % S.tiles_x) * TW, y0 = (lt / S.tiles_x) * TH;
+    const T* in = reinterpret_cast<const T*>(S.in);
+    // input tile with a HALO-pixel replicated border (coordinates clamped)
+    if constexpr (Gm::SMALL) {
+      for (int e = threadIdx.x; e < EH * EW; e += blockDim.x) {
+        const int gy = min(max(y0 - HALO + e / EW, 0), S.H - 1);
+        const int gx = min(max(x0 - HALO + e % EW, 0), S.W - 1);
+        const T* src = in + ((size_t)gy * S.W + gx) * CIN;
+#pragma unroll
+        for (int c = 0; c < CIN; ++c) xl[e * Gm::PSTR + c] = src[c];
+      }
+    } else {
+      constexpr int CH = CIN * sizeof(T) / 16;  // 16-byte chunks per pixel
+#pragma unroll 4
+      for (int e = threadIdx.x; e < EH * EW * CH; e += blockDim.x) {
+        const int pix = e / CH, ch = e % CH;
+        const int gy = min(max(y0 - HALO + pix / EW, 0), S.H - 1);
+        const int gx = min(max(x0 - HALO + pix % EW, 0), S.W - 1);
+        const uint4 v = *reinterpret_cast<const uint4*>(
+            reinterpret_cast<const char*>(in + ((size_t)gy * S.W + gx) * CIN) + ch * 16);
+        *reinterpret_cast<uint4*>(reinterpret_cast<char*>(xl + pix * Gm::PSTR) + ch * 16) = v;
+      }
+    }
+    const int col = lane & 15, g = lane >> 4;
+    T* out = reinterpret_cast<T*>(S.out);
+    for (int pass = 0; pass < Gm::PASSES; ++pass) {
+      if (Gm::PASSES > 1) load_weights(S.wimg, pass * Gm::CT);
+      __syncthreads();
+      floatx4 acc[Gm::MB][4];
+#pragma unroll
+      for (int mb = 0; mb < Gm::MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+      conv_tile<T, KS, CIN, COUT>(wl, xl, acc, wave, lane);
+      // epilogue: bias (+ ReLU); lane holds couts 4g..4g+3 of block mb for pixel col
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int gy = y0 + wave * 4 + nb, gx = x0 + col;
+        if (gy >= S.H || gx >= S.W) continue;
+        T* dst = out + ((size_t)gy * S.W + gx) * COUT;
+#pragma unroll
+        for (int mb = 0; mb < Gm::MB; ++mb) {
+          const int co = pass * Gm::CT + mb * 16 + g * 4;
+          float v0 = acc[mb][nb][0] + S.b[co + 0];
+          float v1 = acc[mb][nb][1] + S.b[co + 1];
+          float v2 = acc[mb][nb][2] + S.b[co + 2];
+          float v3 = acc[mb][nb][3] + S.b[co + 3];
+          if constexpr (RELU) {
+            v0 = fmaxf(v0, 0.f);
+            v1 = fmaxf(v1, 0.f);
+            v2 = fmaxf(v2, 0.f);
+            v3 = fmaxf(v3, 0.f);
+          }
+          if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4*>(dst + co) = make_float4(v0, v1, v2, v3);
+          } else {
+            uint2 pk;
+            pk.x = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+            pk.y = (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16);
+            *reinterpret_cast<uint2*>(dst + co) = pk;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One element of a layer's weight image: row co, column kk of the
+// [Cout][WSTR] LDS layout (storage type, K zero-padded) from the packed
+// FP32 weights W[Cout][KS][KS][Cin].
+template <typename T, int KS, int CIN, int COUT>
+__device__ __forceinline__ void write_wimg(const float* __restrict__ w, T* __restrict__ img, int e) {
+  using Gm = ConvGeom<T, KS, CIN, COUT>;
+  const int co = e / Gm::WSTR, kk = e % Gm::WSTR;
+  const float v = kk < Gm::KTOT ? w[co * Gm::KTOT + kk] : 0.f;
+  img[e] = St<T>::from(v);
+}
+
+// Launch one layer over the tile list of L on stream s (grid: up to 2
+// work-groups per CU, whole tiles per work-group).
+template <typename T, int KS, int CIN, int COUT, bool RELU>
+hipError_t launch_conv(ConvLaunch& L, int cu, hipStream_t s) {
+  using Gm = ConvGeom<T, KS, CIN, COUT>;
+  hipError_t e = hipFuncSetAttribute((const void*)conv_mfma<T, KS, CIN, COUT, RELU>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)Gm::LDS);
+  if (e != hipSuccess) return e;
+  const int tiles = L.total_tiles;
+  if (tiles <= 0) return hipSuccess;
+  const int G = min(tiles, cu * 2);
+  L.tiles_per_wg = (tiles + G - 1) / G;
+  const int nwg = (tiles + L.tiles_per_wg - 1) / L.tiles_per_wg;
+  hipLaunchKernelGGL((conv_mfma<T, KS, CIN, COUT, RELU>), dim3(nwg), dim3(256), Gm::LDS, s, L);
+  return hipGetLastError();
+}
+
+}  // namespace hyp

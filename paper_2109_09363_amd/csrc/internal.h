@@ -38,6 +38,7 @@ constexpr int kStreamBlock = 256;      // threads of the streaming kernels
 
 struct NetShape {
   int scales = 0, channels = 0, precision = 0;
+  int arch = 0;        // HYP_ARCH_*
   bool train = false;  // keep every layer's activations for the backward pass
 };
 
@@ -127,6 +128,10 @@ hipError_t batch_setup(void* area, int ninst, const int* nx, const int* ny, cons
 hipError_t run_jacobi_batch(const Device& dev, void* area, int ninst, int ntiles, bool cooperative,
                             hipStream_t s);
 size_t cnn_weight_image_bytes(const NetShape& net);
+int64_t pn_param_count(int arch);
+size_t pn_weight_image_bytes(const NetShape& net);
+hipError_t run_papernet(const Device& dev, const NetShape& net, const WsLayout& L, int nx, int ny,
+                        double dx, const float* params, const Ws& w, hipStream_t s);
 hipError_t run_cnn(const Device& dev, const NetShape& net, const WsLayout& L, int nx, int ny,
                    double dx, const float* params, const Ws& w, hipStream_t s);
 

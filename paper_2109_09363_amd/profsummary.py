@@ -24,18 +24,20 @@ import sqlite3
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
-    "jacobi_reg": ["csrc/solvers.hip", "csrc/common.h"],
+    "jacobi_reg": ["csrc/solvers.hip", "csrc/common.h", "csrc/jacobi_rows.h", "csrc/tile_table.h"],
     "pcg_reg": ["csrc/solvers.hip", "csrc/common.h"],
-    "conv3x3_relu": ["csrc/cnn.hip", "csrc/common.h"],
-    "jacobi_batch": ["csrc/batched.hip", "csrc/common.h"],
+    "conv_mfma": ["csrc/conv_mfma.h", "csrc/cnn.hip", "csrc/papernets.hip"],
+    "jacobi_batch": ["csrc/batched.hip", "csrc/common.h", "csrc/jacobi_rows.h"],
 }
 
 
 def source_hash(kernel: str) -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES.get(kernel, []):
-        with open(os.path.join(PKG, rel), "rb") as f:
-            h.update(f.read())
+        path = os.path.join(PKG, rel)
+        if os.path.exists(path):
+            with open(path, "rb") as f:
+                h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -12,9 +12,9 @@ def to_dev(a, dtype=torch.float32):
 
 
 def gpu_project(flags, u, v, dx, thr, method="jacobi", dt=1.0, rho0=1.0, params=None,
-                scales=0, channels=0, precision="fp32", p_init=None, **opts):
+                scales=0, channels=0, precision="fp32", p_init=None, arch="parallel", **opts):
     ny, nx = flags.shape
-    pr = hp.Projector(nx, ny, dx, dt, rho0, scales, channels, precision)
+    pr = hp.Projector(nx, ny, dx, dt, rho0, scales, channels, precision, arch=arch)
     tf = to_dev(flags, torch.uint8)
     pr.plan(tf)
     if params is not None:
