@@ -1,6 +1,7 @@
 """Oracle: the paper's cascaded MultiScale network and its SmallScale variant
-(Sec. 3.1, Fig. 3), as the initial guess of the pressure.  Plain FP64
-(optionally emulating BF16 storage).  TEST INFRASTRUCTURE ONLY.
+(Sec. 3.1, Fig. 3) and its Unet (Sec. 3.1, Fig. 4), as the initial guess of
+the pressure.  Plain FP64 (optionally emulating BF16 storage).  TEST
+INFRASTRUCTURE ONLY.
 
 What the paper fixes (Sec. 3.1 and the Fig. 3 caption): three scales of
 n/4, n/2 and n pixels a side; the coarsest scale sees the input
@@ -42,6 +43,28 @@ from .cnn import bf16_round, up2
 
 ARCHS = ("multiscale", "smallscale")
 
+# Unet (Sec. 3.1, Fig. 4, whose widths are missing): five scales n .. n/16;
+# per scale two 3x3 convolutions with ReLU on the way down, 2x2 max pooling
+# between scales; on the way up, bilinear x2 upsampling, concatenation with
+# the same scale's encoder output (skip first, then the upsampled map) and two
+# 3x3 convolutions with ReLU; a linear 1x1 convolution to one channel.
+# Widths (16, 16, 64, 64, 64) give 443,441 parameters (the paper: 443,521).
+UNET_WIDTHS = (16, 16, 64, 64, 64)
+
+
+def unet_layers():
+    """(k, cin, cout, relu) in parameter order: encoder scales 0..4 (two
+    layers each), decoder scales 3..0 (two layers each), output layer."""
+    w = UNET_WIDTHS
+    L, cin = [], 2
+    for wl in w:
+        L += [(3, cin, wl, True), (3, wl, wl, True)]
+        cin = wl
+    for l in range(len(w) - 2, -1, -1):
+        L += [(3, w[l] + w[l + 1], w[l], True), (3, w[l], w[l], True)]
+    L.append((1, w[0], 1, False))
+    return L
+
 
 def branches(arch: str):
     """Per branch (coarse to fine): list of (k, cin, cout, relu)."""
@@ -59,6 +82,8 @@ def branches(arch: str):
 
 
 def param_count(arch: str) -> int:
+    if arch == "unet":
+        return sum(k * k * ci * co + co for (k, ci, co, _r) in unet_layers())
     return sum(k * k * ci * co + co for br in branches(arch) for (k, ci, co, _r) in br)
 
 
@@ -140,3 +165,56 @@ def phi0(P: G.Plan, d: np.ndarray, dx: float, params, arch: str, bf16: bool = Fa
         y = h[:, :, 0]
         ys.append(y)
     return np.where(P.fluid, dx * dx * s * y, 0.0), s, ys
+
+
+def maxpool2(x: np.ndarray) -> np.ndarray:
+    """2x2 max pooling, stride 2."""
+    return np.maximum(np.maximum(x[0::2, 0::2], x[1::2, 0::2]), np.maximum(x[0::2, 1::2], x[1::2, 1::2]))
+
+
+def up2c(t: np.ndarray) -> np.ndarray:
+    """Bilinear x2 of every channel of an (H, W, C) map (as ``up2``)."""
+    return np.stack([up2(t[:, :, c]) for c in range(t.shape[2])], axis=-1)
+
+
+def unet_phi0(P: G.Plan, d: np.ndarray, dx: float, params, bf16: bool = False):
+    """Returns (phi0, s).  ``bf16`` rounds the 3x3 weights, each 3x3 layer's
+    input and output to bfloat16 (the GPU's storage points); max pooling and
+    upsampling act on stored (rounded) maps and their results are stored
+    again; the 1x1 output layer has FP64 weights."""
+    ny, nx = P.shape
+    assert ny % 16 == 0 and nx % 16 == 0
+    params = np.asarray(params, dtype=np.float64)
+    assert params.size == param_count("unet")
+    layers, o = [], 0
+    for (k, ci, co, relu) in unet_layers():
+        W = params[o:o + co * k * k * ci].reshape(co, k, k, ci); o += co * k * k * ci
+        b = params[o:o + co]; o += co
+        layers.append((W, b, relu))
+    sumsq = float(np.sum(np.where(P.fluid, d, 0.0) ** 2))
+    s = np.sqrt(sumsq / P.nF) if P.nF > 0 else 0.0
+    if s == 0.0:
+        return np.zeros(P.shape), 0.0
+    rnd = bf16_round if bf16 else (lambda a: a)
+
+    def conv(h, i):
+        W, b, relu = layers[i]
+        out = conv_replicate(rnd(h), rnd(W), b)
+        return rnd(np.maximum(out, 0.0) if relu else out)
+
+    h = np.stack([np.where(P.fluid, d / s, 0.0), (~P.fluid).astype(np.float64)], axis=-1)
+    skips, li = [], 0
+    nlev = len(UNET_WIDTHS)
+    for lev in range(nlev):
+        h = conv(conv(h, li), li + 1)
+        li += 2
+        if lev < nlev - 1:
+            skips.append(h)
+            h = maxpool2(h)
+    for lev in range(nlev - 2, -1, -1):
+        h = np.concatenate([skips[lev], rnd(up2c(h))], axis=-1)
+        h = conv(conv(h, li), li + 1)
+        li += 2
+    W, b, _ = layers[li]
+    y = conv_replicate(h, W, b)[:, :, 0]
+    return np.where(P.fluid, dx * dx * s * y, 0.0), s

@@ -200,6 +200,15 @@ def zero_weights(scales: int, channels: int) -> np.ndarray:
 # per layer, branches from the coarsest to the finest (used only to size the
 # random initialisation below).
 def paper_net_layers(arch: str):
+    if arch == "unet":  # one "branch": encoder, decoder, output layer
+        w = (16, 16, 64, 64, 64)
+        L, cin = [], 2
+        for wl in w:
+            L += [(3, cin, wl), (3, wl, wl)]
+            cin = wl
+        for l in range(3, -1, -1):
+            L += [(3, w[l] + w[l + 1], w[l]), (3, w[l], w[l])]
+        return [L + [(1, w[0], 1)]]
     a, mid = {"multiscale": (64, 32), "smallscale": (32, 32)}[arch]
     coarse = [(5, 2, a), (3, a, a), (3, a, a), (3, a, a), (1, a, 1)]
     finer = [(5, 3, a), (3, a, a), (3, a, mid), (3, mid, a), (3, a, a), (3, a, a), (1, a, 1)]

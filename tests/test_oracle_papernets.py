@@ -108,3 +108,69 @@ def test_scale_invariance_and_solids():
     assert np.allclose(b, 7.0 * a, rtol=1e-12, atol=1e-15)
     assert np.all(a[~P.fluid] == 0.0)
     assert PN.phi0(P, np.zeros_like(d), sc.dx, w, "smallscale")[1] == 0.0
+
+
+def test_unet_parameter_total_and_pooling():
+    # Fig. 4 caption: 443,521 parameters
+    assert PN.param_count("unet") == 443441
+    assert abs(PN.param_count("unet") - 443521) / 443521 < 3e-4
+    assert scenes.random_paper_weights("unet", 0).size == 443441
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((12, 20, 5))
+    ref = F.max_pool2d(torch.from_numpy(x).permute(2, 0, 1)[None], 2)[0].permute(1, 2, 0).numpy()
+    assert np.array_equal(PN.maxpool2(x), ref)
+    ref = F.interpolate(torch.from_numpy(x).permute(2, 0, 1)[None], scale_factor=2, mode="bilinear",
+                        align_corners=False)[0].permute(1, 2, 0).numpy()
+    assert np.allclose(PN.up2c(x), ref, rtol=0, atol=1e-14)
+
+
+def torch_unet(d, solid, fluid, dx, params):
+    """The Unet of Sec. 3.1 with PyTorch CPU modules: two 3x3 + ReLU per
+    scale, max pooling down, bilinear x2 up, skip concatenated before the
+    upsampled map, linear 1x1 output."""
+    s = float(np.sqrt(np.sum(d[fluid] ** 2) / fluid.sum()))
+    h = torch.from_numpy(np.stack([np.where(fluid, d / s, 0.0), solid.astype(np.float64)]))[None]
+    p = torch.from_numpy(np.asarray(params, np.float64))
+    shapes = scenes.paper_net_layers("unet")[0]
+    o = [0]
+
+    def layer(h, i, relu=True):
+        k, ci, co = shapes[i]
+        W = p[o[0]:o[0] + co * k * k * ci].reshape(co, k, k, ci).permute(0, 3, 1, 2)
+        o[0] += co * k * k * ci
+        b = p[o[0]:o[0] + co]
+        o[0] += co
+        out = F.conv2d(F.pad(h, (k // 2,) * 4, mode="replicate"), W, b)
+        return torch.relu(out) if relu else out
+
+    skips, i = [], 0
+    for lev in range(5):
+        h = layer(layer(h, i), i + 1)
+        i += 2
+        if lev < 4:
+            skips.append(h)
+            h = F.max_pool2d(h, 2)
+    for lev in range(3, -1, -1):
+        up = F.interpolate(h, scale_factor=2, mode="bilinear", align_corners=False)
+        h = torch.cat([skips[lev], up], dim=1)
+        h = layer(layer(h, i), i + 1)
+        i += 2
+    y = layer(h, i, relu=False)
+    assert o[0] == p.numel()
+    return np.where(fluid, dx * dx * s * y[0, 0].numpy(), 0.0)
+
+
+@pytest.mark.parametrize("n,seed", [(32, 0), (48, 1)])
+def test_unet_matches_torch_rendering(n, seed):
+    sc = scenes.plume_scene(n, seed=seed, n_obstacles=1)
+    P = G.plan(sc.flags)
+    u, v = scenes.random_faces(n, n, seed, kind="mixed")
+    d = G.divergence(P, *G.enforce_bc(P, u, v), sc.dx)
+    w = scenes.random_paper_weights("unet", seed)
+    phi, s = PN.unet_phi0(P, d, sc.dx, w)
+    ref = torch_unet(d, ~P.fluid, P.fluid, sc.dx, w)
+    assert np.abs(phi).max() > 0
+    assert np.allclose(phi, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+    # linear in the scale of d
+    phi7, _ = PN.unet_phi0(P, 7.0 * d, sc.dx, w)
+    assert np.allclose(phi7, 7.0 * phi, rtol=1e-12, atol=1e-15)
