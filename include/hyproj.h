@@ -95,12 +95,17 @@ typedef struct hyp_ctx hyp_ctx;
                                    and concatenated to the next branch's input */
 #define HYP_ARCH_SMALLSCALE  2  /* the same cascade with 32 channels (Sec. 3.1's
                                    SmallScale) */
+#define HYP_ARCH_UNET        3  /* the paper's Unet (Sec. 3.1, Fig. 4): scales
+                                   n .. n/16, max pooling down, bilinear x2 up,
+                                   skip concatenation */
 
 /* Network shape.  HYP_ARCH_PARALLEL: scales in 1..5; channels 16, 32 or 64
  * with FP32 (64: inference only, HYP_EUNSUPPORTED with HYP_NET_TRAIN), 32 or
  * 64 with BF16.  HYP_ARCH_MULTISCALE / SMALLSCALE: scales 3 (or 0), channels
  * 64 / 32 (or 0), FP32 or BF16, inference only (HYP_NET_TRAIN gives
- * HYP_EUNSUPPORTED); the grid sides must be multiples of 4. */
+ * HYP_EUNSUPPORTED); the grid sides must be multiples of 4.  HYP_ARCH_UNET:
+ * scales 5 (or 0), channels 64 (or 0), FP32 or BF16, inference only; grid
+ * sides multiples of 16. */
 typedef struct {
   int32_t scales;
   int32_t channels;
@@ -195,7 +200,12 @@ int64_t hyp_param_count(const hyp_ctx* ctx);
  *             3x3 C->C (linear), 1x1 C->1
  * with ReLU after every layer but the last two of a branch, and input
  * channels (normalised divergence, solid mask, upsampled coarser output)
- * (419,459 and 126,819 parameters).  The buffer is read at every projection
+ * (419,459 and 126,819 parameters).  HYP_ARCH_UNET (widths w = 16, 16, 64,
+ * 64, 64 at scales 0..4), each layer as W[Cout][3][3][Cin] then b[Cout]:
+ * encoder scales l = 0..4: 3x3 Cin->w[l], 3x3 w[l]->w[l] (Cin = 2, then
+ * w[l-1]); decoder scales l = 3..0: 3x3 (w[l] + w[l+1])->w[l] on the skip
+ * channels followed by the upsampled ones, 3x3 w[l]->w[l]; then the 1x1
+ * output w[0]->1; ReLU on all but the output (443,441 parameters).  The buffer is read at every projection
  * and must stay valid; it is never copied.  n_params must equal
  * hyp_param_count. */
 int hyp_set_weights(hyp_ctx* ctx, const float* dev_params, int64_t n_params);

@@ -58,7 +58,7 @@ class Projector:
         if arch not in L.ARCHS:
             raise ValueError(f"arch must be one of {sorted(L.ARCHS)}")
         if arch != "parallel":
-            scales = 3  # the cascaded networks have three branches
+            scales = 5 if arch == "unet" else 3  # the paper's networks: fixed scales
         if scales > 0:
             desc = L.NetDesc(int(scales), int(channels), L.PRECISIONS[precision],
                              L.NET_TRAIN if train else 0, L.ARCHS[arch])

@@ -72,6 +72,7 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
     L.cnn_y = take(px * 4);
     L.cnn_t = take(px * 4);
     L.cnn_w = take(cnn_weight_image_bytes(net));
+    if (net.arch == HYP_ARCH_UNET) L.cnn_cat = take(unet_cat_elems(nx, ny) * act_elt);
     if (net.train) {
       const size_t C = net.channels;
       L.cnn_save = take(4 * px * C * act_elt);
@@ -110,6 +111,7 @@ Ws ws_view(void* base, const WsLayout& L) {
   w.cnn_y = L.cnn_y ? (float*)(b + L.cnn_y) : nullptr;
   w.cnn_t = L.cnn_t ? (float*)(b + L.cnn_t) : nullptr;
   w.cnn_w = L.cnn_w ? b + L.cnn_w : nullptr;
+  w.cnn_cat = L.cnn_cat ? b + L.cnn_cat : nullptr;
   w.cnn_save = L.cnn_save ? b + L.cnn_save : nullptr;
   w.bw_cells = L.bw_cells ? (float*)(b + L.bw_cells) : nullptr;
   w.bw_t = L.bw_t ? (float*)(b + L.bw_t) : nullptr;
@@ -154,15 +156,17 @@ int hyp_create(hyp_ctx** out, const hyp_net_desc* net) {
   if (!out) return HYP_EINVAL;
   *out = nullptr;
   NetShape ns;
-  if (net && (net->arch == HYP_ARCH_MULTISCALE || net->arch == HYP_ARCH_SMALLSCALE)) {
-    // the paper's cascaded networks: 3 scales, fixed widths, inference only
-    const int C = net->arch == HYP_ARCH_MULTISCALE ? 64 : 32;
-    if ((net->scales != 0 && net->scales != 3) || (net->channels != 0 && net->channels != C))
+  if (net && (net->arch == HYP_ARCH_MULTISCALE || net->arch == HYP_ARCH_SMALLSCALE ||
+              net->arch == HYP_ARCH_UNET)) {
+    // the paper's networks: fixed scales and widths, inference only
+    const int S = net->arch == HYP_ARCH_UNET ? 5 : 3;
+    const int C = net->arch == HYP_ARCH_SMALLSCALE ? 32 : 64;
+    if ((net->scales != 0 && net->scales != S) || (net->channels != 0 && net->channels != C))
       return HYP_EINVAL;
     if (net->precision != HYP_PREC_FP32 && net->precision != HYP_PREC_BF16) return HYP_EINVAL;
     if (net->flags & ~HYP_NET_TRAIN) return HYP_EINVAL;
     if (net->flags & HYP_NET_TRAIN) return HYP_EUNSUPPORTED;
-    ns.scales = 3;
+    ns.scales = S;
     ns.channels = C;
     ns.precision = net->precision;
     ns.arch = net->arch;

@@ -206,6 +206,7 @@ static hipError_t run_cnn_t(const Device& dev, const NetShape& net, const WsLayo
       D.W = Ly.sc_w[k];
       D.tiles_x = (D.W + TW - 1) / TW;
       D.tile0 = tiles;
+      D.ostr = C;
       tiles += D.tiles_x * ((D.H + TH - 1) / TH);
     }
     L.total_tiles = tiles;

@@ -3,9 +3,10 @@
 //   D[cout][px] = b[cout] + sum_k W[cout][k] X[k][px],  k = (tap, cin).
 // One template serves both precisions: FP32 storage with
 // v_mfma_f32_16x16x4f32, and BF16 storage with the gfx950
-// v_mfma_f32_16x16x32_bf16 (FP32 accumulation).  Activations are NHWC so a
-// lane's K-fragment is 16 contiguous bytes in LDS; inputs of 2 or 3
-// channels (the network inputs) are gathered element by element instead.
+// v_mfma_f32_16x16x32_bf16, or v_mfma_f32_16x16x16_bf16 where the input
+// width is a multiple of 16 but not of 32 (FP32 accumulation).  Activations
+// are NHWC so a lane's K-fragment is 8-16 contiguous bytes in LDS; inputs of
+// 2 or 3 channels (the network inputs) are gathered element by element.
 // A work-group of 4 waves computes 16x16-pixel tiles; every scale of a
 // layer can run in one launch over a concatenated tile list.
 #pragma once
@@ -18,6 +19,7 @@ namespace hyp {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   // round to nearest even (finite inputs)
@@ -47,6 +49,7 @@ struct ScaleDesc {
   const void* wimg;   // weights as the LDS image: [Cout][WSTR] storage type, zero-padded K
   const float* b;     // FP32 bias [Cout]
   int H, W;
+  int ostr;           // output elements per pixel (Cout, or wider inside a concatenation)
   int tiles_x, tile0; // tile columns, first global tile index of this scale
 };
 
@@ -56,23 +59,38 @@ struct ConvLaunch {
 };
 
 // K step of one MFMA fragment and the padded weight row, shared by the
-// kernels and the host code that writes weight images.
-__host__ __device__ constexpr int conv_kstep(int elt) { return elt == 4 ? 16 : 32; }
+// kernels and the host code that writes weight images.  BF16 uses 32-wide
+// fragments unless the (not gathered) input width is an odd multiple of 16.
+__host__ __device__ constexpr int conv_kstep(int elt, int cin) {
+  return elt == 4 ? 16 : ((cin >= 8 && cin % 32 != 0) ? 16 : 32);
+}
 __host__ __device__ constexpr int conv_wstr(int elt, int ks, int cin) {
-  return ((ks * ks * cin + conv_kstep(elt) - 1) / conv_kstep(elt)) * conv_kstep(elt) + 16 / elt;
+  return ((ks * ks * cin + conv_kstep(elt, cin) - 1) / conv_kstep(elt, cin)) * conv_kstep(elt, cin) +
+         16 / elt;
+}
+// Input channels per pass over the input: all of them when the input tile
+// with its border and 16 output rows of weights fit the 160 KB of LDS,
+// else chunks of 64 (FP32 inputs of 128 channels).
+__host__ __device__ constexpr int conv_cc(int elt, int ks, int cin) {
+  return (cin < 8 || (size_t)(TH + ks - 1) * (TW + ks - 1) * (cin + 16 / elt) * elt +
+                             (size_t)16 * conv_wstr(elt, ks, cin) * elt <= 160 * 1024)
+             ? cin
+             : 64;
 }
 
 template <typename T, int KS, int CIN, int COUT>
 struct ConvGeom {
   static constexpr int ELT = sizeof(T);
   static constexpr bool SMALL = CIN < 8;                      // gathered input channels
-  static constexpr int KSTEP = conv_kstep(ELT);               // K per fragment step
+  static constexpr int CC = conv_cc(ELT, KS, CIN);            // input channels per chunk
+  static constexpr int NCH = CIN / CC;                        // chunks
+  static constexpr int KSTEP = conv_kstep(ELT, CC);           // K per fragment step
   static constexpr int HALO = KS / 2;
   static constexpr int EW = TW + KS - 1, EH = TH + KS - 1;    // input tile with halo
-  static constexpr int KTOT = KS * KS * CIN;
+  static constexpr int KTOT = KS * KS * CC;                   // K of one chunk
   static constexpr int KPAD = ((KTOT + KSTEP - 1) / KSTEP) * KSTEP;
-  static constexpr int WSTR = conv_wstr(ELT, KS, CIN);        // LDS weight row stride (elts)
-  static constexpr int PSTR = SMALL ? CIN : CIN + 16 / ELT;   // LDS pixel stride (elts)
+  static constexpr int WSTR = conv_wstr(ELT, KS, CC);         // LDS weight row stride (elts)
+  static constexpr int PSTR = SMALL ? CIN : CC + 16 / ELT;    // LDS pixel stride (elts)
   static constexpr size_t TILE_LDS = (((size_t)EH * EW * PSTR * ELT + 15) / 16) * 16;
   // output channels per pass: all of them unless their weights and the
   // input tile overflow the 160 KB of LDS (FP32 64 -> 64: 16 per pass)
@@ -81,7 +99,8 @@ struct ConvGeom {
   static constexpr int MB = CT / 16;                          // cout blocks per pass
   static constexpr size_t LDS = (size_t)CT * WSTR * ELT + TILE_LDS;
   static_assert(COUT % 16 == 0, "output channels in blocks of 16");
-  static_assert(SMALL || CIN % KSTEP == 0, "input channels in whole K fragments");
+  static_assert(CIN % CC == 0, "whole input chunks");
+  static_assert(SMALL || CC % KSTEP == 0, "input channels in whole K fragments");
   static_assert(KS % 2 == 1, "odd kernel size");
   static_assert(LDS <= 160 * 1024, "tile and weights fit the LDS of a CU");
 };
@@ -145,8 +164,8 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
     for (int tap = 0; tap < KS * KS; ++tap) {
       const int ky = tap / KS, kx = tap % KS;
 #pragma unroll
-      for (int c0 = 0; c0 < CIN; c0 += Gm::KSTEP) {
-        const int k0 = tap * CIN + c0;
+      for (int c0 = 0; c0 < Gm::CC; c0 += Gm::KSTEP) {
+        const int k0 = tap * Gm::CC + c0;
         if constexpr (sizeof(T) == 4) {
           float4 bv[4];
 #pragma unroll
@@ -165,6 +184,23 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bv[nb].z, acc[mb][nb], 0, 0, 0);
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bv[nb].w, acc[mb][nb], 0, 0, 0);
             }
+          }
+        } else if constexpr (Gm::KSTEP == 16) {
+          // BF16 with 16-wide fragments: 4 consecutive K values per lane
+          shortx4 bv[4];
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) {
+            const int row = wave * 4 + nb;
+            bv[nb] = *reinterpret_cast<const shortx4*>(
+                xl + ((row + ky) * EW + col + kx) * Gm::PSTR + c0 + g * 4);
+          }
+#pragma unroll
+          for (int mb = 0; mb < Gm::MB; ++mb) {
+            const shortx4 a =
+                *reinterpret_cast<const shortx4*>(wl + (mb * 16 + col) * Gm::WSTR + k0 + g * 4);
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv[nb], acc[mb][nb], 0, 0, 0);
           }
         } else {
           bf16x8 bv[4];
@@ -199,28 +235,21 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
   const int t_begin = blockIdx.x * L.tiles_per_wg;
   const int t_end = min(t_begin + L.tiles_per_wg, L.total_tiles);
   int cur = -1;
-  // copy cout rows [co0, co0 + CT) of the layer's weight image into LDS with
-  // 16-byte loads, several in flight per thread
-  auto load_weights = [&](const void* img, int co0) {
+  // copy cout rows [co0, co0 + CT) of input chunk ch of the layer's weight
+  // image ([NCH][Cout][WSTR]) into LDS with 16-byte loads, several in flight
+  // per thread
+  auto load_weights = [&](const void* img, int ch, int co0) {
     __syncthreads();
     constexpr int N16 = Gm::CT * Gm::WSTR * Gm::ELT / 16;
-    const uint4* src = reinterpret_cast<const uint4*>(img) + (size_t)co0 * Gm::WSTR * Gm::ELT / 16;
+    const uint4* src = reinterpret_cast<const uint4*>(img) +
+                       ((size_t)ch * COUT + co0) * Gm::WSTR * Gm::ELT / 16;
     uint4* dstl = reinterpret_cast<uint4*>(wl);
 #pragma unroll 8
     for (int e = threadIdx.x; e < N16; e += 256) dstl[e] = src[e];
   };
-  for (int t = t_begin; t < t_end; ++t) {
-    int k = 0;
-    while (k + 1 < L.nscales && t >= L.sc[k + 1].tile0) ++k;
-    const ScaleDesc& S = L.sc[k];
-    if (Gm::PASSES == 1 && k != cur) {
-      load_weights(S.wimg, 0);
-      cur = k;
-    }
-    const int lt = t - S.tile0;
-    const int x0 = (lt % S.tiles_x) * TW, y0 = (lt / S.tiles_x) * TH;
+  // input tile (channels of chunk ch) with a HALO-pixel replicated border
+  auto load_tile = [&](const ScaleDesc& S, int x0, int y0, int ch) {
     const T* in = reinterpret_cast<const T*>(S.in);
-    // input tile with a HALO-pixel replicated border (coordinates clamped)
     if constexpr (Gm::SMALL) {
       for (int e = threadIdx.x; e < EH * EW; e += blockDim.x) {
         const int gy = min(max(y0 - HALO + e / EW, 0), S.H - 1);
@@ -230,34 +259,56 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
         for (int c = 0; c < CIN; ++c) xl[e * Gm::PSTR + c] = src[c];
       }
     } else {
-      constexpr int CH = CIN * sizeof(T) / 16;  // 16-byte chunks per pixel
+      constexpr int CH = Gm::CC * sizeof(T) / 16;  // 16-byte pieces per pixel
 #pragma unroll 4
       for (int e = threadIdx.x; e < EH * EW * CH; e += blockDim.x) {
-        const int pix = e / CH, ch = e % CH;
+        const int pix = e / CH, piece = e % CH;
         const int gy = min(max(y0 - HALO + pix / EW, 0), S.H - 1);
         const int gx = min(max(x0 - HALO + pix % EW, 0), S.W - 1);
-        const uint4 v = *reinterpret_cast<const uint4*>(
-            reinterpret_cast<const char*>(in + ((size_t)gy * S.W + gx) * CIN) + ch * 16);
-        *reinterpret_cast<uint4*>(reinterpret_cast<char*>(xl + pix * Gm::PSTR) + ch * 16) = v;
+        const uint4 v = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(
+            in + ((size_t)gy * S.W + gx) * CIN + ch * Gm::CC) + piece * 16);
+        *reinterpret_cast<uint4*>(reinterpret_cast<char*>(xl + pix * Gm::PSTR) + piece * 16) = v;
       }
     }
+  };
+  for (int t = t_begin; t < t_end; ++t) {
+    int k = 0;
+    while (k + 1 < L.nscales && t >= L.sc[k + 1].tile0) ++k;
+    const ScaleDesc& S = L.sc[k];
+    if (Gm::PASSES == 1 && Gm::NCH == 1 && k != cur) {
+      load_weights(S.wimg, 0, 0);
+      cur = k;
+    }
+    const int lt = t - S.tile0;
+    const int x0 = (lt % S.tiles_x) * TW, y0 = (lt / S.tiles_x) * TH;
+    if (Gm::NCH == 1) load_tile(S, x0, y0, 0);
     const int col = lane & 15, g = lane >> 4;
     T* out = reinterpret_cast<T*>(S.out);
     for (int pass = 0; pass < Gm::PASSES; ++pass) {
-      if (Gm::PASSES > 1) load_weights(S.wimg, pass * Gm::CT);
-      __syncthreads();
       floatx4 acc[Gm::MB][4];
 #pragma unroll
       for (int mb = 0; mb < Gm::MB; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-      conv_tile<T, KS, CIN, COUT>(wl, xl, acc, wave, lane);
+      if constexpr (Gm::NCH == 1) {
+        if (Gm::PASSES > 1) load_weights(S.wimg, 0, pass * Gm::CT);
+        __syncthreads();
+        conv_tile<T, KS, CIN, COUT>(wl, xl, acc, wave, lane);
+      } else {
+        // K walks the input in chunks: weights and tile of each chunk
+        for (int ch = 0; ch < Gm::NCH; ++ch) {
+          load_weights(S.wimg, ch, pass * Gm::CT);
+          load_tile(S, x0, y0, ch);
+          __syncthreads();
+          conv_tile<T, KS, CIN, COUT>(wl, xl, acc, wave, lane);
+        }
+      }
       // epilogue: bias (+ ReLU); lane holds couts 4g..4g+3 of block mb for pixel col
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
         const int gy = y0 + wave * 4 + nb, gx = x0 + col;
         if (gy >= S.H || gx >= S.W) continue;
-        T* dst = out + ((size_t)gy * S.W + gx) * COUT;
+        T* dst = out + ((size_t)gy * S.W + gx) * S.ostr;
 #pragma unroll
         for (int mb = 0; mb < Gm::MB; ++mb) {
           const int co = pass * Gm::CT + mb * 16 + g * 4;
@@ -286,14 +337,20 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
   }
 }
 
-// One element of a layer's weight image: row co, column kk of the
-// [Cout][WSTR] LDS layout (storage type, K zero-padded) from the packed
-// FP32 weights W[Cout][KS][KS][Cin].
+// One element of a layer's weight image: chunk ch, row co, column kk of the
+// [NCH][Cout][WSTR] LDS layout (storage type, K zero-padded) from the packed
+// FP32 weights W[Cout][KS][KS][Cin]; column kk = tap * CC + c holds input
+// channel ch * CC + c.
 template <typename T, int KS, int CIN, int COUT>
 __device__ __forceinline__ void write_wimg(const float* __restrict__ w, T* __restrict__ img, int e) {
   using Gm = ConvGeom<T, KS, CIN, COUT>;
-  const int co = e / Gm::WSTR, kk = e % Gm::WSTR;
-  const float v = kk < Gm::KTOT ? w[co * Gm::KTOT + kk] : 0.f;
+  const int ch = e / (COUT * Gm::WSTR), r = e % (COUT * Gm::WSTR);
+  const int co = r / Gm::WSTR, kk = r % Gm::WSTR;
+  float v = 0.f;
+  if (kk < Gm::KTOT) {
+    const int tap = kk / Gm::CC, c = kk % Gm::CC;
+    v = w[(size_t)co * KS * KS * CIN + tap * CIN + ch * Gm::CC + c];
+  }
   img[e] = St<T>::from(v);
 }
 

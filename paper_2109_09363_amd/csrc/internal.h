@@ -48,7 +48,7 @@ constexpr int kWgBlocks = 128;  // pixel-chunk blocks of the weight-gradient red
 struct WsLayout {
   size_t cell = 0, d = 0, phi = 0, phi_acc = 0, exch = 0, blockpart = 0, partial = 0,
          scalars = 0, reach = 0, pcg = 0, adv = 0, sync = 0;
-  size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0;
+  size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0, cnn_cat = 0;
   size_t cnn_save = 0, bw_cells = 0, bw_t = 0, bw_x = 0, bw_a = 0, bw_b = 0, bw_part = 0;
   size_t bw_part_n = 0;
   size_t total = 0;
@@ -78,6 +78,7 @@ struct Ws {
   float* pcg;         // PCG scratch
   float* adv;         // advection temporaries: 2 x (cells + u faces + v faces)
   void* cnn_in; void* cnn_act0; void* cnn_act1; float* cnn_y; float* cnn_t; void* cnn_w;
+  void* cnn_cat;      // Unet concatenation buffers
   void* cnn_save;     // training: 4 layers x total_px x C activations
   float* bw_cells;    // backward: 3 x cells (lambda ping-pong, lambda_d)
   float* bw_t;        // backward: lambda of t / y, all scales
@@ -130,6 +131,7 @@ hipError_t run_jacobi_batch(const Device& dev, void* area, int ninst, int ntiles
 size_t cnn_weight_image_bytes(const NetShape& net);
 int64_t pn_param_count(int arch);
 size_t pn_weight_image_bytes(const NetShape& net);
+size_t unet_cat_elems(int nx, int ny);
 hipError_t run_papernet(const Device& dev, const NetShape& net, const WsLayout& L, int nx, int ny,
                         double dx, const float* params, const Ws& w, hipStream_t s);
 hipError_t run_cnn(const Device& dev, const NetShape& net, const WsLayout& L, int nx, int ny,

@@ -19,6 +19,18 @@ WHAT:
   dram        the streaming (batched) Jacobi kernel on one large grid
               (default 8192^2, 268 MB per FP32 field) for a fixed number of
               sweeps: algorithmic bytes per second against the HBM peak.
+  validate    model selection for network weights: 512^2 plumes of --seeds
+              (default 100-107, disjoint from the benchmark's seed 0, the
+              experiments' seeds 0-4 and the training scenes), each developed
+              by `warmup` PCG steps, then `steps` hybrid steps to 1e-3 with
+              every candidate in --weights from the same state; mean sweeps
+              and ms per step per candidate.
+  networks    inference time t_inf (divergence + network, the library's phase
+              events) of every network on grids of --sizes (default 512):
+              the parallel 4-scale 64-channel and 3-scale 32-channel nets and
+              the paper's cascaded MultiScale and SmallScale and its Unet,
+              FP32 and BF16;
+              MFMA FLOP/s against the dense peaks (Sec. 5.1, Table 1).
 All inputs are seeded and synthetic; timings use the stream's HIP events
 (through torch.cuda.Event on the current stream, which the library uses).
 """
@@ -258,10 +270,95 @@ def cmd_dram(a, dev):
           "note": "the projection also runs the divergence, gradient and check passes"})
 
 
+def cmd_validate(a, dev):
+    cands = {os.path.basename(f): torch.from_numpy(np.load(f, allow_pickle=False).astype(np.float32)).to(dev)
+             for f in a.weights}
+    first = next(iter(cands.values()))
+    tot = {k: [0.0, 0.0] for k in cands}
+    for seed in a.seeds:
+        pl = Plume(512, seed, a.warmup, dev, first)
+        out = {"what": "validate", "seed": seed, "steps": a.steps, "n_obstacles": len(pl.sc.disks)}
+        for name, w in cands.items():
+            pl.pr.set_weights(w)
+            rows, t = pl.run("hybrid", 1e-3, a.steps)
+            sm = summarize(rows, t, a.steps)
+            out[name] = {"mean_sweeps": sm["mean_iters"], "ms_per_step": sm["ms_per_step"]}
+            tot[name][0] += sm["mean_iters"] / len(a.seeds)
+            tot[name][1] += sm["ms_per_step"] / len(a.seeds)
+        emit(out)
+    emit({"what": "validate", "seeds": a.seeds,
+          "mean": {k: {"mean_sweeps": round(v[0], 1), "ms_per_step": round(v[1], 4)} for k, v in tot.items()}})
+
+
+# network configurations: (label, arch, scales, channels)
+NETWORKS = [("parallel S4 C64", "parallel", 4, 64), ("parallel S3 C32", "parallel", 3, 32),
+            ("MultiScale", "multiscale", 3, 64), ("SmallScale", "smallscale", 3, 32),
+            ("Unet", "unet", 5, 64)]
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+
+
+def net_macs(arch, scales, channels, nx, ny):
+    """Multiply-adds of one inference (every convolution, all scales)."""
+    if arch == "parallel":
+        C = channels
+        per_px = 9 * 2 * C + 3 * 9 * C * C + C
+        return sum(per_px * (nx >> k) * (ny >> k) for k in range(scales))
+    if arch == "unet":
+        layers = scenes.paper_net_layers("unet")[0]
+        levels = [l for l in range(5) for _ in range(2)] + [l for l in range(3, -1, -1) for _ in range(2)]
+        levels.append(0)
+        return sum(k * k * ci * co * (nx >> lv) * (ny >> lv) for (k, ci, co), lv in zip(layers, levels))
+    total = 0
+    for b, br in enumerate(scenes.paper_net_layers(arch)):
+        f = 4 >> b
+        total += sum(k * k * ci * co for (k, ci, co) in br) * (nx // f) * (ny // f)
+    return total
+
+
+def cmd_networks(a, dev):
+    for n in a.sizes:
+        sc = scenes.plume_scene(n, seed=0, n_obstacles=2)
+        u, v = scenes.random_faces(n, n, 0, kind="mixed")
+        flags = torch.from_numpy(sc.flags).to(dev)
+        u0 = torch.from_numpy(u.astype(np.float32)).to(dev)
+        v0 = torch.from_numpy(v.astype(np.float32)).to(dev)
+        p = torch.empty((n, n), dtype=torch.float32, device=dev)
+        for (label, arch, S, C) in NETWORKS:
+            for prec in ("fp32", "bf16"):
+                if arch == "parallel" and prec == "bf16" and C == 16:
+                    continue
+                pr = hp.Projector(n, n, sc.dx, 1.0, 1.0, S, C, prec, device=dev, arch=arch)
+                if arch == "parallel":
+                    w = scenes.random_weights(S, C, 0)
+                else:
+                    w = scenes.random_paper_weights(arch, 0)
+                tw = torch.from_numpy(w).to(dev)
+                pr.set_weights(tw)
+                pr.plan(flags)
+                pr.set_timing(True)
+                ts = []
+                for rep in range(a.reps + 3):
+                    uu, vv = u0.clone(), v0.clone()
+                    pr.project_async(uu, vv, flags, p, 0.0, method="cnn")
+                    torch.cuda.synchronize()
+                    if rep >= 3:
+                        ts.append(pr.timing()["inference"])
+                ms = float(np.median(ts))
+                macs = net_macs(arch, S, C, n, n)
+                tf = 2.0 * macs / (ms * 1e-3) / 1e12
+                emit({"what": "networks", "n": n, "net": label, "params": int(w.size),
+                      "precision": prec, "t_inf_ms": round(ms, 4), "gflop": round(2 * macs / 1e9, 2),
+                      "tflops": round(tf, 1), "mfma_peak_tflops": PEAK_TFLOPS[prec],
+                      "frac_of_peak": round(tf / PEAK_TFLOPS[prec], 4)})
+                del pr
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["thresholds", "gain", "batch", "dram"])
-    ap.add_argument("--seeds", type=int, nargs="*", default=[0, 1, 2, 3, 4])
+    ap.add_argument("what", choices=["thresholds", "gain", "batch", "dram", "networks", "validate"])
+    ap.add_argument("--weights", nargs="*", default=[WEIGHTS])
+    ap.add_argument("--sizes", type=int, nargs="*", default=[512])
+    ap.add_argument("--seeds", type=int, nargs="*", default=None)
     ap.add_argument("--thresholds", type=float, nargs="*", default=[1e-2, 1e-3, 1e-4])
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=30)
@@ -269,9 +366,12 @@ def main():
     ap.add_argument("--sweeps", type=int, default=800)
     ap.add_argument("--reps", type=int, default=3)
     a = ap.parse_args()
+    if a.seeds is None:
+        a.seeds = list(range(100, 108)) if a.what == "validate" else [0, 1, 2, 3, 4]
     dev = torch.device("cuda")
     t0 = time.time()
-    {"thresholds": cmd_thresholds, "gain": cmd_gain, "batch": cmd_batch, "dram": cmd_dram}[a.what](a, dev)
+    {"thresholds": cmd_thresholds, "gain": cmd_gain, "batch": cmd_batch, "dram": cmd_dram,
+     "networks": cmd_networks, "validate": cmd_validate}[a.what](a, dev)
     print(f"# {a.what} done in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
 
 

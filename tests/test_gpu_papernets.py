@@ -1,7 +1,9 @@
 """GPU parity of the paper's cascaded MultiScale and SmallScale networks
 (Sec. 3.1, Fig. 3: branches at n/4, n/2, n; 5x5, 3x3 and 1x1 convolutions on
-MFMA; coarse output upsampled and concatenated) and of the hybrid projection
-that starts from their guess, against the FP64 oracle through the C ABI."""
+MFMA; coarse output upsampled and concatenated), of its Unet (Fig. 4: max
+pooling, bilinear upsampling, skip concatenation) and of the hybrid
+projection that starts from their guess, against the FP64 oracle through the
+C ABI."""
 import numpy as np
 import pytest
 
@@ -32,7 +34,8 @@ def state(nx, ny, seed, nobs):
 # grows with that upstream difference (measured: 3e-5 for the parallel net,
 # 1e-4 for one branch alone, 3e-3 .. 4e-3 for the cascade).  So the cascade is
 # held to 1e-2 (2.5 BF16 ulps, 2^-8 = 3.9e-3) against the emulation and to
-# 3e-2 against the unemulated FP64 network.
+# 3e-2 against the unemulated FP64 network; the Unet, 19 layers deep with the
+# encoder's output re-quantized after pooling and upsampling, to the same.
 BF16_EMULATED, BF16_FP64 = 1e-2, 3e-2
 
 
@@ -44,7 +47,7 @@ def oracle_phi0(sc, u, v, w, arch, bf16):
 
 
 def test_param_counts_match_the_oracle():
-    for arch in PN.ARCHS:
+    for arch in PN.ARCHS + ("unet",):
         pr = hp.Projector(32, 32, 1 / 32, arch=arch)
         assert pr.param_count == PN.param_count(arch) == scenes.random_paper_weights(arch, 0).size
 
@@ -118,12 +121,78 @@ def test_papernet_hybrid_parity(arch, n, prec, seed, thr_rel):
     assert g["res"].e1_final <= 1.01 * thr
 
 
+def unet_oracle(sc, u, v, w, bf16):
+    P = G.plan(sc.flags)
+    d = G.divergence(P, *G.enforce_bc(P, u, v), sc.dx)
+    phi0, s = PN.unet_phi0(P, d, sc.dx, w, bf16=bf16)
+    return P, d, phi0, s
+
+
+@pytest.mark.parametrize("nx,ny,prec,seed", [
+    (64, 64, "fp32", 0),
+    (96, 48, "fp32", 1),     # ragged tiles at every scale, 6x3 at the bottom
+    (64, 64, "bf16", 2),
+    (112, 80, "bf16", 3),
+    (256, 256, "fp32", 4),   # the 128-channel decoder inputs in two chunks (FP32)
+])
+def test_unet_prediction_parity(nx, ny, prec, seed):
+    say("unet", nx, ny, prec)
+    sc, u, v = state(nx, ny, seed, 2)
+    w = scenes.random_paper_weights("unet", seed)
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="cnn", params=w, precision=prec,
+                    arch="unet")
+    bf = prec == "bf16"
+    P, d, phi0, s = unet_oracle(sc, u, v, w, bf)
+    err = rel_l2(g["p"], phi0, P.fluid)
+    say("  rel L2 vs oracle", err)
+    assert g["res"].status == 0 and g["res"].s == pytest.approx(s, rel=1e-6)
+    assert err <= (BF16_EMULATED if bf else 1e-5)
+    assert np.all(g["p"][~P.fluid] == 0)
+    if bf:
+        e64 = rel_l2(g["p"], unet_oracle(sc, u, v, w, False)[2], P.fluid)
+        say("  bf16 vs fp64 network", e64)
+        assert e64 <= BF16_FP64
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_unet_full_size_512(prec):
+    say("unet 512", prec)
+    sc, u, v = state(512, 512, 8, 3)
+    w = scenes.random_paper_weights("unet", 8)
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="cnn", params=w, precision=prec,
+                    arch="unet")
+    P, d, phi0, s = unet_oracle(sc, u, v, w, prec == "bf16")
+    err = rel_l2(g["p"], phi0, P.fluid)
+    say("  rel L2", err)
+    assert err <= (BF16_EMULATED if prec == "bf16" else 1e-5)
+
+
+def test_unet_hybrid_parity():
+    n = 128
+    say("unet hybrid", n)
+    sc, u, v = state(n, n, 5, 2)
+    w = scenes.random_paper_weights("unet", 5, out_scale=0.05)
+    P, d, phi0, s = unet_oracle(sc, u, v, w, False)
+    thr = 0.05 * G.e1(P, d)
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=thr, method="hybrid", params=w, arch="unet",
+                    check_every=4, max_iters=50000)
+    phi_o, ko, st, _ = SV.jacobi(P, d, sc.dx, phi0, thr, 1.0, 4, 50000)
+    kg = g["res"].iters
+    say("  iters gpu", kg, "oracle", ko)
+    assert g["res"].status == 0 and st == SV.STATUS_OK
+    assert abs(kg - ko) <= max(4, 0.01 * ko)
+    phi_f = SV.jacobi(P, d, sc.dx, phi0, 0.0, 1.0, 1, kg, kg)[0] if kg > 0 else phi0
+    assert rel_l2(g["p"], phi_f, P.fluid) <= 1e-4
+
+
 def test_papernet_rejects_training_and_bad_shapes():
     from paper_2109_09363_amd import _lib as L
     with pytest.raises(L.HypError):
         hp.Projector(64, 64, 1 / 64, arch="multiscale", train=True)
     with pytest.raises(L.HypError):
         hp.Projector(64, 64, 1 / 64, channels=32, arch="multiscale")
+    with pytest.raises(L.HypError):
+        hp.Projector(64, 64, 1 / 64, arch="unet", train=True)
     pr = hp.Projector(62, 64, 1 / 64, arch="smallscale")  # sides must be multiples of 4
     import torch
     t = lambda *s: torch.zeros(s, dtype=torch.float32, device="cuda")

@@ -61,7 +61,13 @@ def test_host_side_rejections():
         assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(3, C + 32, 0, 0, arch))) == -1
         assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(4, C, 0, 0, arch))) == -1
         assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(3, C, 0, 1, arch))) == -2
-    assert lib.hyp_create(ctypes.byref(ctx), ctypes.byref(L.NetDesc(3, 32, 0, 0, 3))) == -1
+    c2 = ctypes.c_void_p()
+    assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(0, 0, 1, 0, 3))) == 0
+    assert lib.hyp_param_count(c2) == 443441  # the Unet
+    lib.hyp_destroy(c2)
+    assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(3, 64, 0, 0, 3))) == -1
+    assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(5, 64, 0, 1, 3))) == -2
+    assert lib.hyp_create(ctypes.byref(ctx), ctypes.byref(L.NetDesc(3, 32, 0, 0, 4))) == -1
     good = L.NetDesc(3, 32, 0, 0)
     assert lib.hyp_create(ctypes.byref(ctx), ctypes.byref(good)) == 0
     assert lib.hyp_param_count(ctx) == 85155
