@@ -124,8 +124,10 @@ typedef struct {
 typedef struct {
   float* u;              /* (ny, nx+1) in/out: corrected in place */
   float* v;              /* (ny+1, nx) in/out: corrected in place */
-  const float* rho;      /* (ny, nx) density; accepted, not read by the
-                            constant-coefficient operator of Eq. (3) */
+  const float* rho;      /* (ny, nx) density: read only with
+                            hyp_opts.variable_density (then required, > 0 on
+                            fluid cells); the constant-coefficient operator
+                            of Eq. (3) uses rho0 */
   const uint8_t* flags;  /* (ny, nx) input flags (bit0 solid, bit1 inflow) */
   float* p;              /* (ny, nx) out: pressure p = rho0 * phi / dt */
   const float* p_init;   /* nullable: warm start (as p, same scaling) for
@@ -161,6 +163,15 @@ typedef struct {
                            grid (csrc/tile_table.h), else the smallest that
                            fits one work-group per CU.  EUNSUPPORTED when the
                            tiles do not fit. */
+  int32_t variable_density; /* 1: keep the cell density inside Eq. (3)-(2)
+                           (the paper writes them with rho0, Sec. 2.2):
+                           div(beta grad phi) = div u*, u = u* - beta grad phi
+                           with beta = rho0 / rho_face on open faces (mean of
+                           the two cells' densities; the top cell's on an open
+                           top face), phi = (dt / rho0) p as before.  Jacobi,
+                           PCG, HYBRID (the network's guess is unchanged) and
+                           CNN; needs rho; not with the batch or the adjoint
+                           (EUNSUPPORTED).  0: rho0 everywhere. */
 } hyp_opts;
 
 /* Written by the device when the projection's last kernel completes. */

@@ -18,6 +18,7 @@ struct hyp_ctx {
   // divergence + CNN, the solver launch, and the correction
   bool timing = false;
   bool timed_step = false;
+  bool last_var = false;  // the last forward used the variable-density operator
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -54,6 +55,8 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
   L.phi = take(4 * n);
   L.phi_acc = take(4 * n);
   L.exch = take(8 * n);
+  L.coef = take(8 * n);
+  L.ncell = n;
   L.adv = take(4 * 2 * (n + (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx));
   if (net.scales > 0) {
     size_t px = 0;
@@ -103,6 +106,8 @@ Ws ws_view(void* base, const WsLayout& L) {
   w.phi = (float*)(b + L.phi);
   w.phi_acc = (float*)(b + L.phi_acc);
   w.exch = (float*)(b + L.exch);
+  w.coef_e = (float*)(b + L.coef);
+  w.coef_n = w.coef_e + L.ncell;
   w.pcg = nullptr;
   w.adv = (float*)(b + L.adv);
   w.cnn_in = L.cnn_in ? b + L.cnn_in : nullptr;
@@ -273,6 +278,7 @@ static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, 
   if (o->method < HYP_METHOD_HYBRID || o->method > HYP_METHOD_CNN) return HYP_EINVAL;
   if (o->max_iters < 0 || o->check_every < 1 || o->fixed_iters < 0) return HYP_EINVAL;
   if (o->fold_window < 0 || o->checkpoint_every < 0) return HYP_EINVAL;
+  if (o->variable_density != 0 && o->variable_density != 1) return HYP_EINVAL;
   if (!(threshold >= 0.0)) return HYP_EINVAL;
   const bool use_cnn = o->method == HYP_METHOD_HYBRID || o->method == HYP_METHOD_CNN;
   if (use_cnn) {
@@ -289,14 +295,17 @@ static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, 
 
 // The projection pipeline, enqueued on `stream` (arguments already checked).
 static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* v,
-                              const float* p_init, float* p, float* phi_ckpt, double threshold,
-                              const hyp_opts* o,
+                              const float* rho, const float* p_init, float* p, float* phi_ckpt,
+                              double threshold, const hyp_opts* o,
                               const WsLayout& L, const Ws& w, bool dt_dev, hipStream_t stream,
                               hyp_result* res) {
   const int nx = g->nx, ny = g->ny;
   const bool use_cnn = o->method == HYP_METHOD_HYBRID || o->method == HYP_METHOD_CNN;
+  const bool var = o->variable_density != 0;
+  ctx->last_var = var;
   mark(ctx, 1, stream);
   if (run_div(nx, ny, g->dx, u, v, w, L.nblocks_stream, stream) != hipSuccess) return HYP_EHIP;
+  if (var && run_coef(nx, ny, g->rho0, rho, w, stream) != hipSuccess) return HYP_EHIP;
   if (use_cnn) {
     if (run_cnn(ctx->dev, ctx->net, L, nx, ny, g->dx, ctx->params, w, stream) != hipSuccess)
       return HYP_EHIP;
@@ -307,21 +316,22 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
   mark(ctx, 2, stream);
   if (o->method == HYP_METHOD_CNN) {
     // no sweeps: a zero-length Jacobi pass records E_1 of the prediction
-    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, 0, nullptr, 0, u, v, w, stream);
+    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, 0, nullptr, 0, var, u, v, w,
+                   stream);
   } else if (o->method == HYP_METHOD_PCG) {
     // one persistent launch, defect-correction folds included
     e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
-                o->fixed_iters, u, v, w, stream);
+                o->fixed_iters, var, u, v, w, stream);
   } else {
     // one persistent launch, defect-correction folds included
     e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,
                    o->fixed_iters, o->fold_window, phi_ckpt ? o->checkpoint_every : 0, phi_ckpt,
-                   o->tile_rows, u, v, w, stream);
+                   o->tile_rows, var, u, v, w, stream);
   }
   if (e != hipSuccess) return HYP_EHIP;
   mark(ctx, 3, stream);
   if (run_grad_and_finish(nx, ny, g->dx, g->rho0, g->dt, dt_dev, u, v, p, w, L.nblocks_stream,
-                          res, stream) != hipSuccess)
+                          res, var, stream) != hipSuccess)
     return HYP_EHIP;
   mark(ctx, 4, stream);
   return HYP_OK;
@@ -343,7 +353,8 @@ int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double thr
   if (ws_bytes < L.total) return HYP_EWORKSPACE;
   const Ws w = ws_view(ws, L);
   ctx->timed_step = false;
-  return enqueue_projection(ctx, g, f->u, f->v, f->p_init, f->p,
+  if (o->variable_density && !f->rho) return HYP_EINVAL;
+  return enqueue_projection(ctx, g, f->u, f->v, f->rho, f->p_init, f->p,
                             o->checkpoint_every > 0 ? f->phi_ckpt : nullptr, threshold, o, L, w,
                             false, stream, res);
 }
@@ -354,6 +365,7 @@ int hyp_project_backward(hyp_ctx* ctx, const hyp_grid* g, int32_t sweeps, float 
   if (!ctx || !ws || !grid_ok(g) || sweeps < 0) return HYP_EINVAL;
   if (ctx->net.scales == 0 || !ctx->params) return HYP_ENOWEIGHTS;
   if (!ctx->net.train) return HYP_EUNSUPPORTED;
+  if (ctx->last_var) return HYP_EUNSUPPORTED;  // the adjoint is of the constant-coefficient projection
   const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
   if (ws_bytes < L.total) return HYP_EWORKSPACE;
   const Ws w = ws_view(ws, L);
@@ -407,8 +419,8 @@ int hyp_step(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_s
   if (run_advect(g->nx, g->ny, g->dx, ph->g, ph->rho0, ph->drho, ph->u_in, ph->cfl, st->rho, st->u,
                  st->v, st->xi, w, stream) != hipSuccess)
     return HYP_EHIP;
-  return enqueue_projection(ctx, &gg, st->u, st->v, nullptr, st->p, nullptr, threshold, o, L, w, true,
-                            stream, res);
+  return enqueue_projection(ctx, &gg, st->u, st->v, st->rho, nullptr, st->p, nullptr, threshold, o, L,
+                            w, true, stream, res);
 }
 
 // ---------------------------------------------------------------------------
@@ -457,6 +469,7 @@ int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_s
   if (!ctx || n < 1 || !grids || !states || !thresholds || !o || !ws || !out) return HYP_EINVAL;
   *out = nullptr;
   if (o->method != HYP_METHOD_HYBRID && o->method != HYP_METHOD_JACOBI) return HYP_EUNSUPPORTED;
+  if (o->variable_density != 0) return HYP_EUNSUPPORTED;
   if (o->max_iters < 0 || !(o->omega > 0.f) || o->checkpoint_every != 0) return HYP_EINVAL;
   if (o->method == HYP_METHOD_HYBRID && (ctx->net.scales == 0 || !ctx->params)) return HYP_ENOWEIGHTS;
   for (int i = 0; i < n; ++i) {
@@ -535,7 +548,7 @@ static int batch_enqueue(hyp_batch* b, const hyp_physics* ph, hipStream_t s, hyp
     const hyp_grid& g = b->grids[i];
     const hyp_state& st = b->states[i];
     if (run_grad_and_finish(g.nx, g.ny, g.dx, g.rho0, g.dt > 0.0 ? g.dt : 1.0, ph != nullptr, st.u,
-                            st.v, st.p, b->ws[i], b->layouts[i].nblocks_stream, res + i, s) != hipSuccess)
+                            st.v, st.p, b->ws[i], b->layouts[i].nblocks_stream, res + i, false, s) != hipSuccess)
       return HYP_EHIP;
   }
   return HYP_OK;

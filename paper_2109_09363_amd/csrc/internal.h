@@ -47,7 +47,8 @@ constexpr int kWgBlocks = 128;  // pixel-chunk blocks of the weight-gradient red
 // Byte offsets into the caller's workspace (all 256-byte aligned).
 struct WsLayout {
   size_t cell = 0, d = 0, phi = 0, phi_acc = 0, exch = 0, blockpart = 0, partial = 0,
-         scalars = 0, reach = 0, pcg = 0, adv = 0, sync = 0;
+         scalars = 0, reach = 0, pcg = 0, adv = 0, sync = 0, coef = 0;
+  size_t ncell = 0;
   size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0, cnn_cat = 0;
   size_t cnn_save = 0, bw_cells = 0, bw_t = 0, bw_x = 0, bw_a = 0, bw_b = 0, bw_part = 0;
   size_t bw_part_n = 0;
@@ -79,6 +80,8 @@ struct Ws {
   float* adv;         // advection temporaries: 2 x (cells + u faces + v faces)
   void* cnn_in; void* cnn_act0; void* cnn_act1; float* cnn_y; float* cnn_t; void* cnn_w;
   void* cnn_cat;      // Unet concatenation buffers
+  float* coef_e;      // variable-density face coefficients: east face of each cell
+  float* coef_n;      // ... north face
   void* cnn_save;     // training: 4 layers x total_px x C activations
   float* bw_cells;    // backward: 3 x cells (lambda ping-pong, lambda_d)
   float* bw_t;        // backward: lambda of t / y, all scales
@@ -104,15 +107,17 @@ hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const
                         hipStream_t s);
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      int checkpoint_every, float* phi_ckpt, int tile_rows, float* u, float* v,
-                      const Ws& w, hipStream_t s);
+                      int checkpoint_every, float* phi_ckpt, int tile_rows, bool var, float* u,
+                      float* v, const Ws& w, hipStream_t s);
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters,
                  int tile_rows);
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
-                   int check_every, int fixed_iters, float* u, float* v, const Ws& w, hipStream_t s);
+                   int check_every, int fixed_iters, bool var, float* u, float* v, const Ws& w,
+                   hipStream_t s);
 hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt, bool dt_dev,
                                float* u, float* v, float* p, const Ws& w, int nblocks, void* res,
-                               hipStream_t s);
+                               bool var, hipStream_t s);
+hipError_t run_coef(int nx, int ny, double rho0, const float* rho, const Ws& w, hipStream_t s);
 hipError_t run_advect(int nx, int ny, double dx, double g, double rho0, double drho, double u_in,
                       double cfl, float* rho, float* u, float* v, const float* xi, const Ws& w,
                       hipStream_t s);

@@ -19,6 +19,11 @@
 //  * Jacobi-preconditioned conjugate gradient with FP64 dot products: LDS
 //    tiles with a one-cell halo for the search direction, one merged grid
 //    reduction per iteration, and a stop confirmed on the true residual.
+//
+// Both come in a variable-density form (VAR): the operator weights every
+// open face by beta = rho0 / rho_face (coefficient planes ce, cn), the
+// diagonal is the sum of the four betas, and the fold corrects the faces by
+// beta grad phi.  The constant-coefficient code is the VAR = false instance.
 #include "../../include/hyproj.h"
 #include "common.h"
 #include "internal.h"
@@ -56,14 +61,26 @@ struct JacParams {
   double* partial;      // 2 x kMaxCoopBlocks partial sums
   Scalars* sc;
   unsigned* sync;       // grid barrier
+  const float* ce;      // variable density: beta of each cell's east face
+  const float* cn;      // ... north face
 };
+
+// The four face coefficients of cell g (flags ci): beta of the open faces,
+// 0 on closed ones.
+__device__ __forceinline__ void face_betas(const float* ce, const float* cn, int g, int nx,
+                                           uint8_t ci, float& be, float& bw, float& bn, float& bs) {
+  be = (ci & C_E) ? ce[g] : 0.f;
+  bw = (ci & C_W) ? ce[g - 1] : 0.f;
+  bn = (ci & C_N) ? cn[g] : 0.f;
+  bs = (ci & C_S) ? cn[g - nx] : 0.f;
+}
 
 __device__ __forceinline__ void abort_solve(Scalars* sc) {
   __hip_atomic_fetch_max(&sc->status, (int32_t)HYP_STATUS_ABORTED, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int R>
+template <int R, bool VAR>
 __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
   __shared__ float edge[2][2][4][64];  // [parity][low row / high row][wave][lane]
   __shared__ double red[4];
@@ -81,19 +98,25 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
   // (imask), and the fluid ones among the latter, which enter E_1 (fmask)
   unsigned dmask = 0, imask = 0, fmask = 0;
   float ph[R], dd[R], kk[R], ww[R];
+  float be[R], bw[R], bn[R], bs[R];  // VAR only
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int er = wave * R + r, gy = gy0 + r;
     float d_ = 0.f, k_ = 0.f, w_ = 0.f, p_ = 0.f;
+    be[r] = bw[r] = bn[r] = bs[r] = 0.f;
     if (col_in && gy >= 0 && gy < p.ny) {
       dmask |= 1u << r;
       const int g = gy * p.nx + gx;
       const uint8_t ci = p.cell[g];
       if (!(ci & C_SOLID)) {
-        const int k = cell_k(ci);
-        k_ = (float)k;
+        if constexpr (VAR) {
+          face_betas(p.ce, p.cn, g, p.nx, ci, be[r], bw[r], bn[r], bs[r]);
+          k_ = (be[r] + bw[r]) + (bn[r] + bs[r]);
+        } else {
+          k_ = (float)cell_k(ci);
+        }
         d_ = p.d[g];
-        w_ = p.wfac / (float)k;
+        w_ = p.wfac / k_;
         p_ = p.phi[g];
       }
       if (lane_int && er >= H && er < H + TH) {
@@ -149,7 +172,12 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     if (test) {
       float below, above;
       edges(&below, &above);
-      const double loc = block_sum(jac_rows<R, false>(ph, dd, kk, ww, below, above, p.inv_dx2, fmask), red);
+      double part_loc;
+      if constexpr (VAR)
+        part_loc = jac_rows_var<R, false>(ph, dd, kk, ww, be, bw, bn, bs, below, above, p.inv_dx2, fmask);
+      else
+        part_loc = jac_rows<R, false>(ph, dd, kk, ww, below, above, p.inv_dx2, fmask);
+      const double loc = block_sum(part_loc, red);
       ++t;
       if (threadIdx.x == 0) st_agent(part + blockIdx.x, loc);
     }
@@ -199,17 +227,19 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
           const size_t c = (size_t)gy * p.nx + gx;
           const uint8_t ci = p.cell[c];
           const float pc = ph[r];
+          // face weights: beta for the variable-density operator, else 1
+          const float fw = VAR ? bw[r] : 1.f, fs = VAR ? bs[r] : 1.f, fn = VAR ? bn[r] : 1.f;
           if (ci & C_W) {
             float* f = p.u + (size_t)gy * (p.nx + 1) + gx;
-            st_agent(f, ld_agent(f) - (pc - west) * p.inv_dx);
+            st_agent(f, ld_agent(f) - fw * ((pc - west) * p.inv_dx));
           }
           if (ci & C_S) {
             float* f = p.v + c;
-            st_agent(f, ld_agent(f) - (pc - south) * p.inv_dx);
+            st_agent(f, ld_agent(f) - fs * ((pc - south) * p.inv_dx));
           }
           if (gy == p.ny - 1 && (ci & C_N)) {
             float* f = p.v + plane + gx;
-            st_agent(f, ld_agent(f) - (0.f - pc) * p.inv_dx);
+            st_agent(f, ld_agent(f) - fn * ((0.f - pc) * p.inv_dx));
           }
           p.phi_acc[c] += pc;
         }
@@ -238,7 +268,10 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     for (int s = 0; s < B; ++s) {
       float below, above;
       edges(&below, &above);
-      jac_rows<R, true>(ph, dd, kk, ww, below, above, p.inv_dx2, 0u);
+      if constexpr (VAR)
+        jac_rows_var<R, true>(ph, dd, kk, ww, be, bw, bn, bs, below, above, p.inv_dx2, 0u);
+      else
+        jac_rows<R, true>(ph, dd, kk, ww, below, above, p.inv_dx2, 0u);
     }
     k += B;
     ++j;
@@ -280,6 +313,8 @@ struct PcgParams {
   double* partial;      // 2 x 3 x kMaxCoopBlocks
   Scalars* sc;
   unsigned* sync;
+  const float* ce;      // variable density: beta of each cell's east face
+  const float* cn;      // ... north face
 };
 
 template <int R>
@@ -309,7 +344,25 @@ __device__ __forceinline__ void apply_A(const float (&v)[R], const float (&kk)[R
   }
 }
 
+// y = A v with face coefficients (diagonal kk = sum of the betas)
 template <int R>
+__device__ __forceinline__ void apply_A_var(const float (&v)[R], const float (&kk)[R],
+                                            const float (&be)[R], const float (&bw)[R],
+                                            const float (&bn)[R], const float (&bs)[R], float below,
+                                            float above, float (&y)[R]) {
+  float prev = below;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float c = v[r];
+    const float n = (r + 1 < R) ? v[r + 1] : above;
+    const float e = from_right(c);
+    const float w = from_left(c);
+    y[r] = kk[r] > 0.f ? kk[r] * c - ((be[r] * e + bw[r] * w) + (bn[r] * n + bs[r] * prev)) : 0.f;
+    prev = c;
+  }
+}
+
+template <int R, bool VAR>
 __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
   __shared__ float edge[2][2][4][64];
   __shared__ double red[4];
@@ -325,16 +378,23 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
   if (p.sc->status >= 0) return;
   unsigned dmask = 0, imask = 0;
   float x[R], r[R], u[R], w[R], pp[R], ss[R], kk[R], bb[R];
+  float be[R], bw[R], bn[R], bs[R];  // VAR only
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int er = wave * R + i, gy = gy0 + i;
     float k_ = 0.f, b_ = 0.f, x_ = 0.f;
+    be[i] = bw[i] = bn[i] = bs[i] = 0.f;
     if (col_in && gy >= 0 && gy < p.ny) {
       dmask |= 1u << i;
       const int g = gy * p.nx + gx;
       const uint8_t ci = p.cell[g];
       if (!(ci & C_SOLID)) {
-        k_ = (float)cell_k(ci);
+        if constexpr (VAR) {
+          face_betas(p.ce, p.cn, g, p.nx, ci, be[i], bw[i], bn[i], bs[i]);
+          k_ = (be[i] + bw[i]) + (bn[i] + bs[i]);
+        } else {
+          k_ = (float)cell_k(ci);
+        }
         b_ = -p.dx2 * p.d[g];
         x_ = p.phi[g];
       }
@@ -413,7 +473,8 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
     }
     if (!exchange(u, uex)) return false;
     band_edges<R>(u, edge, q, wave, lane, &below, &above);
-    apply_A<R>(u, kk, below, above, w);
+    if constexpr (VAR) apply_A_var<R>(u, kk, be, bw, bn, bs, below, above, w);
+    else apply_A<R>(u, kk, below, above, w);
     if (!reduce3()) return false;
     alpha = del > 0.0 ? gam / del : 0.0;
     beta = 0.0;
@@ -424,7 +485,8 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
     if (!exchange(x, xex)) return false;
     float ax[R];
     band_edges<R>(x, edge, q, wave, lane, &below, &above);
-    apply_A<R>(x, kk, below, above, ax);
+    if constexpr (VAR) apply_A_var<R>(x, kk, be, bw, bn, bs, below, above, ax);
+    else apply_A<R>(x, kk, below, above, ax);
 #pragma unroll
     for (int i = 0; i < R; ++i) r[i] = kk[i] > 0.f ? bb[i] - ax[i] : 0.f;
     return true;
@@ -452,17 +514,18 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
         const size_t c = (size_t)gy * p.nx + gx;
         const uint8_t ci = p.cell[c];
         const float pc = x[i];
+        const float fw = VAR ? bw[i] : 1.f, fs = VAR ? bs[i] : 1.f, fn = VAR ? bn[i] : 1.f;
         if (ci & C_W) {
           float* f = p.u + (size_t)gy * (p.nx + 1) + gx;
-          st_agent(f, ld_agent(f) - (pc - west) * p.inv_dx);
+          st_agent(f, ld_agent(f) - fw * ((pc - west) * p.inv_dx));
         }
         if (ci & C_S) {
           float* f = p.v + c;
-          st_agent(f, ld_agent(f) - (pc - south) * p.inv_dx);
+          st_agent(f, ld_agent(f) - fs * ((pc - south) * p.inv_dx));
         }
         if (gy == p.ny - 1 && (ci & C_N)) {
           float* f = p.v + plane + gx;
-          st_agent(f, ld_agent(f) - (0.f - pc) * p.inv_dx);
+          st_agent(f, ld_agent(f) - fn * ((0.f - pc) * p.inv_dx));
         }
         p.phi_acc[c] += pc;
       }
@@ -524,7 +587,8 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
     }
     if (!exchange(u, uex)) return;
     band_edges<R>(u, edge, q, wave, lane, &below, &above);
-    apply_A<R>(u, kk, below, above, w);
+    if constexpr (VAR) apply_A_var<R>(u, kk, be, bw, bn, bs, below, above, w);
+    else apply_A<R>(u, kk, below, above, w);
     const double gam_old = gam;
     if (!reduce3()) return;
     beta = gam_old != 0.0 ? gam / gam_old : 0.0;
@@ -612,13 +676,14 @@ bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, i
 template <int R>
 static hipError_t launch_jacobi(JacParams& p, int G, hipStream_t s) {
   void* args[] = {&p};
-  return hipLaunchCooperativeKernel((const void*)jacobi_reg<R>, dim3(G), dim3(256), args, 0, s);
+  const void* k = p.ce ? (const void*)jacobi_reg<R, true> : (const void*)jacobi_reg<R, false>;
+  return hipLaunchCooperativeKernel(k, dim3(G), dim3(256), args, 0, s);
 }
 
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      int checkpoint_every, float* phi_ckpt, int tile_rows, float* u, float* v,
-                      const Ws& w, hipStream_t s) {
+                      int checkpoint_every, float* phi_ckpt, int tile_rows, bool var, float* u,
+                      float* v, const Ws& w, hipStream_t s) {
   JacParams p{};
   int R = 0, H = 0, ntx = 0, nty = 0;
   if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, &R, &H, &ntx, &nty))
@@ -634,6 +699,8 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
   p.ckpt = phi_ckpt;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.phi_acc = w.phi_acc; p.u = u; p.v = v;
   p.exch = w.exch; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
+  p.ce = var ? w.coef_e : nullptr;
+  p.cn = var ? w.coef_n : nullptr;
   const int G = ntx * nty;
   switch (R) {
     case 4: return launch_jacobi<4>(p, G, s);
@@ -649,11 +716,13 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
 template <int R>
 static hipError_t launch_pcg(PcgParams& p, int G, hipStream_t s) {
   void* args[] = {&p};
-  return hipLaunchCooperativeKernel((const void*)pcg_reg<R>, dim3(G), dim3(256), args, 0, s);
+  const void* k = p.ce ? (const void*)pcg_reg<R, true> : (const void*)pcg_reg<R, false>;
+  return hipLaunchCooperativeKernel(k, dim3(G), dim3(256), args, 0, s);
 }
 
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
-                   int check_every, int fixed_iters, float* u, float* v, const Ws& w, hipStream_t s) {
+                   int check_every, int fixed_iters, bool var, float* u, float* v, const Ws& w,
+                   hipStream_t s) {
   PcgParams p{};
   int R = 0, ntx = 0, nty = 0;
   if (!pcg_geom(dev, nx, ny, &R, &ntx, &nty)) return hipErrorInvalidValue;
@@ -665,6 +734,8 @@ hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int
   p.max_iters = max_iters; p.check_every = check_every; p.fixed_iters = fixed_iters;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.phi_acc = w.phi_acc; p.u = u; p.v = v;
   p.exch = w.exch; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
+  p.ce = var ? w.coef_e : nullptr;
+  p.cn = var ? w.coef_n : nullptr;
   const int G = ntx * nty;
   switch (R) {
     case 4: return launch_pcg<4>(p, G, s);

@@ -241,13 +241,20 @@ hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const
 // thread rewrites only the faces it owns, so no face is read after another
 // thread's update.  p = rho0 phi / dt.
 // ---------------------------------------------------------------------------
+// Eq. (2): u -= beta grad phi on the open faces each cell owns (west, south,
+// and the open top face), p = rho0 (phi_acc + phi) / dt.  beta = 1 for the
+// constant-coefficient operator (VAR = false); for the variable-density one
+// beta = rho0 / rho_face from the coefficient planes (ce: east face of each
+// cell, cn: north face).
+template <bool VAR>
 __global__ __launch_bounds__(256) void grad_kernel(int nx, int ny, float inv_dx, double rho0,
                                                    double dt_host, int dt_dev,
                                                    const uint8_t* __restrict__ cell,
                                                    const float* __restrict__ phi,
                                                    const float* __restrict__ phi_acc, float* u,
                                                    float* v, float* __restrict__ p,
-                                                   const Scalars* sc) {
+                                                   const Scalars* sc, const float* __restrict__ ce,
+                                                   const float* __restrict__ cn) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nx * ny) return;
   const float p_scale = (float)(rho0 / (dt_dev ? sc->dt : dt_host));
@@ -255,10 +262,43 @@ __global__ __launch_bounds__(256) void grad_kernel(int nx, int ny, float inv_dx,
   const uint8_t ci = cell[c];
   const bool fl = !(ci & C_SOLID);
   const float pc = phi[c];
-  if (fl && (ci & C_W)) u[j * U + i] -= (pc - phi[c - 1]) * inv_dx;
-  if (fl && (ci & C_S)) v[j * nx + i] -= (pc - phi[c - nx]) * inv_dx;
-  if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= (0.f - pc) * inv_dx;
+  if constexpr (VAR) {
+    if (fl && (ci & C_W)) u[j * U + i] -= ce[c - 1] * ((pc - phi[c - 1]) * inv_dx);
+    if (fl && (ci & C_S)) v[j * nx + i] -= cn[c - nx] * ((pc - phi[c - nx]) * inv_dx);
+    if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= cn[c] * ((0.f - pc) * inv_dx);
+  } else {
+    if (fl && (ci & C_W)) u[j * U + i] -= (pc - phi[c - 1]) * inv_dx;
+    if (fl && (ci & C_S)) v[j * nx + i] -= (pc - phi[c - nx]) * inv_dx;
+    if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= (0.f - pc) * inv_dx;
+  }
   p[c] = fl ? (phi_acc[c] + pc) * p_scale : 0.f;
+}
+
+// Face coefficients of the variable-density operator: beta = rho0 / rho_f on
+// the east and north faces of every non-solid cell, rho_f the mean of the
+// two cells (the cell itself on the open top face), 0 on closed faces.
+__global__ __launch_bounds__(256) void coef_kernel(int nx, int ny, double rho0,
+                                                   const uint8_t* __restrict__ cell,
+                                                   const float* __restrict__ rho,
+                                                   float* __restrict__ ce, float* __restrict__ cn) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nx * ny) return;
+  const int j = c / nx;
+  const uint8_t ci = cell[c];
+  float e = 0.f, n = 0.f;
+  if (!(ci & C_SOLID)) {
+    const double rc = rho[c];
+    if (ci & C_E) e = (float)(rho0 / (0.5 * (rc + (double)rho[c + 1])));
+    if (ci & C_N) n = (float)(j == ny - 1 ? rho0 / rc : rho0 / (0.5 * (rc + (double)rho[c + nx])));
+  }
+  ce[c] = e;
+  cn[c] = n;
+}
+
+hipError_t run_coef(int nx, int ny, double rho0, const float* rho, const Ws& w, hipStream_t s) {
+  const int n = nx * ny;
+  coef_kernel<<<(n + 255) / 256, 256, 0, s>>>(nx, ny, rho0, w.cell, rho, w.coef_e, w.coef_n);
+  return hipGetLastError();
 }
 
 // Divergence of the returned faces: FP64 sum of |div| and max |div|.
@@ -313,11 +353,15 @@ __global__ __launch_bounds__(256) void finish_kernel(int nblocks, const double* 
 
 hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt, bool dt_dev,
                                float* u, float* v, float* p, const Ws& w, int nblocks, void* res,
-                               hipStream_t s) {
+                               bool var, hipStream_t s) {
   if ((size_t)2 * nblocks > w.blockpart_n) return hipErrorInvalidValue;
   const float inv_dx = (float)(1.0 / dx);
-  grad_kernel<<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, rho0, dt, dt_dev ? 1 : 0, w.cell, w.phi,
-                                      w.phi_acc, u, v, p, w.sc);
+  if (var)
+    grad_kernel<true><<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, rho0, dt, dt_dev ? 1 : 0, w.cell, w.phi,
+                                              w.phi_acc, u, v, p, w.sc, w.coef_e, w.coef_n);
+  else
+    grad_kernel<false><<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, rho0, dt, dt_dev ? 1 : 0, w.cell, w.phi,
+                                               w.phi_acc, u, v, p, w.sc, nullptr, nullptr);
   check_kernel<<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, w.cell, u, v, w.blockpart);
   finish_kernel<<<1, 256, 0, s>>>(nblocks, w.blockpart, w.sc, (hyp_result*)res);
   return hipGetLastError();
