@@ -17,67 +17,67 @@
 
 namespace hyp {
 
-// ---- pyramid input: level k pixel = mean over its 2^k x 2^k block of ------
-// [d/s, solid]; stored NHWC with 2 channels in the storage type.
+// ---- pyramid input: level k pixel = mean of the 2x2 level k-1 pixels it ---
+// covers (level 0 = [d/s, solid]); a work-group reduces a 32x32 region of
+// level 0 in LDS level by level (FP32), storing every level NHWC with 2
+// channels in the storage type.  Levels never straddle regions: the grid
+// sides are multiples of 2^(S-1) <= 16.
 struct PyrLaunch {
   void* out[kMaxScales];
   int H[kMaxScales], W[kMaxScales];
   size_t px0[kMaxScales];
   int nscales;
   size_t total_px;
-  int nx;
+  int nx, rtx;  // rtx: 32x32 regions per row
 };
 
 template <typename T>
 __global__ __launch_bounds__(256) void cnn_input(PyrLaunch P, const float* __restrict__ d,
                                                  const uint8_t* __restrict__ cell,
                                                  const Scalars* sc) {
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= P.total_px) return;
-  int k = 0;
-  while (k + 1 < P.nscales && gid >= P.px0[k + 1]) ++k;
-  const int lp = (int)(gid - P.px0[k]);
-  const int X = lp % P.W[k], Y = lp / P.W[k];
-  const int B = 1 << k;
+  __shared__ float lv[2][32][33];  // [channel][y][x] of the current level
+  const int x0 = (blockIdx.x % P.rtx) * 32, y0 = (blockIdx.x / P.rtx) * 32;
   const double s = sc->s;
   const float inv_s = s > 0.0 ? (float)(1.0 / s) : 0.f;
-  float sd = 0.f, ss = 0.f;
-  for (int yy = 0; yy < B; ++yy)
-    for (int xx = 0; xx < B; ++xx) {
-      const int c = (Y * B + yy) * P.nx + X * B + xx;
+  for (int e = threadIdx.x; e < 1024; e += 256) {
+    const int ly = e >> 5, lx = e & 31, gx = x0 + lx, gy = y0 + ly;
+    float vd = 0.f, vs = 0.f;
+    if (gx < P.W[0] && gy < P.H[0]) {
+      const int c = gy * P.nx + gx;
       const bool solid = cell[c] & C_SOLID;
-      sd += solid ? 0.f : d[c] * inv_s;
-      ss += solid ? 1.f : 0.f;
+      vd = solid ? 0.f : d[c] * inv_s;
+      vs = solid ? 1.f : 0.f;
+      T* o = reinterpret_cast<T*>(P.out[0]) + (size_t)c * 2;
+      o[0] = St<T>::from(vd);
+      o[1] = St<T>::from(vs);
     }
-  const float inv_n = 1.f / (float)(B * B);
-  T* o = reinterpret_cast<T*>(P.out[k]) + (size_t)lp * 2;
-  o[0] = St<T>::from(sd * inv_n);
-  o[1] = St<T>::from(ss * inv_n);
-}
-
-// ---- head: y = w_out . act + b_out (1x1, linear) for every pixel ---------
-struct HeadLaunch {
-  const void* act[kMaxScales];
-  const float* w[kMaxScales];
-  const float* b[kMaxScales];
-  size_t px0[kMaxScales];
-  int nscales;
-  size_t total_px;
-};
-
-template <typename T, int C>
-__global__ __launch_bounds__(256) void cnn_head(HeadLaunch Hd, float* __restrict__ y) {
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= Hd.total_px) return;
-  int k = 0;
-  while (k + 1 < Hd.nscales && gid >= Hd.px0[k + 1]) ++k;
-  const size_t lp = gid - Hd.px0[k];
-  const T* a = reinterpret_cast<const T*>(Hd.act[k]) + lp * C;
-  const float* w = Hd.w[k];
-  float acc = 0.f;
-#pragma unroll 8
-  for (int c = 0; c < C; ++c) acc += St<T>::to_f(a[c]) * w[c];
-  y[gid] = acc + Hd.b[k][0];
+    lv[0][ly][lx] = vd;
+    lv[1][ly][lx] = vs;
+  }
+  for (int k = 1; k < P.nscales; ++k) {
+    const int m = 32 >> k;
+    const int t = threadIdx.x, ly = t / m, lx = t % m;
+    const bool act = t < m * m;
+    float a = 0.f, b = 0.f;
+    __syncthreads();
+    if (act) {
+      a = 0.25f * ((lv[0][2 * ly][2 * lx] + lv[0][2 * ly][2 * lx + 1]) +
+                   (lv[0][2 * ly + 1][2 * lx] + lv[0][2 * ly + 1][2 * lx + 1]));
+      b = 0.25f * ((lv[1][2 * ly][2 * lx] + lv[1][2 * ly][2 * lx + 1]) +
+                   (lv[1][2 * ly + 1][2 * lx] + lv[1][2 * ly + 1][2 * lx + 1]));
+    }
+    __syncthreads();
+    if (act) {
+      lv[0][ly][lx] = a;
+      lv[1][ly][lx] = b;
+      const int gx = (x0 >> k) + lx, gy = (y0 >> k) + ly;
+      if (gx < P.W[k] && gy < P.H[k]) {
+        T* o = reinterpret_cast<T*>(P.out[k]) + ((size_t)gy * P.W[k] + gx) * 2;
+        o[0] = St<T>::from(a);
+        o[1] = St<T>::from(b);
+      }
+    }
+  }
 }
 
 // ---- t_k = y_k + up2(t_{k+1}); at k = 0 also phi0 = dx^2 s t on fluid -----
@@ -174,8 +174,9 @@ static hipError_t run_cnn_t(const Device& dev, const NetShape& net, const WsLayo
     P.W[k] = Ly.sc_w[k];
     P.px0[k] = Ly.sc_off_px[k];
   }
-  const int nb_px = (int)((Ly.total_px + 255) / 256);
-  hipLaunchKernelGGL(cnn_input<T>, dim3(nb_px), dim3(256), 0, s, P, w.d, w.cell, w.sc);
+  P.rtx = (nx + 31) / 32;
+  const int nreg = P.rtx * ((ny + 31) / 32);
+  hipLaunchKernelGGL(cnn_input<T>, dim3(nreg), dim3(256), 0, s, P, w.d, w.cell, w.sc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   using WI = WImg<T, C>;
@@ -185,14 +186,17 @@ static hipError_t run_cnn_t(const Device& dev, const NetShape& net, const WsLayo
                      per_scale, S, img);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // four 3x3 layers, all scales per launch
+  // four 3x3 layers, all scales per launch; the last one also forms the 1x1
+  // head y_k in its epilogue (and stores its activations only for training)
   const T* src = in;
   T* bufs[2] = {a0, a1};
   T* save = reinterpret_cast<T*>(w.cnn_save);
+  const size_t hoff = (size_t)C * 18 + C + 3 * ((size_t)C * 9 * C + C);
   for (int l = 0; l < 4; ++l) {
     T* dst = net.train ? save + (size_t)l * Ly.total_px * C : bufs[l & 1];
     ConvLaunch L{};
     L.nscales = S;
+    L.skip_store = (l == 3 && !net.train) ? 1 : 0;
     int tiles = 0;
     const int cin = l == 0 ? 2 : C;
     size_t woff = l == 0 ? 0 : (size_t)C * 18 + C + (size_t)(l - 1) * ((size_t)C * 9 * C + C);
@@ -207,28 +211,21 @@ static hipError_t run_cnn_t(const Device& dev, const NetShape& net, const WsLayo
       D.tiles_x = (D.W + TW - 1) / TW;
       D.tile0 = tiles;
       D.ostr = C;
+      D.hw = params + k * per_scale + hoff;
+      D.y = w.cnn_y + Ly.sc_off_px[k];
       tiles += D.tiles_x * ((D.H + TH - 1) / TH);
     }
     L.total_tiles = tiles;
     // launch on the caller's stream
-    e = l == 0 ? launch_conv<T, 3, 2, C, true>(L, dev.cu, s) : launch_conv<T, 3, C, C, true>(L, dev.cu, s);
+    if (l == 0)
+      e = launch_conv<T, 3, 2, C, true>(L, dev.cu, s);
+    else if (l < 3)
+      e = launch_conv<T, 3, C, C, true>(L, dev.cu, s);
+    else
+      e = launch_conv<T, 3, C, C, true, true>(L, dev.cu, s);
     if (e != hipSuccess) return e;
     src = dst;
   }
-  // 1x1 head for every scale
-  HeadLaunch Hd{};
-  Hd.nscales = S;
-  Hd.total_px = Ly.total_px;
-  const size_t hoff = (size_t)C * 18 + C + 3 * ((size_t)C * 9 * C + C);
-  for (int k = 0; k < S; ++k) {
-    Hd.act[k] = src + Ly.sc_off_px[k] * C;
-    Hd.w[k] = params + k * per_scale + hoff;
-    Hd.b[k] = Hd.w[k] + C;
-    Hd.px0[k] = Ly.sc_off_px[k];
-  }
-  hipLaunchKernelGGL((cnn_head<T, C>), dim3(nb_px), dim3(256), 0, s, Hd, w.cnn_y);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   // coarse-to-fine upsample-sum
   for (int k = S - 1; k >= 0; --k) {
     const int H = Ly.sc_h[k], W = Ly.sc_w[k];

@@ -20,6 +20,7 @@ namespace hyp {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   // round to nearest even (finite inputs)
@@ -51,11 +52,14 @@ struct ScaleDesc {
   int H, W;
   int ostr;           // output elements per pixel (Cout, or wider inside a concatenation)
   int tiles_x, tile0; // tile columns, first global tile index of this scale
+  const float* hw;    // fused 1x1 head (HEAD instances): w[Cout] then bias
+  float* y;           // ... its FP32 output, one value per pixel
 };
 
 struct ConvLaunch {
   ScaleDesc sc[kMaxScales];
   int nscales, total_tiles, tiles_per_wg;
+  int skip_store;     // HEAD instances: 1 = do not store the activations
 };
 
 // K step of one MFMA fragment and the padded weight row, shared by the
@@ -224,7 +228,41 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
   }
 }
 
-template <typename T, int KS, int CIN, int COUT, bool RELU>
+// The 16-byte pieces of an input tile (replicated border) that thread
+// threadIdx.x loads into registers, and their store into the LDS tile.
+template <typename T, int CIN, int EW, int HALO, int PCH, int NPIECE, int NPF>
+__device__ __forceinline__ void conv_prefetch(const ScaleDesc& S, int x0, int y0, u32x4 (&pf)[NPF]) {
+  const T* in = reinterpret_cast<const T*>(S.in);
+#pragma unroll
+  for (int i = 0; i < NPF; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (256 * (i + 1) <= NPIECE || e < NPIECE) {
+      const int pix = e / PCH, piece = e % PCH;
+      const int gy = min(max(y0 - HALO + pix / EW, 0), S.H - 1);
+      const int gx = min(max(x0 - HALO + pix % EW, 0), S.W - 1);
+      pf[i] = *reinterpret_cast<const u32x4*>(
+          reinterpret_cast<const char*>(in + ((size_t)gy * S.W + gx) * CIN) + piece * 16);
+    }
+  }
+}
+
+template <typename T, int PSTR, int PCH, int NPIECE, int NPF>
+__device__ __forceinline__ void conv_commit(T* xl, const u32x4 (&pf)[NPF]) {
+#pragma unroll
+  for (int i = 0; i < NPF; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (256 * (i + 1) <= NPIECE || e < NPIECE) {
+      const int pix = e / PCH, piece = e % PCH;
+      *reinterpret_cast<u32x4*>(reinterpret_cast<char*>(xl + pix * PSTR) + piece * 16) = pf[i];
+    }
+  }
+}
+
+// HEAD: the layer is followed by a linear 1x1 convolution to one channel;
+// its output y = sum_c w_c a_c + b is formed in the epilogue from the
+// activations as stored (rounded to the storage type), summed over the
+// lane's output channels and across the four lane groups of a pixel.
+template <typename T, int KS, int CIN, int COUT, bool RELU, bool HEAD = false>
 __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
   using Gm = ConvGeom<T, KS, CIN, COUT>;
   constexpr int EW = Gm::EW, EH = Gm::EH, HALO = Gm::HALO;
@@ -271,19 +309,41 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
       }
     }
   };
-  for (int t = t_begin; t < t_end; ++t) {
-    int k = 0;
+  // Wide inputs held whole in LDS are software-pipelined: the next tile's
+  // 16-byte pieces are loaded into registers before this tile's MFMAs and
+  // written to LDS after them, so their latency hides behind the math.
+  constexpr bool PIPE = !Gm::SMALL && Gm::NCH == 1;
+  constexpr int PCH = Gm::SMALL ? 1 : Gm::CC * (int)sizeof(T) / 16;  // pieces per pixel
+  constexpr int NPIECE = EH * EW * PCH;
+  constexpr int NPF = PIPE ? (NPIECE + 255) / 256 : 1;
+  u32x4 pf[NPF];
+  auto locate = [&](int t, int& k, int& x0, int& y0) {
+    k = 0;
     while (k + 1 < L.nscales && t >= L.sc[k + 1].tile0) ++k;
+    const int lt = t - L.sc[k].tile0;
+    x0 = (lt % L.sc[k].tiles_x) * TW;
+    y0 = (lt / L.sc[k].tiles_x) * TH;
+  };
+  if constexpr (PIPE) {
+    if (t_begin < t_end) {
+      int k, x0, y0;
+      locate(t_begin, k, x0, y0);
+      conv_prefetch<T, CIN, EW, HALO, PCH, NPIECE, NPF>(L.sc[k], x0, y0, pf);
+      conv_commit<T, Gm::PSTR, PCH, NPIECE, NPF>(xl, pf);
+    }
+  }
+  for (int t = t_begin; t < t_end; ++t) {
+    int k, x0, y0;
+    locate(t, k, x0, y0);
     const ScaleDesc& S = L.sc[k];
     if (Gm::PASSES == 1 && Gm::NCH == 1 && k != cur) {
       load_weights(S.wimg, 0, 0);
       cur = k;
     }
-    const int lt = t - S.tile0;
-    const int x0 = (lt % S.tiles_x) * TW, y0 = (lt / S.tiles_x) * TH;
-    if (Gm::NCH == 1) load_tile(S, x0, y0, 0);
+    if constexpr (!PIPE && Gm::NCH == 1) load_tile(S, x0, y0, 0);
     const int col = lane & 15, g = lane >> 4;
     T* out = reinterpret_cast<T*>(S.out);
+    float hpart[4] = {0.f, 0.f, 0.f, 0.f};  // HEAD: partial 1x1 sums per row
     for (int pass = 0; pass < Gm::PASSES; ++pass) {
       floatx4 acc[Gm::MB][4];
 #pragma unroll
@@ -293,6 +353,15 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
       if constexpr (Gm::NCH == 1) {
         if (Gm::PASSES > 1) load_weights(S.wimg, 0, pass * Gm::CT);
         __syncthreads();
+        // issued after the last barrier before the MFMAs, so that no barrier
+        // waits for these loads before the math starts
+        if constexpr (PIPE) {
+          if (pass == 0 && t + 1 < t_end) {
+            int kn, xn, yn;
+            locate(t + 1, kn, xn, yn);
+            conv_prefetch<T, CIN, EW, HALO, PCH, NPIECE, NPF>(L.sc[kn], xn, yn, pf);
+          }
+        }
         conv_tile<T, KS, CIN, COUT>(wl, xl, acc, wave, lane);
       } else {
         // K walks the input in chunks: weights and tile of each chunk
@@ -304,23 +373,38 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
         }
       }
       // epilogue: bias (+ ReLU); lane holds couts 4g..4g+3 of block mb for pixel col
+      float4 bias[Gm::MB];
+#pragma unroll
+      for (int mb = 0; mb < Gm::MB; ++mb) {
+        // the packed parameters give the bias no 16-byte alignment
+        const float* bp = S.b + pass * Gm::CT + mb * 16 + g * 4;
+        bias[mb] = make_float4(bp[0], bp[1], bp[2], bp[3]);
+      }
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
         const int gy = y0 + wave * 4 + nb, gx = x0 + col;
-        if (gy >= S.H || gx >= S.W) continue;
+        const bool inside = gy < S.H && gx < S.W;
+        if (!HEAD && !inside) continue;
         T* dst = out + ((size_t)gy * S.W + gx) * S.ostr;
 #pragma unroll
         for (int mb = 0; mb < Gm::MB; ++mb) {
           const int co = pass * Gm::CT + mb * 16 + g * 4;
-          float v0 = acc[mb][nb][0] + S.b[co + 0];
-          float v1 = acc[mb][nb][1] + S.b[co + 1];
-          float v2 = acc[mb][nb][2] + S.b[co + 2];
-          float v3 = acc[mb][nb][3] + S.b[co + 3];
+          float v0 = acc[mb][nb][0] + bias[mb].x;
+          float v1 = acc[mb][nb][1] + bias[mb].y;
+          float v2 = acc[mb][nb][2] + bias[mb].z;
+          float v3 = acc[mb][nb][3] + bias[mb].w;
           if constexpr (RELU) {
             v0 = fmaxf(v0, 0.f);
             v1 = fmaxf(v1, 0.f);
             v2 = fmaxf(v2, 0.f);
             v3 = fmaxf(v3, 0.f);
+          }
+          if constexpr (HEAD) {
+            hpart[nb] += St<T>::to_f(St<T>::from(v0)) * S.hw[co + 0] +
+                         St<T>::to_f(St<T>::from(v1)) * S.hw[co + 1] +
+                         St<T>::to_f(St<T>::from(v2)) * S.hw[co + 2] +
+                         St<T>::to_f(St<T>::from(v3)) * S.hw[co + 3];
+            if (!inside || L.skip_store) continue;
           }
           if constexpr (sizeof(T) == 4) {
             *reinterpret_cast<float4*>(dst + co) = make_float4(v0, v1, v2, v3);
@@ -333,7 +417,21 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
         }
       }
     }
+    if constexpr (HEAD) {
+      // the four lane groups (g) of a pixel hold disjoint output channels
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        float hs = hpart[nb];
+        hs += __shfl_xor(hs, 16);
+        hs += __shfl_xor(hs, 32);
+        const int gy = y0 + wave * 4 + nb, gx = x0 + col;
+        if (g == 0 && gy < S.H && gx < S.W) S.y[(size_t)gy * S.W + gx] = hs + S.hw[COUT];
+      }
+    }
     __syncthreads();
+    if constexpr (PIPE) {
+      if (t + 1 < t_end) conv_commit<T, Gm::PSTR, PCH, NPIECE, NPF>(xl, pf);
+    }
   }
 }
 
@@ -356,10 +454,10 @@ __device__ __forceinline__ void write_wimg(const float* __restrict__ w, T* __res
 
 // Launch one layer over the tile list of L on stream s (grid: up to 2
 // work-groups per CU, whole tiles per work-group).
-template <typename T, int KS, int CIN, int COUT, bool RELU>
+template <typename T, int KS, int CIN, int COUT, bool RELU, bool HEAD = false>
 hipError_t launch_conv(ConvLaunch& L, int cu, hipStream_t s) {
   using Gm = ConvGeom<T, KS, CIN, COUT>;
-  hipError_t e = hipFuncSetAttribute((const void*)conv_mfma<T, KS, CIN, COUT, RELU>,
+  hipError_t e = hipFuncSetAttribute((const void*)conv_mfma<T, KS, CIN, COUT, RELU, HEAD>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)Gm::LDS);
   if (e != hipSuccess) return e;
   const int tiles = L.total_tiles;
@@ -367,7 +465,7 @@ hipError_t launch_conv(ConvLaunch& L, int cu, hipStream_t s) {
   const int G = min(tiles, cu * 2);
   L.tiles_per_wg = (tiles + G - 1) / G;
   const int nwg = (tiles + L.tiles_per_wg - 1) / L.tiles_per_wg;
-  hipLaunchKernelGGL((conv_mfma<T, KS, CIN, COUT, RELU>), dim3(nwg), dim3(256), Gm::LDS, s, L);
+  hipLaunchKernelGGL((conv_mfma<T, KS, CIN, COUT, RELU, HEAD>), dim3(nwg), dim3(256), Gm::LDS, s, L);
   return hipGetLastError();
 }
 
