@@ -22,7 +22,7 @@ def project(flags, u, v, dx: float, dt: float = 1.0, rho0: float = 1.0,
             threshold: float = 1e-3, method: str = "hybrid", params=None,
             S: int = 3, C: int = 32, bf16: bool = False, omega: float = 1.0,
             check_every: int = 1, max_iters: int = 200000, fixed_iters: int = 0,
-            phi_init=None):
+            phi_init=None, criterion: str = "e1"):
     assert method in METHODS
     P = G.plan(flags)
     u, v = G.enforce_bc(P, np.asarray(u, np.float64), np.asarray(v, np.float64))
@@ -39,10 +39,10 @@ def project(flags, u, v, dx: float, dt: float = 1.0, rho0: float = 1.0,
     status = SV.STATUS_OK
     if method in ("hybrid", "jacobi"):
         phi, iters, status, _ = SV.jacobi(P, d, dx, phi0, threshold, omega,
-                                          check_every, max_iters, fixed_iters)
+                                          check_every, max_iters, fixed_iters, criterion)
     elif method == "pcg":
         phi, iters, status, _ = SV.pcg(P, d, dx, phi0, threshold, check_every,
-                                       max_iters, fixed_iters)
+                                       max_iters, fixed_iters, criterion)
     else:
         phi, iters = phi0, 0
     u2, v2 = G.correct(P, u, v, phi, dx)

@@ -114,3 +114,26 @@ def test_stop_rule_check_every_and_maxiter():
     d2 = d.copy(); d2[P.fluid.nonzero()[0][0], P.fluid.nonzero()[1][0]] = np.nan
     _, k, st, _ = SV.jacobi(P, d2, dx, None, thr=1e-3)
     assert st == SV.STATUS_NONFINITE and k == 0
+
+
+def test_einf_criterion_stops_on_the_max_residual():
+    # E_inf = max |r| (Sec. 4.1's comparison criterion): the returned iterate
+    # is the first tested one whose max |r| is below the threshold, so it is
+    # later than the E_1 stop at the same threshold (mean <= max), and the
+    # tested iterate before it is above the threshold
+    import scenes
+    sc = scenes.plume_scene(24, seed=3, n_obstacles=1)
+    P = G.plan(sc.flags)
+    u, v = scenes.random_faces(24, 24, 3, kind="mixed")
+    d = G.divergence(P, *G.enforce_bc(P, u, v), sc.dx)
+    thr = 0.05 * G.einf(P, d)
+    phi, k, st, E = SV.jacobi(P, d, sc.dx, thr=thr, check_every=3, criterion="einf")
+    assert st == SV.STATUS_OK and E < thr and k % 3 == 0
+    assert G.einf(P, G.residual(P, d, phi, sc.dx)) == E
+    prev = SV.jacobi(P, d, sc.dx, fixed_iters=k - 3)[0]
+    assert G.einf(P, G.residual(P, d, prev, sc.dx)) >= thr
+    k1 = SV.jacobi(P, d, sc.dx, thr=thr, check_every=3)[1]
+    assert k1 <= k
+    phi_c, kc, stc, Ec = SV.pcg(P, d, sc.dx, thr=thr, criterion="einf")
+    assert stc == SV.STATUS_OK and Ec < thr
+    assert G.einf(P, G.residual(P, d, phi_c, sc.dx)) < thr
