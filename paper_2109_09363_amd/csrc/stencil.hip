@@ -155,29 +155,32 @@ __global__ __launch_bounds__(256) void div_kernel(int nx, int ny, float inv_dx,
                                                   double* __restrict__ blockpart, Scalars* sc,
                                                   unsigned* sync, float* __restrict__ phi_acc) {
   __shared__ double red[4];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  sync_clear(sync, c);
-  if (c == 0) sc->bar = 0;
+  const int c0 = blockIdx.x * blockDim.x + threadIdx.x;
+  sync_clear(sync, c0);
+  if (c0 == 0) sc->bar = 0;
   double a = 0.0, q = 0.0;
-  if (c < nx * ny) {
+  // grid-stride: a bounded grid keeps the per-block reduction cheap at
+  // DRAM-resident sizes; faces are written back only where masking changed them
+#pragma unroll 4
+  for (int c = c0; c < nx * ny; c += gridDim.x * blockDim.x) {
     phi_acc[c] = 0.f;
     const int i = c % nx, j = c / nx, U = nx + 1;
     const uint8_t ci = cell[c];
     const bool fl = !(ci & C_SOLID);
-    float uw = u[j * U + i], ue = u[j * U + i + 1];
-    float vs = v[j * nx + i], vn = v[(j + 1) * nx + i];
-    uw = (fl && (ci & C_W)) ? uw : 0.f;
-    ue = (fl && (ci & C_E)) ? ue : 0.f;
-    vn = (fl && (ci & C_N)) ? vn : 0.f;
-    vs = (j == 0) ? ((fl && (ci & C_INFLOW)) ? vs : 0.f) : ((fl && (ci & C_S)) ? vs : 0.f);
-    u[j * U + i] = uw;
-    v[j * nx + i] = vs;
-    if (i == nx - 1) u[j * U + nx] = 0.f;
-    if (j == ny - 1) v[ny * nx + i] = vn;
-    const float dv = fl ? ((ue - uw) + (vn - vs)) * inv_dx : 0.f;
+    const float uw0 = u[j * U + i], ue = u[j * U + i + 1];
+    const float vs0 = v[j * nx + i], vn0 = v[(j + 1) * nx + i];
+    const float uw = (fl && (ci & C_W)) ? uw0 : 0.f;
+    const float uem = (fl && (ci & C_E)) ? ue : 0.f;
+    const float vn = (fl && (ci & C_N)) ? vn0 : 0.f;
+    const float vs = (j == 0) ? ((fl && (ci & C_INFLOW)) ? vs0 : 0.f) : ((fl && (ci & C_S)) ? vs0 : 0.f);
+    if (uw != uw0) u[j * U + i] = uw;
+    if (vs != vs0) v[j * nx + i] = vs;
+    if (i == nx - 1 && ue != 0.f) u[j * U + nx] = 0.f;
+    if (j == ny - 1 && vn != vn0) v[ny * nx + i] = vn;
+    const float dv = fl ? ((uem - uw) + (vn - vs)) * inv_dx : 0.f;
     d[c] = dv;
-    a = fabs((double)dv);
-    q = (double)dv * (double)dv;
+    a += fabs((double)dv);
+    q += (double)dv * (double)dv;
   }
   a = block_sum(a, red);
   q = block_sum(q, red);
@@ -212,6 +215,7 @@ __global__ __launch_bounds__(256) void div_finish(int nblocks, const double* __r
 hipError_t run_div(int nx, int ny, double dx, float* u, float* v, const Ws& w, int nblocks,
                    hipStream_t s) {
   if ((size_t)2 * nblocks > w.blockpart_n) return hipErrorInvalidValue;
+  nblocks = nblocks < kStreamGrid ? nblocks : kStreamGrid;
   div_kernel<<<nblocks, 256, 0, s>>>(nx, ny, (float)(1.0 / dx), w.cell, u, v, w.d, w.blockpart,
                                      w.sc, w.sync, w.phi_acc);
   div_finish<<<1, 256, 0, s>>>(nblocks, w.blockpart, w.sc);
@@ -255,23 +259,24 @@ __global__ __launch_bounds__(256) void grad_kernel(int nx, int ny, float inv_dx,
                                                    float* v, float* __restrict__ p,
                                                    const Scalars* sc, const float* __restrict__ ce,
                                                    const float* __restrict__ cn) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nx * ny) return;
   const float p_scale = (float)(rho0 / (dt_dev ? sc->dt : dt_host));
-  const int i = c % nx, j = c / nx, U = nx + 1;
-  const uint8_t ci = cell[c];
-  const bool fl = !(ci & C_SOLID);
-  const float pc = phi[c];
-  if constexpr (VAR) {
-    if (fl && (ci & C_W)) u[j * U + i] -= ce[c - 1] * ((pc - phi[c - 1]) * inv_dx);
-    if (fl && (ci & C_S)) v[j * nx + i] -= cn[c - nx] * ((pc - phi[c - nx]) * inv_dx);
-    if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= cn[c] * ((0.f - pc) * inv_dx);
-  } else {
-    if (fl && (ci & C_W)) u[j * U + i] -= (pc - phi[c - 1]) * inv_dx;
-    if (fl && (ci & C_S)) v[j * nx + i] -= (pc - phi[c - nx]) * inv_dx;
-    if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= (0.f - pc) * inv_dx;
+#pragma unroll 4
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nx * ny; c += gridDim.x * blockDim.x) {
+    const int i = c % nx, j = c / nx, U = nx + 1;
+    const uint8_t ci = cell[c];
+    const bool fl = !(ci & C_SOLID);
+    const float pc = phi[c];
+    if constexpr (VAR) {
+      if (fl && (ci & C_W)) u[j * U + i] -= ce[c - 1] * ((pc - phi[c - 1]) * inv_dx);
+      if (fl && (ci & C_S)) v[j * nx + i] -= cn[c - nx] * ((pc - phi[c - nx]) * inv_dx);
+      if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= cn[c] * ((0.f - pc) * inv_dx);
+    } else {
+      if (fl && (ci & C_W)) u[j * U + i] -= (pc - phi[c - 1]) * inv_dx;
+      if (fl && (ci & C_S)) v[j * nx + i] -= (pc - phi[c - nx]) * inv_dx;
+      if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= (0.f - pc) * inv_dx;
+    }
+    p[c] = fl ? (phi_acc[c] + pc) * p_scale : 0.f;
   }
-  p[c] = fl ? (phi_acc[c] + pc) * p_scale : 0.f;
 }
 
 // Face coefficients of the variable-density operator: beta = rho0 / rho_f on
@@ -308,17 +313,19 @@ __global__ __launch_bounds__(256) void check_kernel(int nx, int ny, float inv_dx
                                                     const float* __restrict__ v,
                                                     double* __restrict__ blockpart) {
   __shared__ double red[4];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  double a = 0.0;
-  if (c < nx * ny) {
+  double a = 0.0, m = 0.0;
+#pragma unroll 4
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nx * ny; c += gridDim.x * blockDim.x) {
     const int i = c % nx, j = c / nx, U = nx + 1;
     if (!(cell[c] & C_SOLID)) {
       const float dv = ((u[j * U + i + 1] - u[j * U + i]) + (v[(j + 1) * nx + i] - v[j * nx + i])) * inv_dx;
-      a = fabs((double)dv);
+      const double ad = fabs((double)dv);
+      a += ad;
+      m = fmax(m, ad);
     }
   }
   const double sum = block_sum(a, red);
-  const double mx = block_max(a, red);
+  const double mx = block_max(m, red);
   if (threadIdx.x == 0) {
     blockpart[2 * blockIdx.x] = sum;
     blockpart[2 * blockIdx.x + 1] = mx;
@@ -356,14 +363,15 @@ hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt
                                bool var, hipStream_t s) {
   if ((size_t)2 * nblocks > w.blockpart_n) return hipErrorInvalidValue;
   const float inv_dx = (float)(1.0 / dx);
+  const int ncheck = nblocks < kStreamGrid ? nblocks : kStreamGrid;
   if (var)
-    grad_kernel<true><<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, rho0, dt, dt_dev ? 1 : 0, w.cell, w.phi,
+    grad_kernel<true><<<ncheck, 256, 0, s>>>(nx, ny, inv_dx, rho0, dt, dt_dev ? 1 : 0, w.cell, w.phi,
                                               w.phi_acc, u, v, p, w.sc, w.coef_e, w.coef_n);
   else
-    grad_kernel<false><<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, rho0, dt, dt_dev ? 1 : 0, w.cell, w.phi,
+    grad_kernel<false><<<ncheck, 256, 0, s>>>(nx, ny, inv_dx, rho0, dt, dt_dev ? 1 : 0, w.cell, w.phi,
                                                w.phi_acc, u, v, p, w.sc, nullptr, nullptr);
-  check_kernel<<<nblocks, 256, 0, s>>>(nx, ny, inv_dx, w.cell, u, v, w.blockpart);
-  finish_kernel<<<1, 256, 0, s>>>(nblocks, w.blockpart, w.sc, (hyp_result*)res);
+  check_kernel<<<ncheck, 256, 0, s>>>(nx, ny, inv_dx, w.cell, u, v, w.blockpart);
+  finish_kernel<<<1, 256, 0, s>>>(ncheck, w.blockpart, w.sc, (hyp_result*)res);
   return hipGetLastError();
 }
 
