@@ -80,6 +80,10 @@ extern "C" {
 
 typedef struct hyp_ctx hyp_ctx;
 
+/* hyp_opts.criterion: the quantity compared with the threshold */
+#define HYP_CRIT_E1    0  /* mean |div u| over fluid cells (E_1, Sec. 4.1) */
+#define HYP_CRIT_EINF  1  /* max |div u| over fluid cells (E_inf) */
+
 /* hyp_net_desc.flags */
 #define HYP_NET_TRAIN  1  /* keep every layer's activations (and the backward
                              buffers) in the workspace for hyp_project_backward */
@@ -172,6 +176,12 @@ typedef struct {
                            PCG, HYBRID (the network's guess is unchanged) and
                            CNN; needs rho; not with the batch or the adjoint
                            (EUNSUPPORTED).  0: rho0 everywhere. */
+  int32_t criterion;    /* HYP_CRIT_E1 (the paper's hybrid criterion, mean
+                           |div u| over fluid cells) or HYP_CRIT_EINF (max
+                           |div u|, the earlier work's criterion compared in
+                           Sec. 4.1) for the threshold test; the result's
+                           e1_cnn then holds the chosen measure of the guess.
+                           Not with the batch (EUNSUPPORTED). */
 } hyp_opts;
 
 /* Written by the device when the projection's last kernel completes. */
@@ -179,7 +189,8 @@ typedef struct {
   int32_t iters;       /* sweeps or CG iterations performed */
   int32_t status;      /* HYP_STATUS_* */
   double e1_init;      /* mean |div u*| over fluid cells before projection */
-  double e1_cnn;       /* mean |d - L phi0| of the initial guess */
+  double e1_cnn;       /* mean |d - L phi0| of the initial guess (max with
+                          HYP_CRIT_EINF) */
   double e1_final;     /* mean |div u| recomputed from the returned faces */
   double einf_final;   /* max  |div u| recomputed from the returned faces */
   double s;            /* CNN input scale sqrt(mean d^2) (0 without CNN) */

@@ -13,6 +13,7 @@ STATUS_OK, STATUS_MAXITER, STATUS_NONFINITE, STATUS_FLOOR, STATUS_ABORTED = 0, 1
 METHODS = {"hybrid": 0, "jacobi": 1, "pcg": 2, "cnn": 3}
 PRECISIONS = {"fp32": 0, "bf16": 1}
 NET_TRAIN = 1
+CRITERIA = {"e1": 0, "einf": 1}
 ARCHS = {"parallel": 0, "multiscale": 1, "smallscale": 2, "unet": 3}
 
 c_i32, c_i64, c_f64, c_f32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float, ctypes.c_void_p
@@ -35,7 +36,8 @@ class Fields(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("method", c_i32), ("max_iters", c_i32), ("check_every", c_i32),
                 ("fixed_iters", c_i32), ("omega", c_f32), ("fold_window", c_i32),
-                ("checkpoint_every", c_i32), ("tile_rows", c_i32), ("variable_density", c_i32)]
+                ("checkpoint_every", c_i32), ("tile_rows", c_i32), ("variable_density", c_i32),
+                ("criterion", c_i32)]
 
 
 class Result(ctypes.Structure):

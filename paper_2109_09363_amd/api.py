@@ -104,12 +104,13 @@ class Projector:
                       max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
                       omega: float = 1.0, rho=None, p_init=None, fold_window: int = 0,
                       checkpoint_every: int = 0, phi_ckpt=None, tile_rows: int = 0,
-                      variable_density: bool = False):
+                      variable_density: bool = False, criterion: str = "e1"):
         """Enqueue one projection on the current stream; u, v corrected in
         place, p written.  Read the result with `result()` after a sync.
         With fixed_iters and checkpoint_every > 0, phi_ckpt (n, ny, nx) float32
         receives the Jacobi iterate after every checkpoint_every sweeps.
-        variable_density keeps rho (required then) inside the operator."""
+        variable_density keeps rho (required then) inside the operator;
+        criterion "einf" stops on max |div u| instead of the mean."""
         nx, ny = self.nx, self.ny
         _need(u, torch.float32, (ny, nx + 1), "u")
         _need(v, torch.float32, (ny + 1, nx), "v")
@@ -130,7 +131,7 @@ class Projector:
         f = L.Fields(_ptr(u), _ptr(v), _ptr(rho), _ptr(flags), _ptr(p), _ptr(p_init), _ptr(phi_ckpt))
         o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
                    float(omega), int(fold_window), int(checkpoint_every), int(tile_rows),
-                   1 if variable_density else 0)
+                   1 if variable_density else 0, L.CRITERIA[criterion])
         L.check("hyp_project", self.lib.hyp_project(
             self.ctx, ctypes.byref(self.grid), ctypes.byref(f), float(threshold), ctypes.byref(o),
             _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
@@ -188,7 +189,8 @@ class Projector:
     def step_async(self, rho, u, v, flags, p, xi, threshold: float, g: float, drho: float,
                    u_in: float = 1.0, cfl: float = 0.5, method: str = "hybrid",
                    max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
-                   omega: float = 1.0, fold_window: int = 0, variable_density: bool = False):
+                   omega: float = 1.0, fold_window: int = 0, variable_density: bool = False,
+                   criterion: str = "e1"):
         """Enqueue one full time step (advection, buoyancy, inflow, projection)
         on the current stream.  rho, u, v advance in place; p is written.
         variable_density projects with the advected density in the operator."""
@@ -204,7 +206,8 @@ class Projector:
         ph = L.Physics(float(g), float(self.grid.rho0), float(drho), float(u_in), float(cfl))
         st = L.State(_ptr(rho), _ptr(u), _ptr(v), _ptr(p), _ptr(flags), _ptr(xi))
         o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
-                   float(omega), int(fold_window), 0, 0, 1 if variable_density else 0)
+                   float(omega), int(fold_window), 0, 0, 1 if variable_density else 0,
+                   L.CRITERIA[criterion])
         L.check("hyp_step", self.lib.hyp_step(
             self.ctx, ctypes.byref(self.grid), ctypes.byref(ph), ctypes.byref(st), float(threshold),
             ctypes.byref(o), _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
@@ -249,7 +252,7 @@ class Batch:
                 self.lib.hyp_batch_workspace_size(self.ctx, self.n, G, ctypes.byref(nbytes)))
         self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         self.res = torch.zeros(self.n * ctypes.sizeof(L.Result), dtype=torch.uint8, device=self.device)
-        o = L.Opts(L.METHODS[method], int(max_iters), 8, 0, float(omega), 0, 0, 0, 0)
+        o = L.Opts(L.METHODS[method], int(max_iters), 8, 0, float(omega), 0, 0, 0, 0, 0)
         b = ctypes.c_void_p()
         torch.cuda.synchronize()
         L.check("hyp_batch_create", self.lib.hyp_batch_create(self.ctx, self.n, G, S, T, ctypes.byref(o),

@@ -279,6 +279,7 @@ static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, 
   if (o->max_iters < 0 || o->check_every < 1 || o->fixed_iters < 0) return HYP_EINVAL;
   if (o->fold_window < 0 || o->checkpoint_every < 0) return HYP_EINVAL;
   if (o->variable_density != 0 && o->variable_density != 1) return HYP_EINVAL;
+  if (o->criterion != HYP_CRIT_E1 && o->criterion != HYP_CRIT_EINF) return HYP_EINVAL;
   if (!(threshold >= 0.0)) return HYP_EINVAL;
   const bool use_cnn = o->method == HYP_METHOD_HYBRID || o->method == HYP_METHOD_CNN;
   if (use_cnn) {
@@ -302,6 +303,7 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
   const int nx = g->nx, ny = g->ny;
   const bool use_cnn = o->method == HYP_METHOD_HYBRID || o->method == HYP_METHOD_CNN;
   const bool var = o->variable_density != 0;
+  const bool einf = o->criterion == HYP_CRIT_EINF;
   ctx->last_var = var;
   mark(ctx, 1, stream);
   if (run_div(nx, ny, g->dx, u, v, w, L.nblocks_stream, stream) != hipSuccess) return HYP_EHIP;
@@ -316,17 +318,17 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
   mark(ctx, 2, stream);
   if (o->method == HYP_METHOD_CNN) {
     // no sweeps: a zero-length Jacobi pass records E_1 of the prediction
-    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, 0, nullptr, 0, var, u, v, w,
-                   stream);
+    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, 0, nullptr, 0, var, einf, u, v,
+                   w, stream);
   } else if (o->method == HYP_METHOD_PCG) {
     // one persistent launch, defect-correction folds included
     e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
-                o->fixed_iters, var, u, v, w, stream);
+                o->fixed_iters, var, einf, u, v, w, stream);
   } else {
     // one persistent launch, defect-correction folds included
     e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,
                    o->fixed_iters, o->fold_window, phi_ckpt ? o->checkpoint_every : 0, phi_ckpt,
-                   o->tile_rows, var, u, v, w, stream);
+                   o->tile_rows, var, einf, u, v, w, stream);
   }
   if (e != hipSuccess) return HYP_EHIP;
   mark(ctx, 3, stream);
@@ -469,7 +471,7 @@ int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_s
   if (!ctx || n < 1 || !grids || !states || !thresholds || !o || !ws || !out) return HYP_EINVAL;
   *out = nullptr;
   if (o->method != HYP_METHOD_HYBRID && o->method != HYP_METHOD_JACOBI) return HYP_EUNSUPPORTED;
-  if (o->variable_density != 0) return HYP_EUNSUPPORTED;
+  if (o->variable_density != 0 || o->criterion != HYP_CRIT_E1) return HYP_EUNSUPPORTED;
   if (o->max_iters < 0 || !(o->omega > 0.f) || o->checkpoint_every != 0) return HYP_EINVAL;
   if (o->method == HYP_METHOD_HYBRID && (ctx->net.scales == 0 || !ctx->params)) return HYP_ENOWEIGHTS;
   for (int i = 0; i < n; ++i) {

@@ -35,6 +35,7 @@ constexpr int kSyncSlots = 2 + kMaxCoopBlocks / kSyncGroup;
 constexpr int kSyncBytes = kSyncSlots * 128;
 constexpr int kStatusRunning = -1;     // Scalars::status while a solve is in progress
 constexpr int kStreamBlock = 256;      // threads of the streaming kernels
+constexpr int kStreamGrid = 2048;      // at most this many blocks in the reducing streaming kernels
 
 struct NetShape {
   int scales = 0, channels = 0, precision = 0;
@@ -107,13 +108,13 @@ hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const
                         hipStream_t s);
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      int checkpoint_every, float* phi_ckpt, int tile_rows, bool var, float* u,
-                      float* v, const Ws& w, hipStream_t s);
+                      int checkpoint_every, float* phi_ckpt, int tile_rows, bool var, bool einf,
+                      float* u, float* v, const Ws& w, hipStream_t s);
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters,
                  int tile_rows);
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
-                   int check_every, int fixed_iters, bool var, float* u, float* v, const Ws& w,
-                   hipStream_t s);
+                   int check_every, int fixed_iters, bool var, bool einf, float* u, float* v,
+                   const Ws& w, hipStream_t s);
 hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt, bool dt_dev,
                                float* u, float* v, float* p, const Ws& w, int nblocks, void* res,
                                bool var, hipStream_t s);

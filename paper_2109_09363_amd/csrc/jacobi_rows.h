@@ -20,10 +20,12 @@ __device__ __forceinline__ float jac_cell(float c, float s, float n, float d, fl
   return c - w * res;
 }
 
+// Without UPDATE: the sum of |r| over the rows in rmask, or their maximum
+// (use_max, the E_inf criterion).
 template <int R, bool UPDATE>
 __device__ __forceinline__ double jac_rows(float (&ph)[R], const float (&dd)[R], const float (&kk)[R],
                                            const float (&ww)[R], float below, float above,
-                                           float inv_dx2, unsigned rmask) {
+                                           float inv_dx2, unsigned rmask, bool use_max = false) {
   if (UPDATE) {
     float nv[R];
 #pragma unroll
@@ -45,7 +47,7 @@ __device__ __forceinline__ double jac_rows(float (&ph)[R], const float (&dd)[R],
     const float w = from_left(c);
     const float res = dd[r] - (((e + w) + (n + prev)) - kk[r] * c) * inv_dx2;
     prev = c;
-    if ((rmask >> r) & 1u) acc += fabs((double)res);
+    if ((rmask >> r) & 1u) acc = use_max ? fmax(acc, fabs((double)res)) : acc + fabs((double)res);
   }
   return acc;
 }
@@ -60,7 +62,7 @@ __device__ __forceinline__ double jac_rows_var(float (&ph)[R], const float (&dd)
                                                const float (&be)[R], const float (&bw)[R],
                                                const float (&bn)[R], const float (&bs)[R],
                                                float below, float above, float inv_dx2,
-                                               unsigned rmask) {
+                                               unsigned rmask, bool use_max = false) {
   auto cell = [&](int r, float s, float n) {
     const float c = ph[r];
     const float e = from_right(c);
@@ -83,7 +85,7 @@ __device__ __forceinline__ double jac_rows_var(float (&ph)[R], const float (&dd)
     const float s = r > 0 ? ph[r - 1] : below;
     const float n = (r + 1 < R) ? ph[r + 1] : above;
     const float res = cell(r, s, n);
-    if ((rmask >> r) & 1u) acc += fabs((double)res);
+    if ((rmask >> r) & 1u) acc = use_max ? fmax(acc, fabs((double)res)) : acc + fabs((double)res);
   }
   return acc;
 }

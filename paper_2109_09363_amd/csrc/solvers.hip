@@ -49,6 +49,7 @@ struct JacParams {
   double thr;
   int max_iters, check_every, fixed_iters;
   int fold_window;      // sweeps per stagnation window (0: no folds)
+  int einf;             // 1: stop on E_inf = max |r| instead of E_1 = mean |r|
   int ckpt_every;       // > 0: write the interior iterate after every ckpt_every sweeps
   float* ckpt;          // ... into plane k / ckpt_every - 1 of this buffer
   const uint8_t* cell;
@@ -174,10 +175,11 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
       edges(&below, &above);
       double part_loc;
       if constexpr (VAR)
-        part_loc = jac_rows_var<R, false>(ph, dd, kk, ww, be, bw, bn, bs, below, above, p.inv_dx2, fmask);
+        part_loc = jac_rows_var<R, false>(ph, dd, kk, ww, be, bw, bn, bs, below, above, p.inv_dx2,
+                                          fmask, p.einf != 0);
       else
-        part_loc = jac_rows<R, false>(ph, dd, kk, ww, below, above, p.inv_dx2, fmask);
-      const double loc = block_sum(part_loc, red);
+        part_loc = jac_rows<R, false>(ph, dd, kk, ww, below, above, p.inv_dx2, fmask, p.einf != 0);
+      const double loc = p.einf ? block_max(part_loc, red) : block_sum(part_loc, red);
       ++t;
       if (threadIdx.x == 0) st_agent(part + blockIdx.x, loc);
     }
@@ -192,9 +194,12 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     double E = 0.0;
     if (test) {
       double a = 0.0;
-      for (int i = threadIdx.x; i < G; i += 256) a += ld_agent(part + i);
-      const double tot = block_sum(a, red);
-      E = nF > 0 ? tot / nF : 0.0;
+      for (int i = threadIdx.x; i < G; i += 256) {
+        const double x = ld_agent(part + i);
+        a = p.einf ? fmax(a, x) : a + x;
+      }
+      const double tot = p.einf ? block_max(a, red) : block_sum(a, red);
+      E = p.einf ? tot : (nF > 0 ? tot / nF : 0.0);
       if (k == 0 && blockIdx.x == 0 && threadIdx.x == 0) p.sc->e1_cnn = E;
       st = decide(k, E, p.thr, p.max_iters, p.check_every, p.fixed_iters);
       if (!ref_set) { E_ref = E; ref_set = true; }
@@ -303,6 +308,7 @@ struct PcgParams {
   float dx2, inv_dx;
   double thr, inv_dx2;
   int max_iters, check_every, fixed_iters;
+  int einf;             // 1: stop on max |r| instead of the mean
   const uint8_t* cell;
   float* d;             // recomputed on the interior at a fold
   float* phi;           // in: initial guess, out: returned iterate
@@ -437,11 +443,11 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
       if ((imask >> i) & 1u) {
         a += (double)r[i] * (double)u[i];
         c += (double)w[i] * (double)u[i];
-        e += fabs((double)r[i]);
+        e = p.einf ? fmax(e, fabs((double)r[i])) : e + fabs((double)r[i]);
       }
     a = block_sum(a, red);
     c = block_sum(c, red);
-    e = block_sum(e, red);
+    e = p.einf ? block_max(e, red) : block_sum(e, red);
     double* pa = p.partial + par * 3 * kMaxCoopBlocks;
     if (threadIdx.x == 0) {
       st_agent(pa + blockIdx.x, a);
@@ -454,11 +460,15 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
     for (int i = threadIdx.x; i < G; i += 256) {
       sa += ld_agent(pa + i);
       sc_ += ld_agent(pa + kMaxCoopBlocks + i);
-      se += ld_agent(pa + 2 * kMaxCoopBlocks + i);
+      const double x = ld_agent(pa + 2 * kMaxCoopBlocks + i);
+      se = p.einf ? fmax(se, x) : se + x;
     }
     gam = block_sum(sa, red);
     del = block_sum(sc_, red);
-    E = nF > 0 ? block_sum(se, red) / nF * p.inv_dx2 : 0.0;
+    if (p.einf)
+      E = block_max(se, red) * p.inv_dx2;
+    else
+      E = nF > 0 ? block_sum(se, red) / nF * p.inv_dx2 : 0.0;
     par ^= 1;
     return true;
   };
@@ -682,9 +692,10 @@ static hipError_t launch_jacobi(JacParams& p, int G, hipStream_t s) {
 
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      int checkpoint_every, float* phi_ckpt, int tile_rows, bool var, float* u,
-                      float* v, const Ws& w, hipStream_t s) {
+                      int checkpoint_every, float* phi_ckpt, int tile_rows, bool var, bool einf,
+                      float* u, float* v, const Ws& w, hipStream_t s) {
   JacParams p{};
+  p.einf = einf ? 1 : 0;
   int R = 0, H = 0, ntx = 0, nty = 0;
   if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, &R, &H, &ntx, &nty))
     return hipErrorInvalidValue;
@@ -721,9 +732,10 @@ static hipError_t launch_pcg(PcgParams& p, int G, hipStream_t s) {
 }
 
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
-                   int check_every, int fixed_iters, bool var, float* u, float* v, const Ws& w,
-                   hipStream_t s) {
+                   int check_every, int fixed_iters, bool var, bool einf, float* u, float* v,
+                   const Ws& w, hipStream_t s) {
   PcgParams p{};
+  p.einf = einf ? 1 : 0;
   int R = 0, ntx = 0, nty = 0;
   if (!pcg_geom(dev, nx, ny, &R, &ntx, &nty)) return hipErrorInvalidValue;
   p.nx = nx; p.ny = ny; p.ntx = ntx;

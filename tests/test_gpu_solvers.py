@@ -211,3 +211,34 @@ def test_pcg_reaches_threshold_below_fp32_floor(n, rel):
     assert g["res"].status == 0
     assert g["res"].e1_final < 1.05 * thr
     assert err <= 1e-3
+
+
+@pytest.mark.parametrize("method,n,seed", [("jacobi", 96, 11), ("pcg", 128, 12), ("hybrid", 64, 13)])
+def test_einf_criterion_matches_oracle(method, n, seed):
+    """Stop on max |div u| (the criterion Sec. 4.1 compares E_1 with)."""
+    from oracle import solve as SV
+    from oracle import cnn as CN
+    say("einf", method, n)
+    sc = scenes.plume_scene(n, seed=seed, n_obstacles=2)
+    u, v = (f32(a) for a in scenes.random_faces(n, n, seed, kind="mixed"))
+    P = G.plan(sc.flags)
+    d = G.divergence(P, *G.enforce_bc(P, u, v), sc.dx)
+    thr = 0.1 * G.einf(P, d)
+    kw = {}
+    phi0 = None
+    if method == "hybrid":
+        w = scenes.random_weights(2, 16, seed, out_scale=0.05)
+        kw = dict(params=w, scales=2, channels=16)
+        phi0 = CN.cnn_phi0(P, d, sc.dx, w, 2, 16)[0]
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=thr, method=method, check_every=4, max_iters=200000,
+                    criterion="einf", **kw)
+    if method == "pcg":
+        _, ko, st, _ = SV.pcg(P, d, sc.dx, thr=thr, check_every=4, criterion="einf")
+    else:
+        _, ko, st, _ = SV.jacobi(P, d, sc.dx, phi0, thr, 1.0, 4, 200000, 0, "einf")
+    kg = g["res"].iters
+    say("  iters gpu", kg, "oracle", ko, "einf_final", g["res"].einf_final, "thr", thr)
+    assert g["res"].status == 0 and st == SV.STATUS_OK
+    tol = max(4, 0.01 * ko) if method != "pcg" else max(8, 0.1 * ko)
+    assert abs(kg - ko) <= tol
+    assert g["res"].einf_final < 1.02 * thr

@@ -82,7 +82,7 @@ def test_host_side_rejections():
     # a projection with a too-small workspace is rejected before any launch
     dummy = ctypes.c_void_p(0x1000)
     f = L.Fields(dummy, dummy, None, dummy, dummy, None, None)
-    o = L.Opts(1, 100, 1, 0, 1.0, 0, 0, 0, 0)
+    o = L.Opts(1, 100, 1, 0, 1.0, 0, 0, 0, 0, 0)
     assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
                            16, None, dummy) == -3
     # hybrid without weights
@@ -94,6 +94,11 @@ def test_host_side_rejections():
     o.check_every = 0
     assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
                            nbytes.value, None, dummy) == -1
+    o.check_every = 1
+    o.criterion = 2  # neither E_1 nor E_inf
+    assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
+                           nbytes.value, None, dummy) == -1
+    o.criterion = 0
     o.check_every = 1
     assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), -1.0, ctypes.byref(o), dummy,
                            nbytes.value, None, dummy) == -1
