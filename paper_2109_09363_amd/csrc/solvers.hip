@@ -434,9 +434,11 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
       if (!((imask >> i) & 1u) && kk[i] > 0.f) v[i] = ld_agent(ex + (size_t)(gy0 + i) * p.nx + gx);
     return true;
   };
-  // merged reduction of (r.u, w.u, sum|r|) over the interior
+  // merged reduction of (r.u, w.u, sum|r| or max|r|) over the interior; forced
+  // inline, since an out-of-line call takes r, u, w by reference and moves
+  // them from registers to scratch memory (twice the time per iteration)
   double gam = 0.0, del = 0.0, E = 0.0;
-  auto reduce3 = [&]() -> bool {
+  auto reduce3 = [&]() __attribute__((always_inline)) -> bool {
     double a = 0.0, c = 0.0, e = 0.0;
 #pragma unroll
     for (int i = 0; i < R; ++i)

@@ -25,6 +25,8 @@ WHAT:
               by `warmup` PCG steps, then `steps` hybrid steps to 1e-3 with
               every candidate in --weights from the same state; mean sweeps
               and ms per step per candidate.
+  checks      hybrid ms per step against the E_1 test interval (validation
+              plumes, --intervals).
   networks    inference time t_inf (divergence + network, the library's phase
               events) of every network on grids of --sizes (default 512):
               the parallel 4-scale 64-channel and 3-scale 32-channel nets and
@@ -87,10 +89,13 @@ class Plume:
             dst.copy_(src)
         torch.cuda.synchronize()
 
+    check_every = 8  # E_1 test interval of the hybrid (PCG tests every iteration)
+
     def step(self, method, thr, s, pr=None):
+        ce = self.check_every if method != "pcg" else 1
         (pr or self.pr).step_async(self.rho, self.u, self.v, self.flags, self.p, self.xi[s], thr,
                                    g=self.sc.g, drho=self.sc.drho, u_in=self.sc.u_in, cfl=0.5,
-                                   method=method, max_iters=1000000, check_every=8)
+                                   method=method, max_iters=1000000, check_every=ce)
 
     def run(self, method, thr, steps, pr=None):
         """`steps` time steps from the snapshot; per-step results and the
@@ -270,6 +275,24 @@ def cmd_dram(a, dev):
           "note": "the projection also runs the divergence, gradient and check passes"})
 
 
+def cmd_checks(a, dev):
+    """Hybrid ms per step against the E_1 test interval on the validation
+    plumes (a test costs about one sweep; a long interval overshoots)."""
+    w = load_trained(dev)
+    res = {ce: [0.0, 0.0] for ce in a.intervals}
+    for seed in a.seeds:
+        pl = Plume(512, seed, a.warmup, dev, w)
+        for ce in a.intervals:
+            pl.check_every = ce
+            rows, t = pl.run("hybrid", 1e-3, a.steps)
+            sm = summarize(rows, t, a.steps)
+            res[ce][0] += sm["ms_per_step"] / len(a.seeds)
+            res[ce][1] += sm["mean_iters"] / len(a.seeds)
+    emit({"what": "checks", "seeds": a.seeds, "steps": a.steps,
+          "ms_per_step": {ce: round(v[0], 4) for ce, v in res.items()},
+          "mean_sweeps": {ce: round(v[1], 1) for ce, v in res.items()}})
+
+
 def cmd_validate(a, dev):
     cands = {os.path.basename(f): torch.from_numpy(np.load(f, allow_pickle=False).astype(np.float32)).to(dev)
              for f in a.weights}
@@ -355,7 +378,9 @@ def cmd_networks(a, dev):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["thresholds", "gain", "batch", "dram", "networks", "validate"])
+    ap.add_argument("what", choices=["thresholds", "gain", "batch", "dram", "networks", "validate",
+                                     "checks"])
+    ap.add_argument("--intervals", type=int, nargs="*", default=[8, 16, 32, 64, 128])
     ap.add_argument("--weights", nargs="*", default=[WEIGHTS])
     ap.add_argument("--sizes", type=int, nargs="*", default=[512])
     ap.add_argument("--seeds", type=int, nargs="*", default=None)
@@ -367,11 +392,11 @@ def main():
     ap.add_argument("--reps", type=int, default=3)
     a = ap.parse_args()
     if a.seeds is None:
-        a.seeds = list(range(100, 108)) if a.what == "validate" else [0, 1, 2, 3, 4]
+        a.seeds = list(range(100, 108)) if a.what in ("validate", "checks") else [0, 1, 2, 3, 4]
     dev = torch.device("cuda")
     t0 = time.time()
     {"thresholds": cmd_thresholds, "gain": cmd_gain, "batch": cmd_batch, "dram": cmd_dram,
-     "networks": cmd_networks, "validate": cmd_validate}[a.what](a, dev)
+     "networks": cmd_networks, "validate": cmd_validate, "checks": cmd_checks}[a.what](a, dev)
     print(f"# {a.what} done in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
 
 
