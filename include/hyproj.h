@@ -147,7 +147,7 @@ typedef struct {
   int32_t max_iters;    /* cap on sweeps / CG iterations (>= 0) */
   int32_t check_every;  /* test E_1 every k updates (>= 1) and at max_iters */
   int32_t fixed_iters;  /* > 0: ignore the threshold, do exactly this many */
-  float omega;          /* Jacobi weight, 1 = the paper's undamped form */
+  float omega;          /* Jacobi weight > 0, 1 = the paper's undamped form (else HYP_EINVAL) */
   int32_t fold_window;  /* defect correction (FP32 residual floor): Jacobi
                            folds its pressure into the faces and restarts on
                            the recomputed divergence when E_1 fell by less

@@ -278,6 +278,7 @@ static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, 
   if (o->method < HYP_METHOD_HYBRID || o->method > HYP_METHOD_CNN) return HYP_EINVAL;
   if (o->max_iters < 0 || o->check_every < 1 || o->fixed_iters < 0) return HYP_EINVAL;
   if (o->fold_window < 0 || o->checkpoint_every < 0) return HYP_EINVAL;
+  if (!(o->omega > 0.f)) return HYP_EINVAL;
   if (o->variable_density != 0 && o->variable_density != 1) return HYP_EINVAL;
   if (o->criterion != HYP_CRIT_E1 && o->criterion != HYP_CRIT_EINF) return HYP_EINVAL;
   if (!(threshold >= 0.0)) return HYP_EINVAL;

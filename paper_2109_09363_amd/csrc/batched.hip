@@ -18,7 +18,7 @@ namespace hyp {
 
 struct BatchInstDev {
   int nx, ny, ntx, tile0, ntiles, max_iters;
-  float inv_dx2, wfac;
+  float inv_dx2, wfac, omega;
   double thr;
   const uint8_t* cell;
   const float* d;
@@ -53,11 +53,12 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
   const bool col_in = gx >= 0 && gx < I.nx;
   const bool lane_int = lane >= H && lane < H + TW && col_in;
   unsigned imask = 0, fmask = 0;
-  float ph[R], dd[R], kk[R], ww[R];
+  // scaled form of the update (jac_rows_scaled): a = omega / k, b = -omega dx^2 d / k
+  float ph[R], aa[R], bb[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int er = wave * R + r, gy = gy0 + r;
-    float d_ = 0.f, k_ = 0.f, w_ = 0.f, p_ = 0.f;
+    float a_ = 0.f, b_ = 0.f, p_ = 0.f;
     if (col_in && gy >= 0 && gy < I.ny) {
       // the three loads are independent (masked afterwards): one round trip
       const int g = gy * I.nx + gx;
@@ -65,10 +66,9 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
       const float dv = I.d[g];
       const float pv = from_phi ? I.phi[g] : ld_agent(src + g);
       if (!(ci & C_SOLID)) {
-        const int k = cell_k(ci);
-        k_ = (float)k;
-        d_ = dv;
-        w_ = I.wfac / (float)k;
+        const float k = (float)cell_k(ci);
+        a_ = I.omega / k;
+        b_ = -(I.wfac / k) * dv;
         p_ = pv;
       }
       if (lane_int && er >= H && er < H + TH) {
@@ -76,24 +76,36 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
         if (!(ci & C_SOLID)) fmask |= 1u << r;
       }
     }
-    ph[r] = p_; dd[r] = d_; kk[r] = k_; ww[r] = w_;
+    ph[r] = p_; aa[r] = a_; bb[r] = b_;
   }
   int q = 0;
   float below, above;
-  auto edges = [&]() {
-    edge[q][0][wave][lane] = ph[0];
-    edge[q][1][wave][lane] = ph[R - 1];
+  auto edges_of = [&](const float (&v)[R]) {
+    edge[q][0][wave][lane] = v[0];
+    edge[q][1][wave][lane] = v[R - 1];
     __syncthreads();
     below = wave > 0 ? edge[q][1][wave - 1][lane] : 0.f;
     above = wave < 3 ? edge[q][0][wave + 1][lane] : 0.f;
     q ^= 1;
   };
-  for (int s = 0; s < B; ++s) {
-    edges();
-    jac_rows<R, true>(ph, dd, kk, ww, below, above, I.inv_dx2, 0u);
+  // sweeps in pairs (ph -> tmp -> ph: no register copies between sweeps)
+  const float om1 = 1.f - I.omega;
+  float tmp[R];
+  int s = 0;
+  for (; s + 2 <= B; s += 2) {
+    edges_of(ph);
+    jac_rows_scaled<R, false>(ph, tmp, aa, bb, below, above, om1);
+    edges_of(tmp);
+    jac_rows_scaled<R, false>(tmp, ph, aa, bb, below, above, om1);
   }
-  edges();
-  const double acc = jac_rows<R, false>(ph, dd, kk, ww, below, above, I.inv_dx2, fmask);
+  for (; s < B; ++s) {
+    edges_of(ph);
+    jac_rows_scaled<R, false>(ph, tmp, aa, bb, below, above, om1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) ph[r] = tmp[r];
+  }
+  edges_of(ph);
+  const double acc = jac_resid_scaled<R>(ph, aa, bb, below, above, I.omega, I.inv_dx2, fmask, false);
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if ((imask >> r) & 1u) st_agent(dst + (size_t)(gy0 + r) * I.nx + gx, ph[r]);
@@ -250,6 +262,7 @@ hipError_t batch_setup(void* area, int ninst, const int* nx, const int* ny, cons
     I.max_iters = max_iters;
     I.inv_dx2 = (float)(1.0 / (dx[i] * dx[i]));
     I.wfac = (float)(omega * dx[i] * dx[i]);
+    I.omega = omega;
     I.thr = thr[i];
     I.cell = ws[i].cell; I.d = ws[i].d; I.phi = ws[i].phi; I.exch = ws[i].exch; I.sc = ws[i].sc;
     for (int t = 0; t < I.ntiles; ++t) ht[t0 + t] = i;

@@ -7,47 +7,49 @@
 
 namespace hyp {
 
-// One pass over the R rows of a lane: new value (or residual) of every cell.
-// `below`/`above` are the rows just outside the band (from LDS).  The update
-// computes the rows that need no band edge first, so that the LDS reads of
-// the edges are in flight meanwhile.
-template <int R>
-__device__ __forceinline__ float jac_cell(float c, float s, float n, float d, float k, float w,
-                                          float inv_dx2) {
-  const float e = from_right(c);
-  const float wv = from_left(c);
-  const float res = d - (((e + wv) + (n + s)) - k * c) * inv_dx2;
-  return c - w * res;
+// Constant-coefficient sweep in scaled form.  With a = omega / k and
+// b = -omega dx^2 d / k on fluid cells (0 elsewhere, so those cells stay 0),
+// the weighted Jacobi update phi - omega dx^2 r / k, r = d - (S - k phi) / dx^2
+// and S the sum of the four neighbours, is (1 - omega) phi + a S + b: one FMA
+// after the neighbour sum (two when omega != 1, om1 = 1 - omega).  Reads src,
+// writes dst (two register sets, so that two sweeps need no copies).
+template <int R, bool OMEGA1>
+__device__ __forceinline__ void jac_rows_scaled(const float (&src)[R], float (&dst)[R],
+                                                const float (&aa)[R], const float (&bb)[R],
+                                                float below, float above, float om1) {
+  auto cell = [&](int r, float s, float n) {
+    const float c = src[r];
+    const float S = (from_right(c) + from_left(c)) + (n + s);
+    const float y = fmaf(S, aa[r], bb[r]);
+    return OMEGA1 ? y : fmaf(om1, c, y);
+  };
+#pragma unroll
+  for (int r = 1; r + 1 < R; ++r) dst[r] = cell(r, src[r - 1], src[r + 1]);
+  dst[0] = cell(0, below, src[1]);
+  dst[R - 1] = cell(R - 1, src[R - 2], above);
 }
 
-// Without UPDATE: the sum of |r| over the rows in rmask, or their maximum
-// (use_max, the E_inf criterion).
-template <int R, bool UPDATE>
-__device__ __forceinline__ double jac_rows(float (&ph)[R], const float (&dd)[R], const float (&kk)[R],
-                                           const float (&ww)[R], float below, float above,
-                                           float inv_dx2, unsigned rmask, bool use_max = false) {
-  if (UPDATE) {
-    float nv[R];
-#pragma unroll
-    for (int r = 1; r + 1 < R; ++r)
-      nv[r] = jac_cell<R>(ph[r], ph[r - 1], ph[r + 1], dd[r], kk[r], ww[r], inv_dx2);
-    nv[0] = jac_cell<R>(ph[0], below, ph[1], dd[0], kk[0], ww[0], inv_dx2);
-    nv[R - 1] = jac_cell<R>(ph[R - 1], ph[R - 2], above, dd[R - 1], kk[R - 1], ww[R - 1], inv_dx2);
-#pragma unroll
-    for (int r = 0; r < R; ++r) ph[r] = nv[r];
-    return 0.0;
-  }
-  float prev = below;
+// The residual r = d - (S - k phi) / dx^2 of the scaled form, from
+// k = omega / a and d = -b / (a dx^2): r = (omega phi - a S - b) / (a dx^2),
+// with the hardware reciprocal of a (1 ulp; r only enters E_1 or E_inf).
+// Sum of |r| over the rows in rmask (fluid rows: a > 0), or their maximum.
+template <int R>
+__device__ __forceinline__ double jac_resid_scaled(const float (&ph)[R], const float (&aa)[R],
+                                                   const float (&bb)[R], float below, float above,
+                                                   float omega, float inv_dx2, unsigned rmask,
+                                                   bool use_max) {
   double acc = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const float c = ph[r];
+    const float s = r > 0 ? ph[r - 1] : below;
     const float n = (r + 1 < R) ? ph[r + 1] : above;
-    const float e = from_right(c);
-    const float w = from_left(c);
-    const float res = dd[r] - (((e + w) + (n + prev)) - kk[r] * c) * inv_dx2;
-    prev = c;
-    if ((rmask >> r) & 1u) acc = use_max ? fmax(acc, fabs((double)res)) : acc + fabs((double)res);
+    const float S = (from_right(c) + from_left(c)) + (n + s);
+    const float num = fmaf(-aa[r], S, fmaf(omega, c, -bb[r]));
+    if ((rmask >> r) & 1u) {
+      const double res = fabsf(num * (__builtin_amdgcn_rcpf(aa[r]) * inv_dx2));
+      acc = use_max ? fmax(acc, res) : acc + res;
+    }
   }
   return acc;
 }

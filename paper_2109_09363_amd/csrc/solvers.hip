@@ -24,6 +24,8 @@
 // open face by beta = rho0 / rho_face (coefficient planes ce, cn), the
 // diagonal is the sum of the four betas, and the fold corrects the faces by
 // beta grad phi.  The constant-coefficient code is the VAR = false instance.
+#include <type_traits>
+
 #include "../../include/hyproj.h"
 #include "common.h"
 #include "internal.h"
@@ -46,6 +48,7 @@ __device__ __forceinline__ int decide(int k, double E, double thr, int max_iters
 struct JacParams {
   int nx, ny, H, ntx, nty;
   float inv_dx2, wfac, inv_dx;  // wfac = omega * dx^2
+  float omega, dx2;
   double thr;
   int max_iters, check_every, fixed_iters;
   int fold_window;      // sweeps per stagnation window (0: no folds)
@@ -98,6 +101,10 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
   // rows of this thread inside the domain (dmask), inside the tile interior
   // (imask), and the fluid ones among the latter, which enter E_1 (fmask)
   unsigned dmask = 0, imask = 0, fmask = 0;
+  // VAR: d, k (sum of the betas) and the update weight omega dx^2 / k.  The
+  // constant-coefficient instance keeps the scaled form instead: kk = a =
+  // omega / k and ww = b = -omega dx^2 d / k (dd unused); kk > 0 marks fluid
+  // cells in both.
   float ph[R], dd[R], kk[R], ww[R];
   float be[R], bw[R], bn[R], bs[R];  // VAR only
 #pragma unroll
@@ -119,6 +126,11 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
         d_ = p.d[g];
         w_ = p.wfac / k_;
         p_ = p.phi[g];
+        if constexpr (!VAR) {
+          w_ = -w_ * d_;
+          k_ = p.omega / (float)cell_k(ci);
+          d_ = 0.f;
+        }
       }
       if (lane_int && er >= H && er < H + TH) {
         imask |= 1u << r;
@@ -134,14 +146,15 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
   unsigned j = 0, t = 0, nbar = 0;
   double E_ref = 0.0;
   bool ref_set = false;
-  auto edges = [&](float* below, float* above) {
-    edge[q][0][wave][lane] = ph[0];
-    edge[q][1][wave][lane] = ph[R - 1];
+  auto edges_of = [&](const float (&v)[R], float* below, float* above) {
+    edge[q][0][wave][lane] = v[0];
+    edge[q][1][wave][lane] = v[R - 1];
     __syncthreads();
     *below = wave > 0 ? edge[q][1][wave - 1][lane] : 0.f;
     *above = wave < 3 ? edge[q][0][wave + 1][lane] : 0.f;
     q ^= 1;
   };
+  auto edges = [&](float* below, float* above) { edges_of(ph, below, above); };
   auto finish = [&](int st, double E) {
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -178,7 +191,8 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
         part_loc = jac_rows_var<R, false>(ph, dd, kk, ww, be, bw, bn, bs, below, above, p.inv_dx2,
                                           fmask, p.einf != 0);
       else
-        part_loc = jac_rows<R, false>(ph, dd, kk, ww, below, above, p.inv_dx2, fmask, p.einf != 0);
+        part_loc = jac_resid_scaled<R>(ph, kk, ww, below, above, p.omega, p.inv_dx2, fmask,
+                                       p.einf != 0);
       const double loc = p.einf ? block_max(part_loc, red) : block_sum(part_loc, red);
       ++t;
       if (threadIdx.x == 0) st_agent(part + blockIdx.x, loc);
@@ -261,8 +275,10 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
           const float uw = ld_agent(p.u + gy * U + gx), ue = ld_agent(p.u + gy * U + gx + 1);
           const float vs = ld_agent(p.v + (size_t)gy * p.nx + gx);
           const float vn = ld_agent(p.v + (size_t)(gy + 1) * p.nx + gx);
-          dd[r] = ((ue - uw) + (vn - vs)) * p.inv_dx;
-          if ((imask >> r) & 1u) p.d[(size_t)gy * p.nx + gx] = dd[r];
+          const float dv = ((ue - uw) + (vn - vs)) * p.inv_dx;
+          if constexpr (VAR) dd[r] = dv;
+          else ww[r] = -(kk[r] * p.dx2) * dv;
+          if ((imask >> r) & 1u) p.d[(size_t)gy * p.nx + gx] = dv;
         }
         ph[r] = 0.f;
       }
@@ -270,13 +286,39 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     int B = min(H - 1, end - k);
     if (p.fixed_iters <= 0) B = min(B, p.check_every - k % p.check_every);
     if (p.ckpt_every > 0) B = min(B, p.ckpt_every - k % p.ckpt_every);
-    for (int s = 0; s < B; ++s) {
-      float below, above;
-      edges(&below, &above);
-      if constexpr (VAR)
+    if constexpr (VAR) {
+      for (int s = 0; s < B; ++s) {
+        float below, above;
+        edges(&below, &above);
         jac_rows_var<R, true>(ph, dd, kk, ww, be, bw, bn, bs, below, above, p.inv_dx2, 0u);
-      else
-        jac_rows<R, true>(ph, dd, kk, ww, below, above, p.inv_dx2, 0u);
+      }
+    } else {
+      // sweeps in pairs, ph -> tmp -> ph, so that no register copies are
+      // needed between sweeps (up to R = 16; the larger tiles would spill);
+      // omega = 1 drops one FMA per cell
+      auto sweeps = [&](auto one) {
+        constexpr bool O1 = decltype(one)::value;
+        constexpr bool PAIRS = R <= 16;
+        const float om1 = 1.f - p.omega;
+        float tmp[R];
+        int s = 0;
+        for (; PAIRS && s + 2 <= B; s += 2) {
+          float below, above;
+          edges_of(ph, &below, &above);
+          jac_rows_scaled<R, O1>(ph, tmp, kk, ww, below, above, om1);
+          edges_of(tmp, &below, &above);
+          jac_rows_scaled<R, O1>(tmp, ph, kk, ww, below, above, om1);
+        }
+        for (; s < B; ++s) {
+          float below, above;
+          edges_of(ph, &below, &above);
+          jac_rows_scaled<R, O1>(ph, tmp, kk, ww, below, above, om1);
+#pragma unroll
+          for (int r = 0; r < R; ++r) ph[r] = tmp[r];
+        }
+      };
+      if (R <= 16 && p.omega == 1.f) sweeps(std::true_type{});
+      else sweeps(std::false_type{});
     }
     k += B;
     ++j;
@@ -705,6 +747,8 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
   p.inv_dx2 = (float)(1.0 / (dx * dx));
   p.inv_dx = (float)(1.0 / dx);
   p.wfac = (float)(omega * dx * dx);
+  p.omega = omega;
+  p.dx2 = (float)(dx * dx);
   p.thr = thr;
   p.max_iters = max_iters; p.check_every = check_every; p.fixed_iters = fixed_iters;
   p.fold_window = fold_window > 0 ? fold_window : (fixed_iters > 0 ? 0 : 1024);

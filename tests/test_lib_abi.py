@@ -102,6 +102,11 @@ def test_host_side_rejections():
     o.check_every = 1
     assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), -1.0, ctypes.byref(o), dummy,
                            nbytes.value, None, dummy) == -1
+    for om in (0.0, -1.0, float("nan")):  # the Jacobi weight must be positive
+        o.omega = om
+        assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
+                               nbytes.value, None, dummy) == -1
+    o.omega = 1.0
     # checkpoints: need fixed_iters, a buffer, a Jacobi method, at most 64 planes
     o.checkpoint_every = 5
     assert lib.hyp_project(ctx, ctypes.byref(g), ctypes.byref(f), 1e-3, ctypes.byref(o), dummy,
