@@ -32,7 +32,12 @@ constexpr int kMaxCheckpoints = 64;    // Jacobi checkpoint planes per projectio
 // kSyncGroup blocks, each on its own 128-byte line (common.h)
 constexpr int kSyncGroup = 16;
 constexpr int kSyncSlots = 2 + kMaxCoopBlocks / kSyncGroup;
-constexpr int kSyncBytes = kSyncSlots * 128;
+// followed by one line per work-group holding the step words its 8 adjacent
+// tiles write (neighbour synchronisation of the persistent Jacobi kernel);
+// the whole area is zeroed before every launch that uses it
+constexpr int kFlagSlot0 = kSyncSlots;
+constexpr int kSyncAllSlots = kSyncSlots + kMaxCoopBlocks;
+constexpr int kSyncBytes = kSyncAllSlots * 128;
 constexpr int kStatusRunning = -1;     // Scalars::status while a solve is in progress
 constexpr int kStreamBlock = 256;      // threads of the streaming kernels
 constexpr int kStreamGrid = 2048;      // at most this many blocks in the reducing streaming kernels

@@ -53,6 +53,7 @@ struct JacParams {
   int max_iters, check_every, fixed_iters;
   int fold_window;      // sweeps per stagnation window (0: no folds)
   int einf;             // 1: stop on E_inf = max |r| instead of E_1 = mean |r|
+  int nbsync;           // 1: steps without a test wait for the 8 adjacent tiles only
   int ckpt_every;       // > 0: write the interior iterate after every ckpt_every sweeps
   float* ckpt;          // ... into plane k / ckpt_every - 1 of this buffer
   const uint8_t* cell;
@@ -139,6 +140,9 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     }
     ph[r] = p_; dd[r] = d_; kk[r] = k_; ww[r] = w_;
   }
+  // the tile's loads are complete before the loop (so that its publish
+  // stores need not wait for them on every step)
+  __builtin_amdgcn_s_waitcnt(0);
   const int k0 = p.sc->iters;
   const int end = p.fixed_iters > 0 ? p.fixed_iters : p.max_iters;
   const size_t plane = (size_t)p.nx * p.ny;
@@ -170,6 +174,15 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     if (threadIdx.x == 0) abort_solve(p.sc);
     return false;
   };
+  // The halo of a tile lies in the interiors of its (up to) 8 adjacent tiles
+  // when H <= TW and H <= TH (the host sets nbsync only then).  Lane o < 8 of
+  // wave 0 waits for the o-th of them.
+  int nb = -1;
+  if (p.nbsync && wave == 0 && lane < 8) {
+    const int o = lane < 4 ? lane : lane + 1;  // 3 x 3 block without its centre
+    const int tx = bx + o % 3 - 1, ty = by + o / 3 - 1;
+    if (tx >= 0 && tx < p.ntx && ty >= 0 && ty < p.nty) nb = ty * p.ntx + tx;
+  }
   for (;;) {
     // publish the interior of the state after j steps (read by the
     // neighbours after the barrier)
@@ -197,7 +210,20 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
       ++t;
       if (threadIdx.x == 0) st_agent(part + blockIdx.x, loc);
     }
-    if (!barrier()) return;
+    // A step with a test (or, in fixed-sweep mode, a possible fold) crosses
+    // the grid barrier.  Any other step only needs the adjacent tiles' state
+    // of step j: their words.  The exchange plane of step j is rewritten at
+    // step j + 2, after the writer has seen its neighbours' words of step
+    // j + 1, which they raise only after reading their halo of step j (or
+    // after a grid barrier that follows those reads).
+    const bool full = test || !p.nbsync ||
+                      (p.fixed_iters > 0 && p.fold_window > 0 && k - k_ref >= p.fold_window);
+    if (full) {
+      if (!barrier()) return;
+    } else if (!neighbour_wait_bounded(p.sync, j, nb)) {
+      if (threadIdx.x == 0) abort_solve(p.sc);
+      return;
+    }
     // one round trip: the halo (every non-interior fluid cell) and the partials
     if (j > 0) {
 #pragma unroll
@@ -283,6 +309,10 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
         ph[r] = 0.f;
       }
     }
+    // every load of the step (halo, partials, faces) is complete here: the
+    // sweeps need the halo at once, and no path back to the publish stores
+    // then carries a load in flight (which would make each of them wait)
+    __builtin_amdgcn_s_waitcnt(0);
     int B = min(H - 1, end - k);
     if (p.fixed_iters <= 0) B = min(B, p.check_every - k % p.check_every);
     if (p.ckpt_every > 0) B = min(B, p.ckpt_every - k % p.ckpt_every);
@@ -744,6 +774,7 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
   if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, &R, &H, &ntx, &nty))
     return hipErrorInvalidValue;
   p.nx = nx; p.ny = ny; p.H = H; p.ntx = ntx; p.nty = nty;
+  p.nbsync = (H <= 64 - 2 * H && H <= 4 * R - 2 * H) ? 1 : 0;
   p.inv_dx2 = (float)(1.0 / (dx * dx));
   p.inv_dx = (float)(1.0 / dx);
   p.wfac = (float)(omega * dx * dx);

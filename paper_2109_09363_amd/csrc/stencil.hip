@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void div_kernel(int nx, int ny, float inv_dx,
                                                   unsigned* sync, float* __restrict__ phi_acc) {
   __shared__ double red[4];
   const int c0 = blockIdx.x * blockDim.x + threadIdx.x;
-  sync_clear(sync, c0);
+  for (int i = c0; i < kSyncAllSlots * 8; i += gridDim.x * blockDim.x) sync_clear_words(sync, i);
   if (c0 == 0) sc->bar = 0;
   double a = 0.0, q = 0.0;
   // grid-stride: a bounded grid keeps the per-block reduction cheap at

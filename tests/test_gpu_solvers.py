@@ -79,7 +79,10 @@ def test_jacobi_fixed_sweeps_parity(nx, ny, k, omega, seed):
     assert g["res"].e1_cnn == pytest.approx(o["e1_init"], rel=1e-5)  # zero guess
 
 
-@pytest.mark.parametrize("n,seed,thr_rel,ce", [(64, 0, 0.2, 1), (128, 1, 0.1, 8), (256, 2, 0.3, 4)])
+# intervals above 8 sweeps: the steps between two tests synchronise with the
+# adjacent tiles only (no grid barrier), the tests themselves with the grid
+@pytest.mark.parametrize("n,seed,thr_rel,ce", [(64, 0, 0.2, 1), (128, 1, 0.1, 8), (256, 2, 0.3, 4),
+                                               (256, 6, 0.3, 64), (192, 7, 0.15, 128)])
 def test_jacobi_threshold_parity(n, seed, thr_rel, ce):
     say("jacobi thr", n, seed, thr_rel, ce)
     sc, u, v = plume_state(n, seed, 1)
