@@ -290,7 +290,8 @@ static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, 
   }
   const bool pcg = o->method == HYP_METHOD_PCG;
   if (o->tile_rows < 0 || (pcg && o->tile_rows != 0)) return HYP_EINVAL;
-  if (!solver_fits(ctx->dev, g->nx, g->ny, pcg, o->check_every, o->fixed_iters, o->tile_rows))
+  if (!solver_fits(ctx->dev, g->nx, g->ny, pcg, o->check_every, o->fixed_iters, o->tile_rows,
+                   o->variable_density != 0))
     return HYP_EUNSUPPORTED;
   return HYP_OK;
 }

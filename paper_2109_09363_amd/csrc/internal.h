@@ -116,7 +116,7 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
                       int checkpoint_every, float* phi_ckpt, int tile_rows, bool var, bool einf,
                       float* u, float* v, const Ws& w, hipStream_t s);
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters,
-                 int tile_rows);
+                 int tile_rows, bool var);
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
                    int check_every, int fixed_iters, bool var, bool einf, float* u, float* v,
                    const Ws& w, hipStream_t s);

@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
 constexpr int kMaxFolds = 3;
 
 struct PcgParams {
-  int nx, ny, ntx;
+  int nx, ny, ntx, nty;
   float dx2, inv_dx;
   double thr, inv_dx2;
   int max_iters, check_every, fixed_iters;
@@ -496,11 +496,26 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
     return false;
   };
   // refresh the halo of v from the neighbours' interiors
+  // The one-cell halo lies in the 8 adjacent tiles' interiors, so an exchange
+  // waits for their step words only (lane o < 8 of wave 0 for the o-th).
+  // Every exchange is followed by the merged reduction's grid barrier before
+  // its plane is written again, so no tile overwrites a plane that another
+  // is still reading.
+  int nb = -1;
+  if (wave == 0 && lane < 8) {
+    const int o = lane < 4 ? lane : lane + 1;  // 3 x 3 block without its centre
+    const int tx = bx + o % 3 - 1, ty = by + o / 3 - 1;
+    if (tx >= 0 && tx < p.ntx && ty >= 0 && ty < p.nty) nb = ty * p.ntx + tx;
+  }
+  unsigned nex = 0;
   auto exchange = [&](float (&v)[R], float* ex) -> bool {
 #pragma unroll
     for (int i = 0; i < R; ++i)
       if ((imask >> i) & 1u) st_agent(ex + (size_t)(gy0 + i) * p.nx + gx, v[i]);
-    if (!barrier()) return false;
+    if (!neighbour_wait_bounded(p.sync, ++nex, nb)) {
+      if (threadIdx.x == 0) abort_solve(p.sc);
+      return false;
+    }
 #pragma unroll
     for (int i = 0; i < R; ++i)
       if (!((imask >> i) & 1u) && kk[i] > 0.f) v[i] = ld_agent(ex + (size_t)(gy0 + i) * p.nx + gx);
@@ -685,6 +700,8 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
 // ---------------------------------------------------------------------------
 // Launch geometry.  Jacobi: halo H = B + 1 with B = min(check_every, 8)
 // sweeps per step (8 for fixed_iters), tile interior (64 - 2H) x (4R - 2H),
+// the tuned R (whose tiles may fill two work-groups per CU when the kernel's
+// registers allow it: one sweeps while the other waits for its halo), else
 // the smallest R whose tile count fits one work-group per CU.
 static int jacobi_block_len(int check_every, int fixed_iters) {
   const int kMaxBlock = 8;
@@ -694,10 +711,38 @@ static int jacobi_block_len(int check_every, int fixed_iters) {
 
 static const int kRows[] = {4, 8, 12, 16, 24, 32};
 
-static bool jacobi_fit(const Device& dev, int nx, int ny, int r, int h, int* ntx, int* nty) {
+// Work-groups of jacobi_reg<r> that one CU holds at once (registers, LDS),
+// at most 2; every one of them must be resident for the grid barrier.
+static int jacobi_per_cu(int r, bool var) {
+  static int cache[2][6] = {};
+  int i = 0;
+  while (i < 6 && kRows[i] != r) ++i;
+  if (i == 6) return 1;
+  int& c = cache[var ? 1 : 0][i];
+  if (c == 0) {
+    const void* k = nullptr;
+    switch (r) {
+      case 4: k = var ? (const void*)jacobi_reg<4, true> : (const void*)jacobi_reg<4, false>; break;
+      case 8: k = var ? (const void*)jacobi_reg<8, true> : (const void*)jacobi_reg<8, false>; break;
+      case 12: k = var ? (const void*)jacobi_reg<12, true> : (const void*)jacobi_reg<12, false>; break;
+      case 16: k = var ? (const void*)jacobi_reg<16, true> : (const void*)jacobi_reg<16, false>; break;
+      case 24: k = var ? (const void*)jacobi_reg<24, true> : (const void*)jacobi_reg<24, false>; break;
+      default: k = var ? (const void*)jacobi_reg<32, true> : (const void*)jacobi_reg<32, false>; break;
+    }
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, 0) != hipSuccess || n < 1) n = 1;
+    c = n > 2 ? 2 : n;
+  }
+  return c;
+}
+
+// multi: allow as many work-groups per CU as are resident (tuned or chosen R)
+static bool jacobi_fit(const Device& dev, int nx, int ny, int r, int h, bool var, bool multi,
+                       int* ntx, int* nty) {
   const int tw = 64 - 2 * h, th = 4 * r - 2 * h;
   if (tw < 1 || th < 1) return false;
-  const int cap = dev.cu < kMaxCoopBlocks ? dev.cu : kMaxCoopBlocks;
+  int cap = dev.cu * (multi ? jacobi_per_cu(r, var) : 1);
+  cap = cap < kMaxCoopBlocks ? cap : kMaxCoopBlocks;
   const int tx = (nx + tw - 1) / tw, ty = (ny + th - 1) / th;
   if (tx * ty > cap) return false;
   *ntx = tx;
@@ -707,25 +752,25 @@ static bool jacobi_fit(const Device& dev, int nx, int ny, int r, int h, int* ntx
 
 // rows = 0: the tuned table, else the smallest R that fits; rows > 0: that R
 static bool jacobi_geom(const Device& dev, int nx, int ny, int check_every, int fixed_iters,
-                        int rows, int* R, int* H, int* ntx, int* nty) {
+                        int rows, bool var, int* R, int* H, int* ntx, int* nty) {
   const int h = jacobi_block_len(check_every, fixed_iters) + 1;
   *H = h;
   if (rows > 0) {
     bool known = false;
     for (int r : kRows) known = known || r == rows;
-    if (!known || !jacobi_fit(dev, nx, ny, rows, h, ntx, nty)) return false;
+    if (!known || !jacobi_fit(dev, nx, ny, rows, h, var, true, ntx, nty)) return false;
     *R = rows;
     return true;
   }
   for (int i = 0; i < kTileTableSize; ++i) {
     const TileEntry& t = kTileTable[i];
-    if (t.nx == nx && t.ny == ny && t.H == h && jacobi_fit(dev, nx, ny, t.R, h, ntx, nty)) {
+    if (t.nx == nx && t.ny == ny && t.H == h && jacobi_fit(dev, nx, ny, t.R, h, var, true, ntx, nty)) {
       *R = t.R;
       return true;
     }
   }
   for (int r : kRows) {
-    if (jacobi_fit(dev, nx, ny, r, h, ntx, nty)) {
+    if (jacobi_fit(dev, nx, ny, r, h, var, false, ntx, nty)) {
       *R = r;
       return true;
     }
@@ -748,13 +793,13 @@ static bool pcg_geom(const Device& dev, int nx, int ny, int* R, int* ntx, int* n
 }
 
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters,
-                 int tile_rows) {
+                 int tile_rows, bool var) {
   if (pcg) {
     int R, ntx, nty;
     return pcg_geom(dev, nx, ny, &R, &ntx, &nty);
   }
   int R, H, ntx, nty;
-  return jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, &R, &H, &ntx, &nty);
+  return jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, var, &R, &H, &ntx, &nty);
 }
 
 template <int R>
@@ -771,7 +816,7 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
   JacParams p{};
   p.einf = einf ? 1 : 0;
   int R = 0, H = 0, ntx = 0, nty = 0;
-  if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, &R, &H, &ntx, &nty))
+  if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, var, &R, &H, &ntx, &nty))
     return hipErrorInvalidValue;
   p.nx = nx; p.ny = ny; p.H = H; p.ntx = ntx; p.nty = nty;
   p.nbsync = (H <= 64 - 2 * H && H <= 4 * R - 2 * H) ? 1 : 0;
@@ -815,7 +860,7 @@ hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int
   p.einf = einf ? 1 : 0;
   int R = 0, ntx = 0, nty = 0;
   if (!pcg_geom(dev, nx, ny, &R, &ntx, &nty)) return hipErrorInvalidValue;
-  p.nx = nx; p.ny = ny; p.ntx = ntx;
+  p.nx = nx; p.ny = ny; p.ntx = ntx; p.nty = nty;
   p.dx2 = (float)(dx * dx);
   p.inv_dx = (float)(1.0 / dx);
   p.inv_dx2 = 1.0 / (dx * dx);

@@ -11,13 +11,13 @@ struct TileEntry {
 };
 
 constexpr TileEntry kTileTable[] = {
-    {128, 128, 9, 8},  // 1.286 ms
-    {192, 192, 9, 8},  // 1.286 ms
-    {256, 256, 9, 8},  // 1.295 ms
-    {384, 384, 9, 8},  // 1.329 ms
-    {512, 512, 9, 12},  // 1.551 ms
-    {768, 768, 9, 24},  // 2.173 ms
-    {1024, 1024, 9, 32},  // 2.746 ms
+    {128, 128, 9, 8},  // 1.107 ms
+    {192, 192, 9, 8},  // 1.109 ms
+    {256, 256, 9, 8},  // 1.133 ms
+    {384, 384, 9, 8},  // 1.165 ms
+    {512, 512, 9, 8},  // 1.246 ms
+    {768, 768, 9, 24},  // 1.948 ms
+    {1024, 1024, 9, 32},  // 2.499 ms
 };
 constexpr int kTileTableSize = 7;
 
