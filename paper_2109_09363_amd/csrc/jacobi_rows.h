@@ -54,6 +54,60 @@ __device__ __forceinline__ double jac_resid_scaled(const float (&ph)[R], const f
   return acc;
 }
 
+// Variable-density sweep in scaled form: with the face weights
+// beta'_f = omega beta_f / k (k the sum of the cell's betas) and
+// b = -omega dx^2 d / k, the weighted Jacobi update is
+// (1 - omega) phi + sum_f beta'_f phi_f + b: four FMAs after the east/west
+// shifts (five when omega != 1).  Reads src, writes dst.
+template <int R, bool OMEGA1>
+__device__ __forceinline__ void jac_rows_var_scaled(const float (&src)[R], float (&dst)[R],
+                                                    const float (&be)[R], const float (&bw)[R],
+                                                    const float (&bn)[R], const float (&bs)[R],
+                                                    const float (&bb)[R], float below, float above,
+                                                    float om1) {
+  auto cell = [&](int r, float s, float n) {
+    const float c = src[r];
+    float y = fmaf(be[r], from_right(c), bb[r]);
+    y = fmaf(bw[r], from_left(c), y);
+    y = fmaf(bn[r], n, y);
+    y = fmaf(bs[r], s, y);
+    return OMEGA1 ? y : fmaf(om1, c, y);
+  };
+#pragma unroll
+  for (int r = 1; r + 1 < R; ++r) dst[r] = cell(r, src[r - 1], src[r + 1]);
+  dst[0] = cell(0, below, src[1]);
+  dst[R - 1] = cell(R - 1, src[R - 2], above);
+}
+
+// Its residual r = d - (sum_f beta_f phi_f - k phi) / dx^2 from the scaled
+// quantities: r = (omega phi - sum_f beta'_f phi_f - b) k / (omega dx^2).
+// Sum of |r| over the rows in rmask, or their maximum.
+template <int R>
+__device__ __forceinline__ double jac_resid_var_scaled(const float (&ph)[R], const float (&kk)[R],
+                                                       const float (&be)[R], const float (&bw)[R],
+                                                       const float (&bn)[R], const float (&bs)[R],
+                                                       const float (&bb)[R], float below, float above,
+                                                       float omega, float inv_dx2, unsigned rmask,
+                                                       bool use_max) {
+  const float scale = inv_dx2 / omega;
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float c = ph[r];
+    const float s = r > 0 ? ph[r - 1] : below;
+    const float n = (r + 1 < R) ? ph[r + 1] : above;
+    float y = fmaf(be[r], from_right(c), bb[r]);
+    y = fmaf(bw[r], from_left(c), y);
+    y = fmaf(bn[r], n, y);
+    y = fmaf(bs[r], s, y);
+    if ((rmask >> r) & 1u) {
+      const double res = fabsf((omega * c - y) * (kk[r] * scale));
+      acc = use_max ? fmax(acc, res) : acc + res;
+    }
+  }
+  return acc;
+}
+
 // The variable-density operator: the four face coefficients of every cell
 // (beta = rho0 / rho_face, 0 on closed faces) weight the neighbours, and
 // kk holds their sum (the diagonal).  With every beta = 1 it is the

@@ -86,7 +86,7 @@ __device__ __forceinline__ void abort_solve(Scalars* sc) {
 }
 
 template <int R, bool VAR>
-__global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
+__global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacParams p) {
   __shared__ float edge[2][2][4][64];  // [parity][low row / high row][wave][lane]
   __shared__ double red[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -102,10 +102,10 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
   // rows of this thread inside the domain (dmask), inside the tile interior
   // (imask), and the fluid ones among the latter, which enter E_1 (fmask)
   unsigned dmask = 0, imask = 0, fmask = 0;
-  // VAR: d, k (sum of the betas) and the update weight omega dx^2 / k.  The
-  // constant-coefficient instance keeps the scaled form instead: kk = a =
-  // omega / k and ww = b = -omega dx^2 d / k (dd unused); kk > 0 marks fluid
-  // cells in both.
+  // Scaled forms of the update (dd unused): the constant-coefficient instance
+  // keeps kk = a = omega / k and ww = b = -omega dx^2 d / k; VAR keeps
+  // kk = k (the sum of the betas), ww = b and the face weights
+  // beta' = omega beta / k.  kk > 0 marks fluid cells in both.
   float ph[R], dd[R], kk[R], ww[R];
   float be[R], bw[R], bn[R], bs[R];  // VAR only
 #pragma unroll
@@ -125,12 +125,14 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
           k_ = (float)cell_k(ci);
         }
         d_ = p.d[g];
-        w_ = p.wfac / k_;
+        w_ = -(p.wfac / k_) * d_;
         p_ = p.phi[g];
-        if constexpr (!VAR) {
-          w_ = -w_ * d_;
-          k_ = p.omega / (float)cell_k(ci);
-          d_ = 0.f;
+        d_ = 0.f;
+        if constexpr (VAR) {
+          const float sc = p.omega / k_;
+          be[r] *= sc; bw[r] *= sc; bn[r] *= sc; bs[r] *= sc;
+        } else {
+          k_ = p.omega / k_;
         }
       }
       if (lane_int && er >= H && er < H + TH) {
@@ -201,8 +203,8 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
       edges(&below, &above);
       double part_loc;
       if constexpr (VAR)
-        part_loc = jac_rows_var<R, false>(ph, dd, kk, ww, be, bw, bn, bs, below, above, p.inv_dx2,
-                                          fmask, p.einf != 0);
+        part_loc = jac_resid_var_scaled<R>(ph, kk, be, bw, bn, bs, ww, below, above, p.omega,
+                                           p.inv_dx2, fmask, p.einf != 0);
       else
         part_loc = jac_resid_scaled<R>(ph, kk, ww, below, above, p.omega, p.inv_dx2, fmask,
                                        p.einf != 0);
@@ -272,8 +274,11 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
           const size_t c = (size_t)gy * p.nx + gx;
           const uint8_t ci = p.cell[c];
           const float pc = ph[r];
-          // face weights: beta for the variable-density operator, else 1
-          const float fw = VAR ? bw[r] : 1.f, fs = VAR ? bs[r] : 1.f, fn = VAR ? bn[r] : 1.f;
+          // face weights: beta = beta' k / omega for the variable-density
+          // operator, else 1
+          const float bk = VAR ? kk[r] / p.omega : 0.f;
+          const float fw = VAR ? bw[r] * bk : 1.f, fs = VAR ? bs[r] * bk : 1.f,
+                      fn = VAR ? bn[r] * bk : 1.f;
           if (ci & C_W) {
             float* f = p.u + (size_t)gy * (p.nx + 1) + gx;
             st_agent(f, ld_agent(f) - fw * ((pc - west) * p.inv_dx));
@@ -302,7 +307,7 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
           const float vs = ld_agent(p.v + (size_t)gy * p.nx + gx);
           const float vn = ld_agent(p.v + (size_t)(gy + 1) * p.nx + gx);
           const float dv = ((ue - uw) + (vn - vs)) * p.inv_dx;
-          if constexpr (VAR) dd[r] = dv;
+          if constexpr (VAR) ww[r] = -(p.wfac / kk[r]) * dv;
           else ww[r] = -(kk[r] * p.dx2) * dv;
           if ((imask >> r) & 1u) p.d[(size_t)gy * p.nx + gx] = dv;
         }
@@ -316,18 +321,19 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
     int B = min(H - 1, end - k);
     if (p.fixed_iters <= 0) B = min(B, p.check_every - k % p.check_every);
     if (p.ckpt_every > 0) B = min(B, p.ckpt_every - k % p.ckpt_every);
-    if constexpr (VAR) {
-      for (int s = 0; s < B; ++s) {
-        float below, above;
-        edges(&below, &above);
-        jac_rows_var<R, true>(ph, dd, kk, ww, be, bw, bn, bs, below, above, p.inv_dx2, 0u);
-      }
-    } else {
+    {
       // sweeps in pairs, ph -> tmp -> ph, so that no register copies are
       // needed between sweeps (up to R = 16; the larger tiles would spill);
       // omega = 1 drops one FMA per cell
-      auto sweeps = [&](auto one) {
+      auto rows = [&](auto one, const float (&src)[R], float (&dst)[R], float below, float above,
+                      float om1) {
         constexpr bool O1 = decltype(one)::value;
+        if constexpr (VAR)
+          jac_rows_var_scaled<R, O1>(src, dst, be, bw, bn, bs, ww, below, above, om1);
+        else
+          jac_rows_scaled<R, O1>(src, dst, kk, ww, below, above, om1);
+      };
+      auto sweeps = [&](auto one) {
         constexpr bool PAIRS = R <= 16;
         const float om1 = 1.f - p.omega;
         float tmp[R];
@@ -335,14 +341,14 @@ __global__ __launch_bounds__(256) void jacobi_reg(JacParams p) {
         for (; PAIRS && s + 2 <= B; s += 2) {
           float below, above;
           edges_of(ph, &below, &above);
-          jac_rows_scaled<R, O1>(ph, tmp, kk, ww, below, above, om1);
+          rows(one, ph, tmp, below, above, om1);
           edges_of(tmp, &below, &above);
-          jac_rows_scaled<R, O1>(tmp, ph, kk, ww, below, above, om1);
+          rows(one, tmp, ph, below, above, om1);
         }
         for (; s < B; ++s) {
           float below, above;
           edges_of(ph, &below, &above);
-          jac_rows_scaled<R, O1>(ph, tmp, kk, ww, below, above, om1);
+          rows(one, ph, tmp, below, above, om1);
 #pragma unroll
           for (int r = 0; r < R; ++r) ph[r] = tmp[r];
         }
