@@ -452,8 +452,10 @@ __device__ __forceinline__ void write_wimg(const float* __restrict__ w, T* __res
   img[e] = St<T>::from(v);
 }
 
-// Launch one layer over the tile list of L on stream s (grid: up to 2
-// work-groups per CU, whole tiles per work-group).
+// Launch one layer over the tile list of L on stream s: as many work-groups
+// as the LDS of the CUs holds at once (up to 2 per CU), so that every one
+// loads its weights once and all run in a single round, each over a run of
+// whole tiles.
 template <typename T, int KS, int CIN, int COUT, bool RELU, bool HEAD = false>
 hipError_t launch_conv(ConvLaunch& L, int cu, hipStream_t s) {
   using Gm = ConvGeom<T, KS, CIN, COUT>;
@@ -462,7 +464,8 @@ hipError_t launch_conv(ConvLaunch& L, int cu, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int tiles = L.total_tiles;
   if (tiles <= 0) return hipSuccess;
-  const int G = min(tiles, cu * 2);
+  const int per_cu = (int)((size_t)160 * 1024 / Gm::LDS);
+  const int G = min(tiles, cu * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu)));
   L.tiles_per_wg = (tiles + G - 1) / G;
   const int nwg = (tiles + L.tiles_per_wg - 1) / L.tiles_per_wg;
   hipLaunchKernelGGL((conv_mfma<T, KS, CIN, COUT, RELU, HEAD>), dim3(nwg), dim3(256), Gm::LDS, s, L);
