@@ -164,7 +164,9 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
       }
     }
   } else {
-#pragma unroll 1
+    // taps unrolled: a loop over them made the compiler rotate the
+    // accumulators between registers at every iteration
+#pragma unroll
     for (int tap = 0; tap < KS * KS; ++tap) {
       const int ky = tap / KS, kx = tap % KS;
 #pragma unroll
