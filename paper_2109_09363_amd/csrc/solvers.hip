@@ -5,25 +5,29 @@
 //    r = d - L phi.  Register-resident with temporal blocking: a work-group
 //    owns a 64-column extended tile (interior + halo of width H on every
 //    side), one lane per column; each of the 4 waves keeps R consecutive
-//    rows of its lane's column in registers, together with d, k and the
-//    update weight.  East/west neighbours move between lanes with DPP wave
-//    shifts, north/south come from the same lane's registers (band edges
-//    through LDS).  A step of B <= H - 1 sweeps ends with the interior and,
-//    at a test, the FP64 partial of sum|r| written with agent-scope stores,
-//    one grid barrier, and one round trip that brings back the halo and all
-//    partials together.  E_1 is tested at the steps that end on a multiple
+//    rows of its lane's column in registers, together with the scaled
+//    update's per-cell factors (jacobi_rows.h).  East/west neighbours move
+//    between lanes with DPP wave shifts, north/south come from the same
+//    lane's registers (band edges through LDS).  A step of B <= H - 1 sweeps
+//    ends with the interior written with agent-scope stores.  At a test
+//    step the FP64 partial of sum|r| follows, then one grid barrier and one
+//    round trip that brings back the halo and all partials together; any
+//    other step waits only for the step words of the (up to) 8 adjacent
+//    tiles, whose interiors hold its halo.  E_1 is tested at the steps that end on a multiple
 //    of check_every (and at max_iters); every work-group sums the partials
 //    in the same order, so all take the same decision at the same sweep.
 //    Defect-correction folds (the velocity takes the increment, d is
 //    recomputed from the faces, phi restarts at 0) run inside the launch.
-//  * Jacobi-preconditioned conjugate gradient with FP64 dot products: LDS
-//    tiles with a one-cell halo for the search direction, one merged grid
-//    reduction per iteration, and a stop confirmed on the true residual.
+//  * Jacobi-preconditioned conjugate gradient with FP64 dot products:
+//    register tiles with a one-cell halo exchanged with the adjacent tiles,
+//    one merged grid reduction per iteration, and a stop confirmed on the
+//    true residual.
 //
 // Both come in a variable-density form (VAR): the operator weights every
 // open face by beta = rho0 / rho_face (coefficient planes ce, cn), the
 // diagonal is the sum of the four betas, and the fold corrects the faces by
 // beta grad phi.  The constant-coefficient code is the VAR = false instance.
+#include <atomic>
 #include <type_traits>
 
 #include "../../include/hyproj.h"
@@ -720,11 +724,13 @@ static const int kRows[] = {4, 8, 12, 16, 24, 32};
 // Work-groups of jacobi_reg<r> that one CU holds at once (registers, LDS),
 // at most 2; every one of them must be resident for the grid barrier.
 static int jacobi_per_cu(int r, bool var) {
-  static int cache[2][6] = {};
+  // queried once per instance; threads that race here store the same value
+  static std::atomic<int> cache[2][6] = {};
   int i = 0;
   while (i < 6 && kRows[i] != r) ++i;
   if (i == 6) return 1;
-  int& c = cache[var ? 1 : 0][i];
+  std::atomic<int>& slot = cache[var ? 1 : 0][i];
+  int c = slot.load(std::memory_order_relaxed);
   if (c == 0) {
     const void* k = nullptr;
     switch (r) {
@@ -738,6 +744,7 @@ static int jacobi_per_cu(int r, bool var) {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, 0) != hipSuccess || n < 1) n = 1;
     c = n > 2 ? 2 : n;
+    slot.store(c, std::memory_order_relaxed);
   }
   return c;
 }
