@@ -141,3 +141,84 @@ def test_single_scale_single_channel_closed_form():
     s_ref = np.sqrt(np.mean(d[P.fluid] ** 2))
     ref = np.where(P.fluid, sc.dx ** 2 * s_ref * 2.0 * np.maximum(d / s_ref, 0.0), 0.0)
     assert np.allclose(phi0, ref, atol=1e-15)
+
+
+# ---- the whole multi-scale network against an independent PyTorch CPU
+# rendering (Sec. 3.1: the same input at several resolutions, bilinear
+# resampling, replication padding, ReLU on the hidden layers, a linear
+# output per scale, outputs summed from the coarsest scale to the finest).
+
+def _bf16(t):
+    """Storage rounding of the BF16 path: FP32 value, then round to nearest
+    even bfloat16."""
+    return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+def torch_parallel(d, fluid, dx, params, S, C, bf16=False):
+    s = float(np.sqrt(np.sum(d[fluid] ** 2) / fluid.sum()))
+    x = torch.from_numpy(np.stack([np.where(fluid, d / s, 0.0), (~fluid).astype(np.float64)]))[None]
+    levels = [x]
+    for _ in range(S - 1):
+        levels.append(F.interpolate(levels[-1], scale_factor=0.5, mode="bilinear",
+                                    align_corners=False))
+    rnd = _bf16 if bf16 else (lambda t: t)
+    p = torch.from_numpy(np.asarray(params, np.float64))
+    o, ys = 0, []
+    for k in range(S):
+        h = rnd(levels[k])
+        cin = 2
+        for _ in range(4):
+            W = p[o:o + C * 9 * cin].reshape(C, 3, 3, cin).permute(0, 3, 1, 2); o += C * 9 * cin
+            b = p[o:o + C]; o += C
+            h = rnd(torch.relu(F.conv2d(F.pad(h, (1, 1, 1, 1), mode="replicate"), rnd(W), b)))
+            cin = C
+        wo = p[o:o + C].reshape(1, C, 1, 1); o += C
+        bo = p[o:o + 1]; o += 1
+        ys.append(F.conv2d(h, wo, bo))
+    t = ys[S - 1]
+    for k in range(S - 2, -1, -1):
+        t = ys[k] + F.interpolate(t, scale_factor=2, mode="bilinear", align_corners=False)
+    return np.where(fluid, dx * dx * s * t[0, 0].numpy(), 0.0)
+
+
+@pytest.mark.parametrize("S,C,n,seed,bf16", [(2, 4, 16, 0, False), (3, 8, 24, 1, False),
+                                              (4, 4, 32, 2, False), (3, 8, 24, 3, True),
+                                              (4, 8, 32, 4, True)])
+def test_multiscale_net_matches_torch_rendering(S, C, n, seed, bf16):
+    sc, P, u, v = _plume_state(n, seed, n_obs=2)
+    w = scenes.random_weights(S, C, seed, out_scale=0.5)
+    d = G.divergence(P, u, v, sc.dx)
+    phi, s, cache = CN.cnn_phi0(P, d, sc.dx, w, S, C, bf16=bf16, keep=True)
+    ref = torch_parallel(d, P.fluid, sc.dx, w, S, C, bf16=bf16)
+    assert np.abs(phi).max() > 0
+    assert np.allclose(phi, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # every scale contributes (the test would not see a dropped scale otherwise)
+    for y in cache["ys"]:
+        assert np.abs(y).max() > 1e-3 * np.abs(cache["t"]).max()
+
+
+def _nearest_up2(t):
+    return np.repeat(np.repeat(t, 2, axis=0), 2, axis=1)
+
+
+@pytest.mark.parametrize("mutant", ["nearest_up", "scales_reversed", "no_coarse_sum"])
+def test_torch_rendering_detects_a_wrong_combination(mutant, monkeypatch):
+    """Plausible mistakes in the coarse-to-fine combination, planted in the
+    oracle on the CPU, fail the comparison with the PyTorch rendering."""
+    S, C, n, seed = 3, 8, 24, 1
+    sc, P, u, v = _plume_state(n, seed, n_obs=2)
+    w = scenes.random_weights(S, C, seed, out_scale=0.5)
+    d = G.divergence(P, u, v, sc.dx)
+    ref = torch_parallel(d, P.fluid, sc.dx, w, S, C)
+    if mutant == "nearest_up":
+        monkeypatch.setattr(CN, "up2", _nearest_up2)
+        phi = CN.cnn_phi0(P, d, sc.dx, w, S, C)[0]
+    elif mutant == "scales_reversed":
+        per = CN.param_count(1, C)
+        wr = np.concatenate([w[k * per:(k + 1) * per] for k in reversed(range(S))])
+        phi = CN.cnn_phi0(P, d, sc.dx, wr, S, C)[0]
+    else:
+        real_up2 = CN.up2
+        monkeypatch.setattr(CN, "up2", lambda t: 0.0 * real_up2(t))
+        phi = CN.cnn_phi0(P, d, sc.dx, w, S, C)[0]
+    assert not np.allclose(phi, ref, rtol=0, atol=1e-3 * np.abs(ref).max())
