@@ -86,3 +86,70 @@ def test_batched_hybrid_and_graph_replay():
         assert ie == ig
         for a, c in zip(ue, ug):
             assert np.array_equal(a, c)
+
+
+def _instances(sizes, seed, thr):
+    inst, host = [], []
+    for i, (nx, ny) in enumerate(sizes):
+        sc = scenes.plume_scene(nx, seed=seed + i, n_obstacles=(0, 3), ny=ny)
+        u, v = scenes.random_faces(nx, ny, seed + i, kind="mixed")
+        u, v = f32(u), f32(v)
+        P = G.plan(sc.flags)
+        t = thr if thr is not None else 0.2 * G.e1(P, G.divergence(P, *G.enforce_bc(P, u, v), sc.dx))
+        host.append(dict(sc=sc, u=u, v=v, thr=t))
+        inst.append(dict(nx=nx, ny=ny, dx=sc.dx, flags=to_dev(sc.flags, torch.uint8), u=to_dev(u),
+                         v=to_dev(v), p=torch.zeros((ny, nx), dtype=torch.float32, device="cuda"),
+                         threshold=t, dt=0.01))
+    return inst, host
+
+
+def test_batched_fixed_sweeps_many_tiles_per_workgroup():
+    """More tiles than resident work-groups (one 2048^2 grid is 2,025 tiles
+    of the batched kernel, plus 16 plumes with sides from {128, ..., 512}),
+    so every work-group sweeps several tiles per pass; threshold 0 runs
+    every instance for exactly max_iters sweeps, and each must match the
+    oracle's Jacobi at that count."""
+    rng = np.random.default_rng(5)
+    sides = [128, 192, 256, 384, 512]
+    sizes = [(2048, 2048)] + [(int(s), int(s)) for s in rng.choice(sides, 16)]
+    k = 96
+    inst, host = _instances(sizes, 40, thr=0.0)
+    b = hp.Batch(inst, method="jacobi", max_iters=k)
+    b.project_async()
+    torch.cuda.synchronize()
+    res = b.results()
+    for i, (r, h) in enumerate(zip(res, host)):
+        sc = h["sc"]
+        assert r.status == 1 and r.iters == k  # MAXITER: the fixed count
+        pb = inst[i]["p"].cpu().numpy().astype(np.float64)
+        o = PR.project(sc.flags, h["u"], h["v"], sc.dx, dt=0.01, method="jacobi", fixed_iters=k)
+        err = rel_l2(pb, o["p"], o["plan"].fluid)
+        eu = rel_l2(inst[i]["u"].cpu().numpy().astype(np.float64), o["u"])
+        say("inst", i, sizes[i], "rel L2 p", err, "u", eu)
+        assert err <= 1e-4 and eu <= 1e-5
+
+
+def test_batched_threshold_cfg4_style_draw():
+    """A draw of 20 plumes with sides from {128, ..., 512} and 0-3 disks
+    projected together to 20 % of each one's initial E_1: every instance's
+    sweep count is the single-grid kernel's within one test interval, and
+    its pressure the oracle's at that count."""
+    rng = np.random.default_rng(6)
+    sides = [128, 192, 256, 384, 512]
+    sizes = [(int(s), int(s)) for s in rng.choice(sides, 20)]
+    inst, host = _instances(sizes, 70, thr=None)
+    b = hp.Batch(inst, method="jacobi", max_iters=200000)
+    b.project_async()
+    torch.cuda.synchronize()
+    res = b.results()
+    for i, (r, h) in enumerate(zip(res, host)):
+        sc = h["sc"]
+        g = gpu_project(sc.flags, h["u"], h["v"], sc.dx, thr=h["thr"], method="jacobi", dt=0.01,
+                        check_every=8, max_iters=200000)
+        assert r.status == 0 and abs(r.iters - g["res"].iters) <= 8
+        pb = inst[i]["p"].cpu().numpy().astype(np.float64)
+        o = PR.project(sc.flags, h["u"], h["v"], sc.dx, dt=0.01, method="jacobi", fixed_iters=r.iters)
+        err = rel_l2(pb, o["p"], o["plan"].fluid)
+        say("inst", i, sizes[i], "iters", r.iters, g["res"].iters, "rel L2 p", err)
+        assert err <= 1e-4
+        assert r.e1_final <= 1.01 * h["thr"]

@@ -133,6 +133,24 @@ def test_pcg_fixed_iterations_match_oracle():
     assert rel_l2(g["p"], o["p"], o["plan"].fluid) <= 1e-4
 
 
+@pytest.mark.parametrize("n,k,kind", [(512, 200, "mixed"), (512, 400, "smooth"), (256, 120, "mixed")])
+def test_pcg_fixed_iterations_large(n, k, kind):
+    """The benchmark's size at a few hundred CG iterations: the GPU's FP32
+    iterate (single-reduction recurrence) against the oracle's FP64 PCG at
+    the same iteration count."""
+    say("pcg fixed", n, k, kind)
+    sc, u, v = plume_state(n, 8, 3, kind=kind)
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="pcg", fixed_iters=k)
+    o = PR.project(sc.flags, u, v, sc.dx, method="pcg", fixed_iters=k)
+    assert g["res"].iters == k and g["res"].status == 0
+    P = o["plan"]
+    err = rel_l2(g["p"], o["p"], P.fluid)
+    eu = rel_l2(g["u"], o["u"])
+    say(f"  rel L2 p {err:.2e}, u {eu:.2e}; e1 gpu {g['res'].e1_final:.4e} oracle {o['e1_final']:.4e}")
+    assert err <= 1e-4 and eu <= 1e-4
+    assert g["res"].e1_final == pytest.approx(o["e1_final"], rel=1e-2)
+
+
 def test_nonfinite_and_maxiter_statuses():
     sc, u, v = plume_state(64, 3, 1)
     u2 = u.copy()
