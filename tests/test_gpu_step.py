@@ -182,8 +182,8 @@ def test_rollout_parity_per_step(n, nobs, seed, method):
     """Eight steps of the plume from rest on the GPU; before every step the
     oracle takes the GPU's state and re-steps it: the advection point by
     point, and the projection at the same fixed sweep count (Jacobi) or with
-    its own stop (PCG: iterations within 10 %, both within 1e-3 of the
-    exact solve of the GPU's u*)."""
+    its own stop (PCG: iterations within 10 %, and no farther from the exact
+    solve of the GPU's u* than the oracle's stopped iterate)."""
     say("rollout", n, nobs, method)
     from oracle import solve as SV
     sc = scenes.plume_scene(n, seed=seed, n_obstacles=nobs)
