@@ -24,7 +24,9 @@
  *
  * Ownership: the caller owns every device buffer, including the workspace
  * (size from hyp_workspace_size).  The library allocates no device memory
- * in any call.  A context holds host state only.  Calls are asynchronous on
+ * in any call; its only device memory of its own is the static array of
+ * hyp_project_noalloc (HYP_NOALLOC_MAX_BYTES per GPU, held from the code
+ * object's load until the process ends).  A context holds host state only.  Calls are asynchronous on
  * the given HIP stream; one context/workspace pair must not be used by two
  * streams at once.
  *
@@ -251,6 +253,22 @@ int hyp_plan(hyp_ctx* ctx, const hyp_grid* g, const uint8_t* flags,
 int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f,
                 double threshold, const hyp_opts* o, void* ws,
                 size_t ws_bytes, hipStream_t stream, hyp_result* res);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hyp_plan
+ * on f->flags followed by hyp_project, with the workspace taken from a
+ * static device array of HYP_NOALLOC_MAX_BYTES that the library holds on
+ * every GPU it runs on until the process ends.  Nothing is allocated; the
+ * caller passes inputs and outputs only (device memory, as for
+ * hyp_project; res device or host-pinned).  HYP_EWORKSPACE when the grid
+ * and network need more than HYP_NOALLOC_MAX_BYTES (hyp_workspace_size),
+ * any other rejection as hyp_project; nothing is enqueued then.  All calls
+ * on one GPU share that GPU's array: calls that overlap on one GPU (two
+ * streams or threads) race and must be serialised by the caller.  The
+ * results equal hyp_plan + hyp_project on a caller workspace. */
+#define HYP_NOALLOC_MAX_BYTES (128u << 20)
+int hyp_project_noalloc(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double threshold,
+                        const hyp_opts* o, hipStream_t stream, hyp_result* res);
 
 /* Adjoint of the projection (the gradient of the correction of Eq. 2 is
  * known, Sec. 3.2): gradient of  loss = scale * sum_F r^2,  r = d - L phi_K,

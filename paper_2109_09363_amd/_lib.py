@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhyproj.so")
 
 HYP_OK = 0
+NOALLOC_MAX_BYTES = 128 << 20  # HYP_NOALLOC_MAX_BYTES
 STATUS_OK, STATUS_MAXITER, STATUS_NONFINITE, STATUS_FLOOR, STATUS_ABORTED = 0, 1, 2, 3, 4
 METHODS = {"hybrid": 0, "jacobi": 1, "pcg": 2, "cnn": 3}
 PRECISIONS = {"fp32": 0, "bf16": 1}
@@ -66,6 +67,8 @@ SIGNATURES = {
     "hyp_plan": (c_i32, [c_vp, ctypes.POINTER(Grid), c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hyp_project": (c_i32, [c_vp, ctypes.POINTER(Grid), ctypes.POINTER(Fields), c_f64,
                             ctypes.POINTER(Opts), c_vp, ctypes.c_size_t, c_vp, c_vp]),
+    "hyp_project_noalloc": (c_i32, [c_vp, ctypes.POINTER(Grid), ctypes.POINTER(Fields), c_f64,
+                                    ctypes.POINTER(Opts), c_vp, c_vp]),
     "hyp_set_timing": (c_i32, [c_vp, c_i32]),
     "hyp_get_timing": (c_i32, [c_vp, ctypes.POINTER(c_f32)]),
     "hyp_step": (c_i32, [c_vp, ctypes.POINTER(Grid), ctypes.POINTER(Physics), ctypes.POINTER(State),

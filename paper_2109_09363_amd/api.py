@@ -136,6 +136,34 @@ class Projector:
             self.ctx, ctypes.byref(self.grid), ctypes.byref(f), float(threshold), ctypes.byref(o),
             _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
 
+    def project_noalloc_async(self, u, v, flags, p, threshold: float, method: str = "hybrid",
+                              max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
+                              omega: float = 1.0, rho=None, p_init=None, fold_window: int = 0,
+                              tile_rows: int = 0, variable_density: bool = False,
+                              criterion: str = "e1"):
+        """project_async without the context's workspace: the library plans
+        `flags` and projects in its static per-GPU array (hyp_project_noalloc;
+        grids whose workspace exceeds NOALLOC_MAX_BYTES are rejected).  Calls
+        that overlap on one GPU race on that array."""
+        nx, ny = self.nx, self.ny
+        _need(u, torch.float32, (ny, nx + 1), "u")
+        _need(v, torch.float32, (ny + 1, nx), "v")
+        _need(flags, torch.uint8, (ny, nx), "flags")
+        _need(p, torch.float32, (ny, nx), "p")
+        if rho is not None:
+            _need(rho, torch.float32, (ny, nx), "rho")
+        elif variable_density:
+            raise ValueError("variable_density needs rho")
+        if p_init is not None:
+            _need(p_init, torch.float32, (ny, nx), "p_init")
+        f = L.Fields(_ptr(u), _ptr(v), _ptr(rho), _ptr(flags), _ptr(p), _ptr(p_init), None)
+        o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
+                   float(omega), int(fold_window), 0, int(tile_rows),
+                   1 if variable_density else 0, L.CRITERIA[criterion])
+        L.check("hyp_project_noalloc", self.lib.hyp_project_noalloc(
+            self.ctx, ctypes.byref(self.grid), ctypes.byref(f), float(threshold), ctypes.byref(o),
+            _stream(), _ptr(self.res)))
+
     def advect_async(self, rho, u, v, xi, g: float, drho: float, u_in: float = 1.0,
                      cfl: float = 0.5):
         """Enqueue the advection + force half step: u, v become u*."""

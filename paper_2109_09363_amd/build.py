@@ -16,7 +16,7 @@ SRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libhyproj.so")
 SOURCES = ["api.hip", "stencil.hip", "solvers.hip", "cnn.hip", "advect.hip", "backward.hip", "batched.hip",
-           "papernets.hip"]
+           "papernets.hip", "noalloc.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -344,6 +344,16 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
 int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double threshold,
                 const hyp_opts* o, void* ws, size_t ws_bytes, hipStream_t stream,
                 hyp_result* res) {
+  return hyp::project_checked(ctx, g, f, threshold, o, ws, ws_bytes, stream, res, false);
+}
+
+}  // extern "C"
+
+// hyp_project's checks, then (plan_first) the planner on f->flags and the
+// projection: every argument is validated before anything is enqueued.
+int hyp::project_checked(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double threshold,
+                         const hyp_opts* o, void* ws, size_t ws_bytes, hipStream_t stream,
+                         hyp_result* res, bool plan_first) {
   if (!ctx || !f || !o || !ws || !res || !grid_ok(g)) return HYP_EINVAL;
   if (!f->u || !f->v || !f->flags || !f->p) return HYP_EINVAL;
   int rc = check_opts(ctx, g, o, threshold);
@@ -356,12 +366,16 @@ int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double thr
   const WsLayout L = make_layout(g->nx, g->ny, ctx->net);
   if (ws_bytes < L.total) return HYP_EWORKSPACE;
   const Ws w = ws_view(ws, L);
-  ctx->timed_step = false;
   if (o->variable_density && !f->rho) return HYP_EINVAL;
+  if (plan_first && run_plan(ctx->dev, g->nx, g->ny, f->flags, w, stream) != hipSuccess)
+    return HYP_EHIP;
+  ctx->timed_step = false;
   return enqueue_projection(ctx, g, f->u, f->v, f->rho, f->p_init, f->p,
                             o->checkpoint_every > 0 ? f->phi_ckpt : nullptr, threshold, o, L, w,
                             false, stream, res);
 }
+
+extern "C" {
 
 int hyp_project_backward(hyp_ctx* ctx, const hyp_grid* g, int32_t sweeps, float omega,
                          double scale, int32_t accumulate, float* du, float* dv, float* dparams,

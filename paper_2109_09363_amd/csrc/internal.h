@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/hyproj.h"
+
 namespace hyp {
 
 // Device-resident scalars of one projection (lives in the workspace).
@@ -147,5 +149,11 @@ hipError_t run_papernet(const Device& dev, const NetShape& net, const WsLayout& 
                         double dx, const float* params, const Ws& w, hipStream_t s);
 hipError_t run_cnn(const Device& dev, const NetShape& net, const WsLayout& L, int nx, int ny,
                    double dx, const float* params, const Ws& w, hipStream_t s);
+
+// hyp_project with all of its checks first, then (plan_first) the planner
+// on f->flags ahead of the projection (the no-allocation entry point).
+int project_checked(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f, double threshold,
+                    const hyp_opts* o, void* ws, size_t ws_bytes, hipStream_t stream,
+                    hyp_result* res, bool plan_first);
 
 }  // namespace hyp
