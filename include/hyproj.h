@@ -335,30 +335,46 @@ int hyp_advect(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp
                void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---- batched form: many plumes of uneven sizes ---------------------------
- * A batch fixes the instances (grids, state pointers, thresholds, options)
- * once.  Per step, every instance gets its own advection, divergence and CNN
- * launches, then ONE persistent Jacobi launch sweeps the tiles of all
- * instances (per-instance stop tests; finished instances drop out), then
- * the per-instance corrections.  Methods HYBRID and JACOBI; check_every and
- * fold_window are not used (the batch tests E_1 every 8 sweeps).  The
- * workspace holds the batch tables followed by one projection workspace per
- * instance. */
+ * The batched workload of many independent plumes (the launch-bound regime
+ * of small grids that Sec. 5.2 discusses): a batch fixes the instances
+ * (grids, state pointers, thresholds, physics, options) once.  Every phase
+ * of a step is one launch over all instances (advection passes, boundary
+ * faces + divergence, the network's input, convolution layers and
+ * upsample-sum, the gradient correction and the final check), and the
+ * Jacobi sweeps of every instance run in ONE persistent launch over a
+ * global tile list, with per-instance E_1 tests (every 8 sweeps; finished
+ * instances drop out).  Methods HYBRID (HYP_ARCH_PARALLEL networks) and
+ * JACOBI; check_every and fold_window are not used; criterion E_1 only.
+ * o->variable_density applies the variable-density operator of
+ * hyp_opts.variable_density to every instance (each with its own rho).
+ * o->tile_rows: 0 (the tuned tile rows per grid side), or 8 or 16 for every
+ * constant-density instance (variable-density tiles use 8).  The network
+ * weights are the context's at creation (the buffer's contents may change
+ * between calls, not its address).  The workspace holds the batch tables
+ * followed by one projection workspace per instance. */
 typedef struct hyp_batch hyp_batch;
 
 int hyp_batch_workspace_size(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, size_t* bytes);
 /* Validates, uploads the tables and plans every instance (synchronous).
- * states[i].rho and .xi may be NULL when only hyp_batch_project is used. */
+ * physics: NULL (projection only) or n entries, one per instance (gravity,
+ * density contrast, inflow and CFL of that plume: Eq. 1 gives each its own
+ * g); states[i].rho and .xi may be NULL when only hyp_batch_project is
+ * used (rho is required with variable_density). */
 int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_state* states,
-                     const double* thresholds, const hyp_opts* o, void* ws, size_t ws_bytes,
-                     hyp_batch** out);
+                     const double* thresholds, const hyp_physics* physics, const hyp_opts* o,
+                     void* ws, size_t ws_bytes, hyp_batch** out);
 /* Projection of the current faces of every instance; res: n results
- * (device or host-pinned). */
+ * (device or host-pinned), written at the end of the call's work. */
 int hyp_batch_project(hyp_batch* b, hipStream_t stream, hyp_result* res);
-/* One time step (advection, buoyancy, inflow, projection) of every instance. */
-int hyp_batch_step(hyp_batch* b, const hyp_physics* ph, hipStream_t stream, hyp_result* res);
+/* One time step (advection, buoyancy, inflow, projection) of every instance
+ * with its own physics (HYP_EINVAL when the batch was created without). */
+int hyp_batch_step(hyp_batch* b, hipStream_t stream, hyp_result* res);
 /* Record hyp_batch_step into a hipGraph (replayed by hyp_batch_launch on any
- * stream).  The inflow noise arrays are read at replay time. */
-int hyp_batch_capture(hyp_batch* b, const hyp_physics* ph, hipStream_t stream, hyp_result* res);
+ * stream).  The inflow noise arrays are read at replay time.  Inside the
+ * graph the persistent Jacobi launch is a plain launch of as many
+ * work-groups as the GPU holds at once; its grid barriers give up after 2 s
+ * (status ABORTED) if they are ever not all resident. */
+int hyp_batch_capture(hyp_batch* b, hipStream_t stream, hyp_result* res);
 int hyp_batch_launch(hyp_batch* b, hipStream_t stream);
 int hyp_batch_destroy(hyp_batch* b);
 

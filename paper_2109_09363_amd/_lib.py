@@ -78,11 +78,11 @@ SIGNATURES = {
     "hyp_project_backward": (c_i32, [c_vp, ctypes.POINTER(Grid), c_i32, c_f32, c_f64, c_i32, c_vp,
                                      c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "hyp_batch_workspace_size": (c_i32, [c_vp, c_i32, c_vp, ctypes.POINTER(ctypes.c_size_t)]),
-    "hyp_batch_create": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, ctypes.POINTER(Opts), c_vp,
+    "hyp_batch_create": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(Opts), c_vp,
                                  ctypes.c_size_t, ctypes.POINTER(c_vp)]),
     "hyp_batch_project": (c_i32, [c_vp, c_vp, c_vp]),
-    "hyp_batch_step": (c_i32, [c_vp, ctypes.POINTER(Physics), c_vp, c_vp]),
-    "hyp_batch_capture": (c_i32, [c_vp, ctypes.POINTER(Physics), c_vp, c_vp]),
+    "hyp_batch_step": (c_i32, [c_vp, c_vp, c_vp]),
+    "hyp_batch_capture": (c_i32, [c_vp, c_vp, c_vp]),
     "hyp_batch_launch": (c_i32, [c_vp, c_vp]),
     "hyp_batch_destroy": (c_i32, [c_vp]),
     "hyp_adam": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_f32, c_f32, c_f32, c_f32, c_vp]),

@@ -242,14 +242,16 @@ class Projector:
 
 
 class Batch:
-    """Many plumes of uneven sizes projected (or stepped) together: per
-    instance advection / divergence / CNN launches and one persistent Jacobi
-    launch for all instances.  `instances` is a list of dicts with keys
-    nx, ny, dx, flags, u, v, p and optionally rho, xi, dt, rho0, threshold."""
+    """Many plumes of uneven sizes projected (or stepped) together: one launch
+    per phase over all instances and one persistent Jacobi launch.
+    `instances` is a list of dicts with keys nx, ny, dx, flags, u, v, p and
+    optionally rho, xi, dt, rho0, threshold, and the instance's physics g,
+    drho, u_in, cfl (needed by step_async / capture; each plume its own)."""
 
     def __init__(self, instances, threshold: float = 1e-3, method: str = "hybrid",
                  params=None, scales: int = 0, channels: int = 0, precision: str = "fp32",
-                 max_iters: int = 200000, omega: float = 1.0, device=None):
+                 max_iters: int = 200000, omega: float = 1.0, device=None,
+                 variable_density: bool = False, tile_rows: int = 0):
         self.lib = L.lib()
         self.device = torch.device("cuda" if device is None else device)
         ctx = ctypes.c_void_p()
@@ -259,11 +261,14 @@ class Batch:
         self.n = len(instances)
         self.inst = instances
         if params is not None:
+            _need(params, torch.float32, (int(self.lib.hyp_param_count(self.ctx)),), "params")
             L.check("hyp_set_weights", self.lib.hyp_set_weights(self.ctx, _ptr(params), params.numel()))
             self.params = params
         G = (L.Grid * self.n)()
         S = (L.State * self.n)()
         T = (ctypes.c_double * self.n)()
+        have_phys = all("g" in d for d in instances)
+        PH = (L.Physics * self.n)() if have_phys else None
         for i, d in enumerate(instances):
             nx, ny = int(d["nx"]), int(d["ny"])
             G[i] = L.Grid(nx, ny, float(d["dx"]), float(d.get("dt", 1.0)), float(d.get("rho0", 1.0)))
@@ -271,20 +276,32 @@ class Batch:
             _need(d["v"], torch.float32, (ny + 1, nx), "v")
             _need(d["p"], torch.float32, (ny, nx), "p")
             _need(d["flags"], torch.uint8, (ny, nx), "flags")
+            if d.get("rho") is not None:
+                _need(d["rho"], torch.float32, (ny, nx), "rho")
+            elif variable_density:
+                raise ValueError("variable_density needs rho for every instance")
+            if d.get("xi") is not None:
+                _need(d["xi"], torch.float32, (nx,), "xi")
             S[i] = L.State(_ptr(d.get("rho")), _ptr(d["u"]), _ptr(d["v"]), _ptr(d["p"]),
                            _ptr(d["flags"]), _ptr(d.get("xi")))
             T[i] = float(d.get("threshold", threshold))
-        self._grids, self._states, self._thr = G, S, T
+            if have_phys:
+                PH[i] = L.Physics(float(d["g"]), float(d.get("rho0", 1.0)), float(d.get("drho", 0.01)),
+                                  float(d.get("u_in", 1.0)), float(d.get("cfl", 0.5)))
+        self.has_physics = have_phys
+        self._grids, self._states, self._thr, self._phys = G, S, T, PH
         nbytes = ctypes.c_size_t()
         L.check("hyp_batch_workspace_size",
                 self.lib.hyp_batch_workspace_size(self.ctx, self.n, G, ctypes.byref(nbytes)))
         self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         self.res = torch.zeros(self.n * ctypes.sizeof(L.Result), dtype=torch.uint8, device=self.device)
-        o = L.Opts(L.METHODS[method], int(max_iters), 8, 0, float(omega), 0, 0, 0, 0, 0)
+        o = L.Opts(L.METHODS[method], int(max_iters), 8, 0, float(omega), 0, 0, int(tile_rows),
+                   1 if variable_density else 0, 0)
         b = ctypes.c_void_p()
         torch.cuda.synchronize()
-        L.check("hyp_batch_create", self.lib.hyp_batch_create(self.ctx, self.n, G, S, T, ctypes.byref(o),
-                                                              _ptr(self.ws), self.ws.numel(), ctypes.byref(b)))
+        L.check("hyp_batch_create", self.lib.hyp_batch_create(
+            self.ctx, self.n, G, S, T, PH, ctypes.byref(o), _ptr(self.ws), self.ws.numel(),
+            ctypes.byref(b)))
         self.batch = b
 
     def __del__(self):
@@ -301,21 +318,16 @@ class Batch:
     def project_async(self):
         L.check("hyp_batch_project", self.lib.hyp_batch_project(self.batch, _stream(), _ptr(self.res)))
 
-    def _phys(self, g, drho, u_in, cfl, rho0):
-        return L.Physics(float(g), float(rho0), float(drho), float(u_in), float(cfl))
+    def step_async(self):
+        """One time step of every instance with its own physics."""
+        L.check("hyp_batch_step", self.lib.hyp_batch_step(self.batch, _stream(), _ptr(self.res)))
 
-    def step_async(self, g: float, drho: float, u_in: float = 1.0, cfl: float = 0.5, rho0: float = 1.0):
-        ph = self._phys(g, drho, u_in, cfl, rho0)
-        L.check("hyp_batch_step", self.lib.hyp_batch_step(self.batch, ctypes.byref(ph), _stream(),
-                                                          _ptr(self.res)))
-
-    def capture(self, g: float, drho: float, u_in: float = 1.0, cfl: float = 0.5, rho0: float = 1.0):
+    def capture(self):
         """Record one batched time step as a hipGraph (on a side stream)."""
-        ph = self._phys(g, drho, u_in, cfl, rho0)
         s = torch.cuda.Stream()
         torch.cuda.synchronize()
         with torch.cuda.stream(s):
-            L.check("hyp_batch_capture", self.lib.hyp_batch_capture(self.batch, ctypes.byref(ph), _stream(),
+            L.check("hyp_batch_capture", self.lib.hyp_batch_capture(self.batch, _stream(),
                                                                     _ptr(self.res)))
         torch.cuda.synchronize()
 

@@ -12,6 +12,7 @@
 // trace of pass 1 interpolated.  Sampling is bilinear with positions clamped
 // to the extent of the sampled grid.
 #include "../../include/hyproj.h"
+#include "batch.h"
 #include "common.h"
 #include "internal.h"
 
@@ -69,31 +70,41 @@ __device__ __forceinline__ void locate(const AdvPtrs& A, int gid, int* which, in
   *j = l / A.W[w];
 }
 
-__global__ __launch_bounds__(256) void cfl_kernel(int nu, int nv, const float* __restrict__ u,
-                                                  const float* __restrict__ v,
-                                                  double* __restrict__ blockpart) {
-  __shared__ double red[4];
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void cfl_body(int gid, int nu, int nv, const float* __restrict__ u,
+                                         const float* __restrict__ v, double* __restrict__ slot,
+                                         double* red) {
   double m = 0.0;
   if (gid < nu) m = fabs((double)u[gid]);
   else if (gid < nu + nv) m = fabs((double)v[gid - nu]);
   m = block_max(m, red);
-  if (threadIdx.x == 0) blockpart[blockIdx.x] = m;
+  if (threadIdx.x == 0) *slot = m;
 }
 
-__global__ __launch_bounds__(256) void cfl_finish(int nblocks, const double* __restrict__ blockpart,
-                                                  double dx, double cfl, double u_in, Scalars* sc) {
-  __shared__ double red[4];
+__device__ __forceinline__ void cfl_finish_body(int nblocks, const double* __restrict__ blockpart,
+                                                double dx, double cfl, double u_in, Scalars* sc,
+                                                double* red) {
   double m = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmax(m, blockpart[b]);
   m = block_max(m, red);
   if (threadIdx.x == 0) sc->dt = cfl * dx / fmax(m, u_in);
 }
 
-__global__ __launch_bounds__(256) void advect_pass1(AdvPtrs A, int nx, int ny, float inv_dx,
-                                                    const float* __restrict__ u,
-                                                    const float* __restrict__ v, const Scalars* sc) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void cfl_kernel(int nu, int nv, const float* __restrict__ u,
+                                                  const float* __restrict__ v,
+                                                  double* __restrict__ blockpart) {
+  __shared__ double red[4];
+  cfl_body(blockIdx.x * blockDim.x + threadIdx.x, nu, nv, u, v, blockpart + blockIdx.x, red);
+}
+
+__global__ __launch_bounds__(256) void cfl_finish(int nblocks, const double* __restrict__ blockpart,
+                                                  double dx, double cfl, double u_in, Scalars* sc) {
+  __shared__ double red[4];
+  cfl_finish_body(nblocks, blockpart, dx, cfl, u_in, sc, red);
+}
+
+__device__ __forceinline__ void pass1_body(const AdvPtrs& A, int gid, int nx, int ny, float inv_dx,
+                                           const float* __restrict__ u, const float* __restrict__ v,
+                                           const Scalars* sc) {
   if (gid >= A.n0 + A.n1 + A.n2) return;
   int w, i, j;
   locate(A, gid, &w, &i, &j);
@@ -104,10 +115,9 @@ __global__ __launch_bounds__(256) void advect_pass1(AdvPtrs A, int nx, int ny, f
       sample(A.q[w], A.H[w], A.W[w], (float)i - r * vx, (float)j - r * vy, nullptr, nullptr);
 }
 
-__global__ __launch_bounds__(256) void advect_pass2(AdvPtrs A, int nx, int ny, float inv_dx,
-                                                    const float* __restrict__ u,
-                                                    const float* __restrict__ v, const Scalars* sc) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pass2_body(const AdvPtrs& A, int gid, int nx, int ny, float inv_dx,
+                                           const float* __restrict__ u, const float* __restrict__ v,
+                                           const Scalars* sc) {
   if (gid >= A.n0 + A.n1 + A.n2) return;
   int w, i, j;
   locate(A, gid, &w, &i, &j);
@@ -123,24 +133,34 @@ __global__ __launch_bounds__(256) void advect_pass2(AdvPtrs A, int nx, int ny, f
   A.out[w][l] = fminf(fmaxf(qn, mn), mx);
 }
 
+__global__ __launch_bounds__(256) void advect_pass1(AdvPtrs A, int nx, int ny, float inv_dx,
+                                                    const float* __restrict__ u,
+                                                    const float* __restrict__ v, const Scalars* sc) {
+  pass1_body(A, blockIdx.x * blockDim.x + threadIdx.x, nx, ny, inv_dx, u, v, sc);
+}
+
+__global__ __launch_bounds__(256) void advect_pass2(AdvPtrs A, int nx, int ny, float inv_dx,
+                                                    const float* __restrict__ u,
+                                                    const float* __restrict__ v, const Scalars* sc) {
+  pass2_body(A, blockIdx.x * blockDim.x + threadIdx.x, nx, ny, inv_dx, u, v, sc);
+}
+
 // buoyancy on interior/top v faces, inflow, boundary faces; writes the state
-__global__ __launch_bounds__(256) void advect_pass3(int nx, int ny, const float* __restrict__ rho_n,
-                                                    const float* __restrict__ u_n,
-                                                    const float* __restrict__ v_n,
-                                                    const uint8_t* __restrict__ cell,
-                                                    const float* __restrict__ xi, double g,
-                                                    double rho0, double drho, double u_in,
-                                                    float* __restrict__ rho, float* __restrict__ u,
-                                                    float* __restrict__ v, const Scalars* sc) {
+__device__ __forceinline__ void pass3_body(int gid, int nx, int ny, const float* __restrict__ rho_n,
+                                           const float* __restrict__ u_n,
+                                           const float* __restrict__ v_n,
+                                           const uint8_t* __restrict__ cell,
+                                           const float* __restrict__ xi, double g, double rho0,
+                                           double drho, double u_in, float* __restrict__ rho,
+                                           float* __restrict__ u, float* __restrict__ v,
+                                           const Scalars* sc) {
   const int n = nx * ny, nu = ny * (nx + 1), nv = (ny + 1) * nx;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid < n) {
-    const int i = gid % nx, j = gid / nx;
+    const int j = gid / nx;
     const uint8_t ci = cell[gid];
     float val = rho_n[gid];
     if (j == 0 && (ci & C_INFLOW)) val = (float)(rho0 * (1.0 - drho));
     rho[gid] = val;
-    (void)i;
   } else if (gid < n + nu) {
     const int l = gid - n, U = nx + 1, i = l % U, j = l / U;
     bool open = false;
@@ -173,6 +193,32 @@ __global__ __launch_bounds__(256) void advect_pass3(int nx, int ny, const float*
   }
 }
 
+__global__ __launch_bounds__(256) void advect_pass3(int nx, int ny, const float* __restrict__ rho_n,
+                                                    const float* __restrict__ u_n,
+                                                    const float* __restrict__ v_n,
+                                                    const uint8_t* __restrict__ cell,
+                                                    const float* __restrict__ xi, double g,
+                                                    double rho0, double drho, double u_in,
+                                                    float* __restrict__ rho, float* __restrict__ u,
+                                                    float* __restrict__ v, const Scalars* sc) {
+  pass3_body(blockIdx.x * blockDim.x + threadIdx.x, nx, ny, rho_n, u_n, v_n, cell, xi, g, rho0,
+             drho, u_in, rho, u, v, sc);
+}
+
+// the sample grids and temporaries of one instance (workspace adv area)
+__host__ __device__ __forceinline__ AdvPtrs adv_ptrs(int nx, int ny, const float* rho, const float* u,
+                                                     const float* v, float* adv) {
+  const int n = nx * ny, nu = ny * (nx + 1), nv = (ny + 1) * nx;
+  AdvPtrs A{};
+  A.q[0] = rho; A.q[1] = u; A.q[2] = v;
+  A.hat[0] = adv; A.hat[1] = adv + n; A.hat[2] = adv + n + nu;
+  float* o = adv + n + nu + nv;
+  A.out[0] = o; A.out[1] = o + n; A.out[2] = o + n + nu;
+  A.H[0] = ny; A.W[0] = nx; A.H[1] = ny; A.W[1] = nx + 1; A.H[2] = ny + 1; A.W[2] = nx;
+  A.n0 = n; A.n1 = nu; A.n2 = nv;
+  return A;
+}
+
 hipError_t run_advect(int nx, int ny, double dx, double g, double rho0, double drho, double u_in,
                       double cfl, float* rho, float* u, float* v, const float* xi, const Ws& w,
                       hipStream_t s) {
@@ -181,19 +227,61 @@ hipError_t run_advect(int nx, int ny, double dx, double g, double rho0, double d
   if ((size_t)nbf > w.blockpart_n) return hipErrorInvalidValue;
   cfl_kernel<<<nbf, 256, 0, s>>>(nu, nv, u, v, w.blockpart);
   cfl_finish<<<1, 256, 0, s>>>(nbf, w.blockpart, dx, cfl, u_in, w.sc);
-  AdvPtrs A{};
-  A.q[0] = rho; A.q[1] = u; A.q[2] = v;
-  A.hat[0] = w.adv; A.hat[1] = w.adv + n; A.hat[2] = w.adv + n + nu;
-  float* o = w.adv + n + nu + nv;
-  A.out[0] = o; A.out[1] = o + n; A.out[2] = o + n + nu;
-  A.H[0] = ny; A.W[0] = nx; A.H[1] = ny; A.W[1] = nx + 1; A.H[2] = ny + 1; A.W[2] = nx;
-  A.n0 = n; A.n1 = nu; A.n2 = nv;
+  const AdvPtrs A = adv_ptrs(nx, ny, rho, u, v, w.adv);
   const int tot = n + nu + nv, nb = (tot + 255) / 256;
   const float inv_dx = (float)(1.0 / dx);
   advect_pass1<<<nb, 256, 0, s>>>(A, nx, ny, inv_dx, u, v, w.sc);
   advect_pass2<<<nb, 256, 0, s>>>(A, nx, ny, inv_dx, u, v, w.sc);
   advect_pass3<<<nb, 256, 0, s>>>(nx, ny, A.out[0], A.out[1], A.out[2], w.cell, xi, g, rho0, drho,
                                   u_in, rho, u, v, w.sc);
+  return hipGetLastError();
+}
+
+// ---- batched: one launch per pass over all instances (batch.h) ------------
+__device__ __forceinline__ int adv_loc(const int* __restrict__ first, int n, int* lb) {
+  const int i = batch_find(first, n, blockIdx.x);
+  *lb = blockIdx.x - first[i];
+  return i;
+}
+
+__global__ __launch_bounds__(256) void cfl_batch(const BInst* __restrict__ I, const int* first, int n) {
+  __shared__ double red[4];
+  int lb;
+  const BInst& B = I[adv_loc(first, n, &lb)];
+  const int nu = B.ny * (B.nx + 1), nv = (B.ny + 1) * B.nx;
+  cfl_body(lb * blockDim.x + threadIdx.x, nu, nv, B.u, B.v, B.w.blockpart + lb, red);
+}
+
+__global__ __launch_bounds__(256) void cfl_finish_batch(const BInst* __restrict__ I, const int* first) {
+  __shared__ double red[4];
+  const BInst& B = I[blockIdx.x];
+  cfl_finish_body(first[blockIdx.x + 1] - first[blockIdx.x], B.w.blockpart, B.dx, B.cfl, B.u_in,
+                  B.w.sc, red);
+}
+
+template <int PASS>
+__global__ __launch_bounds__(256) void advect_batch(const BInst* __restrict__ I, const int* first, int n) {
+  int lb;
+  const BInst& B = I[adv_loc(first, n, &lb)];
+  const int gid = lb * blockDim.x + threadIdx.x;
+  const AdvPtrs A = adv_ptrs(B.nx, B.ny, B.rho, B.u, B.v, B.w.adv);
+  const float inv_dx = (float)(1.0 / B.dx);
+  if constexpr (PASS == 1) pass1_body(A, gid, B.nx, B.ny, inv_dx, B.u, B.v, B.w.sc);
+  else if constexpr (PASS == 2) pass2_body(A, gid, B.nx, B.ny, inv_dx, B.u, B.v, B.w.sc);
+  else
+    pass3_body(gid, B.nx, B.ny, A.out[0], A.out[1], A.out[2], B.w.cell, B.xi, B.g, B.rho0, B.drho,
+               B.u_in, B.rho, B.u, B.v, B.w.sc);
+}
+
+hipError_t run_advect_batch(const BInst* I, const BatchRanges& R, hipStream_t s) {
+  if (R.total[RK_FACE] > 0) cfl_batch<<<R.total[RK_FACE], 256, 0, s>>>(I, R.of(RK_FACE), R.n);
+  cfl_finish_batch<<<R.n, 256, 0, s>>>(I, R.of(RK_FACE));
+  const int nb = R.total[RK_ADV];
+  if (nb > 0) {
+    advect_batch<1><<<nb, 256, 0, s>>>(I, R.of(RK_ADV), R.n);
+    advect_batch<2><<<nb, 256, 0, s>>>(I, R.of(RK_ADV), R.n);
+    advect_batch<3><<<nb, 256, 0, s>>>(I, R.of(RK_ADV), R.n);
+  }
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/hyproj.h"
+#include "batch.h"
 #include "internal.h"
 
 struct hyp_ctx {
@@ -441,34 +442,46 @@ int hyp_step(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp_s
                             w, true, stream, res);
 }
 
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
-// Batched projection of many plumes of uneven sizes.
+// Batched projection of many plumes of uneven sizes: per phase one launch
+// over every instance (batch.h), the Jacobi sweeps in one persistent launch.
 struct hyp_batch {
   hyp_ctx* ctx = nullptr;
-  int n = 0, ntiles = 0;
-  std::vector<hyp_grid> grids;
-  std::vector<hyp_state> states;
+  int n = 0, ntiles = 0, ntiles_max = 0;
+  size_t cnn_bytes = 0;
+  int cnn_tiles[4] = {0, 0, 0, 0};
+  int tile_mode = 0;  // tile variants of the persistent Jacobi launch
+  bool cnn = false, var = false, physics = false;
   std::vector<WsLayout> layouts;
   std::vector<Ws> ws;
-  std::vector<double> thr;
-  hyp_opts opts{};
   void* area = nullptr;
+  hyp::BatchDevice dev{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
+// Batch area, then one projection workspace per instance; the tile count is
+// bounded by the smallest tiles (R = 8) so that the size does not depend on
+// the options.
 static size_t batch_layout(hyp_ctx* ctx, int n, const hyp_grid* grids, std::vector<size_t>* offs,
-                           int* ntiles_out) {
-  int ntiles = 0;
-  for (int i = 0; i < n; ++i) ntiles += batch_tiles_of(grids[i].nx, grids[i].ny);
-  size_t o = align256(batch_area_bytes(n, ntiles));
+                           int* ntiles_max, size_t* cnn_bytes) {
+  int nt = 0;
+  for (int i = 0; i < n; ++i) nt += batch_tiles_of(grids[i].nx, grids[i].ny, 8);
+  const size_t cb = ctx->net.scales > 0 && ctx->net.arch == HYP_ARCH_PARALLEL
+                        ? cnn_batch_bytes(ctx->net, n) : 0;
+  size_t o = align256(batch_area_bytes(n, nt, cb));
   for (int i = 0; i < n; ++i) {
     if (offs) offs->push_back(o);
     o = align256(o + make_layout(grids[i].nx, grids[i].ny, ctx->net).total);
   }
-  if (ntiles_out) *ntiles_out = ntiles;
+  if (ntiles_max) *ntiles_max = nt;
+  if (cnn_bytes) *cnn_bytes = cb;
   return o;
 }
+
+extern "C" {
 
 int hyp_batch_workspace_size(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, size_t* bytes) {
   if (!ctx || n < 1 || !grids || !bytes) return HYP_EINVAL;
@@ -477,58 +490,103 @@ int hyp_batch_workspace_size(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, siz
     g.dt = g.dt > 0.0 ? g.dt : 1.0;
     if (!grid_ok(&g)) return HYP_EINVAL;
   }
-  *bytes = batch_layout(ctx, n, grids, nullptr, nullptr);
+  *bytes = batch_layout(ctx, n, grids, nullptr, nullptr, nullptr);
   return HYP_OK;
 }
 
 int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_state* states,
-                     const double* thresholds, const hyp_opts* o, void* ws, size_t ws_bytes,
-                     hyp_batch** out) {
+                     const double* thresholds, const hyp_physics* physics, const hyp_opts* o,
+                     void* ws, size_t ws_bytes, hyp_batch** out) {
   if (!ctx || n < 1 || !grids || !states || !thresholds || !o || !ws || !out) return HYP_EINVAL;
   *out = nullptr;
   if (o->method != HYP_METHOD_HYBRID && o->method != HYP_METHOD_JACOBI) return HYP_EUNSUPPORTED;
-  if (o->variable_density != 0 || o->criterion != HYP_CRIT_E1) return HYP_EUNSUPPORTED;
+  if (o->criterion != HYP_CRIT_E1) return HYP_EUNSUPPORTED;
+  if (o->variable_density != 0 && o->variable_density != 1) return HYP_EINVAL;
   if (o->max_iters < 0 || !(o->omega > 0.f) || o->checkpoint_every != 0) return HYP_EINVAL;
-  if (o->method == HYP_METHOD_HYBRID && (ctx->net.scales == 0 || !ctx->params)) return HYP_ENOWEIGHTS;
+  if (o->tile_rows != 0 && o->tile_rows != 8 && o->tile_rows != 16) return HYP_EINVAL;
+  const bool cnn = o->method == HYP_METHOD_HYBRID;
+  if (cnn && (ctx->net.scales == 0 || !ctx->params)) return HYP_ENOWEIGHTS;
+  if (cnn && (ctx->net.arch != HYP_ARCH_PARALLEL || ctx->net.scales > kBatchMaxScales))
+    return HYP_EUNSUPPORTED;
+  const bool var = o->variable_density != 0;
   for (int i = 0; i < n; ++i) {
     hyp_grid g = grids[i];
     g.dt = g.dt > 0.0 ? g.dt : 1.0;
     if (!grid_ok(&g) || !(thresholds[i] >= 0.0)) return HYP_EINVAL;
-    const hyp_state& s = states[i];
-    if (!s.u || !s.v || !s.p || !s.flags) return HYP_EINVAL;
-    if (o->method == HYP_METHOD_HYBRID) {
+    const hyp_state& st = states[i];
+    if (!st.u || !st.v || !st.p || !st.flags) return HYP_EINVAL;
+    if (var && !st.rho) return HYP_EINVAL;
+    if (physics) {
+      const hyp_physics& ph = physics[i];
+      if (!(ph.cfl > 0.0) || !(ph.u_in > 0.0) || !(ph.rho0 > 0.0)) return HYP_EINVAL;
+    }
+    if (cnn) {
       const int m = 1 << (ctx->net.scales - 1);
       if (g.nx % m || g.ny % m) return HYP_EUNSUPPORTED;
     }
   }
   std::vector<size_t> offs;
-  int ntiles = 0;
-  const size_t need = batch_layout(ctx, n, grids, &offs, &ntiles);
+  int ntiles_max = 0;
+  size_t cnn_bytes = 0;
+  const size_t need = batch_layout(ctx, n, grids, &offs, &ntiles_max, &cnn_bytes);
   if (ws_bytes < need) return HYP_EWORKSPACE;
   hyp_batch* b = new (std::nothrow) hyp_batch;
   if (!b) return HYP_EINTERNAL;
   b->ctx = ctx;
   b->n = n;
-  b->ntiles = ntiles;
-  b->opts = *o;
+  b->ntiles_max = ntiles_max;
+  b->cnn_bytes = cnn_bytes;
+  b->cnn = cnn;
+  b->var = var;
+  b->physics = physics != nullptr;
   b->area = ws;
-  std::vector<int> nx(n), ny(n);
-  std::vector<double> dx(n);
+  std::vector<BInst> binst(n);
+  std::vector<int> rows(n);
+  int ntiles = 0;
   for (int i = 0; i < n; ++i) {
-    b->grids.push_back(grids[i]);
-    b->states.push_back(states[i]);
-    b->thr.push_back(thresholds[i]);
-    b->layouts.push_back(make_layout(grids[i].nx, grids[i].ny, ctx->net));
+    const hyp_grid& g = grids[i];
+    const hyp_state& st = states[i];
+    b->layouts.push_back(make_layout(g.nx, g.ny, ctx->net));
     b->ws.push_back(ws_view((char*)ws + offs[i], b->layouts.back()));
-    nx[i] = grids[i].nx; ny[i] = grids[i].ny; dx[i] = grids[i].dx;
+    const WsLayout& Ly = b->layouts.back();
+    BInst& B = binst[i];
+    B = BInst{};
+    B.nx = g.nx; B.ny = g.ny; B.dx = g.dx; B.rho0 = g.rho0;
+    B.dt = g.dt > 0.0 ? g.dt : 1.0;
+    if (physics) {
+      B.g = physics[i].g; B.drho = physics[i].drho; B.u_in = physics[i].u_in;
+      B.cfl = physics[i].cfl;
+    }
+    B.var = var ? 1 : 0;
+    B.S = cnn ? ctx->net.scales : 0;
+    B.u = st.u; B.v = st.v; B.rho = st.rho; B.p = st.p; B.xi = st.xi; B.flags = st.flags;
+    B.w = b->ws.back();
+    for (int k = 0; k < B.S; ++k) {
+      B.sc_h[k] = Ly.sc_h[k];
+      B.sc_w[k] = Ly.sc_w[k];
+      B.sc_off_px[k] = Ly.sc_off_px[k];
+    }
+    rows[i] = batch_rows_of(g.nx, g.ny, var, o->tile_rows);
+    ntiles += batch_tiles_of(g.nx, g.ny, rows[i]);
   }
-  if (batch_setup(ws, n, nx.data(), ny.data(), dx.data(), b->thr.data(), o->max_iters, o->omega,
-                  b->ws.data()) != hipSuccess) {
+  b->ntiles = ntiles;
+  b->tile_mode = batch_tile_mode(n, rows.data(), var);
+  // the tables sit at the front of the area, sized for ntiles_max tiles
+  const BatchDevice probe = batch_device(ws, n, ntiles, cnn_bytes);
+  for (int i = 0; i < n; ++i) binst[i].res = probe.results + i;
+  std::vector<double> thr(thresholds, thresholds + n);
+  if (batch_setup(ws, n, ntiles, cnn_bytes, binst.data(), rows.data(), thr.data(), o->max_iters,
+                  o->omega, &b->dev) != hipSuccess) {
+    delete b;
+    return HYP_EHIP;
+  }
+  if (cnn && cnn_batch_setup(ctx->net, n, b->layouts.data(), b->ws.data(), ctx->params,
+                             b->dev.cnn_tables, b->cnn_tiles) != hipSuccess) {
     delete b;
     return HYP_EHIP;
   }
   for (int i = 0; i < n; ++i)
-    if (run_plan(ctx->dev, nx[i], ny[i], states[i].flags, b->ws[i], nullptr) != hipSuccess) {
+    if (run_plan(ctx->dev, grids[i].nx, grids[i].ny, states[i].flags, b->ws[i], nullptr) != hipSuccess) {
       delete b;
       return HYP_EHIP;
     }
@@ -540,52 +598,47 @@ int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_s
   return HYP_OK;
 }
 
-static int batch_enqueue(hyp_batch* b, const hyp_physics* ph, hipStream_t s, hyp_result* res,
-                         bool cooperative) {
+}  // extern "C"
+
+static int batch_enqueue(hyp_batch* b, bool step, hipStream_t s, hyp_result* res, bool cooperative) {
   hyp_ctx* ctx = b->ctx;
-  const bool cnn = b->opts.method == HYP_METHOD_HYBRID;
-  for (int i = 0; i < b->n; ++i) {
-    const hyp_grid& g = b->grids[i];
-    const hyp_state& st = b->states[i];
-    const Ws& w = b->ws[i];
-    if (ph && run_advect(g.nx, g.ny, g.dx, ph->g, ph->rho0, ph->drho, ph->u_in, ph->cfl, st.rho,
-                         st.u, st.v, st.xi, w, s) != hipSuccess)
+  const BInst* I = b->dev.binst;
+  const BatchRanges& R = b->dev.ranges;
+  if (step && run_advect_batch(I, R, s) != hipSuccess) return HYP_EHIP;
+  if (run_div_batch(I, R, s) != hipSuccess) return HYP_EHIP;
+  if (b->var && run_coef_batch(I, R, s) != hipSuccess) return HYP_EHIP;
+  if (b->cnn) {
+    if (run_cnn_batch(ctx->dev, ctx->net, I, R, b->dev.cnn_tables, b->cnn_tiles, b->ws[0],
+                      ctx->params, s) != hipSuccess)
       return HYP_EHIP;
-    if (run_div(g.nx, g.ny, g.dx, st.u, st.v, w, b->layouts[i].nblocks_stream, s) != hipSuccess)
-      return HYP_EHIP;
-    if (cnn) {
-      if (run_cnn(ctx->dev, ctx->net, b->layouts[i], g.nx, g.ny, g.dx, ctx->params, w, s) != hipSuccess)
-        return HYP_EHIP;
-    } else if (run_init_phi(g.nx, g.ny, nullptr, 1.0, w, s) != hipSuccess) {
-      return HYP_EHIP;
-    }
-  }
-  if (run_jacobi_batch(ctx->dev, b->area, b->n, b->ntiles, cooperative, s) != hipSuccess)
+  } else if (run_init_phi_batch(I, R, s) != hipSuccess) {
     return HYP_EHIP;
-  for (int i = 0; i < b->n; ++i) {
-    const hyp_grid& g = b->grids[i];
-    const hyp_state& st = b->states[i];
-    if (run_grad_and_finish(g.nx, g.ny, g.dx, g.rho0, g.dt > 0.0 ? g.dt : 1.0, ph != nullptr, st.u,
-                            st.v, st.p, b->ws[i], b->layouts[i].nblocks_stream, res + i, false, s) != hipSuccess)
-      return HYP_EHIP;
   }
+  if (run_jacobi_batch(ctx->dev, b->area, b->n, b->ntiles, b->cnn_bytes, b->tile_mode, cooperative,
+                       s) != hipSuccess)
+    return HYP_EHIP;
+  if (run_grad_finish_batch(I, R, step, b->var, s) != hipSuccess) return HYP_EHIP;
+  if (hipMemcpyAsync(res, b->dev.results, sizeof(hyp_result) * b->n, hipMemcpyDefault, s) != hipSuccess)
+    return HYP_EHIP;
   return HYP_OK;
 }
 
+extern "C" {
+
 int hyp_batch_project(hyp_batch* b, hipStream_t stream, hyp_result* res) {
   if (!b || !res) return HYP_EINVAL;
-  return batch_enqueue(b, nullptr, stream, res, true);
+  return batch_enqueue(b, false, stream, res, true);
 }
 
-int hyp_batch_step(hyp_batch* b, const hyp_physics* ph, hipStream_t stream, hyp_result* res) {
-  if (!b || !ph || !res) return HYP_EINVAL;
-  for (const auto& s : b->states)
-    if (!s.rho || !s.xi) return HYP_EINVAL;
-  return batch_enqueue(b, ph, stream, res, true);
+int hyp_batch_step(hyp_batch* b, hipStream_t stream, hyp_result* res) {
+  if (!b || !res) return HYP_EINVAL;
+  if (!b->physics) return HYP_EINVAL;
+  return batch_enqueue(b, true, stream, res, true);
 }
 
-int hyp_batch_capture(hyp_batch* b, const hyp_physics* ph, hipStream_t stream, hyp_result* res) {
+int hyp_batch_capture(hyp_batch* b, hipStream_t stream, hyp_result* res) {
   if (!b || !res || !stream) return HYP_EINVAL;
+  if (!b->physics) return HYP_EINVAL;
   if (b->exec) {
     (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
@@ -595,7 +648,7 @@ int hyp_batch_capture(hyp_batch* b, const hyp_physics* ph, hipStream_t stream, h
     b->graph = nullptr;
   }
   if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return HYP_EHIP;
-  const int rc = batch_enqueue(b, ph, stream, res, false);
+  const int rc = batch_enqueue(b, true, stream, res, false);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(stream, &g);
   if (rc != HYP_OK || e != hipSuccess) {

@@ -9,15 +9,27 @@
 // one write of the tile per B sweeps.  After each block a grid barrier,
 // per-instance E_1 sums (fixed order, one work-group per instance) and stop
 // decisions, and a second barrier; converged instances drop out of the list.
+//
+// The tile height R is chosen per instance (the tuned table of the batch
+// for its grid side, or forced for tuning), and an instance may use the
+// variable-density operator (face weights beta = rho0 / rho_face, R = 8).
+// Every wait is bounded: a work-group that gives up marks every running
+// instance ABORTED and the launch ends.
+#include <vector>
+
 #include "../../include/hyproj.h"
+#include "batch.h"
 #include "common.h"
 #include "internal.h"
 #include "jacobi_rows.h"
+#include "tile_table.h"
 
 namespace hyp {
 
+constexpr int kBatchH = 9;  // halo: 8 sweeps per pass
+
 struct BatchInstDev {
-  int nx, ny, ntx, tile0, ntiles, max_iters;
+  int nx, ny, ntx, tile0, ntiles, max_iters, R, var;
   float inv_dx2, wfac, omega;
   double thr;
   const uint8_t* cell;
@@ -25,6 +37,8 @@ struct BatchInstDev {
   float* phi;
   float* exch;       // two planes
   Scalars* sc;
+  const float* ce;   // variable density: beta of each cell's east face
+  const float* cn;   // ... north face
 };
 
 struct BatchState {  // per instance, device
@@ -35,16 +49,17 @@ struct BatchState {  // per instance, device
 struct BatchParams {
   const BatchInstDev* inst;
   const int* tile_inst;  // instance of each global tile
-  int ninst, ntiles, H;
+  int ninst, ntiles;
   double* tile_part;     // [2][ntiles]
   BatchState* st;
   unsigned* sync;
 };
 
-template <int R>
-__device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int H, int B,
-                                             const float* src, float* dst, bool from_phi,
-                                             float (*edge)[2][4][64], double* red) {
+template <int R, bool VAR>
+__device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int B, const float* src,
+                                             float* dst, bool from_phi, float (*edge)[2][4][64],
+                                             double* red) {
+  constexpr int H = kBatchH;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int TW = 64 - 2 * H, TH = 4 * R - 2 * H;
   const int bx = lt % I.ntx, by = lt / I.ntx;
@@ -53,22 +68,36 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
   const bool col_in = gx >= 0 && gx < I.nx;
   const bool lane_int = lane >= H && lane < H + TW && col_in;
   unsigned imask = 0, fmask = 0;
-  // scaled form of the update (jac_rows_scaled): a = omega / k, b = -omega dx^2 d / k
+  // scaled forms of the update (jacobi_rows.h): constant coefficients keep
+  // aa = omega / k and bb = -omega dx^2 d / k; VAR keeps aa = k, bb and the
+  // face weights beta' = omega beta / k
   float ph[R], aa[R], bb[R];
+  float be[VAR ? R : 1], bw[VAR ? R : 1], bn[VAR ? R : 1], bs[VAR ? R : 1];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int er = wave * R + r, gy = gy0 + r;
     float a_ = 0.f, b_ = 0.f, p_ = 0.f;
+    if constexpr (VAR) be[r] = bw[r] = bn[r] = bs[r] = 0.f;
     if (col_in && gy >= 0 && gy < I.ny) {
-      // the three loads are independent (masked afterwards): one round trip
+      // the loads are independent (masked afterwards): one round trip
       const int g = gy * I.nx + gx;
       const uint8_t ci = I.cell[g];
       const float dv = I.d[g];
       const float pv = from_phi ? I.phi[g] : ld_agent(src + g);
       if (!(ci & C_SOLID)) {
-        const float k = (float)cell_k(ci);
-        a_ = I.omega / k;
-        b_ = -(I.wfac / k) * dv;
+        if constexpr (VAR) {
+          const float e_ = (ci & C_E) ? I.ce[g] : 0.f, w_ = (ci & C_W) ? I.ce[g - 1] : 0.f;
+          const float n_ = (ci & C_N) ? I.cn[g] : 0.f, s_ = (ci & C_S) ? I.cn[g - I.nx] : 0.f;
+          const float k = (e_ + w_) + (n_ + s_);
+          const float sc = I.omega / k;
+          be[r] = e_ * sc; bw[r] = w_ * sc; bn[r] = n_ * sc; bs[r] = s_ * sc;
+          a_ = k;
+          b_ = -(I.wfac / k) * dv;
+        } else {
+          const float k = (float)cell_k(ci);
+          a_ = I.omega / k;
+          b_ = -(I.wfac / k) * dv;
+        }
         p_ = pv;
       }
       if (lane_int && er >= H && er < H + TH) {
@@ -88,24 +117,33 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
     above = wave < 3 ? edge[q][0][wave + 1][lane] : 0.f;
     q ^= 1;
   };
+  auto rows = [&](const float (&s_)[R], float (&d_)[R], float om1) {
+    if constexpr (VAR) jac_rows_var_scaled<R, false>(s_, d_, be, bw, bn, bs, bb, below, above, om1);
+    else jac_rows_scaled<R, false>(s_, d_, aa, bb, below, above, om1);
+  };
   // sweeps in pairs (ph -> tmp -> ph: no register copies between sweeps)
   const float om1 = 1.f - I.omega;
   float tmp[R];
   int s = 0;
   for (; s + 2 <= B; s += 2) {
     edges_of(ph);
-    jac_rows_scaled<R, false>(ph, tmp, aa, bb, below, above, om1);
+    rows(ph, tmp, om1);
     edges_of(tmp);
-    jac_rows_scaled<R, false>(tmp, ph, aa, bb, below, above, om1);
+    rows(tmp, ph, om1);
   }
   for (; s < B; ++s) {
     edges_of(ph);
-    jac_rows_scaled<R, false>(ph, tmp, aa, bb, below, above, om1);
+    rows(ph, tmp, om1);
 #pragma unroll
     for (int r = 0; r < R; ++r) ph[r] = tmp[r];
   }
   edges_of(ph);
-  const double acc = jac_resid_scaled<R>(ph, aa, bb, below, above, I.omega, I.inv_dx2, fmask, false);
+  double acc;
+  if constexpr (VAR)
+    acc = jac_resid_var_scaled<R>(ph, aa, be, bw, bn, bs, bb, below, above, I.omega, I.inv_dx2, fmask,
+                                  false);
+  else
+    acc = jac_resid_scaled<R>(ph, aa, bb, below, above, I.omega, I.inv_dx2, fmask, false);
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if ((imask >> r) & 1u) st_agent(dst + (size_t)(gy0 + r) * I.nx + gx, ph[r]);
@@ -114,15 +152,44 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
   return t;
 }
 
+// every running instance ends with ABORTED (a work-group gave up waiting)
+__device__ void batch_abort(const BatchParams& P) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < P.ninst; ++i)
+    __hip_atomic_fetch_max(&P.inst[i].sc->status, (int32_t)HYP_STATUS_ABORTED, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tile variants present in a launch (bits): constant-coefficient R = 16,
+// constant-coefficient R = 8, variable density (R = 8).  Each combination
+// is its own instance of the kernel, so that a launch carries only the
+// register footprint of the variants its instances use.
+constexpr int kTileR16 = 1, kTileR8 = 2, kTileVar = 4;
+
+template <int MODE>
+__device__ __forceinline__ double batch_tile_any(const BatchInstDev& I, int lt, int B,
+                                                 const float* src, float* dst, bool from_phi,
+                                                 float (*edge)[2][4][64], double* red) {
+  if constexpr ((MODE & kTileVar) != 0) {
+    if (I.var) return batch_tile<8, true>(I, lt, B, src, dst, from_phi, edge, red);
+  }
+  if constexpr ((MODE & kTileR8) != 0) {
+    if ((MODE & kTileR16) == 0 || I.R == 8)
+      return batch_tile<8, false>(I, lt, B, src, dst, from_phi, edge, red);
+  }
+  if constexpr ((MODE & kTileR16) != 0) return batch_tile<16, false>(I, lt, B, src, dst, from_phi, edge, red);
+  return 0.0;
+}
+
 // at most 128 VGPRs: four work-groups per CU, so that one work-group's
 // loads overlap the others' sweeps (with 3 the 8192^2 DRAM case runs 15 %
 // slower)
-template <int R>
+template <int MODE>
 __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
   __shared__ float edge[2][2][4][64];
   __shared__ double red[4];
   const int G = gridDim.x;
-  const int B = P.H - 1;
+  const int B = kBatchH - 1;
   unsigned nbar = 0;
   int par = 0;  // plane read this block (written by the previous one)
   for (int nb = 0;; ++nb) {
@@ -134,12 +201,16 @@ __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
       if (sti >= 0) continue;
       const int k = __hip_atomic_load(&P.st[i].iters, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const int b = nb == 0 ? 0 : min(B, I.max_iters - k);
-      const double s = batch_tile<R>(I, t - I.tile0, P.H, b, I.exch + (size_t)par * I.nx * I.ny,
-                                     I.exch + (size_t)(par ^ 1) * I.nx * I.ny, nb == 0, edge, red);
+      const float* src = I.exch + (size_t)par * I.nx * I.ny;
+      float* dst = I.exch + (size_t)(par ^ 1) * I.nx * I.ny;
+      const int lt = t - I.tile0;
+      const double s = batch_tile_any<MODE>(I, lt, b, src, dst, nb == 0, edge, red);
       if (threadIdx.x == 0) st_agent(P.tile_part + (size_t)(par ^ 1) * P.ntiles + t, s);
     }
-    ++nbar;
-    grid_barrier(P.sync, nbar, (unsigned)G);
+    if (!grid_barrier_bounded(P.sync, ++nbar, (unsigned)G)) {
+      batch_abort(P);
+      return;
+    }
     // phase B: one work-group per instance sums its tiles in order and decides
     for (int i = blockIdx.x; i < P.ninst; i += G) {
       const BatchInstDev& I = P.inst[i];
@@ -167,8 +238,10 @@ __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
       }
       __syncthreads();
     }
-    ++nbar;
-    grid_barrier(P.sync, nbar, (unsigned)G);
+    if (!grid_barrier_bounded(P.sync, ++nbar, (unsigned)G)) {
+      batch_abort(P);
+      return;
+    }
     int running = 0;
     for (int i = threadIdx.x; i < P.ninst; i += blockDim.x)
       running += __hip_atomic_load(&P.st[i].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0;
@@ -182,7 +255,7 @@ __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
     const BatchInstDev& I = P.inst[i];
     const int fp = __hip_atomic_load(&P.st[i].fpar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const float* src = I.exch + (size_t)fp * I.nx * I.ny;
-    const int H = P.H, TW = 64 - 2 * H, TH = 4 * R - 2 * H;
+    const int TW = 64 - 2 * kBatchH, TH = 4 * I.R - 2 * kBatchH;
     const int lt = t - I.tile0, bx = lt % I.ntx, by = lt / I.ntx;
     for (int e = threadIdx.x; e < TW * TH; e += blockDim.x) {
       const int gx = bx * TW + e % TW, gy = by * TH + e / TW;
@@ -202,107 +275,173 @@ __global__ void batch_reset(BatchState* st, int n, unsigned* sync) {
   }
 }
 
-int batch_rows() { return 16; }
+// Tile rows of an instance: VAR tiles keep four face weights per row in
+// registers, so they use R = 8; otherwise the forced R, else the tuned one
+// for the grid side, else 16.
+int batch_rows_of(int nx, int ny, bool var, int forced) {
+  if (var) return 8;
+  if (forced == 8 || forced == 16) return forced;
+  for (int i = 0; i < kBatchTileTableSize; ++i)
+    if (kBatchTileTable[i].nx == nx && kBatchTileTable[i].ny == ny) return kBatchTileTable[i].R;
+  return 16;
+}
 
-// Host view of the batch area and the launch.
+int batch_tile_mode(int n, const int* rows, bool var) {
+  if (var) return kTileVar;
+  int m = 0;
+  for (int i = 0; i < n; ++i) m |= rows[i] == 8 ? kTileR8 : kTileR16;
+  return m;
+}
+
+int batch_tiles_of(int nx, int ny, int R) {
+  const int TW = 64 - 2 * kBatchH, TH = 4 * R - 2 * kBatchH;
+  return ((nx + TW - 1) / TW) * ((ny + TH - 1) / TH);
+}
+
+// ---------------------------------------------------------------------------
+// Host side: the one layout of the batch area.  carve() places every table,
+// and the area size is what carve() takes from a null base.
+// ---------------------------------------------------------------------------
 struct BatchArea {
+  unsigned* sync;
+  BInst* binst;
+  hyp_result* results;
+  int* ranges;           // RK_COUNT x (n + 1)
   BatchInstDev* inst;
   int* tile_inst;
   double* tile_part;
   BatchState* st;
-  unsigned* sync;
+  void* cnn;             // network descriptor tables
 };
 
-// The one layout of the batch area: carve() places every table, and the
-// area size is what carve() takes from a null base.
-static BatchArea carve(void* base, int ninst, int ntiles, size_t* bytes = nullptr) {
+static BatchArea carve(void* base, int n, int ntiles, size_t cnn_bytes, size_t* bytes = nullptr) {
   const uintptr_t b = reinterpret_cast<uintptr_t>(base);
   size_t o = 0;
-  auto take = [&](size_t n) {
+  auto take = [&](size_t k) {
     const size_t at = o;
-    o = (o + n + 255) & ~(size_t)255;
+    o = (o + k + 255) & ~(size_t)255;
     return reinterpret_cast<char*>(b + at);
   };
   BatchArea A;
   A.sync = (unsigned*)take(kSyncBytes);
-  A.inst = (BatchInstDev*)take(sizeof(BatchInstDev) * ninst);
+  A.binst = (BInst*)take(sizeof(BInst) * n);
+  A.results = (hyp_result*)take(sizeof(hyp_result) * n);
+  A.ranges = (int*)take(sizeof(int) * RK_COUNT * (n + 1));
+  A.inst = (BatchInstDev*)take(sizeof(BatchInstDev) * n);
   A.tile_inst = (int*)take(sizeof(int) * ntiles);
   A.tile_part = (double*)take(sizeof(double) * 2 * ntiles);
-  A.st = (BatchState*)take(sizeof(BatchState) * ninst);
+  A.st = (BatchState*)take(sizeof(BatchState) * n);
+  A.cnn = cnn_bytes ? (void*)take(cnn_bytes) : nullptr;
   if (bytes) *bytes = o;
   return A;
 }
 
-size_t batch_area_bytes(int ninst, int ntiles) {
-  size_t n = 0;
-  (void)carve(nullptr, ninst, ntiles, &n);
-  return n;
+size_t batch_area_bytes(int n, int ntiles, size_t cnn_bytes) {
+  size_t k = 0;
+  (void)carve(nullptr, n, ntiles, cnn_bytes, &k);
+  return k;
 }
 
-int batch_tiles_of(int nx, int ny) {
-  const int H = 9, R = batch_rows();
-  const int TW = 64 - 2 * H, TH = 4 * R - 2 * H;
-  return ((nx + TW - 1) / TW) * ((ny + TH - 1) / TH);
+BatchDevice batch_device(void* area, int n, int ntiles, size_t cnn_bytes) {
+  const BatchArea A = carve(area, n, ntiles, cnn_bytes);
+  BatchDevice D;
+  D.binst = A.binst;
+  D.results = A.results;
+  D.cnn_tables = A.cnn;
+  D.ranges.first = A.ranges;
+  D.ranges.n = n;
+  for (int r = 0; r < RK_COUNT; ++r) D.ranges.total[r] = 0;
+  return D;
 }
 
-// Upload the instance and tile tables (synchronous; done once per batch).
-hipError_t batch_setup(void* area, int ninst, const int* nx, const int* ny, const double* dx,
-                       const double* thr, int max_iters, float omega, const Ws* ws) {
-  int ntiles = 0;
-  for (int i = 0; i < ninst; ++i) ntiles += batch_tiles_of(nx[i], ny[i]);
-  BatchArea A = carve(area, ninst, ntiles);
-  const int H = 9, R = batch_rows(), TW = 64 - 2 * H;
-  (void)R;
-  BatchInstDev* hi = new BatchInstDev[ninst];
-  int* ht = new int[ntiles];
+// Upload the instance, range and tile tables (synchronous; once per batch).
+hipError_t batch_setup(void* area, int n, int ntiles, size_t cnn_bytes, const BInst* binst,
+                       const int* rows, const double* thr, int max_iters, float omega,
+                       BatchDevice* out) {
+  BatchArea A = carve(area, n, ntiles, cnn_bytes);
+  std::vector<BatchInstDev> hi(n);
+  std::vector<int> ht(ntiles);
+  std::vector<int> hr((size_t)RK_COUNT * (n + 1), 0);
+  const int TW = 64 - 2 * kBatchH;
   int t0 = 0;
-  for (int i = 0; i < ninst; ++i) {
+  for (int i = 0; i < n; ++i) {
+    const BInst& B = binst[i];
     BatchInstDev& I = hi[i];
-    I.nx = nx[i]; I.ny = ny[i];
-    I.ntx = (nx[i] + TW - 1) / TW;
+    I.nx = B.nx; I.ny = B.ny;
+    I.R = rows[i];
+    I.var = B.var;
+    I.ntx = (B.nx + TW - 1) / TW;
     I.tile0 = t0;
-    I.ntiles = batch_tiles_of(nx[i], ny[i]);
+    I.ntiles = batch_tiles_of(B.nx, B.ny, I.R);
     I.max_iters = max_iters;
-    I.inv_dx2 = (float)(1.0 / (dx[i] * dx[i]));
-    I.wfac = (float)(omega * dx[i] * dx[i]);
+    I.inv_dx2 = (float)(1.0 / (B.dx * B.dx));
+    I.wfac = (float)(omega * B.dx * B.dx);
     I.omega = omega;
     I.thr = thr[i];
-    I.cell = ws[i].cell; I.d = ws[i].d; I.phi = ws[i].phi; I.exch = ws[i].exch; I.sc = ws[i].sc;
+    I.cell = B.w.cell; I.d = B.w.d; I.phi = B.w.phi; I.exch = B.w.exch; I.sc = B.w.sc;
+    I.ce = B.w.coef_e; I.cn = B.w.coef_n;
     for (int t = 0; t < I.ntiles; ++t) ht[t0 + t] = i;
     t0 += I.ntiles;
+    // work-groups of each launch shape
+    const int nc = B.nx * B.ny, nu = B.ny * (B.nx + 1), nv = (B.ny + 1) * B.nx;
+    int cnt[RK_COUNT] = {0};
+    cnt[RK_CELL] = (nc + 255) / 256;
+    cnt[RK_FACE] = (nu + nv + 255) / 256;
+    cnt[RK_ADV] = (nc + nu + nv + 255) / 256;
+    cnt[RK_REG] = B.S > 0 ? ((B.nx + 31) / 32) * ((B.ny + 31) / 32) : 0;
+    for (int k = 0; k < B.S && k < kBatchMaxScales; ++k)
+      cnt[RK_LVL0 + k] = (B.sc_h[k] * B.sc_w[k] + 255) / 256;
+    for (int r = 0; r < RK_COUNT; ++r)
+      hr[(size_t)r * (n + 1) + i + 1] = hr[(size_t)r * (n + 1) + i] + cnt[r];
   }
-  hipError_t e = hipMemcpy(A.inst, hi, sizeof(BatchInstDev) * ninst, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(A.tile_inst, ht, sizeof(int) * ntiles, hipMemcpyHostToDevice);
-  delete[] hi;
-  delete[] ht;
-  return e;
+  if (t0 != ntiles) return hipErrorInvalidValue;
+  hipError_t e = hipMemcpy(A.inst, hi.data(), sizeof(BatchInstDev) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(A.tile_inst, ht.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(A.binst, binst, sizeof(BInst) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(A.ranges, hr.data(), sizeof(int) * hr.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  *out = batch_device(area, n, ntiles, cnn_bytes);
+  for (int r = 0; r < RK_COUNT; ++r) out->ranges.total[r] = hr[(size_t)r * (n + 1) + n];
+  return hipSuccess;
 }
 
-hipError_t run_jacobi_batch(const Device& dev, void* area, int ninst, int ntiles, bool cooperative,
-                            hipStream_t s) {
-  BatchArea A = carve(area, ninst, ntiles);
-  batch_reset<<<(ninst + 63) / 64 + 1, 64, 0, s>>>(A.st, ninst, A.sync);
+static const void* jacobi_batch_kernel(int mode) {
+  switch (mode) {
+    case kTileR16: return (const void*)jacobi_batch<kTileR16>;
+    case kTileR8: return (const void*)jacobi_batch<kTileR8>;
+    case kTileR8 | kTileR16: return (const void*)jacobi_batch<kTileR8 | kTileR16>;
+    case kTileVar: return (const void*)jacobi_batch<kTileVar>;
+    default: return nullptr;
+  }
+}
+
+hipError_t run_jacobi_batch(const Device& dev, void* area, int n, int ntiles, size_t cnn_bytes,
+                            int mode, bool cooperative, hipStream_t s) {
+  const void* kern = jacobi_batch_kernel(mode);
+  if (!kern) return hipErrorInvalidValue;
+  BatchArea A = carve(area, n, ntiles, cnn_bytes);
+  batch_reset<<<(n + 63) / 64 + kSyncSlots / 64 + 1, 64, 0, s>>>(A.st, n, A.sync);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   BatchParams P{};
-  P.inst = A.inst; P.tile_inst = A.tile_inst; P.ninst = ninst; P.ntiles = ntiles; P.H = 9;
+  P.inst = A.inst; P.tile_inst = A.tile_inst; P.ninst = n; P.ntiles = ntiles;
   P.tile_part = A.tile_part; P.st = A.st; P.sync = A.sync;
   // as many work-groups per CU as fit (up to 4), so that one work-group's
-  // loads overlap another's sweeps; every one of them is resident (the
-  // occupancy query accounts for registers and LDS), which the grid barrier
-  // needs, also for the plain launch used inside stream capture
+  // loads overlap another's sweeps; the occupancy query accounts for
+  // registers and LDS, so all of them are resident when the GPU runs
+  // nothing else, which the grid barrier needs (inside stream capture the
+  // launch is a plain one; a barrier that is not reached within its bound
+  // ends the launch with ABORTED instead of hanging)
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)jacobi_batch<16>, 256, 0) !=
-          hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;
   per_cu = per_cu > 4 ? 4 : per_cu;
   int G = dev.cu * per_cu;
   G = G < kMaxCoopBlocks ? G : kMaxCoopBlocks;
   void* args[] = {&P};
-  if (cooperative)
-    return hipLaunchCooperativeKernel((const void*)jacobi_batch<16>, dim3(G), dim3(256), args, 0, s);
-  hipLaunchKernelGGL(jacobi_batch<16>, dim3(G), dim3(256), 0, s, P);
-  return hipGetLastError();
+  if (cooperative) return hipLaunchCooperativeKernel(kern, dim3(G), dim3(256), args, 0, s);
+  return hipLaunchKernel(kern, dim3(G), dim3(256), args, 0, s);
 }
 
 }  // namespace hyp

@@ -10,7 +10,10 @@
 // scales of a layer run in one launch over a concatenated tile list.
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "../../include/hyproj.h"
+#include "batch.h"
 #include "common.h"
 #include "conv_mfma.h"
 #include "internal.h"
@@ -32,11 +35,11 @@ struct PyrLaunch {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void cnn_input(PyrLaunch P, const float* __restrict__ d,
-                                                 const uint8_t* __restrict__ cell,
-                                                 const Scalars* sc) {
-  __shared__ float lv[2][32][33];  // [channel][y][x] of the current level
-  const int x0 = (blockIdx.x % P.rtx) * 32, y0 = (blockIdx.x / P.rtx) * 32;
+__device__ __forceinline__ void cnn_input_body(const PyrLaunch& P, int region,
+                                               const float* __restrict__ d,
+                                               const uint8_t* __restrict__ cell, const Scalars* sc,
+                                               float (*lv)[32][33]) {
+  const int x0 = (region % P.rtx) * 32, y0 = (region / P.rtx) * 32;
   const double s = sc->s;
   const float inv_s = s > 0.0 ? (float)(1.0 / s) : 0.f;
   for (int e = threadIdx.x; e < 1024; e += 256) {
@@ -80,13 +83,20 @@ __global__ __launch_bounds__(256) void cnn_input(PyrLaunch P, const float* __res
   }
 }
 
-// ---- t_k = y_k + up2(t_{k+1}); at k = 0 also phi0 = dx^2 s t on fluid -----
-__global__ __launch_bounds__(256) void cnn_upsum(int H, int W, const float* __restrict__ yk,
-                                                 const float* __restrict__ tc, int Hc, int Wc,
-                                                 float* __restrict__ tk, int last, float dx2,
+template <typename T>
+__global__ __launch_bounds__(256) void cnn_input(PyrLaunch P, const float* __restrict__ d,
                                                  const uint8_t* __restrict__ cell,
-                                                 float* __restrict__ phi, const Scalars* sc) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+                                                 const Scalars* sc) {
+  __shared__ float lv[2][32][33];  // [channel][y][x] of the current level
+  cnn_input_body<T>(P, blockIdx.x, d, cell, sc, lv);
+}
+
+// ---- t_k = y_k + up2(t_{k+1}); at k = 0 also phi0 = dx^2 s t on fluid -----
+__device__ __forceinline__ void upsum_body(int gid, int H, int W, const float* __restrict__ yk,
+                                           const float* __restrict__ tc, int Hc, int Wc,
+                                           float* __restrict__ tk, int last, float dx2,
+                                           const uint8_t* __restrict__ cell,
+                                           float* __restrict__ phi, const Scalars* sc) {
   if (gid >= H * W) return;
   const int X = gid % W, Y = gid / W;
   float t = yk[gid];
@@ -107,6 +117,15 @@ __global__ __launch_bounds__(256) void cnn_upsum(int H, int W, const float* __re
     const bool fl = !(cell[gid] & C_SOLID);
     phi[gid] = (fl && s > 0.0) ? (float)((double)dx2 * s) * t : 0.f;
   }
+}
+
+__global__ __launch_bounds__(256) void cnn_upsum(int H, int W, const float* __restrict__ yk,
+                                                 const float* __restrict__ tc, int Hc, int Wc,
+                                                 float* __restrict__ tk, int last, float dx2,
+                                                 const uint8_t* __restrict__ cell,
+                                                 float* __restrict__ phi, const Scalars* sc) {
+  upsum_body(blockIdx.x * blockDim.x + threadIdx.x, H, W, yk, tc, Hc, Wc, tk, last, dx2, cell, phi,
+             sc);
 }
 
 // ---- weight images: every 3x3 layer's weights in the LDS layout of the conv
@@ -254,6 +273,180 @@ hipError_t run_cnn(const Device& dev, const NetShape& net, const WsLayout& L, in
     case 16: return run_cnn_t<float, 16>(dev, net, L, nx, ny, dx, params, w, s);
     case 32: return run_cnn_t<float, 32>(dev, net, L, nx, ny, dx, params, w, s);
     case 64: return run_cnn_t<float, 64>(dev, net, L, nx, ny, dx, params, w, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A batch of grids (batch.h) through the same network: one launch per phase
+// over every instance.  The pyramid input and the upsample-sum find their
+// instance in the batch's range tables; the four convolution launches walk
+// descriptor tables of (scale, instance) pairs in device memory, ordered
+// scale by scale so that consecutive tiles share the weights held in LDS;
+// one weight image (in the first instance's workspace) serves every
+// instance.  Device layout of the tables: 4 x ndesc ScaleDesc, then one
+// PyrLaunch per instance.
+// ---------------------------------------------------------------------------
+size_t cnn_batch_bytes(const NetShape& net, int n) {
+  const size_t ndesc = (size_t)n * net.scales;
+  return 4 * ndesc * sizeof(ScaleDesc) + (size_t)n * sizeof(PyrLaunch);
+}
+
+template <typename T, int C>
+static void cnn_batch_fill(const NetShape& net, int n, const WsLayout* Ly, const Ws* ws,
+                           const float* params, ScaleDesc* desc, PyrLaunch* pyr, int* tiles) {
+  const int S = net.scales;
+  const size_t per_scale = (size_t)C * 18 + C + 3 * ((size_t)C * 9 * C + C) + C + 1;
+  const size_t hoff = (size_t)C * 18 + C + 3 * ((size_t)C * 9 * C + C);
+  using WI = WImg<T, C>;
+  const T* img = reinterpret_cast<const T*>(ws[0].cnn_w);
+  for (int l = 0; l < 4; ++l) {
+    const int cin = l == 0 ? 2 : C;
+    const size_t woff = l == 0 ? 0 : (size_t)C * 18 + C + (size_t)(l - 1) * ((size_t)C * 9 * C + C);
+    int t = 0;
+    ScaleDesc* out = desc + (size_t)l * n * S;
+    for (int k = 0; k < S; ++k) {
+      for (int i = 0; i < n; ++i) {
+        // layer l reads the previous layer's output (act0/act1 alternate)
+        const T* in = reinterpret_cast<const T*>(l == 0 ? ws[i].cnn_in
+                                                        : (l & 1 ? ws[i].cnn_act0 : ws[i].cnn_act1));
+        T* dst = reinterpret_cast<T*>(l & 1 ? ws[i].cnn_act1 : ws[i].cnn_act0);
+        ScaleDesc& D = out[(size_t)k * n + i];
+        D.in = in + Ly[i].sc_off_px[k] * cin;
+        D.out = dst + Ly[i].sc_off_px[k] * C;
+        D.wimg = img + k * WI::PER_SCALE + (l == 0 ? 0 : WI::L0 + (size_t)(l - 1) * WI::L1);
+        D.b = params + k * per_scale + woff + (size_t)C * 9 * cin;
+        D.H = Ly[i].sc_h[k];
+        D.W = Ly[i].sc_w[k];
+        D.tiles_x = (D.W + TW - 1) / TW;
+        D.tile0 = t;
+        D.ostr = C;
+        D.hw = params + k * per_scale + hoff;
+        D.y = ws[i].cnn_y + Ly[i].sc_off_px[k];
+        t += D.tiles_x * ((D.H + TH - 1) / TH);
+      }
+    }
+    tiles[l] = t;
+  }
+  for (int i = 0; i < n; ++i) {
+    PyrLaunch& P = pyr[i];
+    P = PyrLaunch{};
+    P.nscales = S;
+    P.total_px = Ly[i].total_px;
+    P.nx = Ly[i].sc_w[0];
+    for (int k = 0; k < S; ++k) {
+      P.out[k] = reinterpret_cast<T*>(ws[i].cnn_in) + Ly[i].sc_off_px[k] * 2;
+      P.H[k] = Ly[i].sc_h[k];
+      P.W[k] = Ly[i].sc_w[k];
+      P.px0[k] = Ly[i].sc_off_px[k];
+    }
+    P.rtx = (P.nx + 31) / 32;
+  }
+}
+
+// Fills the tables on the host and uploads them (synchronous, once per batch).
+hipError_t cnn_batch_setup(const NetShape& net, int n, const WsLayout* Ly, const Ws* ws,
+                           const float* params, void* dev_tables, int* tiles) {
+  if (net.arch != HYP_ARCH_PARALLEL || net.train) return hipErrorInvalidValue;
+  const size_t ndesc = (size_t)n * net.scales;
+  std::vector<ScaleDesc> desc(4 * ndesc);
+  std::vector<PyrLaunch> pyr(n);
+  if (net.precision == HYP_PREC_BF16) {
+    if (net.channels == 32) cnn_batch_fill<uint16_t, 32>(net, n, Ly, ws, params, desc.data(), pyr.data(), tiles);
+    else if (net.channels == 64) cnn_batch_fill<uint16_t, 64>(net, n, Ly, ws, params, desc.data(), pyr.data(), tiles);
+    else return hipErrorInvalidValue;
+  } else {
+    if (net.channels == 16) cnn_batch_fill<float, 16>(net, n, Ly, ws, params, desc.data(), pyr.data(), tiles);
+    else if (net.channels == 32) cnn_batch_fill<float, 32>(net, n, Ly, ws, params, desc.data(), pyr.data(), tiles);
+    else if (net.channels == 64) cnn_batch_fill<float, 64>(net, n, Ly, ws, params, desc.data(), pyr.data(), tiles);
+    else return hipErrorInvalidValue;
+  }
+  char* d = reinterpret_cast<char*>(dev_tables);
+  hipError_t e = hipMemcpy(d, desc.data(), desc.size() * sizeof(ScaleDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(d + desc.size() * sizeof(ScaleDesc), pyr.data(), pyr.size() * sizeof(PyrLaunch),
+                  hipMemcpyHostToDevice);
+  return e;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cnn_input_batch(const BInst* __restrict__ I,
+                                                       const PyrLaunch* __restrict__ pyr,
+                                                       const int* first, int n) {
+  __shared__ float lv[2][32][33];
+  const int i = batch_find(first, n, blockIdx.x);
+  const BInst& B = I[i];
+  cnn_input_body<T>(pyr[i], blockIdx.x - first[i], B.w.d, B.w.cell, B.w.sc, lv);
+}
+
+__global__ __launch_bounds__(256) void upsum_batch(const BInst* __restrict__ I, const int* first,
+                                                   int n, int k) {
+  const int i = batch_find(first, n, blockIdx.x);
+  const BInst& B = I[i];
+  const int H = B.sc_h[k], W = B.sc_w[k];
+  const bool top = k + 1 >= B.S;
+  upsum_body((blockIdx.x - first[i]) * blockDim.x + threadIdx.x, H, W, B.w.cnn_y + B.sc_off_px[k],
+             top ? nullptr : B.w.cnn_t + B.sc_off_px[k + 1], top ? 0 : B.sc_h[k + 1],
+             top ? 0 : B.sc_w[k + 1], B.w.cnn_t + B.sc_off_px[k], k == 0 ? 1 : 0,
+             (float)(B.dx * B.dx), B.w.cell, B.w.phi, B.w.sc);
+}
+
+template <typename T, int C>
+static hipError_t run_cnn_batch_t(const Device& dev, const NetShape& net, const BInst* I,
+                                  const BatchRanges& R, const void* tables, const int* tiles,
+                                  const Ws& w0, const float* params, hipStream_t s) {
+  const int S = net.scales, n = R.n;
+  const size_t ndesc = (size_t)n * S;
+  const ScaleDesc* desc = reinterpret_cast<const ScaleDesc*>(tables);
+  const PyrLaunch* pyr = reinterpret_cast<const PyrLaunch*>(desc + 4 * ndesc);
+  if (R.total[RK_REG] > 0)
+    hipLaunchKernelGGL(cnn_input_batch<T>, dim3(R.total[RK_REG]), dim3(256), 0, s, I, pyr,
+                       R.of(RK_REG), n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  using WI = WImg<T, C>;
+  const size_t per_scale = (size_t)C * 18 + C + 3 * ((size_t)C * 9 * C + C) + C + 1;
+  const size_t nimg = WI::PER_SCALE * S;
+  hipLaunchKernelGGL((cnn_wimg<T, C>), dim3((unsigned)((nimg + 255) / 256)), dim3(256), 0, s, params,
+                     per_scale, S, reinterpret_cast<T*>(w0.cnn_w));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int l = 0; l < 4; ++l) {
+    ConvLaunch L{};
+    L.table = desc + (size_t)l * ndesc;
+    L.ndesc = (int)ndesc;
+    L.total_tiles = tiles[l];
+    L.skip_store = l == 3 ? 1 : 0;
+    if (l == 0) e = launch_conv<T, 3, 2, C, true>(L, dev.cu, s);
+    else if (l < 3) e = launch_conv<T, 3, C, C, true>(L, dev.cu, s);
+    else e = launch_conv<T, 3, C, C, true, true>(L, dev.cu, s);
+    if (e != hipSuccess) return e;
+  }
+  for (int k = S - 1; k >= 0; --k) {
+    const int nb = R.total[RK_LVL0 + k];
+    if (nb > 0)
+      hipLaunchKernelGGL(upsum_batch, dim3(nb), dim3(256), 0, s, I, R.of(RK_LVL0 + k), n, k);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_cnn_batch(const Device& dev, const NetShape& net, const BInst* I,
+                         const BatchRanges& R, const void* tables, const int* tiles, const Ws& w0,
+                         const float* params, hipStream_t s) {
+  if (net.arch != HYP_ARCH_PARALLEL) return hipErrorInvalidValue;
+  if (net.precision == HYP_PREC_BF16) {
+    switch (net.channels) {
+      case 32: return run_cnn_batch_t<uint16_t, 32>(dev, net, I, R, tables, tiles, w0, params, s);
+      case 64: return run_cnn_batch_t<uint16_t, 64>(dev, net, I, R, tables, tiles, w0, params, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (net.channels) {
+    case 16: return run_cnn_batch_t<float, 16>(dev, net, I, R, tables, tiles, w0, params, s);
+    case 32: return run_cnn_batch_t<float, 32>(dev, net, I, R, tables, tiles, w0, params, s);
+    case 64: return run_cnn_batch_t<float, 64>(dev, net, I, R, tables, tiles, w0, params, s);
     default: return hipErrorInvalidValue;
   }
 }

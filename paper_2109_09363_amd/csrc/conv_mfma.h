@@ -58,6 +58,8 @@ struct ScaleDesc {
 
 struct ConvLaunch {
   ScaleDesc sc[kMaxScales];
+  const ScaleDesc* table;  // non-null: `ndesc` descriptors in device memory in
+  int ndesc;               // tile0 order instead of sc[] (batches of grids)
   int nscales, total_tiles, tiles_per_wg;
   int skip_store;     // HEAD instances: 1 = do not store the activations
 };
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t_begin = blockIdx.x * L.tiles_per_wg;
   const int t_end = min(t_begin + L.tiles_per_wg, L.total_tiles);
-  int cur = -1;
+  const void* cur = nullptr;  // weight image in LDS
   // copy cout rows [co0, co0 + CT) of input chunk ch of the layer's weight
   // image ([NCH][Cout][WSTR]) into LDS with 16-byte loads, several in flight
   // per thread
@@ -319,28 +321,42 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
   constexpr int NPIECE = EH * EW * PCH;
   constexpr int NPF = PIPE ? (NPIECE + 255) / 256 : 1;
   u32x4 pf[NPF];
-  auto locate = [&](int t, int& k, int& x0, int& y0) {
-    k = 0;
-    while (k + 1 < L.nscales && t >= L.sc[k + 1].tile0) ++k;
-    const int lt = t - L.sc[k].tile0;
-    x0 = (lt % L.sc[k].tiles_x) * TW;
-    y0 = (lt / L.sc[k].tiles_x) * TH;
+  // the descriptor of global tile t (a scale, or a scale of one grid of a
+  // batch) and the tile's origin
+  auto locate = [&](int t, int& x0, int& y0) -> ScaleDesc {
+    ScaleDesc D;
+    if (L.table) {
+      int lo = 0, hi = L.ndesc;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (L.table[mid].tile0 <= t) lo = mid;
+        else hi = mid;
+      }
+      D = L.table[lo];
+    } else {
+      int k = 0;
+      while (k + 1 < L.nscales && t >= L.sc[k + 1].tile0) ++k;
+      D = L.sc[k];
+    }
+    const int lt = t - D.tile0;
+    x0 = (lt % D.tiles_x) * TW;
+    y0 = (lt / D.tiles_x) * TH;
+    return D;
   };
   if constexpr (PIPE) {
     if (t_begin < t_end) {
-      int k, x0, y0;
-      locate(t_begin, k, x0, y0);
-      conv_prefetch<T, CIN, EW, HALO, PCH, NPIECE, NPF>(L.sc[k], x0, y0, pf);
+      int x0, y0;
+      const ScaleDesc D = locate(t_begin, x0, y0);
+      conv_prefetch<T, CIN, EW, HALO, PCH, NPIECE, NPF>(D, x0, y0, pf);
       conv_commit<T, Gm::PSTR, PCH, NPIECE, NPF>(xl, pf);
     }
   }
   for (int t = t_begin; t < t_end; ++t) {
-    int k, x0, y0;
-    locate(t, k, x0, y0);
-    const ScaleDesc& S = L.sc[k];
-    if (Gm::PASSES == 1 && Gm::NCH == 1 && k != cur) {
+    int x0, y0;
+    const ScaleDesc S = locate(t, x0, y0);
+    if (Gm::PASSES == 1 && Gm::NCH == 1 && S.wimg != cur) {
       load_weights(S.wimg, 0, 0);
-      cur = k;
+      cur = S.wimg;
     }
     if constexpr (!PIPE && Gm::NCH == 1) load_tile(S, x0, y0, 0);
     const int col = lane & 15, g = lane >> 4;
@@ -359,9 +375,9 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
         // waits for these loads before the math starts
         if constexpr (PIPE) {
           if (pass == 0 && t + 1 < t_end) {
-            int kn, xn, yn;
-            locate(t + 1, kn, xn, yn);
-            conv_prefetch<T, CIN, EW, HALO, PCH, NPIECE, NPF>(L.sc[kn], xn, yn, pf);
+            int xn, yn;
+            const ScaleDesc Dn = locate(t + 1, xn, yn);
+            conv_prefetch<T, CIN, EW, HALO, PCH, NPIECE, NPF>(Dn, xn, yn, pf);
           }
         }
         conv_tile<T, KS, CIN, COUT>(wl, xl, acc, wave, lane);

@@ -135,12 +135,6 @@ hipError_t run_backward(const NetShape& net, const WsLayout& L, int nx, int ny, 
                         double* loss_out, const Ws& w, hipStream_t s);
 hipError_t run_adam(float* params, const float* grads, float* m, float* v, int64_t n, int step,
                     float lr, float b1, float b2, float eps, hipStream_t s);
-int batch_tiles_of(int nx, int ny);
-size_t batch_area_bytes(int ninst, int ntiles);
-hipError_t batch_setup(void* area, int ninst, const int* nx, const int* ny, const double* dx,
-                       const double* thr, int max_iters, float omega, const Ws* ws);
-hipError_t run_jacobi_batch(const Device& dev, void* area, int ninst, int ntiles, bool cooperative,
-                            hipStream_t s);
 size_t cnn_weight_image_bytes(const NetShape& net);
 int64_t pn_param_count(int arch);
 size_t pn_weight_image_bytes(const NetShape& net);

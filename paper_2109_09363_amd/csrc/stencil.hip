@@ -1,9 +1,10 @@
 // Streaming stencil kernels of the projection: planner (pocket fill and
 // neighbour bits), boundary faces + divergence, initial guess, gradient
 // correction (Eq. 2) and the final divergence check.
+#include "../../include/hyproj.h"
+#include "batch.h"
 #include "common.h"
 #include "internal.h"
-#include "../../include/hyproj.h"
 
 namespace hyp {
 
@@ -148,21 +149,24 @@ hipError_t run_plan(const Device& dev, int nx, int ny, const uint8_t* flags, con
 // south faces (plus the east wall face of the last column and the open top
 // face of the last row).  A cell reads its east/north faces, which their
 // owners may rewrite concurrently with the identical masked value.
+// The kernel bodies take the work-group's index within its grid (lb of nb)
+// so that the single-grid launches and the batched ones (one launch over
+// all instances, batch.h) share them.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void div_kernel(int nx, int ny, float inv_dx,
-                                                  const uint8_t* __restrict__ cell, float* u,
-                                                  float* v, float* __restrict__ d,
-                                                  double* __restrict__ blockpart, Scalars* sc,
-                                                  unsigned* sync, float* __restrict__ phi_acc) {
-  __shared__ double red[4];
-  const int c0 = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int i = c0; i < kSyncAllSlots * 8; i += gridDim.x * blockDim.x) sync_clear_words(sync, i);
+__device__ __forceinline__ void div_body(int lb, int nb, int nx, int ny, float inv_dx,
+                                         const uint8_t* __restrict__ cell, float* u, float* v,
+                                         float* __restrict__ d, double* __restrict__ blockpart,
+                                         Scalars* sc, unsigned* sync, float* __restrict__ phi_acc,
+                                         double* red) {
+  const int c0 = lb * blockDim.x + threadIdx.x;
+  const int stride = nb * blockDim.x;
+  for (int i = c0; i < kSyncAllSlots * 8; i += stride) sync_clear_words(sync, i);
   if (c0 == 0) sc->bar = 0;
   double a = 0.0, q = 0.0;
   // grid-stride: a bounded grid keeps the per-block reduction cheap at
   // DRAM-resident sizes; faces are written back only where masking changed them
 #pragma unroll 4
-  for (int c = c0; c < nx * ny; c += gridDim.x * blockDim.x) {
+  for (int c = c0; c < nx * ny; c += stride) {
     phi_acc[c] = 0.f;
     const int i = c % nx, j = c / nx, U = nx + 1;
     const uint8_t ci = cell[c];
@@ -185,14 +189,13 @@ __global__ __launch_bounds__(256) void div_kernel(int nx, int ny, float inv_dx,
   a = block_sum(a, red);
   q = block_sum(q, red);
   if (threadIdx.x == 0) {
-    blockpart[2 * blockIdx.x] = a;
-    blockpart[2 * blockIdx.x + 1] = q;
+    blockpart[2 * lb] = a;
+    blockpart[2 * lb + 1] = q;
   }
 }
 
-__global__ __launch_bounds__(256) void div_finish(int nblocks, const double* __restrict__ blockpart,
-                                                  Scalars* sc) {
-  __shared__ double red[4];
+__device__ __forceinline__ void div_finish_body(int nblocks, const double* __restrict__ blockpart,
+                                                Scalars* sc, double* red) {
   double a = 0.0, q = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
     a += blockpart[2 * b];
@@ -210,6 +213,21 @@ __global__ __launch_bounds__(256) void div_finish(int nblocks, const double* __r
     sc->iters = 0;
     sc->status = kStatusRunning;
   }
+}
+
+__global__ __launch_bounds__(256) void div_kernel(int nx, int ny, float inv_dx,
+                                                  const uint8_t* __restrict__ cell, float* u,
+                                                  float* v, float* __restrict__ d,
+                                                  double* __restrict__ blockpart, Scalars* sc,
+                                                  unsigned* sync, float* __restrict__ phi_acc) {
+  __shared__ double red[4];
+  div_body(blockIdx.x, gridDim.x, nx, ny, inv_dx, cell, u, v, d, blockpart, sc, sync, phi_acc, red);
+}
+
+__global__ __launch_bounds__(256) void div_finish(int nblocks, const double* __restrict__ blockpart,
+                                                  Scalars* sc) {
+  __shared__ double red[4];
+  div_finish_body(nblocks, blockpart, sc, red);
 }
 
 hipError_t run_div(int nx, int ny, double dx, float* u, float* v, const Ws& w, int nblocks,
@@ -240,28 +258,22 @@ hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const
 }
 
 // ---------------------------------------------------------------------------
-// Gradient correction, Eq. (2): each open face between two non-solid cells
-// (and each open top face, ghost phi = 0) loses (phi_R - phi_L)/dx.  Each
-// thread rewrites only the faces it owns, so no face is read after another
-// thread's update.  p = rho0 phi / dt.
+// Gradient correction, Eq. (2): u -= beta grad phi on the open faces each
+// cell owns (west, south, and the open top face with ghost phi = 0), so no
+// face is read after another thread's update; p = rho0 (phi_acc + phi) / dt.
+// beta = 1 for the constant-coefficient operator (VAR = false); for the
+// variable-density one beta = rho0 / rho_face from the coefficient planes
+// (ce: east face of each cell, cn: north face).
 // ---------------------------------------------------------------------------
-// Eq. (2): u -= beta grad phi on the open faces each cell owns (west, south,
-// and the open top face), p = rho0 (phi_acc + phi) / dt.  beta = 1 for the
-// constant-coefficient operator (VAR = false); for the variable-density one
-// beta = rho0 / rho_face from the coefficient planes (ce: east face of each
-// cell, cn: north face).
 template <bool VAR>
-__global__ __launch_bounds__(256) void grad_kernel(int nx, int ny, float inv_dx, double rho0,
-                                                   double dt_host, int dt_dev,
-                                                   const uint8_t* __restrict__ cell,
-                                                   const float* __restrict__ phi,
-                                                   const float* __restrict__ phi_acc, float* u,
-                                                   float* v, float* __restrict__ p,
-                                                   const Scalars* sc, const float* __restrict__ ce,
-                                                   const float* __restrict__ cn) {
-  const float p_scale = (float)(rho0 / (dt_dev ? sc->dt : dt_host));
+__device__ __forceinline__ void grad_body(int lb, int nb, int nx, int ny, float inv_dx, float p_scale,
+                                          const uint8_t* __restrict__ cell,
+                                          const float* __restrict__ phi,
+                                          const float* __restrict__ phi_acc, float* u, float* v,
+                                          float* __restrict__ p, const float* __restrict__ ce,
+                                          const float* __restrict__ cn) {
 #pragma unroll 4
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nx * ny; c += gridDim.x * blockDim.x) {
+  for (int c = lb * blockDim.x + threadIdx.x; c < nx * ny; c += nb * blockDim.x) {
     const int i = c % nx, j = c / nx, U = nx + 1;
     const uint8_t ci = cell[c];
     const bool fl = !(ci & C_SOLID);
@@ -279,14 +291,26 @@ __global__ __launch_bounds__(256) void grad_kernel(int nx, int ny, float inv_dx,
   }
 }
 
+template <bool VAR>
+__global__ __launch_bounds__(256) void grad_kernel(int nx, int ny, float inv_dx, double rho0,
+                                                   double dt_host, int dt_dev,
+                                                   const uint8_t* __restrict__ cell,
+                                                   const float* __restrict__ phi,
+                                                   const float* __restrict__ phi_acc, float* u,
+                                                   float* v, float* __restrict__ p,
+                                                   const Scalars* sc, const float* __restrict__ ce,
+                                                   const float* __restrict__ cn) {
+  const float p_scale = (float)(rho0 / (dt_dev ? sc->dt : dt_host));
+  grad_body<VAR>(blockIdx.x, gridDim.x, nx, ny, inv_dx, p_scale, cell, phi, phi_acc, u, v, p, ce, cn);
+}
+
 // Face coefficients of the variable-density operator: beta = rho0 / rho_f on
 // the east and north faces of every non-solid cell, rho_f the mean of the
 // two cells (the cell itself on the open top face), 0 on closed faces.
-__global__ __launch_bounds__(256) void coef_kernel(int nx, int ny, double rho0,
-                                                   const uint8_t* __restrict__ cell,
-                                                   const float* __restrict__ rho,
-                                                   float* __restrict__ ce, float* __restrict__ cn) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void coef_body(int c, int nx, int ny, double rho0,
+                                          const uint8_t* __restrict__ cell,
+                                          const float* __restrict__ rho, float* __restrict__ ce,
+                                          float* __restrict__ cn) {
   if (c >= nx * ny) return;
   const int j = c / nx;
   const uint8_t ci = cell[c];
@@ -300,6 +324,13 @@ __global__ __launch_bounds__(256) void coef_kernel(int nx, int ny, double rho0,
   cn[c] = n;
 }
 
+__global__ __launch_bounds__(256) void coef_kernel(int nx, int ny, double rho0,
+                                                   const uint8_t* __restrict__ cell,
+                                                   const float* __restrict__ rho,
+                                                   float* __restrict__ ce, float* __restrict__ cn) {
+  coef_body(blockIdx.x * blockDim.x + threadIdx.x, nx, ny, rho0, cell, rho, ce, cn);
+}
+
 hipError_t run_coef(int nx, int ny, double rho0, const float* rho, const Ws& w, hipStream_t s) {
   const int n = nx * ny;
   coef_kernel<<<(n + 255) / 256, 256, 0, s>>>(nx, ny, rho0, w.cell, rho, w.coef_e, w.coef_n);
@@ -307,15 +338,13 @@ hipError_t run_coef(int nx, int ny, double rho0, const float* rho, const Ws& w, 
 }
 
 // Divergence of the returned faces: FP64 sum of |div| and max |div|.
-__global__ __launch_bounds__(256) void check_kernel(int nx, int ny, float inv_dx,
-                                                    const uint8_t* __restrict__ cell,
-                                                    const float* __restrict__ u,
-                                                    const float* __restrict__ v,
-                                                    double* __restrict__ blockpart) {
-  __shared__ double red[4];
+__device__ __forceinline__ void check_body(int lb, int nb, int nx, int ny, float inv_dx,
+                                           const uint8_t* __restrict__ cell,
+                                           const float* __restrict__ u, const float* __restrict__ v,
+                                           double* __restrict__ blockpart, double* red) {
   double a = 0.0, m = 0.0;
 #pragma unroll 4
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nx * ny; c += gridDim.x * blockDim.x) {
+  for (int c = lb * blockDim.x + threadIdx.x; c < nx * ny; c += nb * blockDim.x) {
     const int i = c % nx, j = c / nx, U = nx + 1;
     if (!(cell[c] & C_SOLID)) {
       const float dv = ((u[j * U + i + 1] - u[j * U + i]) + (v[(j + 1) * nx + i] - v[j * nx + i])) * inv_dx;
@@ -327,14 +356,13 @@ __global__ __launch_bounds__(256) void check_kernel(int nx, int ny, float inv_dx
   const double sum = block_sum(a, red);
   const double mx = block_max(m, red);
   if (threadIdx.x == 0) {
-    blockpart[2 * blockIdx.x] = sum;
-    blockpart[2 * blockIdx.x + 1] = mx;
+    blockpart[2 * lb] = sum;
+    blockpart[2 * lb + 1] = mx;
   }
 }
 
-__global__ __launch_bounds__(256) void finish_kernel(int nblocks, const double* __restrict__ blockpart,
-                                                     const Scalars* sc, hyp_result* res) {
-  __shared__ double red[4];
+__device__ __forceinline__ void finish_body(int nblocks, const double* __restrict__ blockpart,
+                                            const Scalars* sc, hyp_result* res, double* red) {
   double a = 0.0, m = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
     a += blockpart[2 * b];
@@ -358,6 +386,21 @@ __global__ __launch_bounds__(256) void finish_kernel(int nblocks, const double* 
   }
 }
 
+__global__ __launch_bounds__(256) void check_kernel(int nx, int ny, float inv_dx,
+                                                    const uint8_t* __restrict__ cell,
+                                                    const float* __restrict__ u,
+                                                    const float* __restrict__ v,
+                                                    double* __restrict__ blockpart) {
+  __shared__ double red[4];
+  check_body(blockIdx.x, gridDim.x, nx, ny, inv_dx, cell, u, v, blockpart, red);
+}
+
+__global__ __launch_bounds__(256) void finish_kernel(int nblocks, const double* __restrict__ blockpart,
+                                                     const Scalars* sc, hyp_result* res) {
+  __shared__ double red[4];
+  finish_body(nblocks, blockpart, sc, res, red);
+}
+
 hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt, bool dt_dev,
                                float* u, float* v, float* p, const Ws& w, int nblocks, void* res,
                                bool var, hipStream_t s) {
@@ -372,6 +415,106 @@ hipError_t run_grad_and_finish(int nx, int ny, double dx, double rho0, double dt
                                                w.phi_acc, u, v, p, w.sc, nullptr, nullptr);
   check_kernel<<<ncheck, 256, 0, s>>>(nx, ny, inv_dx, w.cell, u, v, w.blockpart);
   finish_kernel<<<1, 256, 0, s>>>(ncheck, w.blockpart, w.sc, (hyp_result*)res);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches (batch.h): one grid over all instances per phase; a
+// work-group finds its instance in the prefix table of its range and runs
+// the same body on that instance's arrays, one work-group per 256 cells.
+// The per-instance reductions that follow run one work-group per instance.
+// ---------------------------------------------------------------------------
+struct BLoc {
+  int i, lb, nb;
+};
+__device__ __forceinline__ BLoc batch_loc(const int* __restrict__ first, int n) {
+  BLoc l;
+  l.i = batch_find(first, n, blockIdx.x);
+  l.lb = blockIdx.x - first[l.i];
+  l.nb = first[l.i + 1] - first[l.i];
+  return l;
+}
+
+__global__ __launch_bounds__(256) void div_batch(const BInst* __restrict__ I, const int* first, int n) {
+  __shared__ double red[4];
+  const BLoc l = batch_loc(first, n);
+  const BInst& B = I[l.i];
+  div_body(l.lb, l.nb, B.nx, B.ny, (float)(1.0 / B.dx), B.w.cell, B.u, B.v, B.w.d, B.w.blockpart,
+           B.w.sc, B.w.sync, B.w.phi_acc, red);
+}
+
+__global__ __launch_bounds__(256) void div_finish_batch(const BInst* __restrict__ I, const int* first) {
+  __shared__ double red[4];
+  const BInst& B = I[blockIdx.x];
+  div_finish_body(first[blockIdx.x + 1] - first[blockIdx.x], B.w.blockpart, B.w.sc, red);
+}
+
+hipError_t run_div_batch(const BInst* I, const BatchRanges& R, hipStream_t s) {
+  if (R.total[RK_CELL] > 0)
+    div_batch<<<R.total[RK_CELL], 256, 0, s>>>(I, R.of(RK_CELL), R.n);
+  div_finish_batch<<<R.n, 256, 0, s>>>(I, R.of(RK_CELL));
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void coef_batch(const BInst* __restrict__ I, const int* first, int n) {
+  const BLoc l = batch_loc(first, n);
+  const BInst& B = I[l.i];
+  if (!B.var) return;
+  coef_body(l.lb * blockDim.x + threadIdx.x, B.nx, B.ny, B.rho0, B.w.cell, B.rho, B.w.coef_e,
+            B.w.coef_n);
+}
+
+hipError_t run_coef_batch(const BInst* I, const BatchRanges& R, hipStream_t s) {
+  if (R.total[RK_CELL] > 0) coef_batch<<<R.total[RK_CELL], 256, 0, s>>>(I, R.of(RK_CELL), R.n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void init_phi_batch(const BInst* __restrict__ I, const int* first,
+                                                      int n) {
+  const BLoc l = batch_loc(first, n);
+  const BInst& B = I[l.i];
+  const int c = l.lb * blockDim.x + threadIdx.x;
+  if (c < B.nx * B.ny) B.w.phi[c] = 0.f;
+}
+
+hipError_t run_init_phi_batch(const BInst* I, const BatchRanges& R, hipStream_t s) {
+  if (R.total[RK_CELL] > 0) init_phi_batch<<<R.total[RK_CELL], 256, 0, s>>>(I, R.of(RK_CELL), R.n);
+  return hipGetLastError();
+}
+
+template <bool VAR>
+__global__ __launch_bounds__(256) void grad_batch(const BInst* __restrict__ I, const int* first, int n,
+                                                  int dt_dev) {
+  const BLoc l = batch_loc(first, n);
+  const BInst& B = I[l.i];
+  if (B.var != (VAR ? 1 : 0)) return;
+  const float p_scale = (float)(B.rho0 / (dt_dev ? B.w.sc->dt : B.dt));
+  grad_body<VAR>(l.lb, l.nb, B.nx, B.ny, (float)(1.0 / B.dx), p_scale, B.w.cell, B.w.phi,
+                 B.w.phi_acc, B.u, B.v, B.p, B.w.coef_e, B.w.coef_n);
+}
+
+__global__ __launch_bounds__(256) void check_batch(const BInst* __restrict__ I, const int* first, int n) {
+  __shared__ double red[4];
+  const BLoc l = batch_loc(first, n);
+  const BInst& B = I[l.i];
+  check_body(l.lb, l.nb, B.nx, B.ny, (float)(1.0 / B.dx), B.w.cell, B.u, B.v, B.w.blockpart, red);
+}
+
+__global__ __launch_bounds__(256) void finish_batch(const BInst* __restrict__ I, const int* first) {
+  __shared__ double red[4];
+  const BInst& B = I[blockIdx.x];
+  finish_body(first[blockIdx.x + 1] - first[blockIdx.x], B.w.blockpart, B.w.sc, B.res, red);
+}
+
+hipError_t run_grad_finish_batch(const BInst* I, const BatchRanges& R, bool dt_dev, bool var,
+                                 hipStream_t s) {
+  const int nb = R.total[RK_CELL];
+  if (nb > 0) {
+    grad_batch<false><<<nb, 256, 0, s>>>(I, R.of(RK_CELL), R.n, dt_dev ? 1 : 0);
+    if (var) grad_batch<true><<<nb, 256, 0, s>>>(I, R.of(RK_CELL), R.n, dt_dev ? 1 : 0);
+    check_batch<<<nb, 256, 0, s>>>(I, R.of(RK_CELL), R.n);
+  }
+  finish_batch<<<R.n, 256, 0, s>>>(I, R.of(RK_CELL));
   return hipGetLastError();
 }
 

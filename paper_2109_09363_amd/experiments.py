@@ -198,13 +198,16 @@ def batch_instances(dev, n_inst=128, seed=0):
 
 
 def cmd_batch(a, dev):
+    """The batched workload: 128 plumes with their own sides, obstacles and
+    density ratios (so their own g), developed by PCG-projected steps, then
+    one projection of all of them and batched time steps (each plume its own
+    physics) replayed from one captured hipGraph."""
     inst = batch_instances(dev)
     cells = sum(d["nx"] * d["ny"] for d in inst)
     w = load_trained(dev)
-    # every instance has its own g (Ri 0.1) and drho; the batched step takes
-    # one g/drho, so instances are developed individually first with PCG
     for d in inst:
         sc = d["scene"]
+        d["g"], d["drho"], d["u_in"] = sc.g, sc.drho, sc.u_in
         pr = hp.Projector(d["nx"], d["ny"], sc.dx, 1.0, sc.rho0, S4, C64, "bf16", device=dev)
         pr.set_weights(w)
         pr.plan(d["flags"])
@@ -212,37 +215,62 @@ def cmd_batch(a, dev):
             xi = torch.from_numpy(scenes.inflow_noise(1000, s, d["nx"]).astype(np.float32)).to(dev)
             pr.step_async(d["rho"], d["u"], d["v"], d["flags"], d["p"], xi, 1e-3, g=sc.g, drho=sc.drho,
                           method="pcg", max_iters=200000)
-        # the batch projects the next advected state
-        xi = torch.from_numpy(scenes.inflow_noise(1000, a.warmup, d["nx"]).astype(np.float32)).to(dev)
-        pr.advect_async(d["rho"], d["u"], d["v"], xi, g=sc.g, drho=sc.drho)
+        d["_pr"] = pr
     torch.cuda.synchronize()
-    snap = [(d["u"].clone(), d["v"].clone(), d["p"].clone()) for d in inst]
+    # developed (projected) states, the start of the timed steps
+    snap_step = [(d["rho"].clone(), d["u"].clone(), d["v"].clone(), d["p"].clone()) for d in inst]
+    # and their next advected states, what the timed projections receive
+    for d in inst:
+        sc = d["scene"]
+        xi = torch.from_numpy(scenes.inflow_noise(1000, a.warmup, d["nx"]).astype(np.float32)).to(dev)
+        d.pop("_pr").advect_async(d["rho"], d["u"], d["v"], xi, g=sc.g, drho=sc.drho)
+    torch.cuda.synchronize()
+    snap_proj = [(d["rho"].clone(), d["u"].clone(), d["v"].clone(), d["p"].clone()) for d in inst]
 
-    def restore():
-        for d, (u, v, p) in zip(inst, snap):
-            d["u"].copy_(u); d["v"].copy_(v); d["p"].copy_(p)
+    def restore(snap):
+        for d, (r, u, v, p) in zip(inst, snap):
+            d["rho"].copy_(r); d["u"].copy_(u); d["v"].copy_(v); d["p"].copy_(p)
         torch.cuda.synchronize()
+
+    def timed(fn, reps, snap):
+        ts = []
+        for _ in range(reps):
+            restore(snap)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
 
     out = {"what": "batch", "instances": len(inst), "cells": cells, "threshold": 1e-3,
-           "sides": sorted(set(d["nx"] for d in inst))}
+           "sides": sorted(set(d["nx"] for d in inst)), "variable_density": bool(a.var)}
     for method in ("hybrid", "jacobi"):
         b = hp.Batch(inst, threshold=1e-3, method=method, params=w, scales=S4, channels=C64,
-                     precision="bf16", max_iters=400000)
-        restore()
+                     precision="bf16", max_iters=400000, variable_density=bool(a.var))
+        restore(snap_proj)
         b.project_async()          # warm
         torch.cuda.synchronize()
-        restore()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.project_async()
-        e1.record()
-        torch.cuda.synchronize()
+        ms_proj = timed(b.project_async, 3, snap_proj)
         res = b.results()
         it = np.array([r.iters for r in res], dtype=np.float64)
-        out[method] = {"ms_per_projection_of_all": round(e0.elapsed_time(e1), 3),
-                       "mean_sweeps": round(float(it.mean()), 1), "max_sweeps": int(it.max()),
-                       "min_sweeps": int(it.min()), "statuses": sorted(set(int(r.status) for r in res)),
-                       "max_e1_final": max(r.e1_final for r in res)}
+        row = {"ms_per_projection_of_all": round(ms_proj, 3),
+               "mean_sweeps": round(float(it.mean()), 1), "max_sweeps": int(it.max()),
+               "min_sweeps": int(it.min()), "statuses": sorted(set(int(r.status) for r in res)),
+               "max_e1_final": max(r.e1_final for r in res)}
+        if method == "hybrid":
+            # batched time steps, each plume with its own g, drho and dt
+            ms_eager = timed(b.step_async, 3, snap_step)
+            b.capture()
+            ms_graph = timed(b.launch_async, 3, snap_step)
+            res = b.results()
+            row.update({"ms_per_step_of_all_eager": round(ms_eager, 3),
+                        "ms_per_step_of_all_graph": round(ms_graph, 3),
+                        "timesteps_per_s_per_plume_graph": round(1e3 / ms_graph, 2),
+                        "step_statuses": sorted(set(int(r.status) for r in res)),
+                        "step_mean_sweeps": round(float(np.mean([r.iters for r in res])), 1)})
+        out[method] = row
         del b
     emit(out)
 
@@ -390,6 +418,7 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--sweeps", type=int, default=800)
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--var", action="store_true", help="batch: variable-density operator")
     a = ap.parse_args()
     if a.seeds is None:
         a.seeds = list(range(100, 108)) if a.what in ("validate", "checks") else [0, 1, 2, 3, 4]
