@@ -1,12 +1,16 @@
-"""Tile autotuner of the persistent Jacobi kernel.
+"""Tile autotuner of the persistent Jacobi kernels.
 
-For each grid size, time a fixed number of sweeps (check every 8, halo 9)
-with every tile height R that fits the GPU (one work-group per CU) and keep
-the fastest.  The result is the C header the library compiles
-(csrc/tile_table.h); grids without an entry use the smallest R that fits.
+Single grids: for each grid size, time a fixed number of sweeps (check every
+8, halo 9) with every tile height R that fits the GPU and keep the fastest;
+the result is the C header the library compiles (csrc/tile_table.h), and
+grids without an entry use the smallest R that fits.
+
+Batches (--batch): for each grid side, time the batched projection of a
+batch of plumes of that side at a fixed sweep count with R = 8 and R = 16
+for every instance, and keep the faster (csrc/batch_tile_table.h).
 
 python -m paper_2109_09363_amd.autotune [--sizes 128 192 256 384 512 768 1024]
-        [--sweeps 512] [--reps 3] [--out paper_2109_09363_amd/csrc/tile_table.h]
+        [--sweeps 512] [--reps 3] [--batch [--per-batch 16]] [--out HEADER]
 """
 from __future__ import annotations
 
@@ -89,15 +93,86 @@ def write_header(path, entries):
         f.write("\n".join(lines))
 
 
+def time_batch_rows(n, count, sweeps, reps, dev):
+    """ms of one batched projection (fixed sweeps) of `count` plumes of side n
+    with every instance's tiles at R = 8 and at R = 16."""
+    inst = []
+    for i in range(count):
+        sc = scenes.plume_scene(n, seed=200 + i, n_obstacles=(0, 3))
+        u, v = scenes.random_faces(n, n, 200 + i, kind="mixed")
+        inst.append(dict(nx=n, ny=n, dx=sc.dx, flags=torch.from_numpy(sc.flags).to(dev),
+                         u=torch.from_numpy(u.astype(np.float32)).to(dev),
+                         v=torch.from_numpy(v.astype(np.float32)).to(dev),
+                         p=torch.zeros((n, n), dtype=torch.float32, device=dev)))
+    u0 = [d["u"].clone() for d in inst]
+    v0 = [d["v"].clone() for d in inst]
+    out = {}
+    for r in (8, 16):
+        b = hp.Batch(inst, threshold=0.0, method="jacobi", max_iters=sweeps, tile_rows=r, device=dev)
+        ts = []
+        for rep in range(reps + 1):
+            for d, uu, vv in zip(inst, u0, v0):
+                d["u"].copy_(uu)
+                d["v"].copy_(vv)
+            a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            b.project_async()
+            e.record()
+            torch.cuda.synchronize()
+            if rep > 0:
+                ts.append(a.elapsed_time(e))
+        out[r] = float(np.median(ts))
+        del b
+    return out
+
+
+def write_batch_header(path, entries):
+    lines = [
+        "// Tile rows of the batched (streaming) Jacobi kernel per grid side: for",
+        "// batches of grids of nx x ny cells, the rows per wave R (8 or 16) that ran",
+        "// fastest on MI355X.  Written by paper_2109_09363_amd/autotune.py --batch",
+        "// (do not edit by hand); sides without an entry use R = 16.",
+        "#pragma once",
+        "",
+        "namespace hyp {",
+        "",
+        "struct BatchTileEntry {",
+        "  int nx, ny, R;",
+        "};",
+        "",
+        "constexpr BatchTileEntry kBatchTileTable[] = {",
+    ]
+    for (n, r, ms) in entries:
+        lines.append(f"    {{{n}, {n}, {r}}},  // {ms:.3f} ms")
+    lines += ["};", f"constexpr int kBatchTileTableSize = {len(entries)};", "", "}  // namespace hyp", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sizes", type=int, nargs="*", default=[128, 192, 256, 384, 512, 768, 1024])
     ap.add_argument("--sweeps", type=int, default=512)
     ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                                   "csrc", "tile_table.h"))
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--batch", action="store_true", help="tune the batched kernel's rows per side")
+    ap.add_argument("--per-batch", type=int, default=16, help="--batch: plumes per timed batch")
     a = ap.parse_args()
     dev = torch.device("cuda")
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    if a.batch:
+        entries = []
+        for n in a.sizes:
+            t = time_batch_rows(n, a.per_batch, a.sweeps, a.reps, dev)
+            best = min(t, key=t.get)
+            entries.append((n, best, t[best]))
+            print(json.dumps({"n": n, "instances": a.per_batch, "sweeps": a.sweeps, "ms_by_rows": t,
+                              "best_rows": best}), flush=True)
+        out = a.out or os.path.join(csrc, "batch_tile_table.h")
+        write_batch_header(out, entries)
+        print(f"# wrote {out}", file=sys.stderr, flush=True)
+        return
+    a.out = a.out or os.path.join(csrc, "tile_table.h")
     entries = []
     for n in a.sizes:
         t = time_rows(n, ROWS, a.sweeps, a.reps, dev)

@@ -22,7 +22,7 @@
 #include "common.h"
 #include "internal.h"
 #include "jacobi_rows.h"
-#include "tile_table.h"
+#include "batch_tile_table.h"
 
 namespace hyp {
 

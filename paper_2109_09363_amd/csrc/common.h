@@ -65,6 +65,33 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   for (int i = 0; i < nw; ++i) t += scratch[i];
   return t;
 }
+// Three block reductions in one exchange through shared memory: the sums of
+// a and c, and the sum (or, with e_max, the maximum) of e, valid in every
+// thread.  `scratch` must hold 3 * blockDim.x/64 doubles.
+__device__ __forceinline__ void block_sum3(double& a, double& c, double& e, bool e_max,
+                                           double* scratch) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  a = wave_sum_dpp(a);
+  c = wave_sum_dpp(c);
+  e = e_max ? wave_max(e) : wave_sum_dpp(e);
+  __syncthreads();
+  if (lane == 0) {
+    scratch[3 * w] = a;
+    scratch[3 * w + 1] = c;
+    scratch[3 * w + 2] = e;
+  }
+  __syncthreads();
+  a = 0.0;
+  c = 0.0;
+  e = e_max ? scratch[2] : 0.0;
+  for (int i = 0; i < nw; ++i) {
+    a += scratch[3 * i];
+    c += scratch[3 * i + 1];
+    e = e_max ? fmax(e, scratch[3 * i + 2]) : e + scratch[3 * i + 2];
+  }
+}
+
 __device__ __forceinline__ double block_max(double v, double* scratch) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;

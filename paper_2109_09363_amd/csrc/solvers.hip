@@ -453,7 +453,7 @@ __device__ __forceinline__ void apply_A_var(const float (&v)[R], const float (&k
 template <int R, bool VAR>
 __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
   __shared__ float edge[2][2][4][64];
-  __shared__ double red[4];
+  __shared__ double red3[12];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int TW = 62, TH = 4 * R - 2;
   const int G = gridDim.x;
@@ -544,9 +544,7 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
         c += (double)w[i] * (double)u[i];
         e = p.einf ? fmax(e, fabs((double)r[i])) : e + fabs((double)r[i]);
       }
-    a = block_sum(a, red);
-    c = block_sum(c, red);
-    e = p.einf ? block_max(e, red) : block_sum(e, red);
+    block_sum3(a, c, e, p.einf != 0, red3);
     double* pa = p.partial + par * 3 * kMaxCoopBlocks;
     if (threadIdx.x == 0) {
       st_agent(pa + blockIdx.x, a);
@@ -562,12 +560,13 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
       const double x = ld_agent(pa + 2 * kMaxCoopBlocks + i);
       se = p.einf ? fmax(se, x) : se + x;
     }
-    gam = block_sum(sa, red);
-    del = block_sum(sc_, red);
+    block_sum3(sa, sc_, se, p.einf != 0, red3);
+    gam = sa;
+    del = sc_;
     if (p.einf)
-      E = block_max(se, red) * p.inv_dx2;
+      E = se * p.inv_dx2;
     else
-      E = nF > 0 ? block_sum(se, red) / nF * p.inv_dx2 : 0.0;
+      E = nF > 0 ? se / nF * p.inv_dx2 : 0.0;
     par ^= 1;
     return true;
   };

@@ -21,12 +21,4 @@ constexpr TileEntry kTileTable[] = {
 };
 constexpr int kTileTableSize = 7;
 
-// Tile rows of the batched (streaming) Jacobi kernel per grid side; sides
-// without an entry use R = 16.  Written by autotune.py --batch.
-struct BatchTileEntry {
-  int nx, ny, R;
-};
-constexpr BatchTileEntry kBatchTileTable[] = {{0, 0, 16}};
-constexpr int kBatchTileTableSize = 0;
-
 }  // namespace hyp
