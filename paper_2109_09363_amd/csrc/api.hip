@@ -9,6 +9,7 @@
 #include "../../include/hyproj.h"
 #include "batch.h"
 #include "internal.h"
+#include "unet.h"
 
 struct hyp_ctx {
   hyp::NetShape net;
@@ -77,7 +78,19 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
     L.cnn_t = take(px * 4);
     L.cnn_w = take(cnn_weight_image_bytes(net));
     if (net.arch == HYP_ARCH_UNET) L.cnn_cat = take(unet_cat_elems(nx, ny) * act_elt);
-    if (net.train) {
+    if (net.train && net.arch == HYP_ARCH_UNET) {
+      // every layer's FP32 output and the skip gradients (unet.h); lambda
+      // maps of up to 32 channels at full resolution (the concatenation)
+      const size_t C = net.channels;
+      L.cnn_save = take(4 * unet_save_layout(nx, ny).total);
+      L.bw_cells = take(3 * 4 * n);
+      L.bw_t = take(4 * px);
+      L.bw_x = take(4 * px);
+      L.bw_a = take(4 * px * C);
+      L.bw_b = take(4 * px * C);
+      L.bw_part_n = (size_t)kWgBlocks * (C * 9 * C + C);
+      L.bw_part = take(4 * L.bw_part_n);
+    } else if (net.train) {
       const size_t C = net.channels;
       L.cnn_save = take(4 * px * C * act_elt);
       L.bw_cells = take(3 * 4 * n);
@@ -171,11 +184,15 @@ int hyp_create(hyp_ctx** out, const hyp_net_desc* net) {
       return HYP_EINVAL;
     if (net->precision != HYP_PREC_FP32 && net->precision != HYP_PREC_BF16) return HYP_EINVAL;
     if (net->flags & ~HYP_NET_TRAIN) return HYP_EINVAL;
-    if (net->flags & HYP_NET_TRAIN) return HYP_EUNSUPPORTED;
+    // training: the Unet in FP32 (the cascades are inference only)
+    if ((net->flags & HYP_NET_TRAIN) &&
+        (net->arch != HYP_ARCH_UNET || net->precision != HYP_PREC_FP32))
+      return HYP_EUNSUPPORTED;
     ns.scales = S;
     ns.channels = C;
     ns.precision = net->precision;
     ns.arch = net->arch;
+    ns.train = (net->flags & HYP_NET_TRAIN) != 0;
   } else if (net) {
     if (net->arch != HYP_ARCH_PARALLEL) return HYP_EINVAL;
     if (net->scales < 1 || net->scales > 5) return HYP_EINVAL;

@@ -17,6 +17,7 @@
 #include "../../include/hyproj.h"
 #include "common.h"
 #include "internal.h"
+#include "unet.h"
 
 namespace hyp {
 
@@ -496,6 +497,293 @@ static hipError_t backward_cnn(const NetShape& net, const WsLayout& Ly, int nx, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The Unet's backward pass (Sec. 3.1's Unet, FP32 training).  The forward
+// kept every layer's output (unet.h); lambda maps alternate between bw_a
+// and bw_b.  Decoder scales 0..3 first (the reverse of the forward), each
+// splitting the gradient of its concatenation into the skip part (kept per
+// scale) and the part of the upsampled coarser map (upsampling adjoint, then
+// that map's ReLU mask); then encoder scales 4..0, where the gradient of a
+// pooled map goes to the window maxima (max-pooling adjoint), is added to
+// the skip part and masked by the encoder output's ReLU.
+// ---------------------------------------------------------------------------
+
+// Weight and bias gradients of a 3x3 layer over input channels
+// [ci0, ci0 + CC) of a CIN-channel input (chunks keep the tile in LDS):
+// part[bx][e], e over (co, tap, c) of the chunk, then the biases (chunk 0).
+template <int CIN, int CC, int COUT, int NACC>
+__global__ __launch_bounds__(256) void bw_wgrad_c(int H, int W, const float* __restrict__ in, int ci0,
+                                                  const float* __restrict__ lam_pre,
+                                                  float* __restrict__ part) {
+  extern __shared__ __attribute__((aligned(16))) float lds_c[];
+  float* lt = lds_c;                  // [BT*BT][COUT]
+  float* xt = lds_c + BT * BT * COUT; // [BE*BE][CC]
+  const int nw = COUT * 9 * CC, nout = nw + (ci0 == 0 ? COUT : 0);
+  const int tiles_x = (W + BT - 1) / BT, tiles = tiles_x * ((H + BT - 1) / BT);
+  const int e0 = blockIdx.y * 256 * NACC;
+  float acc[NACC];
+#pragma unroll
+  for (int m = 0; m < NACC; ++m) acc[m] = 0.f;
+  for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int x0 = (t % tiles_x) * BT, y0 = (t / tiles_x) * BT;
+    __syncthreads();
+    for (int e = threadIdx.x; e < BT * BT * COUT; e += 256) {
+      const int q = e / COUT, co = e % COUT;
+      const int gy = y0 + q / BT, gx = x0 + q % BT;
+      lt[e] = (gy < H && gx < W) ? lam_pre[((size_t)gy * W + gx) * COUT + co] : 0.f;
+    }
+    for (int e = threadIdx.x; e < BE * BE * CC; e += 256) {
+      const int q = e / CC, c = e % CC;
+      const int gy = min(max(y0 - 1 + q / BE, 0), H - 1);
+      const int gx = min(max(x0 - 1 + q % BE, 0), W - 1);
+      xt[e] = in[((size_t)gy * W + gx) * CIN + ci0 + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NACC; ++m) {
+      const int e = e0 + m * 256 + threadIdx.x;
+      if (e >= nout) break;
+      float a = 0.f;
+      if (e < nw) {
+        const int co = e / (9 * CC), rem = e % (9 * CC), tap = rem / CC, c = rem % CC;
+        const int ky = tap / 3, kx = tap % 3;
+        for (int q = 0; q < BT * BT; ++q)
+          a += lt[q * COUT + co] * xt[((q / BT + ky) * BE + (q % BT) + kx) * CC + c];
+      } else {
+        const int co = e - nw;
+        for (int q = 0; q < BT * BT; ++q) a += lt[q * COUT + co];
+      }
+      acc[m] += a;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NACC; ++m) {
+    const int e = e0 + m * 256 + threadIdx.x;
+    if (e < nout) part[(size_t)blockIdx.x * nout + e] = acc[m];
+  }
+}
+
+// fixed-order sum of a chunk's partials into the layer's packed gradient
+// (W[Cout][3][3][Cin] then b[Cout])
+__global__ __launch_bounds__(256) void bw_part_finish_c(int nblocks, int cin, int cc, int cout,
+                                                        int ci0, const float* __restrict__ part,
+                                                        float* __restrict__ out, int accumulate) {
+  const int nw = cout * 9 * cc, nout = nw + (ci0 == 0 ? cout : 0);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nout) return;
+  float acc = 0.f;
+  for (int b = 0; b < nblocks; ++b) acc += part[(size_t)b * nout + e];
+  size_t idx;
+  if (e < nw) {
+    const int co = e / (9 * cc), rem = e % (9 * cc), tap = rem / cc, c = rem % cc;
+    idx = (size_t)co * 9 * cin + (size_t)tap * cin + ci0 + c;
+  } else {
+    idx = (size_t)cout * 9 * cin + (e - nw);
+  }
+  out[idx] = accumulate ? out[idx] + acc : acc;
+}
+
+template <int CIN, int CC, int COUT>
+static hipError_t unet_wgrad_t(int H, int W, const float* in, const float* lam_pre, float* part,
+                               size_t part_n, float* dst, int accumulate, hipStream_t s) {
+  constexpr int NACC = 36;
+  const int tiles = ((W + BT - 1) / BT) * ((H + BT - 1) / BT);
+  const int gx = min(tiles, kWgBlocks);
+  const size_t lds = sizeof(float) * (BT * BT * COUT + BE * BE * CC);
+  auto k = bw_wgrad_c<CIN, CC, COUT, NACC>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  for (int ci0 = 0; ci0 < CIN; ci0 += CC) {
+    const int nout = COUT * 9 * CC + (ci0 == 0 ? COUT : 0);
+    if ((size_t)gx * nout > part_n) return hipErrorInvalidValue;
+    const int gy = (nout + 256 * NACC - 1) / (256 * NACC);
+    hipLaunchKernelGGL(k, dim3(gx, gy), dim3(256), lds, s, H, W, in, ci0, lam_pre, part);
+    hipLaunchKernelGGL(bw_part_finish_c, dim3((nout + 255) / 256), dim3(256), 0, s, gx, CIN, CC, COUT,
+                       ci0, part, dst, accumulate);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t unet_wgrad(int cin, int cout, int H, int W, const float* in, const float* lam_pre,
+                             float* part, size_t part_n, float* dst, int acc, hipStream_t s) {
+  if (cin == 2 && cout == 16) return unet_wgrad_t<2, 2, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 16 && cout == 16) return unet_wgrad_t<16, 16, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 16 && cout == 64) return unet_wgrad_t<16, 16, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 64 && cout == 64) return unet_wgrad_t<64, 64, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 128 && cout == 64) return unet_wgrad_t<128, 64, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 80 && cout == 16) return unet_wgrad_t<80, 80, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 32 && cout == 16) return unet_wgrad_t<32, 32, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  return hipErrorInvalidValue;
+}
+
+// input gradient; mask: multiply by (h_in > 0), the ReLU of the input map
+static hipError_t unet_dgrad(int cin, int cout, bool mask, int H, int W, const float* lam_pre,
+                             const float* Wt, const float* h_in, float* lam_in, hipStream_t s) {
+  if (cin == 16 && cout == 16)
+    return mask ? dgrad_layer<float, 16, 16, true, false>(H, W, lam_pre, Wt, h_in, lam_in, s)
+                : dgrad_layer<float, 16, 16, false, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
+  if (cin == 64 && cout == 64)
+    return mask ? dgrad_layer<float, 64, 64, true, false>(H, W, lam_pre, Wt, h_in, lam_in, s)
+                : dgrad_layer<float, 64, 64, false, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
+  if (mask) return hipErrorInvalidValue;
+  if (cin == 16 && cout == 64) return dgrad_layer<float, 16, 64, false, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
+  if (cin == 128 && cout == 64) return dgrad_layer<float, 128, 64, false, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
+  if (cin == 80 && cout == 16) return dgrad_layer<float, 80, 16, false, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
+  if (cin == 32 && cout == 16) return dgrad_layer<float, 32, 16, false, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
+  return hipErrorInvalidValue;
+}
+
+// channels [0, C) of a map with `istr` elements per pixel into a contiguous map
+__global__ __launch_bounds__(256) void unet_skip_copy(size_t npx, int C, const float* __restrict__ src,
+                                                      int istr, float* __restrict__ dst) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= npx * C) return;
+  dst[gid] = src[(gid / C) * istr + gid % C];
+}
+
+// Max-pooling adjoint at fine scale (H, W, C): a fine element receives its
+// window's gradient when it is the window's maximum (the first of the
+// window, row-major, that attains it); plus the skip gradient; times the
+// ReLU mask of the encoder output c2 (channels [0, C) of a map with
+// `istr` elements per pixel).
+__global__ __launch_bounds__(256) void unet_pool_bw(int H, int W, int C, const float* __restrict__ c2,
+                                                    int istr, const float* __restrict__ lam_pool,
+                                                    const float* __restrict__ skip,
+                                                    float* __restrict__ out) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)H * W * C) return;
+  const int c = (int)(gid % C);
+  const size_t px = gid / C;
+  const int x = (int)(px % W), y = (int)(px / W);
+  const int X = x >> 1, Y = y >> 1, Wo = W >> 1;
+  const float* wnd = c2 + ((size_t)(2 * Y) * W + 2 * X) * istr + c;
+  const float v0 = wnd[0], v1 = wnd[istr], v2 = wnd[(size_t)W * istr], v3 = wnd[(size_t)W * istr + istr];
+  const float m = fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
+  const int first = v0 == m ? 0 : (v1 == m ? 1 : (v2 == m ? 2 : 3));
+  const int me = (y & 1) * 2 + (x & 1);
+  float g = skip[gid];
+  if (me == first) g += lam_pool[((size_t)Y * Wo + X) * C + c];
+  out[gid] = c2[px * istr + c] > 0.f ? g : 0.f;
+}
+
+// Upsampling adjoint: coarse (Hc, Wc, C) from the fine gradient's channels
+// [off, off + C) (`istr` per pixel), times the ReLU mask of the coarse map.
+__global__ __launch_bounds__(256) void unet_up_bw(int Hc, int Wc, int C, const float* __restrict__ fine,
+                                                  int istr, int off, const float* __restrict__ act,
+                                                  float* __restrict__ out) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)Hc * Wc * C) return;
+  const int c = (int)(gid % C);
+  const size_t px = gid / C;
+  const int X = (int)(px % Wc), Y = (int)(px / Wc);
+  const int Hf = 2 * Hc, Wf = 2 * Wc;
+  float acc = 0.f;
+  for (int J = max(2 * Y - 2, 0); J <= min(2 * Y + 3, Hf - 1); ++J) {
+    int y0, y1;
+    float fy;
+    up_axis(J, Hc, &y0, &y1, &fy);
+    const float wy = (y0 == Y ? 1.f - fy : 0.f) + (y1 == Y ? fy : 0.f);
+    if (wy == 0.f) continue;
+    for (int I = max(2 * X - 2, 0); I <= min(2 * X + 3, Wf - 1); ++I) {
+      int x0, x1;
+      float fx;
+      up_axis(I, Wc, &x0, &x1, &fx);
+      const float wx = (x0 == X ? 1.f - fx : 0.f) + (x1 == X ? fx : 0.f);
+      if (wx == 0.f) continue;
+      acc += wy * wx * fine[((size_t)J * Wf + I) * istr + off + c];
+    }
+  }
+  out[gid] = act[gid] > 0.f ? acc : 0.f;
+}
+
+static hipError_t unet_backward(int nx, int ny, const float* params, float* dparams, int acc,
+                                const Ws& w, hipStream_t s) {
+  const UnetSave SV = unet_save_layout(nx, ny);
+  const float* save = reinterpret_cast<const float*>(w.cnn_save);
+  float* skipg = reinterpret_cast<float*>(w.cnn_save);
+  const float* cat = reinterpret_cast<const float*>(w.cnn_cat);
+  const float* x = reinterpret_cast<const float*>(w.cnn_in);
+  // parameter offsets of the layers (unet.h order)
+  size_t poff[kUnetLayers + 1];
+  int lcin[kUnetLayers], lcout[kUnetLayers];
+  {
+    int n = 0, cin = 2;
+    for (int l = 0; l < kUnetLevels; ++l) {
+      lcin[n] = cin; lcout[n++] = kUnetW[l];
+      lcin[n] = kUnetW[l]; lcout[n++] = kUnetW[l];
+      cin = kUnetW[l];
+    }
+    for (int l = kUnetLevels - 2; l >= 0; --l) {
+      lcin[n] = kUnetW[l] + kUnetW[l + 1]; lcout[n++] = kUnetW[l];
+      lcin[n] = kUnetW[l]; lcout[n++] = kUnetW[l];
+    }
+    lcin[n] = kUnetW[0]; lcout[n++] = 1;
+    size_t o = 0;
+    for (int i = 0; i < kUnetLayers; ++i) {
+      poff[i] = o;
+      const int k = i == kUnetLayers - 1 ? 1 : 3;
+      o += (size_t)k * k * lcin[i] * lcout[i] + lcout[i];
+    }
+    poff[kUnetLayers] = o;
+  }
+  float* A = w.bw_a;
+  float* B = w.bw_b;
+  hipError_t e = hipSuccess;
+  auto grad_of = [&](int i) { return dparams ? dparams + poff[i] : nullptr; };
+  auto layer_bw = [&](int i, int H, int W, const float* in, const float* lam_pre, bool mask,
+                      const float* h_in, float* lam_in) -> hipError_t {
+    hipError_t r = hipSuccess;
+    if (dparams) r = unet_wgrad(lcin[i], lcout[i], H, W, in, lam_pre, w.bw_part, w.bw_part_n, grad_of(i), acc, s);
+    if (r != hipSuccess || !lam_in) return r;
+    return unet_dgrad(lcin[i], lcout[i], mask, H, W, lam_pre, params + poff[i], h_in, lam_in, s);
+  };
+  // the 1x1 output: lambda of the last decoder layer's pre-activation
+  const int n = nx * ny, head = kUnetLayers - 1, nbh = (n + 255) / 256;
+  if ((size_t)nbh * (kUnetW[0] + 1) > w.bw_part_n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((bw_head<float, 16>), dim3(nbh), dim3(256), 0, s, n, w.bw_t, save + SV.d2[0],
+                     params + poff[head], A, w.bw_part);
+  if (dparams)
+    hipLaunchKernelGGL(bw_part_finish, dim3(1), dim3(256), 0, s, nbh, kUnetW[0] + 1, w.bw_part,
+                       grad_of(head), acc);
+  // decoder scales 0..3: A holds the lambda of the second layer's pre-activation
+  for (int l = 0; l + 1 < kUnetLevels; ++l) {
+    const int H = ny >> l, W = nx >> l, wl = kUnetW[l], wu = kUnetW[l + 1], cs = wl + wu;
+    const int L2 = kUnetLayers - 2 - 2 * l, L1 = L2 - 1;
+    const float* cl = cat + unet_cat_offset(nx, ny, l);
+    if ((e = layer_bw(L2, H, W, save + SV.d1[l], A, true, save + SV.d1[l], B)) != hipSuccess) return e;
+    if ((e = layer_bw(L1, H, W, cl, B, false, nullptr, A)) != hipSuccess) return e;
+    const size_t npx = (size_t)H * W;
+    hipLaunchKernelGGL(unet_skip_copy, dim3((unsigned)((npx * wl + 255) / 256)), dim3(256), 0, s, npx, wl, A,
+                       cs, skipg + SV.skip_grad[l]);
+    const float* coarse = l + 2 < kUnetLevels ? save + SV.d2[l + 1] : save + SV.c2_bottom;
+    const size_t nc = (size_t)(H / 2) * (W / 2) * wu;
+    hipLaunchKernelGGL(unet_up_bw, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, H / 2, W / 2, wu, A,
+                       cs, wl, coarse, B);
+    float* t = A; A = B; B = t;
+  }
+  // encoder scales 4..0: A holds the lambda of the second layer's pre-activation
+  for (int l = kUnetLevels - 1; l >= 0; --l) {
+    const int H = ny >> l, W = nx >> l, wl = kUnetW[l];
+    const int L2 = 2 * l + 1, L1 = 2 * l;
+    if ((e = layer_bw(L2, H, W, save + SV.c1[l], A, true, save + SV.c1[l], B)) != hipSuccess) return e;
+    if (l == 0) {
+      if (dparams && (e = unet_wgrad(2, wl, H, W, x, B, w.bw_part, w.bw_part_n, grad_of(L1), acc, s)) != hipSuccess)
+        return e;
+      if ((e = dgrad_layer<float, 2, 16, false, true>(H, W, B, params + poff[L1], nullptr, w.bw_x, s)) != hipSuccess)
+        return e;
+    } else {
+      const int wp = kUnetW[l - 1], csp = wp + wl;
+      if ((e = layer_bw(L1, H, W, save + SV.pool[l - 1], B, false, nullptr, A)) != hipSuccess) return e;
+      const float* c2 = cat + unet_cat_offset(nx, ny, l - 1);
+      const size_t nf = (size_t)(2 * H) * (2 * W) * wp;
+      hipLaunchKernelGGL(unet_pool_bw, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, 2 * H, 2 * W, wp,
+                         c2, csp, A, save + SV.skip_grad[l - 1], B);
+      float* t = A; A = B; B = t;
+    }
+  }
+  return hipGetLastError();
+}
+
 hipError_t run_backward(const NetShape& net, const WsLayout& Ly, int nx, int ny, double dx,
                         int sweeps, float omega, double scale, bool accumulate,
                         const float* params, float* du, float* dv, float* dparams,
@@ -517,10 +805,12 @@ hipError_t run_backward(const NetShape& net, const WsLayout& Ly, int nx, int ny,
     bw_jacobi<<<nb, 256, 0, s>>>(nx, ny, omega, wdx2, w.cell, cur, nxt, lamD);
     float* t = cur; cur = nxt; nxt = t;
   }
-  // CNN
-  bw_phi0<<<nb, 256, 0, s>>>(n, (float)(dx * dx), w.cell, cur, w.cnn_t, w.bw_t, w.blockpart, w.sc);
+  // CNN (the Unet's output y is the full-resolution map phi0 = dx^2 s y)
+  const bool unet = net.arch == HYP_ARCH_UNET;
+  bw_phi0<<<nb, 256, 0, s>>>(n, (float)(dx * dx), w.cell, cur, unet ? w.cnn_y : w.cnn_t, w.bw_t,
+                             w.blockpart, w.sc);
   bw_lams_set<<<1, 256, 0, s>>>(nb, w.blockpart, dx * dx, w.sc);
-  for (int k = 0; k + 1 < net.scales; ++k) {
+  for (int k = 0; !unet && k + 1 < net.scales; ++k) {
     const int Hc = Ly.sc_h[k + 1], Wc = Ly.sc_w[k + 1];
     bw_up2T<<<(Hc * Wc + 255) / 256, 256, 0, s>>>(Hc, Wc, w.bw_t + Ly.sc_off_px[k],
                                                   w.bw_t + Ly.sc_off_px[k + 1]);
@@ -528,7 +818,10 @@ hipError_t run_backward(const NetShape& net, const WsLayout& Ly, int nx, int ny,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int acc = accumulate ? 1 : 0;
-  if (net.precision == HYP_PREC_BF16) {
+  if (unet) {
+    if (net.precision != HYP_PREC_FP32) return hipErrorInvalidValue;
+    e = unet_backward(nx, ny, params, dparams, acc, w, s);
+  } else if (net.precision == HYP_PREC_BF16) {
     switch (net.channels) {
       case 32: e = backward_cnn<uint16_t, 32>(net, Ly, nx, ny, params, dparams, acc, w, s); break;
       case 64: e = backward_cnn<uint16_t, 64>(net, Ly, nx, ny, params, dparams, acc, w, s); break;
@@ -543,8 +836,8 @@ hipError_t run_backward(const NetShape& net, const WsLayout& Ly, int nx, int ny,
   }
   if (e != hipSuccess) return e;
   PyrT P{};
-  P.nscales = net.scales;
-  for (int k = 0; k < net.scales; ++k) P.lx[k] = w.bw_x + Ly.sc_off_px[k];
+  P.nscales = unet ? 1 : net.scales;
+  for (int k = 0; k < P.nscales; ++k) P.lx[k] = w.bw_x + Ly.sc_off_px[k];
   bw_pyr_sum<<<nb, 256, 0, s>>>(nx, ny, P, w.cell, w.d, w.blockpart);
   bw_lams_add<<<1, 256, 0, s>>>(nb, w.blockpart, w.sc);
   bw_dnorm<<<nb, 256, 0, s>>>(nx, ny, P, w.cell, w.d, lamD, w.sc);

@@ -31,6 +31,7 @@
 #include "common.h"
 #include "conv_mfma.h"
 #include "internal.h"
+#include "unet.h"
 
 namespace hyp {
 
@@ -42,9 +43,6 @@ struct PnLayer {
 constexpr int kPnMaxLayers = 7;
 static int pn_branch_def(int arch, int b, PnLayer* out);
 static int pn_branch(int arch, int b, PnLayer* out) { return pn_branch_def(arch, b, out); }
-constexpr int kUnetLevels = 5;
-constexpr int kUnetLayers = 4 * kUnetLevels - 1;  // 10 encoder, 8 decoder, 1 output
-constexpr int kUnetW[kUnetLevels] = {16, 16, 64, 64, 64};
 
 // Unet layers in parameter order: encoder scales 0..4 (two each), decoder
 // scales 3..0 (two each), the 1x1 output.
@@ -77,13 +75,6 @@ static size_t wimg_elems(const PnLayer& l, int elt) {
   return (size_t)(l.cin / cc) * l.cout * conv_wstr(elt, l.ks, cc);
 }
 
-// Concatenation buffer of Unet scale l (0..3): (ny >> l) x (nx >> l) pixels of
-// kUnetW[l] skip channels then kUnetW[l + 1] upsampled ones; element offsets.
-static size_t unet_cat_offset(int nx, int ny, int l) {
-  size_t o = 0;
-  for (int k = 0; k < l; ++k) o += (size_t)(nx >> k) * (ny >> k) * (kUnetW[k] + kUnetW[k + 1]);
-  return o;
-}
 size_t unet_cat_elems(int nx, int ny) { return unet_cat_offset(nx, ny, kUnetLevels - 1); }
 
 // Layers of branch b (0 = coarsest); returns the layer count.
@@ -412,6 +403,9 @@ __global__ __launch_bounds__(256) void unet_up2(int Hc, int Wc, int C, const T* 
       St<T>::from((1.f - wy) * ((1.f - wx) * a + wx * b) + wy * ((1.f - wx) * e + wx * f));
 }
 
+// With net.train every layer output goes to its own buffer of the saved
+// activations (unet.h) instead of the two alternating maps, so that the
+// backward pass finds them.
 template <typename T>
 static hipError_t run_unet_t(const Device& dev, const NetShape& net, int nx, int ny, double dx,
                              const float* params, const Ws& w, hipStream_t s) {
@@ -420,9 +414,17 @@ static hipError_t run_unet_t(const Device& dev, const NetShape& net, int nx, int
   hipError_t err = pn_weights<T>(net, params, img, P, s);
   if (err != hipSuccess) return err;
   T* in = reinterpret_cast<T*>(w.cnn_in);
-  T* a0 = reinterpret_cast<T*>(w.cnn_act0);
-  T* a1 = reinterpret_cast<T*>(w.cnn_act1);
   T* cat = reinterpret_cast<T*>(w.cnn_cat);
+  const bool train = net.train && w.cnn_save;
+  const UnetSave SV = unet_save_layout(nx, ny);
+  T* save = reinterpret_cast<T*>(w.cnn_save);
+  T* act0 = reinterpret_cast<T*>(w.cnn_act0);
+  T* act1 = reinterpret_cast<T*>(w.cnn_act1);
+  auto c1 = [&](int l) { return train ? save + SV.c1[l] : act0; };
+  auto c2_bottom = [&]() { return train ? save + SV.c2_bottom : act1; };
+  auto pooled = [&](int l) { return train ? save + SV.pool[l] : act1; };
+  auto d1 = [&](int l) { return train ? save + SV.d1[l] : act0; };
+  auto d2 = [&](int l) { return train ? save + SV.d2[l] : act1; };
   hipLaunchKernelGGL((pn_input<T>), dim3((nx * ny + 255) / 256), dim3(256), 0, s, ny, nx, 1, nx,
                      w.d, w.cell, w.sc, (const float*)nullptr, 0, 0, in);
   err = hipGetLastError();
@@ -430,44 +432,46 @@ static hipError_t run_unet_t(const Device& dev, const NetShape& net, int nx, int
   int li = 0;
   const T* src = in;
   // encoder: the second layer of scale l writes the skip channels of the
-  // scale's concatenation buffer (the bottom scale writes a1)
+  // scale's concatenation buffer (the bottom scale its own map)
   for (int l = 0; l < kUnetLevels; ++l) {
     const int H = ny >> l, W = nx >> l;
-    err = pn_layer<T>(dev, P, li++, params, img, src, a0, kUnetW[l], H, W, s);
+    err = pn_layer<T>(dev, P, li++, params, img, src, c1(l), kUnetW[l], H, W, s);
     if (err != hipSuccess) return err;
     if (l + 1 < kUnetLevels) {
       T* cl = cat + unet_cat_offset(nx, ny, l);
       const int cs = kUnetW[l] + kUnetW[l + 1];
-      err = pn_layer<T>(dev, P, li++, params, img, a0, cl, cs, H, W, s);
+      err = pn_layer<T>(dev, P, li++, params, img, c1(l), cl, cs, H, W, s);
       if (err != hipSuccess) return err;
       const size_t nout = (size_t)(H / 2) * (W / 2) * kUnetW[l];
       hipLaunchKernelGGL((unet_pool<T>), dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, H / 2,
-                         W / 2, kUnetW[l], cl, cs, a1);
+                         W / 2, kUnetW[l], cl, cs, pooled(l));
       err = hipGetLastError();
       if (err != hipSuccess) return err;
+      src = pooled(l);
     } else {
-      err = pn_layer<T>(dev, P, li++, params, img, a0, a1, kUnetW[l], H, W, s);
+      err = pn_layer<T>(dev, P, li++, params, img, c1(l), c2_bottom(), kUnetW[l], H, W, s);
       if (err != hipSuccess) return err;
+      src = c2_bottom();
     }
-    src = a1;
   }
-  // decoder: upsample a1 into the upper channels of the concatenation
-  // buffer, two layers, result in a1
+  // decoder: upsample the coarser output into the upper channels of the
+  // concatenation buffer, then two layers
   for (int l = kUnetLevels - 2; l >= 0; --l) {
     const int H = ny >> l, W = nx >> l;
     T* cl = cat + unet_cat_offset(nx, ny, l);
     const int cs = kUnetW[l] + kUnetW[l + 1];
     const size_t nup = (size_t)H * W * kUnetW[l + 1];
     hipLaunchKernelGGL((unet_up2<T>), dim3((unsigned)((nup + 255) / 256)), dim3(256), 0, s, H / 2, W / 2,
-                       kUnetW[l + 1], a1, cl + kUnetW[l], cs);
+                       kUnetW[l + 1], src, cl + kUnetW[l], cs);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
-    err = pn_layer<T>(dev, P, li++, params, img, cl, a0, kUnetW[l], H, W, s);
+    err = pn_layer<T>(dev, P, li++, params, img, cl, d1(l), kUnetW[l], H, W, s);
     if (err != hipSuccess) return err;
-    err = pn_layer<T>(dev, P, li++, params, img, a0, a1, kUnetW[l], H, W, s);
+    err = pn_layer<T>(dev, P, li++, params, img, d1(l), d2(l), kUnetW[l], H, W, s);
     if (err != hipSuccess) return err;
+    src = d2(l);
   }
-  return pn_head_launch<T>(P, li, params, a1, nx * ny, w.cnn_y, 1, dx, w, s);
+  return pn_head_launch<T>(P, li, params, src, nx * ny, w.cnn_y, 1, dx, w, s);
 }
 
 hipError_t run_papernet(const Device& dev, const NetShape& net, const WsLayout& L, int nx, int ny,

@@ -1,4 +1,5 @@
-"""Solver-in-the-loop training of the multi-scale CNN on the GPU.
+"""Solver-in-the-loop training of the multi-scale CNN (or the paper's Unet,
+--arch unet, FP32) on the GPU.
 
 The physics-driven loss of Sec. 3.2: the divergence left in the corrected
 velocity, here after the CNN guess and K Jacobi sweeps (the hybrid's own
@@ -18,6 +19,9 @@ projection, CNN forward/backward and Adam.
 
 python -m paper_2109_09363_amd.train --n 128 --scales 4 --channels 64 \
     --precision bf16 --steps 400 --out weights.npy
+The paper's Unet (Sec. 3.1, Fig. 4):
+python -m paper_2109_09363_amd.train --arch unet --n 128 --precision fp32 \
+    --steps 600 --sweeps 16 --eval 8 --out unet.npy
 Fine-tuning at the benchmark resolution from existing weights, judged by the
 Jacobi sweeps the hybrid needs to reach a threshold on held-out plume states:
 python -m paper_2109_09363_amd.train --n 512 --init w.npy --random 0 \
@@ -130,16 +134,25 @@ def unrolled_backward(pr, smp: Sample, sweeps: int, n_unroll: int, alpha: float,
     return norm_long
 
 
+def initial_weights(arch: str, scales: int, channels: int, seed: int):
+    """Seeded random init with a small output layer (the first guesses stay
+    near zero)."""
+    if arch == "unet":
+        return scenes.random_paper_weights("unet", seed, out_scale=0.1)
+    return scenes.random_weights(scales, channels, seed, out_scale=0.1)
+
+
 def train(samples, n: int, scales: int, channels: int, precision: str = "fp32",
           steps: int = 200, batch: int = 4, lr: float = 1e-3, sweeps: int = 4,
           params0=None, seed: int = 0, device="cuda", log=print, log_every: int = 20,
-          alpha: float = 1.0, beta: float = 0.0):
+          alpha: float = 1.0, beta: float = 0.0, arch: str = "parallel"):
     """Adam on  alpha * short-term + beta * long-term  normalised divergence
     losses (beta = 0: the single-step loss); returns (params, loss history)."""
     dx = 1.0 / n
-    pr = api.Projector(n, n, dx, 1.0, 1.0, scales, channels, precision, device=device, train=True)
+    pr = api.Projector(n, n, dx, 1.0, 1.0, scales, channels, precision, device=device, train=True,
+                       arch=arch)
     if params0 is None:
-        params0 = scenes.random_weights(scales, channels, seed, out_scale=0.1)
+        params0 = initial_weights(arch, scales, channels, seed)
     params = _dev(params0, device=device)
     m = torch.zeros_like(params)
     v2 = torch.zeros_like(params)
@@ -210,9 +223,9 @@ def plume_states(n: int, n_scenes: int, steps: int, seed: int, device="cuda"):
 
 
 def evaluate(states, n: int, scales: int, channels: int, precision: str, params, thr: float = 1e-3,
-             device="cuda"):
+             device="cuda", arch: str = "parallel"):
     """Mean and max Jacobi sweeps the hybrid needs to reach mean|div| < thr."""
-    pr = api.Projector(n, n, 1.0 / n, 1.0, 1.0, scales, channels, precision, device=device)
+    pr = api.Projector(n, n, 1.0 / n, 1.0, 1.0, scales, channels, precision, device=device, arch=arch)
     pr.set_weights(_dev(params, device=device))
     p = torch.empty((n, n), dtype=torch.float32, device=device)
     its = []
@@ -244,6 +257,7 @@ def main():
     ap.add_argument("--alpha", type=float, default=1.0, help="weight of the short-term loss")
     ap.add_argument("--beta", type=float, default=0.0,
                     help="weight of the long-term loss (4 or 16 unrolled steps)")
+    ap.add_argument("--arch", default="parallel", choices=["parallel", "unet"])
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     params0 = None
@@ -251,15 +265,15 @@ def main():
         params0 = np.load(a.init, allow_pickle=False).astype(np.float32)
     held = plume_states(a.n, a.eval, a.eval_steps, seed=900000 + a.seed) if a.eval > 0 else []
     if held and params0 is not None:
-        m, mx = evaluate(held, a.n, a.scales, a.channels, a.precision, params0)
+        m, mx = evaluate(held, a.n, a.scales, a.channels, a.precision, params0, arch=a.arch)
         print(f"eval before: mean sweeps to 1e-3 {m:.1f} (max {mx}) on {len(held)} held-out states",
               flush=True)
     data = generate_dataset(a.n, n_scenes=a.scenes, steps=a.sim_steps, n_random=a.random, seed=a.seed)
     w, hist = train(data, a.n, a.scales, a.channels, a.precision, steps=a.steps, batch=a.batch,
                     lr=a.lr, sweeps=a.sweeps, seed=a.seed, params0=params0, alpha=a.alpha,
-                    beta=a.beta)
+                    beta=a.beta, arch=a.arch)
     if held:
-        m, mx = evaluate(held, a.n, a.scales, a.channels, a.precision, w)
+        m, mx = evaluate(held, a.n, a.scales, a.channels, a.precision, w, arch=a.arch)
         print(f"eval after: mean sweeps to 1e-3 {m:.1f} (max {mx}) on {len(held)} held-out states",
               flush=True)
     if a.out:

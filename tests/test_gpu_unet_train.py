@@ -1,0 +1,165 @@
+"""Training of the paper's Unet (Sec. 3.1, Fig. 4) with the solver in the
+loop (Sec. 3.2) on the GPU: the hand-written adjoint (max-pooling, upsampling
+and concatenation adjoints included) against the FP64 oracle gradient and
+against central differences of the GPU's own loss, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import scenes
+import paper_2109_09363_amd as hp
+from oracle import unet_adjoint as UA
+from tests.gpu_util import to_dev, f32, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+class UnetRun:
+    def __init__(self, sc):
+        self.pr = hp.Projector(sc.nx, sc.ny, sc.dx, 1.0, 1.0, precision="fp32", arch="unet", train=True)
+        self.tf = to_dev(sc.flags, torch.uint8)
+        self.pr.plan(self.tf)
+
+    def __call__(self, u, v, w, K, grads=True):
+        pr = self.pr
+        tw = to_dev(w)
+        pr.set_weights(tw)
+        tu, tv = to_dev(u), to_dev(v)
+        p = torch.empty((pr.ny, pr.nx), dtype=torch.float32, device="cuda")
+        pr.project_async(tu, tv, self.tf, p, 0.0, method="hybrid" if K > 0 else "cnn", fixed_iters=K)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        du = torch.empty((pr.ny, pr.nx + 1), dtype=torch.float32, device="cuda") if grads else None
+        dv = torch.empty((pr.ny + 1, pr.nx), dtype=torch.float32, device="cuda") if grads else None
+        dp = torch.empty(pr.param_count, dtype=torch.float32, device="cuda") if grads else None
+        pr.backward_async(K, 1.0, 1.0, du=du, dv=dv, dparams=dp, loss=loss)
+        torch.cuda.synchronize()
+        out = dict(loss=float(loss.item()))
+        if grads:
+            out.update(du=du.cpu().numpy().astype(np.float64), dv=dv.cpu().numpy().astype(np.float64),
+                       dp=dp.cpu().numpy().astype(np.float64))
+        return out
+
+
+def case(n, seed, nobs):
+    sc = scenes.plume_scene(n, seed=seed, n_obstacles=nobs)
+    u, v = scenes.random_faces(n, n, seed, kind="mixed")
+    w = f32(scenes.random_paper_weights("unet", seed))
+    return sc, f32(u), f32(v), w
+
+
+def linear_regime(sc, u, v, w, margin=0.05):
+    """Raise every hidden layer's biases, layer by layer on the oracle's own
+    forward pass, so that each ReLU unit's pre-activation exceeds margin
+    times the layer's largest: no unit then sits within FP32 rounding of its
+    kink and the network is smooth except for the pooling decisions."""
+    from oracle import grid as G, papernets as PN
+    P = G.plan(sc.flags)
+    d = G.divergence(P, *G.enforce_bc(P, u, v), sc.dx)
+    w = w.astype(np.float64).copy()
+    offs, o = [], 0
+    for (k, ci, co, _r) in PN.unet_layers():
+        offs.append(o)
+        o += k * k * ci * co + co
+    for li, (k, ci, co, relu) in enumerate(PN.unet_layers()):
+        if not relu:
+            continue
+        _phi, Fw = UA.unet_forward(P, d, sc.dx, w)
+        pre = Fw["outs"][li]  # post-ReLU; recompute the pre-activation
+        W = w[offs[li]:offs[li] + co * k * k * ci].reshape(co, k, k, ci)
+        b = w[offs[li] + co * k * k * ci:offs[li] + co * k * k * ci + co]
+        z = PN.conv_replicate(Fw["ins"][li], W, b)
+        low = z.reshape(-1, co).min(axis=0)
+        top = np.abs(z).max()
+        w[offs[li] + co * k * k * ci:offs[li] + co * k * k * ci + co] += np.maximum(margin * top - low, 0.0)
+    return f32(w)
+
+
+@pytest.mark.parametrize("n,K,seed,nobs,linear", [(32, 0, 0, 1, False), (64, 6, 1, 2, False),
+                                                  (128, 4, 2, 3, False), (128, 4, 2, 3, True)])
+def test_unet_backward_matches_oracle(n, K, seed, nobs, linear):
+    """Random weights: a few units within FP32 rounding of a ReLU kink or a
+    pooling tie take the other branch on the GPU (bar 1e-3); in the linear
+    regime (every unit active) the bar is 1e-4."""
+    say("unet adjoint", n, K, "linear" if linear else "")
+    sc, u, v, w = case(n, seed, nobs)
+    if linear:
+        w = linear_regime(sc, u, v, w)
+    g = UnetRun(sc)(u, v, w, K)
+    loss, gu, gv, gp = UA.loss_and_grad(sc.flags, u, v, sc.dx, w, K)
+    ep, eu, ev = rel_l2(g["dp"], gp), rel_l2(g["du"], gu), rel_l2(g["dv"], gv)
+    say(f"  loss {g['loss']:.8e} vs {loss:.8e}; rel L2 dparams {ep:.2e} du {eu:.2e} dv {ev:.2e}")
+    assert g["loss"] == pytest.approx(loss, rel=1e-5)
+    bar = 1e-4 if linear else 1e-3
+    assert ep <= bar and eu <= bar and ev <= bar
+
+
+def test_unet_gradient_matches_its_own_central_differences():
+    """The GPU's gradient of the output layer (where the loss is a smooth
+    quadratic, no ReLU or pooling decision in between) against central
+    differences of the GPU's FP64-reduced loss, per weight and for the
+    bias."""
+    sc, u, v, w = case(32, 3, 1)
+    run = UnetRun(sc)
+    g = run(u, v, w, 3)
+    for i in list(range(w.size - 17, w.size - 13)) + [w.size - 1]:
+        # the loss is quadratic in these parameters, so a large step leaves
+        # no truncation error and keeps the FP32 noise of the loss small
+        # against the difference; the perturbed values are FP32 numbers
+        h = 2.0 ** -5
+        wp, wm = f32(w.copy()), f32(w.copy())
+        wp[i] = f32(w[i] + h)
+        wm[i] = f32(w[i] - h)
+        h = 0.5 * (wp[i] - wm[i])
+        fd = (run(u, v, wp, 3, grads=False)["loss"] - run(u, v, wm, 3, grads=False)["loss"]) / (2 * h)
+        say("  param", i, "fd", fd, "adjoint", g["dp"][i])
+        assert g["dp"][i] == pytest.approx(fd, rel=1e-4, abs=1e-7 * abs(g["loss"]))
+
+
+def test_unet_training_reduces_the_loss():
+    """A few Adam steps on one sample (the training loop of train.py uses
+    the same calls) lower the normalised loss."""
+    sc, u, v, w = case(64, 5, 2)
+    run = UnetRun(sc)
+    pr = run.pr
+    tw = to_dev(w * np.where(np.arange(w.size) >= w.size - 17, 0.05, 1.0))
+    m, vv = torch.zeros_like(tw), torch.zeros_like(tw)
+    tu, tv = to_dev(u), to_dev(v)
+    losses = []
+    for step in range(1, 31):
+        pr.set_weights(tw)
+        p = torch.empty((pr.ny, pr.nx), dtype=torch.float32, device="cuda")
+        uu, vv2 = tu.clone(), tv.clone()
+        pr.project_async(uu, vv2, run.tf, p, 0.0, method="hybrid", fixed_iters=8)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dp = torch.empty_like(tw)
+        pr.backward_async(8, 1.0, 1.0, dparams=dp, loss=loss)
+        hp.adam_async(tw, dp, m, vv, step, lr=1e-3)
+        torch.cuda.synchronize()
+        losses.append(float(loss.item()))
+    say("  losses", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_unet_training_gain():
+    """Solver-in-the-loop training of the Unet on plume states and
+    divergence sources (train.py, FP32, 64^2): on held-out plume states the
+    trained network's guess leaves less divergence than no guess, and the
+    hybrid needs fewer sweeps than plain Jacobi."""
+    from paper_2109_09363_amd import train as TR
+    n = 64
+    data = TR.generate_dataset(n, n_scenes=6, steps=20, keep_every=2, n_random=24, seed=5, log=say)
+    w, hist = TR.train(data, n, 0, 0, "fp32", steps=300, batch=4, lr=1e-3, sweeps=8, seed=2,
+                       log=say, log_every=50, arch="unet")
+    say("loss history", hist)
+    assert hist[-1][1] < 0.5 * hist[0][1]
+    held = TR.plume_states(n, 6, 30, seed=777)
+    zero = w.copy()
+    zero[-17:] = 0.0  # output layer 0: the guess is 0, plain Jacobi
+    it_t, mx_t = TR.evaluate(held, n, 0, 0, "fp32", w, arch="unet")
+    it_z, mx_z = TR.evaluate(held, n, 0, 0, "fp32", zero, arch="unet")
+    say("held-out mean sweeps to 1e-3: trained Unet", it_t, "zero output", it_z)
+    assert it_t < it_z
