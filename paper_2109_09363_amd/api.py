@@ -392,7 +392,8 @@ def project(u, v, rho, flags, threshold: float, *, dx: float, dt: float = 1.0, r
     """project(u, v, rho, flags, threshold) -> (p, u, v, iters).
 
     u, v are corrected in place (and returned); p is a new tensor.  A context
-    and workspace are cached per (shape, network) and re-planned per call."""
+    and workspace are cached per (shape, network); the flags are planned
+    again only when they differ from the last planned ones."""
     ny, nx = flags.shape
     key = (nx, ny, scales, channels, precision, u.device)
     pr = _CACHE.get(key)
@@ -402,7 +403,10 @@ def project(u, v, rho, flags, threshold: float, *, dx: float, dt: float = 1.0, r
     pr.grid.dx, pr.grid.dt, pr.grid.rho0 = float(dx), float(dt), float(rho0)
     if params is not None:
         pr.set_weights(params)
-    pr.plan(flags)
+    planned = getattr(pr, "_planned_flags", None)
+    if planned is None or not torch.equal(planned, flags):
+        pr.plan(flags)
+        pr._planned_flags = flags.clone()
     p = torch.empty((ny, nx), dtype=torch.float32, device=u.device)
     pr.project_async(u, v, flags, p, threshold, method=method, rho=rho, **opts)
     res = pr.result()

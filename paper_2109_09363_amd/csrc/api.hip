@@ -52,7 +52,7 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
   L.blockpart = take(sizeof(double) * nbp);
   L.blockpart_n = nbp;
   L.cell = take(n);
-  L.reach = take(n);
+  L.reach = take(plan_bytes(nx, ny));
   L.d = take(4 * n);
   L.phi = take(4 * n);
   L.phi_acc = take(4 * n);
@@ -115,7 +115,7 @@ Ws ws_view(void* base, const WsLayout& L) {
   w.blockpart = (double*)(b + L.blockpart);
   w.blockpart_n = L.blockpart_n;
   w.cell = (uint8_t*)(b + L.cell);
-  w.reach = (uint8_t*)(b + L.reach);
+  w.reach = (uint64_t*)(b + L.reach);
   w.d = (float*)(b + L.d);
   w.phi = (float*)(b + L.phi);
   w.phi_acc = (float*)(b + L.phi_acc);

@@ -83,7 +83,7 @@ struct Ws {
   double* partial;    // 6 x kMaxCoopBlocks cooperative partials
   Scalars* sc;
   unsigned* sync;     // grid barrier: counter at [0], generation flag at [32]
-  uint8_t* reach;
+  uint64_t* reach;   // planner bit words: fluid, then linked (plan_bytes)
   float* pcg;         // PCG scratch
   float* adv;         // advection temporaries: 2 x (cells + u faces + v faces)
   void* cnn_in; void* cnn_act0; void* cnn_act1; float* cnn_y; float* cnn_t; void* cnn_w;
@@ -107,6 +107,7 @@ struct Device {
 };
 
 // ---- launch wrappers (return hipSuccess or the first error) ----
+size_t plan_bytes(int nx, int ny);
 hipError_t run_plan(const Device& dev, int nx, int ny, const uint8_t* flags, const Ws& w,
                     hipStream_t s);
 hipError_t run_div(int nx, int ny, double dx, float* u, float* v, const Ws& w,

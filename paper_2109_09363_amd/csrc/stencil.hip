@@ -9,17 +9,57 @@
 namespace hyp {
 
 // ---------------------------------------------------------------------------
-// Planner.  State per cell in `reach`: 0 solid/outside, 1 fluid not yet
-// linked to the open top, 2 fluid linked.  Seeds are the fluid cells of the
-// top row; a cooperative flood fill over 32x32 tiles propagates in LDS until
-// no work-group changes a cell in a whole round.
+// Planner: the fluid cells linked to the open top by 4-connected fluid
+// paths (the others are enclosed pockets and become solid), neighbour bits
+// and the fluid count.
+//
+// The sets are bit words: for row j and tile column t (64 cells), word
+// j * ntx + t of `fbits` holds the fluid cells (static) and of `rbits` the
+// cells linked so far, seeded with the fluid cells of the top row.  A
+// cooperative flood fill over 64x64 tiles, one wave per tile (lane l owns
+// row y0 + l), repeats rounds until no tile links a cell in a whole round.
+// In a row, every run of fluid cells that holds a linked cell is linked
+// whole at once: adding R to F sends a carry from each linked bit up through
+// the rest of its run (the bits the add flips inside F), and the same on the
+// bit-reversed words spreads it down.  Columns likewise, on the transposed
+// tile; rows and columns alternate until neither adds a cell, so a path
+// crosses a tile in as many alternations as it has turns.
 // ---------------------------------------------------------------------------
-constexpr int PT = 32;
-constexpr int PE = PT + 2;
+constexpr int PT = 64;
 
-__global__ __launch_bounds__(256) void plan_init(int nx, int ny, const uint8_t* __restrict__ flags,
-                                                 uint8_t* __restrict__ reach, Scalars* sc,
-                                                 unsigned* sync) {
+__device__ __forceinline__ uint64_t run_fill_up(uint64_t r, uint64_t f) {
+  return (((f + r) ^ f) & f) | r;
+}
+// every run of f (maximal set of adjacent bits) that meets r, r a subset of f
+__device__ __forceinline__ uint64_t run_fill(uint64_t r, uint64_t f) {
+  const uint64_t up = run_fill_up(r, f);
+  const uint64_t dn = __builtin_bitreverse64(
+      run_fill_up(__builtin_bitreverse64(r), __builtin_bitreverse64(f)));
+  return up | dn;
+}
+// 64x64 bit transpose across the wave (bit c of lane r -> bit r of lane c):
+// at stage k, lanes l and l ^ k swap the k-wide bit blocks that sit where
+// bit k of the lane and of the bit index differ
+__device__ __forceinline__ uint64_t transpose64(uint64_t m, int lane) {
+  constexpr uint64_t keep[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                                0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int k = 32 >> s;
+    const uint64_t y = __shfl_xor(m, k);
+    m = (lane & k) ? ((m & ~keep[s]) | ((y >> k) & keep[s])) : ((m & keep[s]) | ((y << k) & ~keep[s]));
+  }
+  return m;
+}
+
+__host__ __device__ inline size_t plan_words(int nx, int ny) {
+  return (size_t)ny * ((nx + PT - 1) / PT);
+}
+
+// one thread per word: the fluid bits of 64 cells of a row, and the seeds
+__global__ __launch_bounds__(256) void plan_init(int nx, int ny, int ntx, const uint8_t* __restrict__ flags,
+                                                 uint64_t* __restrict__ fbits, uint64_t* __restrict__ rbits,
+                                                 Scalars* sc, unsigned* sync) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   sync_clear(sync, c);
   if (c == 0) {
@@ -27,86 +67,90 @@ __global__ __launch_bounds__(256) void plan_init(int nx, int ny, const uint8_t* 
     sc->nF = 0;
     sc->plan_rounds = 0;
   }
-  if (c >= nx * ny) return;
-  const int j = c / nx;
-  const bool solid = flags[c] & 1;
-  reach[c] = solid ? 0 : (j == ny - 1 ? 2 : 1);
+  if (c >= ny * ntx) return;
+  const int j = c / ntx, x0 = (c % ntx) * PT;
+  const int w = min(PT, nx - x0);
+  const uint8_t* row = flags + (size_t)j * nx + x0;
+  uint64_t f = 0;
+  for (int i = 0; i < w; ++i) f |= (uint64_t)((row[i] & 1) == 0) << i;
+  fbits[c] = f;
+  rbits[c] = j == ny - 1 ? f : 0;
 }
 
-__global__ __launch_bounds__(256) void plan_flood(int nx, int ny, uint8_t* reach, double* partial,
-                                                  Scalars* sc, unsigned* sync, int ntx, int nty,
-                                                  unsigned max_rounds) {
-  __shared__ uint8_t s[PE * PE];
-  __shared__ int changed;
+// One tile: its linked words, seeds across its four borders (the adjacent
+// tiles' edge bits, the rows below and above), closure under row and column
+// runs, the grown words stored back; returns how many cells this lane linked.
+__device__ __forceinline__ int flood_tile(int ny, int ntx, int nty, const uint64_t* __restrict__ fbits,
+                                          uint64_t* rbits, int t, int lane) {
+  const int tx = t % ntx, y0 = (t / ntx) * PT;
+  const int gy = y0 + lane;
+  const bool row_in = gy < ny;
+  const size_t wi = (size_t)gy * ntx + tx;
+  const uint64_t F = row_in ? fbits[wi] : 0;
+  const uint64_t R0 = row_in ? ld_agent(rbits + wi) : 0;
+  uint64_t R = R0;
+  if (row_in && tx > 0) R |= F & (ld_agent(rbits + wi - 1) >> 63);
+  if (row_in && tx + 1 < ntx) R |= F & (ld_agent(rbits + wi + 1) << 63);
+  if (lane == 0 && y0 > 0) R |= F & ld_agent(rbits + (size_t)(y0 - 1) * ntx + tx);
+  if (lane == PT - 1 && y0 + PT < ny) R |= F & ld_agent(rbits + (size_t)(y0 + PT) * ntx + tx);
+  const uint64_t Fc = transpose64(F, lane);
+  for (int it = 0; it < PT * PT; ++it) {  // each alternation links >= 1 cell or ends
+    const uint64_t C = run_fill(transpose64(run_fill(R, F), lane), Fc);
+    const uint64_t R2 = transpose64(C, lane);
+    const bool grew = __ballot(R2 != R) != 0;
+    R = R2;
+    if (!grew) break;
+  }
+  if (R != R0) st_agent(rbits + wi, R);
+  return __builtin_popcountll(R & ~R0);
+}
+
+__global__ __launch_bounds__(256) void plan_flood(int ny, int ntx, int nty, const uint64_t* fbits,
+                                                  uint64_t* rbits, double* partial, Scalars* sc,
+                                                  unsigned* sync, unsigned max_rounds) {
   __shared__ double red[4];
   const int G = gridDim.x;
   const int ntiles = ntx * nty;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned round = 0;
   for (;;) {
     double my_changes = 0.0;
-    for (int t = blockIdx.x; t < ntiles; t += G) {
-      const int x0 = (t % ntx) * PT, y0 = (t / ntx) * PT;
-      for (int c = threadIdx.x; c < PE * PE; c += blockDim.x) {
-        const int gx = x0 - 1 + c % PE, gy = y0 - 1 + c / PE;
-        uint8_t st = 0;
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) st = ld_agent(reach + gy * nx + gx);
-        s[c] = st;
-      }
-      __syncthreads();
-      for (int pass = 0; pass < PT * PT; ++pass) {  // each pass marks >= 1 cell or ends
-        if (threadIdx.x == 0) changed = 0;
-        __syncthreads();
-        for (int c = threadIdx.x; c < PT * PT; c += blockDim.x) {
-          const int idx = (1 + c / PT) * PE + 1 + c % PT;
-          if (s[idx] == 1 && (s[idx - 1] == 2 || s[idx + 1] == 2 || s[idx - PE] == 2 ||
-                              s[idx + PE] == 2)) {
-            s[idx] = 2;
-            changed = 1;
-            my_changes += 1.0;
-          }
-        }
-        __syncthreads();
-        const bool any = changed != 0;
-        __syncthreads();
-        if (!any) break;
-      }
-      for (int c = threadIdx.x; c < PT * PT; c += blockDim.x) {
-        const int gx = x0 + c % PT, gy = y0 + c / PT;
-        if (gx < nx && gy < ny) {
-          const uint8_t nv = s[(1 + c / PT) * PE + 1 + c % PT];
-          if (nv != ld_agent(reach + gy * nx + gx)) st_agent(reach + gy * nx + gx, nv);
-        }
-      }
-      __syncthreads();
-    }
+    for (int t = blockIdx.x * 4 + wave; t < ntiles; t += 4 * G)
+      my_changes += flood_tile(ny, ntx, nty, fbits, rbits, t, lane);
     const double tot_local = block_sum(my_changes, red);
     double* part = partial + (round & 1) * kMaxCoopBlocks;
     if (threadIdx.x == 0) st_agent(part + blockIdx.x, tot_local);
     ++round;
-    grid_barrier(sync, round, (unsigned)G);
+    if (!grid_barrier_bounded(sync, round, (unsigned)G)) {
+      if (threadIdx.x == 0) sc->plan_rounds = -1;  // a work-group never arrived
+      return;
+    }
     const double tot = sum_partials(part, G, red);
     if (tot == 0.0 || round >= max_rounds) break;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->plan_rounds = (int)round;
 }
 
-__global__ __launch_bounds__(256) void plan_finalize(int nx, int ny, const uint8_t* __restrict__ flags,
-                                                     const uint8_t* __restrict__ reach,
+__global__ __launch_bounds__(256) void plan_finalize(int nx, int ny, int ntx, const uint8_t* __restrict__ flags,
+                                                     const uint64_t* __restrict__ rbits,
                                                      uint8_t* __restrict__ cell, Scalars* sc) {
   __shared__ double red[4];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  auto linked = [&](int i, int j) {
+    return (rbits[(size_t)j * ntx + i / PT] >> (i % PT)) & 1ull;
+  };
+  // grid-stride over a bounded grid: one count per work-group
   double fl_count = 0.0;
-  if (c < nx * ny) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nx * ny; c += gridDim.x * blockDim.x) {
     const int i = c % nx, j = c / nx;
-    const bool fl = reach[c] == 2;
+    const bool fl = linked(i, j);
     uint8_t out = fl ? 0 : C_SOLID;
     if (fl) {
-      if (i + 1 < nx && reach[c + 1] == 2) out |= C_E;
-      if (i > 0 && reach[c - 1] == 2) out |= C_W;
-      if (j + 1 >= ny || reach[c + nx] == 2) out |= C_N;
-      if (j > 0 && reach[c - nx] == 2) out |= C_S;
+      if (i + 1 < nx && linked(i + 1, j)) out |= C_E;
+      if (i > 0 && linked(i - 1, j)) out |= C_W;
+      if (j + 1 >= ny || linked(i, j + 1)) out |= C_N;
+      if (j > 0 && linked(i, j - 1)) out |= C_S;
       if (j == 0 && (flags[c] & 2)) out |= C_INFLOW;
-      fl_count = 1.0;
+      fl_count += 1.0;
     }
     cell[c] = out;
   }
@@ -114,15 +158,20 @@ __global__ __launch_bounds__(256) void plan_finalize(int nx, int ny, const uint8
   if (threadIdx.x == 0 && n > 0.0) atomicAdd(&sc->nF, (int)n);
 }
 
+size_t plan_bytes(int nx, int ny) { return 2 * sizeof(uint64_t) * plan_words(nx, ny); }
+
 hipError_t run_plan(const Device& dev, int nx, int ny, const uint8_t* flags, const Ws& w,
                     hipStream_t s) {
   const int n = nx * ny;
-  const int nb = (n + 255) / 256;
-  plan_init<<<nb, 256, 0, s>>>(nx, ny, flags, w.reach, w.sc, w.sync);
+  const int ntx = (nx + PT - 1) / PT, nty = (ny + PT - 1) / PT;
+  const size_t words = plan_words(nx, ny);
+  uint64_t* fbits = w.reach;
+  uint64_t* rbits = w.reach + words;
+  const int nbw = (int)((words > (size_t)kSyncSlots ? words : (size_t)kSyncSlots) + 255) / 256;
+  plan_init<<<nbw, 256, 0, s>>>(nx, ny, ntx, flags, fbits, rbits, w.sc, w.sync);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int ntx = (nx + PT - 1) / PT, nty = (ny + PT - 1) / PT;
-  int G = ntx * nty;
+  int G = (ntx * nty + 3) / 4;  // four tiles (waves) per work-group
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, plan_flood, 256, 0);
   if (e != hipSuccess) return e;
@@ -130,16 +179,15 @@ hipError_t run_plan(const Device& dev, int nx, int ny, const uint8_t* flags, con
   if (G > cap) G = cap;
   if (G > kMaxCoopBlocks) G = kMaxCoopBlocks;
   unsigned max_rounds = (unsigned)n + 2u;
-  int nx_ = nx, ny_ = ny;
-  uint8_t* reach = w.reach;
+  int ny_ = ny, ntx_ = ntx, nty_ = nty;
+  const uint64_t* fb = fbits;
   double* partial = w.partial;
   Scalars* sc = w.sc;
   unsigned* sync = w.sync;
-  int ntx_ = ntx, nty_ = nty;
-  void* args[] = {&nx_, &ny_, &reach, &partial, &sc, &sync, &ntx_, &nty_, &max_rounds};
+  void* args[] = {&ny_, &ntx_, &nty_, &fb, &rbits, &partial, &sc, &sync, &max_rounds};
   e = hipLaunchCooperativeKernel((const void*)plan_flood, dim3(G), dim3(256), args, 0, s);
   if (e != hipSuccess) return e;
-  plan_finalize<<<nb, 256, 0, s>>>(nx, ny, flags, w.reach, w.cell, w.sc);
+  plan_finalize<<<min((n + 255) / 256, 2048), 256, 0, s>>>(nx, ny, ntx, flags, rbits, w.cell, w.sc);
   return hipGetLastError();
 }
 

@@ -99,7 +99,7 @@ class Plume:
 
     def run(self, method, thr, steps, pr=None):
         """`steps` time steps from the snapshot; per-step results and the
-        event-timed total."""
+        event-timed total.  The first step's pressure is kept in first_p."""
         self.restore()
         pr = pr or self.pr
         rows = []
@@ -112,7 +112,47 @@ class Plume:
             torch.cuda.synchronize()
             t_ms += a.elapsed_time(b)
             rows.append(pr.result())
+            if s == self.warmup:
+                self.first_p = self.p.cpu().numpy().copy()
+                self.first_dt = rows[-1].dt
         return rows, t_ms
+
+    def first_inputs(self):
+        """What the first timed step's projection receives: the snapshot
+        advected once (deterministic, the same for every method), with that
+        step's dt."""
+        self.restore()
+        rho, u, v = self.rho.clone(), self.u.clone(), self.v.clone()
+        self.pr.advect_async(rho, u, v, self.xi[self.warmup], g=self.sc.g, drho=self.sc.drho,
+                             u_in=self.sc.u_in, cfl=0.5)
+        torch.cuda.synchronize()
+        return dict(flags=self.sc.flags, u=u.cpu().numpy(), v=v.cpu().numpy(), dx=self.sc.dx,
+                    dt=self.first_dt, rho0=self.sc.rho0)
+
+
+class Saver:
+    """--save DIR: per plume, the first timed step's projection inputs and
+    every method's returned pressure for that step (float32 .npz), so that
+    the errors against the FP64 oracle can be computed afterwards by a
+    separate process (the library never runs the oracle)."""
+
+    def __init__(self, root, what):
+        self.dir = os.path.join(root, what) if root else None
+        if self.dir:
+            os.makedirs(self.dir, exist_ok=True)
+
+    def save(self, name, inputs, cases):
+        if not self.dir:
+            return
+        arrays = {"flags": inputs["flags"], "u": inputs["u"], "v": inputs["v"],
+                  "scalars": np.array([inputs["dx"], inputs["dt"], inputs["rho0"]])}
+        meta = []
+        for i, c in enumerate(cases):
+            arrays[f"p{i}"] = c.pop("p").astype(np.float32)
+            meta.append(c)
+        np.savez(os.path.join(self.dir, name + ".npz"), **arrays)
+        with open(os.path.join(self.dir, name + ".json"), "w") as f:
+            json.dump(meta, f)
 
 
 def summarize(rows, t_ms, steps):
@@ -130,8 +170,10 @@ def load_trained(dev):
 
 def cmd_thresholds(a, dev):
     w = load_trained(dev)
+    saver = Saver(a.save, "thresholds")
     for seed in a.seeds:
         pl = Plume(512, seed, a.warmup, dev, w)
+        cases = []
         pr32 = hp.Projector(512, 512, pl.sc.dx, 1.0, pl.sc.rho0, S4, C64, "fp32", device=dev)
         pr32.set_weights(w)
         pr32.plan(pl.flags)
@@ -152,31 +194,45 @@ def cmd_thresholds(a, dev):
                    "steps": a.steps, "cnn_guess_bf16_vs_fp32_rel_l2": d_guess}
             rows, t = pl.run("hybrid", thr, a.steps)
             out["hybrid_bf16"] = summarize(rows, t, a.steps)
+            cases.append(dict(method="hybrid", precision="bf16", threshold=thr, iters=int(rows[0].iters),
+                              check_every=pl.check_every, p=pl.first_p))
             p_bf = pl.p.clone()
             rows, t = pl.run("hybrid", thr, a.steps, pr32)
             out["hybrid_fp32"] = summarize(rows, t, a.steps)
+            cases.append(dict(method="hybrid", precision="fp32", threshold=thr, iters=int(rows[0].iters),
+                              check_every=pl.check_every, p=pl.first_p))
             out["final_p_bf16_vs_fp32_rel_l2"] = float(torch.linalg.norm(p_bf - pl.p) / torch.linalg.norm(pl.p))
             rows, t = pl.run("pcg", thr, a.steps)
             out["pcg"] = summarize(rows, t, a.steps)
+            cases.append(dict(method="pcg", precision="fp32", threshold=thr, iters=int(rows[0].iters),
+                              check_every=1, p=pl.first_p))
             out["hybrid_over_pcg"] = round(out["pcg"]["ms_per_step"] / out["hybrid_bf16"]["ms_per_step"], 4)
             emit(out)
+        saver.save(f"seed{seed}", pl.first_inputs(), cases)
 
 
 def cmd_gain(a, dev):
     nets = {"trained": load_trained(dev),
             "zero": torch.zeros(scenes.cnn_param_count(S4, C64), dtype=torch.float32, device=dev),
             "random": torch.from_numpy(scenes.random_weights(S4, C64, 7).astype(np.float32)).to(dev)}
+    saver = Saver(a.save, "gain")
     for seed in a.seeds:
         pl = Plume(512, seed, a.warmup, dev, nets["trained"])
         out = {"what": "gain", "seed": seed, "threshold": 1e-3, "steps": a.steps, "n_obstacles": len(pl.sc.disks)}
+        cases = []
         for name, w in nets.items():
             pl.pr.set_weights(w)
             rows, t = pl.run("hybrid", 1e-3, a.steps)
             out["hybrid_" + name] = summarize(rows, t, a.steps)
+            cases.append(dict(method="hybrid", precision="bf16", weights=name, threshold=1e-3,
+                              iters=int(rows[0].iters), check_every=pl.check_every, p=pl.first_p))
         pl.pr.set_weights(nets["trained"])
         rows, t = pl.run("pcg", 1e-3, a.steps)
         out["pcg"] = summarize(rows, t, a.steps)
+        cases.append(dict(method="pcg", precision="fp32", threshold=1e-3, iters=int(rows[0].iters),
+                          check_every=1, p=pl.first_p))
         emit(out)
+        saver.save(f"seed{seed}", pl.first_inputs(), cases)
 
 
 def batch_instances(dev, n_inst=128, seed=0):
@@ -246,6 +302,9 @@ def cmd_batch(a, dev):
 
     out = {"what": "batch", "instances": len(inst), "cells": cells, "threshold": 1e-3,
            "sides": sorted(set(d["nx"] for d in inst)), "variable_density": bool(a.var)}
+    saver = Saver(a.save, "batch")
+    sample = list(range(0, len(inst), 8))  # the instances whose results are saved
+    cases = {i: [] for i in sample}
     for method in ("hybrid", "jacobi"):
         b = hp.Batch(inst, threshold=1e-3, method=method, params=w, scales=S4, channels=C64,
                      precision="bf16", max_iters=400000, variable_density=bool(a.var))
@@ -254,6 +313,10 @@ def cmd_batch(a, dev):
         torch.cuda.synchronize()
         ms_proj = timed(b.project_async, 3, snap_proj)
         res = b.results()
+        for i in sample:
+            cases[i].append(dict(method=method, precision="bf16", weights="trained" if method == "hybrid"
+                                 else "none", threshold=1e-3, iters=int(res[i].iters), check_every=8,
+                                 variable_density=bool(a.var), p=inst[i]["p"].cpu().numpy().copy()))
         it = np.array([r.iters for r in res], dtype=np.float64)
         row = {"ms_per_projection_of_all": round(ms_proj, 3),
                "mean_sweeps": round(float(it.mean()), 1), "max_sweeps": int(it.max()),
@@ -273,6 +336,12 @@ def cmd_batch(a, dev):
         out[method] = row
         del b
     emit(out)
+    for i in sample:
+        d, (r, u, v, _p) = inst[i], snap_proj[i]
+        saver.save(f"inst{i:03d}", dict(flags=d["scene"].flags, u=u.cpu().numpy(), v=v.cpu().numpy(),
+                                        dx=d["dx"], dt=d["dt"], rho0=d["rho0"]), cases[i])
+        if saver.dir:
+            np.save(os.path.join(saver.dir, f"inst{i:03d}_rho.npy"), r.cpu().numpy())
 
 
 def cmd_dram(a, dev):
@@ -419,6 +488,9 @@ def main():
     ap.add_argument("--sweeps", type=int, default=800)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--var", action="store_true", help="batch: variable-density operator")
+    ap.add_argument("--save", default=None,
+                    help="thresholds, gain, batch: write the first step's projection inputs and "
+                         "pressures under this folder (for the error against the FP64 oracle)")
     a = ap.parse_args()
     if a.seeds is None:
         a.seeds = list(range(100, 108)) if a.what in ("validate", "checks") else [0, 1, 2, 3, 4]

@@ -48,6 +48,45 @@ def test_plan_and_faces_bit_exact(nx, ny, seed):
     assert P.nF < nx * ny  # the masks do contain solids
 
 
+def serpentine_mask(nx, ny, seed):
+    """Walls every 3 rows, each open at alternating ends, and random solid
+    cells in one row of each corridor: the fluid reachable from the open
+    top is one corridor that turns at every wall and at every obstacle and
+    crosses every tile many times."""
+    rng = np.random.default_rng(seed)
+    flags = np.zeros((ny, nx), np.uint8)
+    for k, j in enumerate(range(ny - 3, 0, -3)):
+        flags[j, :] = 1
+        flags[j - 1, :] = rng.random(nx) < 0.2  # obstacles in one of the corridor's two rows
+        if k % 2 == 0:
+            flags[j, nx - 2:] = 0
+        else:
+            flags[j, :2] = 0
+    flags[0, nx // 3: 2 * nx // 3] |= 2
+    return flags
+
+
+@pytest.mark.parametrize("nx,ny,seed,kind", [(300, 260, 4, "pocket"), (1024, 1024, 5, "pocket"),
+                                             (200, 190, 6, "serpentine"), (700, 129, 7, "serpentine")])
+def test_plan_large_masks(nx, ny, seed, kind):
+    """The planner's flood fill over many 64x64 tiles with ragged edges:
+    random pockets (most fluid cells sealed off) and a corridor that snakes
+    down the whole grid (the fill crosses tile borders hundreds of times);
+    the fluid count and every face mask against the oracle's plan."""
+    say("plan", kind, nx, ny, seed)
+    flags = pocket_mask(nx, ny, seed, p=0.4) if kind == "pocket" else serpentine_mask(nx, ny, seed)
+    u, v = scenes.random_faces(nx, ny, seed, kind="white")
+    u, v = f32(u), f32(v)
+    g = gpu_project(flags, u, v, 1.0 / nx, thr=0.0, method="jacobi", fixed_iters=1)
+    P = G.plan(flags)
+    say("  fluid", P.nF, "of", nx * ny)
+    assert g["res"].n_fluid == P.nF
+    ou, ov = G.enforce_bc(P, u, v)
+    assert np.array_equal(g["u"][~P.uopen], ou[~P.uopen])
+    assert np.array_equal(g["v"][~P.vopen], ov[~P.vopen])
+    assert np.all(g["p"][~P.fluid] == 0)
+
+
 @pytest.mark.parametrize("n,seed,nobs", [(64, 0, 0), (256, 1, 3), (512, 2, 3)])
 def test_divergence_and_init_error(n, seed, nobs):
     say("div", n, seed)
@@ -263,3 +302,23 @@ def test_einf_criterion_matches_oracle(method, n, seed):
     tol = max(4, 0.01 * ko) if method != "pcg" else max(8, 0.1 * ko)
     assert abs(kg - ko) <= tol
     assert g["res"].einf_final < 1.02 * thr
+
+
+def test_project_call_plans_only_when_the_flags_change():
+    """project(u, v, rho, flags, threshold) -> p, u, v, iters: the cached
+    context re-plans only for new flags, and every call equals the explicit
+    plan + projection."""
+    import torch
+    import paper_2109_09363_amd as hp
+    from tests.gpu_util import to_dev
+    outs = []
+    for seed, nobs in ((0, 2), (0, 2), (1, 3)):
+        sc, u, v = plume_state(96, seed, nobs)
+        tf = to_dev(sc.flags, torch.uint8)
+        p, uu, vv, it = hp.project(to_dev(u), to_dev(v), None, tf, 1e-1, dx=sc.dx, method="jacobi",
+                                   check_every=8)
+        g = gpu_project(sc.flags, u, v, sc.dx, thr=1e-1, method="jacobi", check_every=8)
+        assert it == g["res"].iters
+        assert np.array_equal(p.cpu().numpy().astype(np.float64), g["p"])
+        outs.append(it)
+    assert outs[0] == outs[1]
