@@ -109,6 +109,13 @@ def oracle_leg(sc, flags, pre, ustar, gpu, w_np):
     def rel(a, b):
         return float(np.linalg.norm((a - b)[P.fluid]) / max(np.linalg.norm(b[P.fluid]), 1e-300))
 
+    def rel_uv(p_a):
+        # the velocity a pressure leaves (Eq. 2) against the exactly projected one
+        ue, ve = G.correct(P, ub, vb, ex * dt / sc.rho0, sc.dx)
+        ua, va = G.correct(P, ub, vb, p_a * dt / sc.rho0, sc.dx)
+        return float(np.sqrt((np.sum((ua - ue) ** 2) + np.sum((va - ve) ** 2))
+                             / (np.sum(ue ** 2) + np.sum(ve ** 2))))
+
     errors = {
         "step": "first timed step; oracle inputs = the GPU's pre-step state (advection) and its advected faces (projections)",
         "hybrid_p_vs_oracle_same_algorithm": rel(gpu["p_hybrid"], o["p"]),
@@ -116,6 +123,8 @@ def oracle_leg(sc, flags, pre, ustar, gpu, w_np):
         "hybrid_p_vs_exact_solve": rel(gpu["p_hybrid"], ex),
         "oracle_hybrid_p_vs_exact_solve": rel(o["p"], ex),
         "pcg_p_vs_exact_solve": rel(gpu["p_pcg"], ex),
+        "hybrid_uv_vs_exact_projection": rel_uv(gpu["p_hybrid"]),
+        "pcg_uv_vs_exact_projection": rel_uv(gpu["p_pcg"]),
         "oracle_pcg_p_vs_exact_solve": rel(o_pcg["p"], ex),
         "hybrid_sweeps": k, "oracle_pcg_iters": int(o_pcg["iters"]), "pcg_iters": gpu["pcg_iters"],
         "bars": "same-algorithm relative L2 of p: 1e-3 (BF16 network), 1e-4 (FP32)",

@@ -7,7 +7,8 @@
 // width is a multiple of 16 but not of 32 (FP32 accumulation).  Activations
 // are NHWC so a lane's K-fragment is 8-16 contiguous bytes in LDS; inputs of
 // 2 or 3 channels (the network inputs) are gathered element by element.
-// A work-group of 4 waves computes 16x16-pixel tiles; every scale of a
+// A work-group computes 16x16-pixel tiles (BF16 layers on wide inputs with
+// 8 waves of 2 rows, the others with 4 waves of 4 rows); every scale of a
 // layer can run in one launch over a concatenated tile list.
 #pragma once
 
@@ -42,7 +43,7 @@ template <> struct St<uint16_t> {
 
 constexpr int kMaxScales = 5;
 constexpr int TW = 16;  // tile width (pixels)
-constexpr int TH = 16;  // tile height: 4 waves x 4 rows
+constexpr int TH = 16;  // tile height
 
 struct ScaleDesc {
   const void* in;     // NHWC input activations (storage type)
@@ -103,7 +104,17 @@ struct ConvGeom {
   static constexpr int CT = ((size_t)COUT * WSTR * ELT + TILE_LDS <= 160 * 1024) ? COUT : 16;
   static constexpr int PASSES = COUT / CT;
   static constexpr int MB = CT / 16;                          // cout blocks per pass
-  static constexpr size_t LDS = (size_t)CT * WSTR * ELT + TILE_LDS;
+  // bias and (head layers) the 1x1 head's weights of the scale, FP32
+  static constexpr size_t PARAM_LDS = (size_t)(2 * COUT + 4) * 4;
+  static constexpr size_t LDS = (size_t)CT * WSTR * ELT + TILE_LDS + PARAM_LDS;
+  // waves per work-group: BF16 layers on wide inputs run 8 waves of 2 tile
+  // rows, so that two waves share each SIMD and one's epilogue, barrier and
+  // LDS waits overlap the other's MFMAs (their 220+ registers allow no
+  // second work-group per CU); the rest 4 waves of 4 rows
+  static constexpr int NW = (ELT == 2 && !SMALL) ? 8 : 4;
+  static constexpr int RPW = TH / NW;                         // tile rows per wave
+  static constexpr int NT = 64 * NW;                          // threads
+  static_assert(TH % NW == 0, "whole rows per wave");
   static_assert(COUT % 16 == 0, "output channels in blocks of 16");
   static_assert(CIN % CC == 0, "whole input chunks");
   static_assert(SMALL || CC % KSTEP == 0, "input channels in whole K fragments");
@@ -115,7 +126,7 @@ struct ConvGeom {
 // feeds them to 4 MFMAs; BF16: 8 consecutive K values (16 bytes) for one MFMA.
 template <typename T, int KS, int CIN, int COUT>
 __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __restrict__ xl,
-                                          floatx4 (&acc)[ConvGeom<T, KS, CIN, COUT>::MB][4],
+                                          floatx4 (&acc)[ConvGeom<T, KS, CIN, COUT>::MB][ConvGeom<T, KS, CIN, COUT>::RPW],
                                           int wave, int lane) {
   using Gm = ConvGeom<T, KS, CIN, COUT>;
   constexpr int EW = Gm::EW;
@@ -124,10 +135,10 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
     // K = KS*KS*CIN (tap, cin) gathered per element, zero-padded to KPAD
     for (int k0 = 0; k0 < Gm::KPAD; k0 += Gm::KSTEP) {
       constexpr int PER = (sizeof(T) == 4) ? 4 : 8;
-      T bv[4][PER];
+      T bv[Gm::RPW][PER];
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const int row = wave * 4 + nb;
+      for (int nb = 0; nb < Gm::RPW; ++nb) {
+        const int row = wave * Gm::RPW + nb;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
           const int k = k0 + g * PER + e;
@@ -145,7 +156,7 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
         if constexpr (sizeof(T) == 4) {
           const float4 a = *reinterpret_cast<const float4*>(wrow);
 #pragma unroll
-          for (int nb = 0; nb < 4; ++nb) {
+          for (int nb = 0; nb < Gm::RPW; ++nb) {
             acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bv[nb][0], acc[mb][nb], 0, 0, 0);
             acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bv[nb][1], acc[mb][nb], 0, 0, 0);
             acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bv[nb][2], acc[mb][nb], 0, 0, 0);
@@ -154,7 +165,7 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
         } else {
           const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wrow));
 #pragma unroll
-          for (int nb = 0; nb < 4; ++nb) {
+          for (int nb = 0; nb < Gm::RPW; ++nb) {
             uint4 raw;
             uint16_t* r16 = reinterpret_cast<uint16_t*>(&raw);
 #pragma unroll
@@ -175,10 +186,10 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
       for (int c0 = 0; c0 < Gm::CC; c0 += Gm::KSTEP) {
         const int k0 = tap * Gm::CC + c0;
         if constexpr (sizeof(T) == 4) {
-          float4 bv[4];
+          float4 bv[Gm::RPW];
 #pragma unroll
-          for (int nb = 0; nb < 4; ++nb) {
-            const int row = wave * 4 + nb;
+          for (int nb = 0; nb < Gm::RPW; ++nb) {
+            const int row = wave * Gm::RPW + nb;
             bv[nb] = *reinterpret_cast<const float4*>(
                 xl + ((row + ky) * EW + col + kx) * Gm::PSTR + c0 + g * 4);
           }
@@ -186,7 +197,7 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
           for (int mb = 0; mb < Gm::MB; ++mb) {
             const float4 a = *reinterpret_cast<const float4*>(wl + (mb * 16 + col) * Gm::WSTR + k0 + g * 4);
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
+            for (int nb = 0; nb < Gm::RPW; ++nb) {
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bv[nb].x, acc[mb][nb], 0, 0, 0);
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bv[nb].y, acc[mb][nb], 0, 0, 0);
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bv[nb].z, acc[mb][nb], 0, 0, 0);
@@ -195,10 +206,10 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
           }
         } else if constexpr (Gm::KSTEP == 16) {
           // BF16 with 16-wide fragments: 4 consecutive K values per lane
-          shortx4 bv[4];
+          shortx4 bv[Gm::RPW];
 #pragma unroll
-          for (int nb = 0; nb < 4; ++nb) {
-            const int row = wave * 4 + nb;
+          for (int nb = 0; nb < Gm::RPW; ++nb) {
+            const int row = wave * Gm::RPW + nb;
             bv[nb] = *reinterpret_cast<const shortx4*>(
                 xl + ((row + ky) * EW + col + kx) * Gm::PSTR + c0 + g * 4);
           }
@@ -207,14 +218,14 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
             const shortx4 a =
                 *reinterpret_cast<const shortx4*>(wl + (mb * 16 + col) * Gm::WSTR + k0 + g * 4);
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
+            for (int nb = 0; nb < Gm::RPW; ++nb)
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv[nb], acc[mb][nb], 0, 0, 0);
           }
         } else {
-          bf16x8 bv[4];
+          bf16x8 bv[Gm::RPW];
 #pragma unroll
-          for (int nb = 0; nb < 4; ++nb) {
-            const int row = wave * 4 + nb;
+          for (int nb = 0; nb < Gm::RPW; ++nb) {
+            const int row = wave * Gm::RPW + nb;
             bv[nb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
                 xl + ((row + ky) * EW + col + kx) * Gm::PSTR + c0 + g * 8));
           }
@@ -223,7 +234,7 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
             const bf16x8 a = __builtin_bit_cast(
                 bf16x8, *reinterpret_cast<const uint4*>(wl + (mb * 16 + col) * Gm::WSTR + k0 + g * 8));
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
+            for (int nb = 0; nb < Gm::RPW; ++nb)
               acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv[nb], acc[mb][nb], 0, 0, 0);
           }
         }
@@ -234,13 +245,13 @@ __device__ __forceinline__ void conv_tile(const T* __restrict__ wl, const T* __r
 
 // The 16-byte pieces of an input tile (replicated border) that thread
 // threadIdx.x loads into registers, and their store into the LDS tile.
-template <typename T, int CIN, int EW, int HALO, int PCH, int NPIECE, int NPF>
+template <typename T, int CIN, int EW, int HALO, int PCH, int NPIECE, int NPF, int NT>
 __device__ __forceinline__ void conv_prefetch(const ScaleDesc& S, int x0, int y0, u32x4 (&pf)[NPF]) {
   const T* in = reinterpret_cast<const T*>(S.in);
 #pragma unroll
   for (int i = 0; i < NPF; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    if (256 * (i + 1) <= NPIECE || e < NPIECE) {
+    const int e = threadIdx.x + NT * i;
+    if (NT * (i + 1) <= NPIECE || e < NPIECE) {
       const int pix = e / PCH, piece = e % PCH;
       const int gy = min(max(y0 - HALO + pix / EW, 0), S.H - 1);
       const int gx = min(max(x0 - HALO + pix % EW, 0), S.W - 1);
@@ -250,12 +261,12 @@ __device__ __forceinline__ void conv_prefetch(const ScaleDesc& S, int x0, int y0
   }
 }
 
-template <typename T, int PSTR, int PCH, int NPIECE, int NPF>
+template <typename T, int PSTR, int PCH, int NPIECE, int NPF, int NT>
 __device__ __forceinline__ void conv_commit(T* xl, const u32x4 (&pf)[NPF]) {
 #pragma unroll
   for (int i = 0; i < NPF; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    if (256 * (i + 1) <= NPIECE || e < NPIECE) {
+    const int e = threadIdx.x + NT * i;
+    if (NT * (i + 1) <= NPIECE || e < NPIECE) {
       const int pix = e / PCH, piece = e % PCH;
       *reinterpret_cast<u32x4*>(reinterpret_cast<char*>(xl + pix * PSTR) + piece * 16) = pf[i];
     }
@@ -267,12 +278,13 @@ __device__ __forceinline__ void conv_commit(T* xl, const u32x4 (&pf)[NPF]) {
 // activations as stored (rounded to the storage type), summed over the
 // lane's output channels and across the four lane groups of a pixel.
 template <typename T, int KS, int CIN, int COUT, bool RELU, bool HEAD = false>
-__global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
+__global__ __launch_bounds__((ConvGeom<T, KS, CIN, COUT>::NT)) void conv_mfma(ConvLaunch L) {
   using Gm = ConvGeom<T, KS, CIN, COUT>;
   constexpr int EW = Gm::EW, EH = Gm::EH, HALO = Gm::HALO;
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
   T* wl = reinterpret_cast<T*>(lds_raw);
   T* xl = wl + Gm::CT * Gm::WSTR;
+  float* pl = reinterpret_cast<float*>(lds_raw + Gm::CT * Gm::WSTR * Gm::ELT + Gm::TILE_LDS);  // bias, head
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t_begin = blockIdx.x * L.tiles_per_wg;
   const int t_end = min(t_begin + L.tiles_per_wg, L.total_tiles);
@@ -280,14 +292,25 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
   // copy cout rows [co0, co0 + CT) of input chunk ch of the layer's weight
   // image ([NCH][Cout][WSTR]) into LDS with 16-byte loads, several in flight
   // per thread
-  auto load_weights = [&](const void* img, int ch, int co0) {
+  // LDS row R = 16 mb + 4 g + i (the MFMA's output row) holds local output
+  // channel (CT / 4) g + 4 mb + i, so that the lanes of group g end up with
+  // CT / 4 consecutive channels of their pixel
+  auto load_weights = [&](const ScaleDesc& S, int ch, int co0) {
     __syncthreads();
-    constexpr int N16 = Gm::CT * Gm::WSTR * Gm::ELT / 16;
-    const uint4* src = reinterpret_cast<const uint4*>(img) +
-                       ((size_t)ch * COUT + co0) * Gm::WSTR * Gm::ELT / 16;
+    constexpr int RP = Gm::WSTR * Gm::ELT / 16;  // 16-byte pieces per row
+    constexpr int N16 = Gm::CT * RP;
+    const uint4* src = reinterpret_cast<const uint4*>(S.wimg) + ((size_t)ch * COUT + co0) * RP;
     uint4* dstl = reinterpret_cast<uint4*>(wl);
 #pragma unroll 8
-    for (int e = threadIdx.x; e < N16; e += 256) dstl[e] = src[e];
+    for (int e = threadIdx.x; e < N16; e += Gm::NT) {
+      const int R = e / RP, r = R & 15;
+      const int c = (Gm::CT / 4) * (r >> 2) + 4 * (R >> 4) + (r & 3);
+      dstl[e] = src[c * RP + e % RP];
+    }
+    // the epilogue's parameters: every bias, then the head's weights and bias
+    for (int e = threadIdx.x; e < COUT; e += Gm::NT) pl[e] = S.b[e];
+    if constexpr (HEAD)
+      for (int e = threadIdx.x; e <= COUT; e += Gm::NT) pl[COUT + e] = S.hw[e];
   };
   // input tile (channels of chunk ch) with a HALO-pixel replicated border
   auto load_tile = [&](const ScaleDesc& S, int x0, int y0, int ch) {
@@ -319,7 +342,7 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
   constexpr bool PIPE = !Gm::SMALL && Gm::NCH == 1;
   constexpr int PCH = Gm::SMALL ? 1 : Gm::CC * (int)sizeof(T) / 16;  // pieces per pixel
   constexpr int NPIECE = EH * EW * PCH;
-  constexpr int NPF = PIPE ? (NPIECE + 255) / 256 : 1;
+  constexpr int NPF = PIPE ? (NPIECE + Gm::NT - 1) / Gm::NT : 1;
   u32x4 pf[NPF];
   // the descriptor of global tile t (a scale, or a scale of one grid of a
   // batch) and the tile's origin
@@ -347,29 +370,29 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
     if (t_begin < t_end) {
       int x0, y0;
       const ScaleDesc D = locate(t_begin, x0, y0);
-      conv_prefetch<T, CIN, EW, HALO, PCH, NPIECE, NPF>(D, x0, y0, pf);
-      conv_commit<T, Gm::PSTR, PCH, NPIECE, NPF>(xl, pf);
+      conv_prefetch<T, CIN, EW, HALO, PCH, NPIECE, NPF, Gm::NT>(D, x0, y0, pf);
+      conv_commit<T, Gm::PSTR, PCH, NPIECE, NPF, Gm::NT>(xl, pf);
     }
   }
   for (int t = t_begin; t < t_end; ++t) {
     int x0, y0;
     const ScaleDesc S = locate(t, x0, y0);
     if (Gm::PASSES == 1 && Gm::NCH == 1 && S.wimg != cur) {
-      load_weights(S.wimg, 0, 0);
+      load_weights(S, 0, 0);
       cur = S.wimg;
     }
     if constexpr (!PIPE && Gm::NCH == 1) load_tile(S, x0, y0, 0);
     const int col = lane & 15, g = lane >> 4;
     T* out = reinterpret_cast<T*>(S.out);
-    float hpart[4] = {0.f, 0.f, 0.f, 0.f};  // HEAD: partial 1x1 sums per row
+    float hpart[Gm::RPW] = {};  // HEAD: partial 1x1 sums per row
     for (int pass = 0; pass < Gm::PASSES; ++pass) {
-      floatx4 acc[Gm::MB][4];
+      floatx4 acc[Gm::MB][Gm::RPW];
 #pragma unroll
       for (int mb = 0; mb < Gm::MB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < Gm::RPW; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
       if constexpr (Gm::NCH == 1) {
-        if (Gm::PASSES > 1) load_weights(S.wimg, 0, pass * Gm::CT);
+        if (Gm::PASSES > 1) load_weights(S, 0, pass * Gm::CT);
         __syncthreads();
         // issued after the last barrier before the MFMAs, so that no barrier
         // waits for these loads before the math starts
@@ -377,60 +400,64 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
           if (pass == 0 && t + 1 < t_end) {
             int xn, yn;
             const ScaleDesc Dn = locate(t + 1, xn, yn);
-            conv_prefetch<T, CIN, EW, HALO, PCH, NPIECE, NPF>(Dn, xn, yn, pf);
+            conv_prefetch<T, CIN, EW, HALO, PCH, NPIECE, NPF, Gm::NT>(Dn, xn, yn, pf);
           }
         }
         conv_tile<T, KS, CIN, COUT>(wl, xl, acc, wave, lane);
       } else {
         // K walks the input in chunks: weights and tile of each chunk
         for (int ch = 0; ch < Gm::NCH; ++ch) {
-          load_weights(S.wimg, ch, pass * Gm::CT);
+          load_weights(S, ch, pass * Gm::CT);
           load_tile(S, x0, y0, ch);
           __syncthreads();
           conv_tile<T, KS, CIN, COUT>(wl, xl, acc, wave, lane);
         }
       }
-      // epilogue: bias (+ ReLU); lane holds couts 4g..4g+3 of block mb for pixel col
-      float4 bias[Gm::MB];
+      // epilogue: bias (+ ReLU); the lanes of group g hold output channels
+      // c0 .. c0 + CT/4 - 1 of pixel col of row nb (block mb: 4 of them)
 #pragma unroll
-      for (int mb = 0; mb < Gm::MB; ++mb) {
-        // the packed parameters give the bias no 16-byte alignment
-        const float* bp = S.b + pass * Gm::CT + mb * 16 + g * 4;
-        bias[mb] = make_float4(bp[0], bp[1], bp[2], bp[3]);
-      }
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const int gy = y0 + wave * 4 + nb, gx = x0 + col;
+      for (int nb = 0; nb < Gm::RPW; ++nb) {
+        const int gy = y0 + wave * Gm::RPW + nb, gx = x0 + col;
         const bool inside = gy < S.H && gx < S.W;
         if (!HEAD && !inside) continue;
-        T* dst = out + ((size_t)gy * S.W + gx) * S.ostr;
+        const int c0 = pass * Gm::CT + g * (Gm::CT / 4);
+        float v[Gm::MB][4];
 #pragma unroll
         for (int mb = 0; mb < Gm::MB; ++mb) {
-          const int co = pass * Gm::CT + mb * 16 + g * 4;
-          float v0 = acc[mb][nb][0] + bias[mb].x;
-          float v1 = acc[mb][nb][1] + bias[mb].y;
-          float v2 = acc[mb][nb][2] + bias[mb].z;
-          float v3 = acc[mb][nb][3] + bias[mb].w;
-          if constexpr (RELU) {
-            v0 = fmaxf(v0, 0.f);
-            v1 = fmaxf(v1, 0.f);
-            v2 = fmaxf(v2, 0.f);
-            v3 = fmaxf(v3, 0.f);
-          }
+          const float4 bias = *reinterpret_cast<const float4*>(pl + c0 + 4 * mb);
+          v[mb][0] = acc[mb][nb][0] + bias.x;
+          v[mb][1] = acc[mb][nb][1] + bias.y;
+          v[mb][2] = acc[mb][nb][2] + bias.z;
+          v[mb][3] = acc[mb][nb][3] + bias.w;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if constexpr (RELU) v[mb][i] = fmaxf(v[mb][i], 0.f);
           if constexpr (HEAD) {
-            hpart[nb] += St<T>::to_f(St<T>::from(v0)) * S.hw[co + 0] +
-                         St<T>::to_f(St<T>::from(v1)) * S.hw[co + 1] +
-                         St<T>::to_f(St<T>::from(v2)) * S.hw[co + 2] +
-                         St<T>::to_f(St<T>::from(v3)) * S.hw[co + 3];
-            if (!inside || L.skip_store) continue;
+            const float4 hw = *reinterpret_cast<const float4*>(pl + COUT + c0 + 4 * mb);
+            hpart[nb] += St<T>::to_f(St<T>::from(v[mb][0])) * hw.x + St<T>::to_f(St<T>::from(v[mb][1])) * hw.y +
+                         St<T>::to_f(St<T>::from(v[mb][2])) * hw.z + St<T>::to_f(St<T>::from(v[mb][3])) * hw.w;
           }
-          if constexpr (sizeof(T) == 4) {
-            *reinterpret_cast<float4*>(dst + co) = make_float4(v0, v1, v2, v3);
-          } else {
-            uint2 pk;
-            pk.x = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
-            pk.y = (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16);
-            *reinterpret_cast<uint2*>(dst + co) = pk;
+        }
+        if (HEAD && (!inside || L.skip_store)) continue;
+        T* dst = out + ((size_t)gy * S.W + gx) * S.ostr + c0;
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+          for (int mb = 0; mb < Gm::MB; ++mb)
+            *reinterpret_cast<float4*>(dst + 4 * mb) = make_float4(v[mb][0], v[mb][1], v[mb][2], v[mb][3]);
+        } else {
+          // 8 channels (16 bytes) per store
+#pragma unroll
+          for (int h = 0; h < Gm::MB; h += 2) {
+            uint4 pk;
+            pk.x = (uint32_t)f2bf(v[h][0]) | ((uint32_t)f2bf(v[h][1]) << 16);
+            pk.y = (uint32_t)f2bf(v[h][2]) | ((uint32_t)f2bf(v[h][3]) << 16);
+            if (h + 1 < Gm::MB) {
+              pk.z = (uint32_t)f2bf(v[h + 1][0]) | ((uint32_t)f2bf(v[h + 1][1]) << 16);
+              pk.w = (uint32_t)f2bf(v[h + 1][2]) | ((uint32_t)f2bf(v[h + 1][3]) << 16);
+              *reinterpret_cast<uint4*>(dst + 4 * h) = pk;
+            } else {
+              *reinterpret_cast<uint2*>(dst + 4 * h) = make_uint2(pk.x, pk.y);
+            }
           }
         }
       }
@@ -438,17 +465,17 @@ __global__ __launch_bounds__(256) void conv_mfma(ConvLaunch L) {
     if constexpr (HEAD) {
       // the four lane groups (g) of a pixel hold disjoint output channels
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
+      for (int nb = 0; nb < Gm::RPW; ++nb) {
         float hs = hpart[nb];
         hs += __shfl_xor(hs, 16);
         hs += __shfl_xor(hs, 32);
-        const int gy = y0 + wave * 4 + nb, gx = x0 + col;
-        if (g == 0 && gy < S.H && gx < S.W) S.y[(size_t)gy * S.W + gx] = hs + S.hw[COUT];
+        const int gy = y0 + wave * Gm::RPW + nb, gx = x0 + col;
+        if (g == 0 && gy < S.H && gx < S.W) S.y[(size_t)gy * S.W + gx] = hs + pl[2 * COUT];
       }
     }
     __syncthreads();
     if constexpr (PIPE) {
-      if (t + 1 < t_end) conv_commit<T, Gm::PSTR, PCH, NPIECE, NPF>(xl, pf);
+      if (t + 1 < t_end) conv_commit<T, Gm::PSTR, PCH, NPIECE, NPF, Gm::NT>(xl, pf);
     }
   }
 }
@@ -486,7 +513,7 @@ hipError_t launch_conv(ConvLaunch& L, int cu, hipStream_t s) {
   const int G = min(tiles, cu * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu)));
   L.tiles_per_wg = (tiles + G - 1) / G;
   const int nwg = (tiles + L.tiles_per_wg - 1) / L.tiles_per_wg;
-  hipLaunchKernelGGL((conv_mfma<T, KS, CIN, COUT, RELU, HEAD>), dim3(nwg), dim3(256), Gm::LDS, s, L);
+  hipLaunchKernelGGL((conv_mfma<T, KS, CIN, COUT, RELU, HEAD>), dim3(nwg), dim3(Gm::NT), Gm::LDS, s, L);
   return hipGetLastError();
 }
 

@@ -11,6 +11,10 @@ each case this prints one JSON line with
   p_vs_exact       relative L2 (fluid cells) of the GPU's pressure against
                    the exact FP64 solve of Eq. (3) (what a threshold stop
                    leaves of the pressure: the method's error, not the GPU's)
+  uv_vs_exact      relative L2 over all faces of the velocity that pressure
+                   leaves (u* - grad phi, phi = dt p / rho0, the correction of
+                   Eq. 2 applied by the oracle) against the exactly projected
+                   velocity: what the next time step carries forward
   p_vs_replica     relative L2 against the oracle running the same algorithm
                    on the same faces: the hybrid with the same network
                    (BF16 rounding emulated where the GPU used BF16) and the
@@ -84,6 +88,10 @@ def evaluate(path, replica_max):
             exact = rho0 / dt * SV.exact_solve(P, d, dx)
         if not var:
             row["p_vs_exact"] = rel(P, p, exact)
+            ue, ve = G.correct(P, ub, vb, exact * dt / rho0, dx)
+            ug, vg = G.correct(P, ub, vb, p * dt / rho0, dx)
+            row["uv_vs_exact"] = float(np.sqrt((np.sum((ug - ue) ** 2) + np.sum((vg - ve) ** 2))
+                                               / (np.sum(ue ** 2) + np.sum(ve ** 2))))
         k = int(c["iters"])
         if c["method"] == "pcg" and not var:
             o = PR.project(flags, u, v, dx, dt=dt, rho0=rho0, method="pcg", threshold=c["threshold"],
@@ -125,8 +133,10 @@ def main():
     for key, rs in groups.items():
         e = [r["p_vs_exact"] for r in rs if "p_vs_exact" in r]
         q = [r["p_vs_replica"] for r in rs if "p_vs_replica" in r]
+        uv = [r["uv_vs_exact"] for r in rs if "uv_vs_exact" in r]
         summary[key] = {"cases": len(rs),
                         "mean_p_vs_exact": float(np.mean(e)) if e else None,
+                        "mean_uv_vs_exact": float(np.mean(uv)) if uv else None,
                         "max_p_vs_replica": float(np.max(q)) if q else None,
                         "replicated": len(q)}
     line = json.dumps({"summary": summary})
