@@ -184,6 +184,13 @@ typedef struct {
                            Sec. 4.1) for the threshold test; the result's
                            e1_cnn then holds the chosen measure of the guess.
                            Not with the batch (EUNSUPPORTED). */
+  int32_t block_sweeps; /* Jacobi sweeps between halo exchanges, 1..16 (a
+                           halo of block_sweeps + 1 cells is recomputed by
+                           each tile; the iterates do not depend on it); 0:
+                           the tuned table for this grid (csrc/tile_table.h)
+                           when its block fits check_every, else
+                           min(check_every, 8).  Clipped to check_every when
+                           a threshold decides.  EINVAL outside 0..16. */
 } hyp_opts;
 
 /* Written by the device when the projection's last kernel completes. */

@@ -38,7 +38,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("method", c_i32), ("max_iters", c_i32), ("check_every", c_i32),
                 ("fixed_iters", c_i32), ("omega", c_f32), ("fold_window", c_i32),
                 ("checkpoint_every", c_i32), ("tile_rows", c_i32), ("variable_density", c_i32),
-                ("criterion", c_i32)]
+                ("criterion", c_i32), ("block_sweeps", c_i32)]
 
 
 class Result(ctypes.Structure):

@@ -104,7 +104,7 @@ class Projector:
                       max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
                       omega: float = 1.0, rho=None, p_init=None, fold_window: int = 0,
                       checkpoint_every: int = 0, phi_ckpt=None, tile_rows: int = 0,
-                      variable_density: bool = False, criterion: str = "e1"):
+                      variable_density: bool = False, criterion: str = "e1", block_sweeps: int = 0):
         """Enqueue one projection on the current stream; u, v corrected in
         place, p written.  Read the result with `result()` after a sync.
         With fixed_iters and checkpoint_every > 0, phi_ckpt (n, ny, nx) float32
@@ -131,7 +131,7 @@ class Projector:
         f = L.Fields(_ptr(u), _ptr(v), _ptr(rho), _ptr(flags), _ptr(p), _ptr(p_init), _ptr(phi_ckpt))
         o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
                    float(omega), int(fold_window), int(checkpoint_every), int(tile_rows),
-                   1 if variable_density else 0, L.CRITERIA[criterion])
+                   1 if variable_density else 0, L.CRITERIA[criterion], int(block_sweeps))
         L.check("hyp_project", self.lib.hyp_project(
             self.ctx, ctypes.byref(self.grid), ctypes.byref(f), float(threshold), ctypes.byref(o),
             _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))
@@ -218,7 +218,7 @@ class Projector:
                    u_in: float = 1.0, cfl: float = 0.5, method: str = "hybrid",
                    max_iters: int = 200000, check_every: int = 8, fixed_iters: int = 0,
                    omega: float = 1.0, fold_window: int = 0, variable_density: bool = False,
-                   criterion: str = "e1"):
+                   criterion: str = "e1", tile_rows: int = 0, block_sweeps: int = 0):
         """Enqueue one full time step (advection, buoyancy, inflow, projection)
         on the current stream.  rho, u, v advance in place; p is written.
         variable_density projects with the advected density in the operator."""
@@ -234,8 +234,8 @@ class Projector:
         ph = L.Physics(float(g), float(self.grid.rho0), float(drho), float(u_in), float(cfl))
         st = L.State(_ptr(rho), _ptr(u), _ptr(v), _ptr(p), _ptr(flags), _ptr(xi))
         o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), int(fixed_iters),
-                   float(omega), int(fold_window), 0, 0, 1 if variable_density else 0,
-                   L.CRITERIA[criterion])
+                   float(omega), int(fold_window), 0, int(tile_rows), 1 if variable_density else 0,
+                   L.CRITERIA[criterion], int(block_sweeps))
         L.check("hyp_step", self.lib.hyp_step(
             self.ctx, ctypes.byref(self.grid), ctypes.byref(ph), ctypes.byref(st), float(threshold),
             ctypes.byref(o), _ptr(self.ws), self.ws.numel(), _stream(), _ptr(self.res)))

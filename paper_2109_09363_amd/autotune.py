@@ -1,16 +1,18 @@
 """Tile autotuner of the persistent Jacobi kernels.
 
-Single grids: for each grid size, time a fixed number of sweeps (check every
-8, halo 9) with every tile height R that fits the GPU and keep the fastest;
-the result is the C header the library compiles (csrc/tile_table.h), and
-grids without an entry use the smallest R that fits.
+Single grids: for each grid size, time a number of sweeps (E_1 tested every
+128, as in the benchmark) with every
+tile height R that fits the GPU and every block length B (sweeps between
+halo exchanges, halo B + 1) of --blocks, and keep the fastest pair; the
+result is the C header the library compiles (csrc/tile_table.h), and grids
+without an entry use B = 8 and the smallest R that fits.
 
 Batches (--batch): for each grid side, time the batched projection of a
 batch of plumes of that side at a fixed sweep count with R = 8 and R = 16
 for every instance, and keep the faster (csrc/batch_tile_table.h).
 
 python -m paper_2109_09363_amd.autotune [--sizes 128 192 256 384 512 768 1024]
-        [--sweeps 512] [--reps 3] [--batch [--per-batch 16]] [--out HEADER]
+        [--blocks 8 12 16] [--sweeps 512] [--reps 3] [--batch [--per-batch 16]] [--out HEADER]
 """
 from __future__ import annotations
 
@@ -31,10 +33,9 @@ import paper_2109_09363_amd as hp  # noqa: E402
 from paper_2109_09363_amd import _lib as L  # noqa: E402
 
 ROWS = (4, 8, 12, 16, 24, 32)
-HALO = 9  # check_every 8 (and fixed-sweep runs): 8 sweeps per step
 
 
-def time_rows(n, rows, sweeps, reps, dev):
+def time_rows(n, rows, sweeps, reps, dev, block=8):
     sc = scenes.plume_scene(n, seed=0, n_obstacles=2)
     u, v = scenes.random_faces(n, n, 0, kind="mixed")
     pr = hp.Projector(n, n, sc.dx, 1.0, 1.0, 0, 0, "fp32", device=dev)
@@ -51,8 +52,12 @@ def time_rows(n, rows, sweeps, reps, dev):
                 uu, vv = u0.clone(), v0.clone()
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record()
-                pr.project_async(uu, vv, flags, p, 0.0, method="jacobi", fixed_iters=sweeps,
-                                 check_every=8, tile_rows=r)
+                # the benchmark's pattern: E_1 tested every 128 sweeps (a
+                # grid barrier), the others neighbour-synchronised; a zero
+                # threshold runs to max_iters, no folds
+                pr.project_async(uu, vv, flags, p, 0.0, method="jacobi", max_iters=sweeps,
+                                 check_every=128, fold_window=1 << 30, tile_rows=r,
+                                 block_sweeps=block)
                 b.record()
                 torch.cuda.synchronize()
                 if rep > 0:
@@ -65,10 +70,11 @@ def time_rows(n, rows, sweeps, reps, dev):
 
 def write_header(path, entries):
     lines = [
-        "// Tuned tile heights of the persistent Jacobi kernel: for a grid of",
-        "// nx x ny cells and halo H, the rows per wave R that ran fastest on MI355X.",
-        "// Written by paper_2109_09363_amd/autotune.py (do not edit by hand); a grid",
-        "// without an entry uses the smallest R whose tiles fit one work-group per CU.",
+        "// Tuned tiles of the persistent Jacobi kernel: for a grid of nx x ny cells,",
+        "// the halo H (H - 1 sweeps between exchanges) and rows per wave R that ran",
+        "// fastest on MI355X.  Written by paper_2109_09363_amd/autotune.py (do not",
+        "// edit by hand); a grid without an entry uses H = 9 and the smallest R",
+        "// whose tiles fit one work-group per CU.",
         "#pragma once",
         "",
         "namespace hyp {",
@@ -80,8 +86,8 @@ def write_header(path, entries):
     ]
     if entries:
         lines.append("constexpr TileEntry kTileTable[] = {")
-        for (n, r, ms) in entries:
-            lines.append(f"    {{{n}, {n}, {HALO}, {r}}},  // {ms:.3f} ms")
+        for (n, b, r, ms) in entries:
+            lines.append(f"    {{{n}, {n}, {b + 1}, {r}}},  // {ms:.3f} ms")
         lines.append("};")
         lines.append(f"constexpr int kTileTableSize = {len(entries)};")
     else:
@@ -153,6 +159,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sizes", type=int, nargs="*", default=[128, 192, 256, 384, 512, 768, 1024])
     ap.add_argument("--sweeps", type=int, default=512)
+    ap.add_argument("--blocks", type=int, nargs="*", default=[8, 12, 16],
+                    help="block lengths (sweeps between halo exchanges) to try")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=None)
     ap.add_argument("--batch", action="store_true", help="tune the batched kernel's rows per side")
@@ -175,13 +183,18 @@ def main():
     a.out = a.out or os.path.join(csrc, "tile_table.h")
     entries = []
     for n in a.sizes:
-        t = time_rows(n, ROWS, a.sweeps, a.reps, dev)
+        t = {}
+        for b in a.blocks:
+            for r, ms in time_rows(n, ROWS, a.sweeps, a.reps, dev, block=b).items():
+                t[(b, r)] = ms
         if not t:
             print(json.dumps({"n": n, "fits": False}), flush=True)
             continue
         best = min(t, key=t.get)
-        entries.append((n, best, t[best]))
-        print(json.dumps({"n": n, "sweeps": a.sweeps, "ms_by_rows": t, "best_rows": best,
+        entries.append((n, best[0], best[1], t[best]))
+        print(json.dumps({"n": n, "sweeps": a.sweeps,
+                          "ms_by_block_rows": {f"B{b}_R{r}": round(ms, 4) for (b, r), ms in sorted(t.items())},
+                          "best_block": best[0], "best_rows": best[1],
                           "us_per_sweep": round(1e3 * t[best] / a.sweeps, 3)}), flush=True)
     write_header(a.out, entries)
     print(f"# wrote {a.out}", file=sys.stderr, flush=True)

@@ -308,8 +308,9 @@ static int check_opts(const hyp_ctx* ctx, const hyp_grid* g, const hyp_opts* o, 
   }
   const bool pcg = o->method == HYP_METHOD_PCG;
   if (o->tile_rows < 0 || (pcg && o->tile_rows != 0)) return HYP_EINVAL;
+  if (o->block_sweeps < 0 || o->block_sweeps > 16 || (pcg && o->block_sweeps != 0)) return HYP_EINVAL;
   if (!solver_fits(ctx->dev, g->nx, g->ny, pcg, o->check_every, o->fixed_iters, o->tile_rows,
-                   o->variable_density != 0))
+                   o->block_sweeps, o->variable_density != 0))
     return HYP_EUNSUPPORTED;
   return HYP_OK;
 }
@@ -338,8 +339,8 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
   mark(ctx, 2, stream);
   if (o->method == HYP_METHOD_CNN) {
     // no sweeps: a zero-length Jacobi pass records E_1 of the prediction
-    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, 0, nullptr, 0, var, einf, u, v,
-                   w, stream);
+    e = run_jacobi(ctx->dev, nx, ny, g->dx, HUGE_VAL, 1.0f, 0, 1, 0, 0, 0, nullptr, 0, 0, var, einf, u,
+                   v, w, stream);
   } else if (o->method == HYP_METHOD_PCG) {
     // one persistent launch, defect-correction folds included
     e = run_pcg(ctx->dev, nx, ny, g->dx, threshold, o->max_iters, o->check_every,
@@ -348,7 +349,7 @@ static int enqueue_projection(hyp_ctx* ctx, const hyp_grid* g, float* u, float* 
     // one persistent launch, defect-correction folds included
     e = run_jacobi(ctx->dev, nx, ny, g->dx, threshold, o->omega, o->max_iters, o->check_every,
                    o->fixed_iters, o->fold_window, phi_ckpt ? o->checkpoint_every : 0, phi_ckpt,
-                   o->tile_rows, var, einf, u, v, w, stream);
+                   o->tile_rows, o->block_sweeps, var, einf, u, v, w, stream);
   }
   if (e != hipSuccess) return HYP_EHIP;
   mark(ctx, 3, stream);
@@ -521,6 +522,7 @@ int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_s
   if (o->variable_density != 0 && o->variable_density != 1) return HYP_EINVAL;
   if (o->max_iters < 0 || !(o->omega > 0.f) || o->checkpoint_every != 0) return HYP_EINVAL;
   if (o->tile_rows != 0 && o->tile_rows != 8 && o->tile_rows != 16) return HYP_EINVAL;
+  if (o->block_sweeps != 0) return HYP_EINVAL;  // the batch sweeps 8 per exchange
   const bool cnn = o->method == HYP_METHOD_HYBRID;
   if (cnn && (ctx->net.scales == 0 || !ctx->params)) return HYP_ENOWEIGHTS;
   if (cnn && (ctx->net.arch != HYP_ARCH_PARALLEL || ctx->net.scales > kBatchMaxScales))

@@ -307,10 +307,13 @@ __global__ __launch_bounds__((ConvGeom<T, KS, CIN, COUT>::NT)) void conv_mfma(Co
       const int c = (Gm::CT / 4) * (r >> 2) + 4 * (R >> 4) + (r & 3);
       dstl[e] = src[c * RP + e % RP];
     }
-    // the epilogue's parameters: every bias, then the head's weights and bias
-    for (int e = threadIdx.x; e < COUT; e += Gm::NT) pl[e] = S.b[e];
-    if constexpr (HEAD)
-      for (int e = threadIdx.x; e <= COUT; e += Gm::NT) pl[COUT + e] = S.hw[e];
+    // the epilogue's parameters (every bias, then the head's weights and
+    // bias), once per tile: they serve all passes
+    if (ch == 0 && co0 == 0) {
+      for (int e = threadIdx.x; e < COUT; e += Gm::NT) pl[e] = S.b[e];
+      if constexpr (HEAD)
+        for (int e = threadIdx.x; e <= COUT; e += Gm::NT) pl[COUT + e] = S.hw[e];
+    }
   };
   // input tile (channels of chunk ch) with a HALO-pixel replicated border
   auto load_tile = [&](const ScaleDesc& S, int x0, int y0, int ch) {

@@ -116,10 +116,11 @@ hipError_t run_init_phi(int nx, int ny, const float* p_init, double scale, const
                         hipStream_t s);
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      int checkpoint_every, float* phi_ckpt, int tile_rows, bool var, bool einf,
+                      int checkpoint_every, float* phi_ckpt, int tile_rows, int block, bool var,
+                      bool einf,
                       float* u, float* v, const Ws& w, hipStream_t s);
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters,
-                 int tile_rows, bool var);
+                 int tile_rows, int block, bool var);
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,
                    int check_every, int fixed_iters, bool var, bool einf, float* u, float* v,
                    const Ws& w, hipStream_t s);

@@ -707,15 +707,17 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// Launch geometry.  Jacobi: halo H = B + 1 with B = min(check_every, 8)
-// sweeps per step (8 for fixed_iters), tile interior (64 - 2H) x (4R - 2H),
-// the tuned R (whose tiles may fill two work-groups per CU when the kernel's
-// registers allow it: one sweeps while the other waits for its halo), else
-// the smallest R whose tile count fits one work-group per CU.
-static int jacobi_block_len(int check_every, int fixed_iters) {
-  const int kMaxBlock = 8;
-  if (fixed_iters > 0) return kMaxBlock;
-  return check_every < kMaxBlock ? check_every : kMaxBlock;
+// Launch geometry.  Jacobi: halo H = B + 1 for B sweeps per step, tile
+// interior (64 - 2H) x (4R - 2H).  The tuned table gives (R, H) per grid
+// (its tiles may fill two work-groups per CU when the kernel's registers
+// allow it: one sweeps while the other waits for its halo); otherwise B =
+// min(check_every, 8) (8 for fixed_iters) and the smallest R whose tile
+// count fits one work-group per CU.  A caller's block length replaces B
+// (clipped to check_every when a threshold decides).
+static int jacobi_block_len(int check_every, int fixed_iters, int block) {
+  const int b = block > 0 ? block : 8;
+  if (fixed_iters > 0) return b;
+  return check_every < b ? check_every : b;
 }
 
 static const int kRows[] = {4, 8, 12, 16, 24, 32};
@@ -762,10 +764,24 @@ static bool jacobi_fit(const Device& dev, int nx, int ny, int r, int h, bool var
   return true;
 }
 
-// rows = 0: the tuned table, else the smallest R that fits; rows > 0: that R
+// rows = 0: the tuned table, else the smallest R that fits; rows > 0: that R.
+// block = 0: the table's block when it fits check_every, else the default.
 static bool jacobi_geom(const Device& dev, int nx, int ny, int check_every, int fixed_iters,
-                        int rows, bool var, int* R, int* H, int* ntx, int* nty) {
-  const int h = jacobi_block_len(check_every, fixed_iters) + 1;
+                        int rows, int block, bool var, int* R, int* H, int* ntx, int* nty) {
+  if (rows == 0) {
+    for (int i = 0; i < kTileTableSize; ++i) {
+      const TileEntry& t = kTileTable[i];
+      const int th = block > 0 ? jacobi_block_len(check_every, fixed_iters, block) + 1 : t.H;
+      const bool fits_checks = fixed_iters > 0 || t.H - 1 <= check_every;
+      if (t.nx == nx && t.ny == ny && th == t.H && fits_checks &&
+          jacobi_fit(dev, nx, ny, t.R, t.H, var, true, ntx, nty)) {
+        *R = t.R;
+        *H = t.H;
+        return true;
+      }
+    }
+  }
+  const int h = jacobi_block_len(check_every, fixed_iters, block) + 1;
   *H = h;
   if (rows > 0) {
     bool known = false;
@@ -773,13 +789,6 @@ static bool jacobi_geom(const Device& dev, int nx, int ny, int check_every, int 
     if (!known || !jacobi_fit(dev, nx, ny, rows, h, var, true, ntx, nty)) return false;
     *R = rows;
     return true;
-  }
-  for (int i = 0; i < kTileTableSize; ++i) {
-    const TileEntry& t = kTileTable[i];
-    if (t.nx == nx && t.ny == ny && t.H == h && jacobi_fit(dev, nx, ny, t.R, h, var, true, ntx, nty)) {
-      *R = t.R;
-      return true;
-    }
   }
   for (int r : kRows) {
     if (jacobi_fit(dev, nx, ny, r, h, var, false, ntx, nty)) {
@@ -805,13 +814,13 @@ static bool pcg_geom(const Device& dev, int nx, int ny, int* R, int* ntx, int* n
 }
 
 bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, int fixed_iters,
-                 int tile_rows, bool var) {
+                 int tile_rows, int block, bool var) {
   if (pcg) {
     int R, ntx, nty;
     return pcg_geom(dev, nx, ny, &R, &ntx, &nty);
   }
   int R, H, ntx, nty;
-  return jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, var, &R, &H, &ntx, &nty);
+  return jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, block, var, &R, &H, &ntx, &nty);
 }
 
 template <int R>
@@ -823,12 +832,12 @@ static hipError_t launch_jacobi(JacParams& p, int G, hipStream_t s) {
 
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
                       int max_iters, int check_every, int fixed_iters, int fold_window,
-                      int checkpoint_every, float* phi_ckpt, int tile_rows, bool var, bool einf,
-                      float* u, float* v, const Ws& w, hipStream_t s) {
+                      int checkpoint_every, float* phi_ckpt, int tile_rows, int block, bool var,
+                      bool einf, float* u, float* v, const Ws& w, hipStream_t s) {
   JacParams p{};
   p.einf = einf ? 1 : 0;
   int R = 0, H = 0, ntx = 0, nty = 0;
-  if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, var, &R, &H, &ntx, &nty))
+  if (!jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, block, var, &R, &H, &ntx, &nty))
     return hipErrorInvalidValue;
   p.nx = nx; p.ny = ny; p.H = H; p.ntx = ntx; p.nty = nty;
   p.nbsync = (H <= 64 - 2 * H && H <= 4 * R - 2 * H) ? 1 : 0;

@@ -7,6 +7,7 @@ import scenes
 from oracle import grid as G
 from oracle import solve as SV
 from oracle import project as PR
+from paper_2109_09363_amd import _lib as L
 from tests.gpu_util import gpu_project, f32, rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -322,3 +323,41 @@ def test_project_call_plans_only_when_the_flags_change():
         assert np.array_equal(p.cpu().numpy().astype(np.float64), g["p"])
         outs.append(it)
     assert outs[0] == outs[1]
+
+
+@pytest.mark.parametrize("n,rows", [(512, 0), (512, 12), (256, 16), (200, 24)])
+def test_jacobi_block_length_does_not_change_the_iterates(n, rows):
+    """Sweeps between halo exchanges (halo B + 1 recomputed per tile) only
+    change how the work is cut: every cell takes the same arithmetic, so
+    the iterate is bit for bit the same for B = 1 .. 16, at fixed sweeps
+    and with a threshold stop (tests every 128 sweeps; B clipped to the
+    interval), and equals the oracle's Jacobi at that count."""
+    say("block length", n, rows)
+    sc, u, v = plume_state(n, 3, 2)
+    P = G.plan(sc.flags)
+    ref = None
+    for block in (8, 1, 5, 12, 16):
+        kw = dict(tile_rows=rows) if rows else {}
+        try:
+            g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="jacobi", fixed_iters=203,
+                            block_sweeps=block, **kw)
+        except L.HypError as e:  # these tiles do not fit with this halo
+            say("  block", block, "skipped:", e)
+            continue
+        if ref is None:
+            ref = g
+            o = PR.project(sc.flags, u, v, sc.dx, method="jacobi", fixed_iters=203)
+            assert rel_l2(g["p"], o["p"], P.fluid) <= 1e-5
+            continue
+        say("  block", block, "iters", g["res"].iters)
+        assert np.array_equal(g["p"], ref["p"]) and np.array_equal(g["u"], ref["u"])
+        assert np.array_equal(g["v"], ref["v"])
+    thr_ref = None
+    for block in (8, 16):
+        g = gpu_project(sc.flags, u, v, sc.dx, thr=2e-2, method="jacobi", check_every=128,
+                        block_sweeps=block)
+        if thr_ref is None:
+            thr_ref = g
+            continue
+        assert g["res"].iters == thr_ref["res"].iters
+        assert np.array_equal(g["p"], thr_ref["p"])
