@@ -108,10 +108,10 @@ typedef struct hyp_ctx hyp_ctx;
 /* Network shape.  HYP_ARCH_PARALLEL: scales in 1..5; channels 16, 32 or 64
  * with FP32 (64: inference only, HYP_EUNSUPPORTED with HYP_NET_TRAIN), 32 or
  * 64 with BF16.  HYP_ARCH_MULTISCALE / SMALLSCALE: scales 3 (or 0), channels
- * 64 / 32 (or 0), FP32 or BF16, inference only (HYP_NET_TRAIN gives
- * HYP_EUNSUPPORTED); the grid sides must be multiples of 4.  HYP_ARCH_UNET:
- * scales 5 (or 0), channels 64 (or 0), FP32 or BF16, inference only; grid
- * sides multiples of 16. */
+ * 64 / 32 (or 0), FP32 or BF16; the grid sides must be multiples of 4.
+ * HYP_ARCH_UNET: scales 5 (or 0), channels 64 (or 0), FP32 or BF16; grid
+ * sides multiples of 16.  The paper's networks train in FP32 only
+ * (HYP_NET_TRAIN with BF16 gives HYP_EUNSUPPORTED). */
 typedef struct {
   int32_t scales;
   int32_t channels;

@@ -9,6 +9,7 @@
 #include "../../include/hyproj.h"
 #include "batch.h"
 #include "internal.h"
+#include "cascade.h"
 #include "unet.h"
 
 struct hyp_ctx {
@@ -78,7 +79,20 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
     L.cnn_t = take(px * 4);
     L.cnn_w = take(cnn_weight_image_bytes(net));
     if (net.arch == HYP_ARCH_UNET) L.cnn_cat = take(unet_cat_elems(nx, ny) * act_elt);
-    if (net.train && net.arch == HYP_ARCH_UNET) {
+    if (net.train && (net.arch == HYP_ARCH_MULTISCALE || net.arch == HYP_ARCH_SMALLSCALE)) {
+      // every branch input and layer output (cascade.h); lambda maps of up
+      // to C channels at full resolution; the branches' input lambdas (2-3
+      // channels) go to bw_b
+      const size_t C = net.channels;
+      L.cnn_save = take(4 * pn_save_layout(net.arch, nx, ny).total);
+      L.bw_cells = take(3 * 4 * n);
+      L.bw_t = take(4 * px);
+      L.bw_x = take(4 * px);
+      L.bw_a = take(4 * n * C);
+      L.bw_b = take(4 * n * C);
+      L.bw_part_n = (size_t)kWgBlocks * (C * 9 * C + C);
+      L.bw_part = take(4 * L.bw_part_n);
+    } else if (net.train && net.arch == HYP_ARCH_UNET) {
       // every layer's FP32 output and the skip gradients (unet.h); lambda
       // maps of up to 32 channels at full resolution (the concatenation)
       const size_t C = net.channels;
@@ -177,17 +191,15 @@ int hyp_create(hyp_ctx** out, const hyp_net_desc* net) {
   NetShape ns;
   if (net && (net->arch == HYP_ARCH_MULTISCALE || net->arch == HYP_ARCH_SMALLSCALE ||
               net->arch == HYP_ARCH_UNET)) {
-    // the paper's networks: fixed scales and widths, inference only
+    // the paper's networks: fixed scales and widths
     const int S = net->arch == HYP_ARCH_UNET ? 5 : 3;
     const int C = net->arch == HYP_ARCH_SMALLSCALE ? 32 : 64;
     if ((net->scales != 0 && net->scales != S) || (net->channels != 0 && net->channels != C))
       return HYP_EINVAL;
     if (net->precision != HYP_PREC_FP32 && net->precision != HYP_PREC_BF16) return HYP_EINVAL;
     if (net->flags & ~HYP_NET_TRAIN) return HYP_EINVAL;
-    // training: the Unet in FP32 (the cascades are inference only)
-    if ((net->flags & HYP_NET_TRAIN) &&
-        (net->arch != HYP_ARCH_UNET || net->precision != HYP_PREC_FP32))
-      return HYP_EUNSUPPORTED;
+    // training: FP32 only
+    if ((net->flags & HYP_NET_TRAIN) && net->precision != HYP_PREC_FP32) return HYP_EUNSUPPORTED;
     ns.scales = S;
     ns.channels = C;
     ns.precision = net->precision;

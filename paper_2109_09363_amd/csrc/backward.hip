@@ -17,6 +17,7 @@
 #include "../../include/hyproj.h"
 #include "common.h"
 #include "internal.h"
+#include "cascade.h"
 #include "unet.h"
 
 namespace hyp {
@@ -182,8 +183,9 @@ __global__ __launch_bounds__(256) void bw_up2T(int Hc, int Wc, const float* __re
 }
 
 // ---- CNN part ---------------------------------------------------------------
-// head: lam_pre3[px][c] = lam_y[px] wo[c] (h4 > 0); partial dwo, dbo
-template <typename T, int C>
+// head: lam_pre3[px][c] = lam_y[px] wo[c] (times h4 > 0 when the head's
+// input layer has a ReLU); partial dwo, dbo
+template <typename T, int C, bool MASK = true>
 __global__ __launch_bounds__(256) void bw_head(int npx, const float* __restrict__ lam_y,
                                                const T* __restrict__ h4,
                                                const float* __restrict__ wo,
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void bw_head(int npx, const float* __restrict_
     const float ly = lam_y[px];
     for (int c = 0; c < C; ++c) {
       const float h = ld<T>(h4 + (size_t)px * C + c);
-      lam_pre[(size_t)px * C + c] = h > 0.f ? ly * wo[c] : 0.f;
+      lam_pre[(size_t)px * C + c] = (!MASK || h > 0.f) ? ly * wo[c] : 0.f;
     }
   }
   if (threadIdx.x <= C) {
@@ -508,17 +510,18 @@ static hipError_t backward_cnn(const NetShape& net, const WsLayout& Ly, int nx, 
 // the skip part and masked by the encoder output's ReLU.
 // ---------------------------------------------------------------------------
 
-// Weight and bias gradients of a 3x3 layer over input channels
+// Weight and bias gradients of a KS x KS layer over input channels
 // [ci0, ci0 + CC) of a CIN-channel input (chunks keep the tile in LDS):
 // part[bx][e], e over (co, tap, c) of the chunk, then the biases (chunk 0).
-template <int CIN, int CC, int COUT, int NACC>
+template <int KS, int CIN, int CC, int COUT, int NACC>
 __global__ __launch_bounds__(256) void bw_wgrad_c(int H, int W, const float* __restrict__ in, int ci0,
                                                   const float* __restrict__ lam_pre,
                                                   float* __restrict__ part) {
+  constexpr int HK = KS / 2, BK = BT + KS - 1, NT = KS * KS;
   extern __shared__ __attribute__((aligned(16))) float lds_c[];
   float* lt = lds_c;                  // [BT*BT][COUT]
-  float* xt = lds_c + BT * BT * COUT; // [BE*BE][CC]
-  const int nw = COUT * 9 * CC, nout = nw + (ci0 == 0 ? COUT : 0);
+  float* xt = lds_c + BT * BT * COUT; // [BK*BK][CC]
+  const int nw = COUT * NT * CC, nout = nw + (ci0 == 0 ? COUT : 0);
   const int tiles_x = (W + BT - 1) / BT, tiles = tiles_x * ((H + BT - 1) / BT);
   const int e0 = blockIdx.y * 256 * NACC;
   float acc[NACC];
@@ -532,10 +535,10 @@ __global__ __launch_bounds__(256) void bw_wgrad_c(int H, int W, const float* __r
       const int gy = y0 + q / BT, gx = x0 + q % BT;
       lt[e] = (gy < H && gx < W) ? lam_pre[((size_t)gy * W + gx) * COUT + co] : 0.f;
     }
-    for (int e = threadIdx.x; e < BE * BE * CC; e += 256) {
+    for (int e = threadIdx.x; e < BK * BK * CC; e += 256) {
       const int q = e / CC, c = e % CC;
-      const int gy = min(max(y0 - 1 + q / BE, 0), H - 1);
-      const int gx = min(max(x0 - 1 + q % BE, 0), W - 1);
+      const int gy = min(max(y0 - HK + q / BK, 0), H - 1);
+      const int gx = min(max(x0 - HK + q % BK, 0), W - 1);
       xt[e] = in[((size_t)gy * W + gx) * CIN + ci0 + c];
     }
     __syncthreads();
@@ -545,10 +548,10 @@ __global__ __launch_bounds__(256) void bw_wgrad_c(int H, int W, const float* __r
       if (e >= nout) break;
       float a = 0.f;
       if (e < nw) {
-        const int co = e / (9 * CC), rem = e % (9 * CC), tap = rem / CC, c = rem % CC;
-        const int ky = tap / 3, kx = tap % 3;
+        const int co = e / (NT * CC), rem = e % (NT * CC), tap = rem / CC, c = rem % CC;
+        const int ky = tap / KS, kx = tap % KS;
         for (int q = 0; q < BT * BT; ++q)
-          a += lt[q * COUT + co] * xt[((q / BT + ky) * BE + (q % BT) + kx) * CC + c];
+          a += lt[q * COUT + co] * xt[((q / BT + ky) * BK + (q % BT) + kx) * CC + c];
       } else {
         const int co = e - nw;
         for (int q = 0; q < BT * BT; ++q) a += lt[q * COUT + co];
@@ -564,55 +567,60 @@ __global__ __launch_bounds__(256) void bw_wgrad_c(int H, int W, const float* __r
 }
 
 // fixed-order sum of a chunk's partials into the layer's packed gradient
-// (W[Cout][3][3][Cin] then b[Cout])
-__global__ __launch_bounds__(256) void bw_part_finish_c(int nblocks, int cin, int cc, int cout,
+// (W[Cout][ks][ks][Cin] then b[Cout])
+__global__ __launch_bounds__(256) void bw_part_finish_c(int nblocks, int ks, int cin, int cc, int cout,
                                                         int ci0, const float* __restrict__ part,
                                                         float* __restrict__ out, int accumulate) {
-  const int nw = cout * 9 * cc, nout = nw + (ci0 == 0 ? cout : 0);
+  const int nt = ks * ks;
+  const int nw = cout * nt * cc, nout = nw + (ci0 == 0 ? cout : 0);
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nout) return;
   float acc = 0.f;
   for (int b = 0; b < nblocks; ++b) acc += part[(size_t)b * nout + e];
   size_t idx;
   if (e < nw) {
-    const int co = e / (9 * cc), rem = e % (9 * cc), tap = rem / cc, c = rem % cc;
-    idx = (size_t)co * 9 * cin + (size_t)tap * cin + ci0 + c;
+    const int co = e / (nt * cc), rem = e % (nt * cc), tap = rem / cc, c = rem % cc;
+    idx = (size_t)co * nt * cin + (size_t)tap * cin + ci0 + c;
   } else {
-    idx = (size_t)cout * 9 * cin + (e - nw);
+    idx = (size_t)cout * nt * cin + (e - nw);
   }
   out[idx] = accumulate ? out[idx] + acc : acc;
 }
 
-template <int CIN, int CC, int COUT>
+template <int KS, int CIN, int CC, int COUT>
 static hipError_t unet_wgrad_t(int H, int W, const float* in, const float* lam_pre, float* part,
                                size_t part_n, float* dst, int accumulate, hipStream_t s) {
-  constexpr int NACC = 36;
+  constexpr int NACC = 36, BK = BT + KS - 1;
   const int tiles = ((W + BT - 1) / BT) * ((H + BT - 1) / BT);
   const int gx = min(tiles, kWgBlocks);
-  const size_t lds = sizeof(float) * (BT * BT * COUT + BE * BE * CC);
-  auto k = bw_wgrad_c<CIN, CC, COUT, NACC>;
+  const size_t lds = sizeof(float) * (BT * BT * COUT + BK * BK * CC);
+  auto k = bw_wgrad_c<KS, CIN, CC, COUT, NACC>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   for (int ci0 = 0; ci0 < CIN; ci0 += CC) {
-    const int nout = COUT * 9 * CC + (ci0 == 0 ? COUT : 0);
+    const int nout = COUT * KS * KS * CC + (ci0 == 0 ? COUT : 0);
     if ((size_t)gx * nout > part_n) return hipErrorInvalidValue;
     const int gy = (nout + 256 * NACC - 1) / (256 * NACC);
     hipLaunchKernelGGL(k, dim3(gx, gy), dim3(256), lds, s, H, W, in, ci0, lam_pre, part);
-    hipLaunchKernelGGL(bw_part_finish_c, dim3((nout + 255) / 256), dim3(256), 0, s, gx, CIN, CC, COUT,
+    hipLaunchKernelGGL(bw_part_finish_c, dim3((nout + 255) / 256), dim3(256), 0, s, gx, KS, CIN, CC, COUT,
                        ci0, part, dst, accumulate);
   }
   return hipGetLastError();
 }
 
+// weight gradients of the FP32 layers of the Unet and of the cascades
 static hipError_t unet_wgrad(int cin, int cout, int H, int W, const float* in, const float* lam_pre,
                              float* part, size_t part_n, float* dst, int acc, hipStream_t s) {
-  if (cin == 2 && cout == 16) return unet_wgrad_t<2, 2, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
-  if (cin == 16 && cout == 16) return unet_wgrad_t<16, 16, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
-  if (cin == 16 && cout == 64) return unet_wgrad_t<16, 16, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
-  if (cin == 64 && cout == 64) return unet_wgrad_t<64, 64, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
-  if (cin == 128 && cout == 64) return unet_wgrad_t<128, 64, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
-  if (cin == 80 && cout == 16) return unet_wgrad_t<80, 80, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
-  if (cin == 32 && cout == 16) return unet_wgrad_t<32, 32, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 2 && cout == 16) return unet_wgrad_t<3, 2, 2, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 16 && cout == 16) return unet_wgrad_t<3, 16, 16, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 16 && cout == 64) return unet_wgrad_t<3, 16, 16, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 64 && cout == 64) return unet_wgrad_t<3, 64, 64, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 128 && cout == 64) return unet_wgrad_t<3, 128, 64, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 80 && cout == 16) return unet_wgrad_t<3, 80, 80, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 32 && cout == 16) return unet_wgrad_t<3, 32, 32, 16>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 64 && cout == 32) return unet_wgrad_t<3, 64, 64, 32>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 32 && cout == 64) return unet_wgrad_t<3, 32, 32, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+  if (cin == 32 && cout == 32) return unet_wgrad_t<3, 32, 32, 32>(H, W, in, lam_pre, part, part_n, dst, acc, s);
   return hipErrorInvalidValue;
 }
 
@@ -625,6 +633,9 @@ static hipError_t unet_dgrad(int cin, int cout, bool mask, int H, int W, const f
   if (cin == 64 && cout == 64)
     return mask ? dgrad_layer<float, 64, 64, true, false>(H, W, lam_pre, Wt, h_in, lam_in, s)
                 : dgrad_layer<float, 64, 64, false, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
+  if (cin == 32 && cout == 32 && mask) return dgrad_layer<float, 32, 32, true, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
+  if (cin == 64 && cout == 32 && mask) return dgrad_layer<float, 64, 32, true, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
+  if (cin == 32 && cout == 64 && mask) return dgrad_layer<float, 32, 64, true, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
   if (mask) return hipErrorInvalidValue;
   if (cin == 16 && cout == 64) return dgrad_layer<float, 16, 64, false, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
   if (cin == 128 && cout == 64) return dgrad_layer<float, 128, 64, false, false>(H, W, lam_pre, Wt, h_in, lam_in, s);
@@ -667,7 +678,8 @@ __global__ __launch_bounds__(256) void unet_pool_bw(int H, int W, int C, const f
 }
 
 // Upsampling adjoint: coarse (Hc, Wc, C) from the fine gradient's channels
-// [off, off + C) (`istr` per pixel), times the ReLU mask of the coarse map.
+// [off, off + C) (`istr` per pixel), times the ReLU mask of the coarse map
+// `act` (none when act is null).
 __global__ __launch_bounds__(256) void unet_up_bw(int Hc, int Wc, int C, const float* __restrict__ fine,
                                                   int istr, int off, const float* __restrict__ act,
                                                   float* __restrict__ out) {
@@ -693,7 +705,7 @@ __global__ __launch_bounds__(256) void unet_up_bw(int Hc, int Wc, int C, const f
       acc += wy * wx * fine[((size_t)J * Wf + I) * istr + off + c];
     }
   }
-  out[gid] = act[gid] > 0.f ? acc : 0.f;
+  out[gid] = (!act || act[gid] > 0.f) ? acc : 0.f;
 }
 
 static hipError_t unet_backward(int nx, int ny, const float* params, float* dparams, int acc,
@@ -784,6 +796,200 @@ static hipError_t unet_backward(int nx, int ny, const float* params, float* dpar
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The cascade's backward pass (Sec. 3.1's MultiScale / SmallScale, FP32
+// training).  The forward kept every branch input and layer output
+// (cascade.h).  Branches from the finest to the coarsest: the 1x1 head, the
+// 3x3 layers (ReLU masks of the layer below), the opening 5x5 layer down to
+// the gradient of the branch input, whose channel 0 (d / s) is kept per
+// scale and whose channel 2 (the up-sampled coarser output) goes through
+// the transposed bilinear x2 to the coarser branch's output.  Finally the
+// three channel-0 maps are summed at full resolution through the adjoints
+// of the input down-sampling (to 1/2: the 2x2 mean; to 1/4: the mean of the
+// central 2x2 pixels of every 4x4 block).
+// ---------------------------------------------------------------------------
+
+// Input gradient of a KS x KS layer (odd KS) with the replicate-padding
+// adjoint: output pixel p reads input clamp(p + o) at tap offset o, so
+// input pixel q receives every p with clamp(p + o) = q (one inside the map;
+// at the first and last row or column the ones that clamp onto it).
+template <int KS, int CIN, int COUT, bool MASK>
+__global__ __launch_bounds__(256) void bw_dgrad_k(int H, int W, const float* __restrict__ lam_pre,
+                                                  const float* __restrict__ Wt,
+                                                  const float* __restrict__ h_in,
+                                                  float* __restrict__ lam_in) {
+  constexpr int HK = KS / 2, BK = BT + 2 * HK;
+  extern __shared__ __attribute__((aligned(16))) float lds_k[];  // [BK*BK][COUT]
+  const int tiles_x = (W + BT - 1) / BT;
+  const int x0 = (blockIdx.x % tiles_x) * BT, y0 = (blockIdx.x / tiles_x) * BT;
+  for (int e = threadIdx.x; e < BK * BK * COUT; e += 256) {
+    const int q = e / COUT, co = e % COUT;
+    const int gy = y0 - HK + q / BK, gx = x0 - HK + q % BK;
+    lds_k[e] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? lam_pre[((size_t)gy * W + gx) * COUT + co] : 0.f;
+  }
+  __syncthreads();
+  const int y = y0 + threadIdx.x / BT, x = x0 + threadIdx.x % BT;
+  if (y >= H || x >= W) return;
+  // the range [lo, hi] of output positions p with clamp(p + o) = q
+  auto range = [](int q, int o, int n, int* lo, int* hi) {
+    if (q > 0 && q < n - 1) {
+      *lo = *hi = q - o;
+      if (q - o < 0 || q - o >= n) *hi = *lo - 1;
+    } else if (q == 0) {
+      *lo = 0;
+      *hi = o <= 0 ? min(-o, n - 1) : -1;
+    } else {
+      *lo = o >= 0 ? max(n - 1 - o, 0) : n;
+      *hi = n - 1;
+    }
+  };
+  float acc[CIN];
+#pragma unroll
+  for (int ci = 0; ci < CIN; ++ci) acc[ci] = 0.f;
+  for (int ky = 0; ky < KS; ++ky) {
+    int ya, yb;
+    range(y, ky - HK, H, &ya, &yb);
+    for (int kx = 0; kx < KS; ++kx) {
+      int xa, xb;
+      range(x, kx - HK, W, &xa, &xb);
+      const float* wk = Wt + (ky * KS + kx) * CIN;
+      for (int py = ya; py <= yb; ++py)
+        for (int px = xa; px <= xb; ++px) {
+          const float* lp = lds_k + ((py - y0 + HK) * BK + (px - x0 + HK)) * COUT;
+          for (int co = 0; co < COUT; ++co) {
+            const float l = lp[co];
+            const float* wr = wk + (size_t)co * KS * KS * CIN;
+#pragma unroll
+            for (int ci = 0; ci < CIN; ++ci) acc[ci] += wr[ci] * l;
+          }
+        }
+    }
+  }
+  const size_t pix = (size_t)y * W + x;
+#pragma unroll
+  for (int ci = 0; ci < CIN; ++ci) {
+    float v = acc[ci];
+    if (MASK) v = h_in[pix * CIN + ci] > 0.f ? v : 0.f;
+    lam_in[pix * CIN + ci] = v;
+  }
+}
+
+template <int KS, int CIN, int COUT>
+static hipError_t dgrad_k(int H, int W, const float* lam_pre, const float* Wt, float* lam_in,
+                          hipStream_t s) {
+  constexpr int BK = BT + KS - 1;
+  const int tiles = ((W + BT - 1) / BT) * ((H + BT - 1) / BT);
+  const size_t lds = sizeof(float) * BK * BK * COUT;
+  auto k = bw_dgrad_k<KS, CIN, COUT, false>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(tiles), dim3(256), lds, s, H, W, lam_pre, Wt, nullptr, lam_in);
+  return hipGetLastError();
+}
+
+// the opening 5x5 layer of a branch: weight gradient and input gradient
+static hipError_t pn_first_bw(int cin, int cout, int H, int W, const float* in, const float* lam_pre,
+                              const float* Wt, float* part, size_t part_n, float* dst, int acc,
+                              float* lam_in, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (cin == 2 && cout == 64) {
+    if (dst) e = unet_wgrad_t<5, 2, 2, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+    return e != hipSuccess ? e : dgrad_k<5, 2, 64>(H, W, lam_pre, Wt, lam_in, s);
+  }
+  if (cin == 3 && cout == 64) {
+    if (dst) e = unet_wgrad_t<5, 3, 3, 64>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+    return e != hipSuccess ? e : dgrad_k<5, 3, 64>(H, W, lam_pre, Wt, lam_in, s);
+  }
+  if (cin == 2 && cout == 32) {
+    if (dst) e = unet_wgrad_t<5, 2, 2, 32>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+    return e != hipSuccess ? e : dgrad_k<5, 2, 32>(H, W, lam_pre, Wt, lam_in, s);
+  }
+  if (cin == 3 && cout == 32) {
+    if (dst) e = unet_wgrad_t<5, 3, 3, 32>(H, W, in, lam_pre, part, part_n, dst, acc, s);
+    return e != hipSuccess ? e : dgrad_k<5, 3, 32>(H, W, lam_pre, Wt, lam_in, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// lam_x at full resolution += the adjoints of the down-sampled copies:
+// a quarter of the half-resolution value of the 2x2 block, and a quarter of
+// the quarter-resolution value for the central 2x2 pixels of a 4x4 block
+__global__ __launch_bounds__(256) void pn_x_combine(int nx, int ny, float* __restrict__ l0,
+                                                    const float* __restrict__ l1,
+                                                    const float* __restrict__ l2) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nx * ny) return;
+  const int i = c % nx, j = c / nx;
+  float a = l0[c] + 0.25f * l1[(j >> 1) * (nx >> 1) + (i >> 1)];
+  const int ri = i & 3, rj = j & 3;
+  if ((ri == 1 || ri == 2) && (rj == 1 || rj == 2)) a += 0.25f * l2[(j >> 2) * (nx >> 2) + (i >> 2)];
+  l0[c] = a;
+}
+
+static hipError_t cascade_backward(int arch, const WsLayout& Ly, int nx, int ny, const float* params,
+                                   float* dparams, int acc, const Ws& w, hipStream_t s) {
+  const PnSave SV = pn_save_layout(arch, nx, ny);
+  const float* save = reinterpret_cast<const float*>(w.cnn_save);
+  PnLayer Lb[kPnBranches][kPnMaxLayers];
+  size_t poff[kPnBranches][kPnMaxLayers];
+  int nl[kPnBranches];
+  size_t o = 0;
+  for (int b = 0; b < kPnBranches; ++b) {
+    nl[b] = pn_branch(arch, b, Lb[b]);
+    for (int i = 0; i < nl[b]; ++i) {
+      poff[b][i] = o;
+      o += (size_t)Lb[b][i].ks * Lb[b][i].ks * Lb[b][i].cin * Lb[b][i].cout + Lb[b][i].cout;
+    }
+  }
+  float* A = w.bw_a;
+  float* B = w.bw_b;
+  hipError_t e = hipSuccess;
+  for (int b = kPnBranches - 1; b >= 0; --b) {
+    const int k = kPnBranches - 1 - b;  // scale index, 0 = finest
+    const int H = Ly.sc_h[k], W = Ly.sc_w[k], npx = H * W;
+    const float* lam_y = w.bw_t + Ly.sc_off_px[k];
+    // the 1x1 head; its input layer has no ReLU
+    const int hi = nl[b] - 1, C = Lb[b][hi].cin, nbh = (npx + 255) / 256;
+    if ((size_t)nbh * (C + 1) > w.bw_part_n) return hipErrorInvalidValue;
+    const float* hin = save + SV.out[b][hi - 1];
+    if (C == 64)
+      hipLaunchKernelGGL((bw_head<float, 64, false>), dim3(nbh), dim3(256), 0, s, npx, lam_y, hin,
+                         params + poff[b][hi], A, w.bw_part);
+    else
+      hipLaunchKernelGGL((bw_head<float, 32, false>), dim3(nbh), dim3(256), 0, s, npx, lam_y, hin,
+                         params + poff[b][hi], A, w.bw_part);
+    if (dparams)
+      hipLaunchKernelGGL(bw_part_finish, dim3(1), dim3(256), 0, s, nbh, C + 1, w.bw_part,
+                         dparams + poff[b][hi], acc);
+    // 3x3 layers: A holds the gradient of layer i's pre-activation
+    for (int i = hi - 1; i >= 1; --i) {
+      const PnLayer& l = Lb[b][i];
+      const float* in = save + SV.out[b][i - 1];
+      if (dparams && (e = unet_wgrad(l.cin, l.cout, H, W, in, A, w.bw_part, w.bw_part_n, dparams + poff[b][i],
+                                     acc, s)) != hipSuccess)
+        return e;
+      if ((e = unet_dgrad(l.cin, l.cout, Lb[b][i - 1].relu, H, W, A, params + poff[b][i], in, B, s)) != hipSuccess)
+        return e;
+      float* t = A; A = B; B = t;
+    }
+    // the opening 5x5 layer down to the branch input's gradient (in B)
+    const PnLayer& l0 = Lb[b][0];
+    if ((e = pn_first_bw(l0.cin, l0.cout, H, W, save + SV.in[b], A, params + poff[b][0], w.bw_part,
+                         w.bw_part_n, dparams ? dparams + poff[b][0] : nullptr, acc, B, s)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(unet_skip_copy, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, (size_t)npx, 1, B,
+                       l0.cin, w.bw_x + Ly.sc_off_px[k]);
+    if (b > 0) {
+      const size_t nc = (size_t)(H / 2) * (W / 2);
+      hipLaunchKernelGGL(unet_up_bw, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, H / 2, W / 2, 1, B,
+                         l0.cin, 2, (const float*)nullptr, w.bw_t + Ly.sc_off_px[k + 1]);
+    }
+  }
+  hipLaunchKernelGGL(pn_x_combine, dim3((nx * ny + 255) / 256), dim3(256), 0, s, nx, ny,
+                     w.bw_x + Ly.sc_off_px[0], w.bw_x + Ly.sc_off_px[1], w.bw_x + Ly.sc_off_px[2]);
+  return hipGetLastError();
+}
+
 hipError_t run_backward(const NetShape& net, const WsLayout& Ly, int nx, int ny, double dx,
                         int sweeps, float omega, double scale, bool accumulate,
                         const float* params, float* du, float* dv, float* dparams,
@@ -805,8 +1011,8 @@ hipError_t run_backward(const NetShape& net, const WsLayout& Ly, int nx, int ny,
     bw_jacobi<<<nb, 256, 0, s>>>(nx, ny, omega, wdx2, w.cell, cur, nxt, lamD);
     float* t = cur; cur = nxt; nxt = t;
   }
-  // CNN (the Unet's output y is the full-resolution map phi0 = dx^2 s y)
-  const bool unet = net.arch == HYP_ARCH_UNET;
+  // CNN (the paper networks' output y is the full-resolution map phi0 = dx^2 s y)
+  const bool unet = net.arch != HYP_ARCH_PARALLEL;
   bw_phi0<<<nb, 256, 0, s>>>(n, (float)(dx * dx), w.cell, cur, unet ? w.cnn_y : w.cnn_t, w.bw_t,
                              w.blockpart, w.sc);
   bw_lams_set<<<1, 256, 0, s>>>(nb, w.blockpart, dx * dx, w.sc);
@@ -820,7 +1026,8 @@ hipError_t run_backward(const NetShape& net, const WsLayout& Ly, int nx, int ny,
   const int acc = accumulate ? 1 : 0;
   if (unet) {
     if (net.precision != HYP_PREC_FP32) return hipErrorInvalidValue;
-    e = unet_backward(nx, ny, params, dparams, acc, w, s);
+    e = net.arch == HYP_ARCH_UNET ? unet_backward(nx, ny, params, dparams, acc, w, s)
+                                  : cascade_backward(net.arch, Ly, nx, ny, params, dparams, acc, w, s);
   } else if (net.precision == HYP_PREC_BF16) {
     switch (net.channels) {
       case 32: e = backward_cnn<uint16_t, 32>(net, Ly, nx, ny, params, dparams, acc, w, s); break;

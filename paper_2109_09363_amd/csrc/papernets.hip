@@ -31,18 +31,11 @@
 #include "common.h"
 #include "conv_mfma.h"
 #include "internal.h"
+#include "cascade.h"
 #include "unet.h"
 
 namespace hyp {
 
-struct PnLayer {
-  int ks, cin, cout;
-  bool relu;
-};
-
-constexpr int kPnMaxLayers = 7;
-static int pn_branch_def(int arch, int b, PnLayer* out);
-static int pn_branch(int arch, int b, PnLayer* out) { return pn_branch_def(arch, b, out); }
 
 // Unet layers in parameter order: encoder scales 0..4 (two each), decoder
 // scales 3..0 (two each), the 1x1 output.
@@ -76,22 +69,6 @@ static size_t wimg_elems(const PnLayer& l, int elt) {
 }
 
 size_t unet_cat_elems(int nx, int ny) { return unet_cat_offset(nx, ny, kUnetLevels - 1); }
-
-// Layers of branch b (0 = coarsest); returns the layer count.
-static int pn_branch_def(int arch, int b, PnLayer* out) {
-  const int a = arch == HYP_ARCH_MULTISCALE ? 64 : 32;
-  const int mid = 32;
-  if (b == 0) {
-    const PnLayer L[5] = {{5, 2, a, true}, {3, a, a, true}, {3, a, a, true}, {3, a, a, false},
-                          {1, a, 1, false}};
-    for (int i = 0; i < 5; ++i) out[i] = L[i];
-    return 5;
-  }
-  const PnLayer L[7] = {{5, 3, a, true},   {3, a, a, true}, {3, a, mid, true}, {3, mid, a, true},
-                        {3, a, a, true},   {3, a, a, false}, {1, a, 1, false}};
-  for (int i = 0; i < 7; ++i) out[i] = L[i];
-  return 7;
-}
 
 int64_t pn_param_count(int arch) {
   PnLayer L[kUnetLayers];
@@ -328,6 +305,11 @@ static hipError_t run_pn_t(const Device& dev, const NetShape& net, const WsLayou
   if (err != hipSuccess) return err;
   T* in = reinterpret_cast<T*>(w.cnn_in);
   T* bufs[2] = {reinterpret_cast<T*>(w.cnn_act0), reinterpret_cast<T*>(w.cnn_act1)};
+  // with net.train every branch input and layer output goes to its own
+  // buffer of the saved activations (cascade.h) for the backward pass
+  const bool train = net.train && w.cnn_save;
+  const PnSave SV = pn_save_layout(net.arch, nx, ny);
+  T* save = reinterpret_cast<T*>(w.cnn_save);
   const float* yc = nullptr;
   int Hc = 0, Wc = 0, li = 0;
   for (int b = 0; b < 3; ++b) {
@@ -336,14 +318,15 @@ static hipError_t run_pn_t(const Device& dev, const NetShape& net, const WsLayou
     const int npx = H * W;
     PnLayer L[kPnMaxLayers];
     const int nl = pn_branch(net.arch, b, L);
+    T* bin = train ? save + SV.in[b] : in;
     hipLaunchKernelGGL((pn_input<T>), dim3((npx + 255) / 256), dim3(256), 0, s, H, W, f, nx, w.d,
-                       w.cell, w.sc, yc, Hc, Wc, in);
+                       w.cell, w.sc, yc, Hc, Wc, bin);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
-    const T* src = in;
+    const T* src = bin;
     int used = 0;
     for (int i = 0; i + 1 < nl; ++i, ++li) {
-      T* dst = bufs[used];
+      T* dst = train ? save + SV.out[b][i] : bufs[used];
       used ^= 1;
       err = pn_layer<T>(dev, P, li, params, img, src, dst, P.layer[li].cout, H, W, s);
       if (err != hipSuccess) return err;

@@ -1,5 +1,5 @@
-"""Solver-in-the-loop training of the multi-scale CNN (or the paper's Unet,
---arch unet, FP32) on the GPU.
+"""Solver-in-the-loop training of the multi-scale CNN (or of the paper's own
+networks, --arch multiscale / smallscale / unet, FP32) on the GPU.
 
 The physics-driven loss of Sec. 3.2: the divergence left in the corrected
 velocity, here after the CNN guess and K Jacobi sweeps (the hybrid's own
@@ -19,7 +19,7 @@ projection, CNN forward/backward and Adam.
 
 python -m paper_2109_09363_amd.train --n 128 --scales 4 --channels 64 \
     --precision bf16 --steps 400 --out weights.npy
-The paper's Unet (Sec. 3.1, Fig. 4):
+The paper's Unet (Sec. 3.1, Fig. 4), or its cascaded MultiScale (Fig. 3):
 python -m paper_2109_09363_amd.train --arch unet --n 128 --precision fp32 \
     --steps 600 --sweeps 16 --eval 8 --out unet.npy
 Fine-tuning at the benchmark resolution from existing weights, judged by the
@@ -137,8 +137,8 @@ def unrolled_backward(pr, smp: Sample, sweeps: int, n_unroll: int, alpha: float,
 def initial_weights(arch: str, scales: int, channels: int, seed: int):
     """Seeded random init with a small output layer (the first guesses stay
     near zero)."""
-    if arch == "unet":
-        return scenes.random_paper_weights("unet", seed, out_scale=0.1)
+    if arch in ("unet", "multiscale", "smallscale"):
+        return scenes.random_paper_weights(arch, seed, out_scale=0.1)
     return scenes.random_weights(scales, channels, seed, out_scale=0.1)
 
 
@@ -257,7 +257,7 @@ def main():
     ap.add_argument("--alpha", type=float, default=1.0, help="weight of the short-term loss")
     ap.add_argument("--beta", type=float, default=0.0,
                     help="weight of the long-term loss (4 or 16 unrolled steps)")
-    ap.add_argument("--arch", default="parallel", choices=["parallel", "unet"])
+    ap.add_argument("--arch", default="parallel", choices=["parallel", "multiscale", "smallscale", "unet"])
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     params0 = None

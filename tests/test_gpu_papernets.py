@@ -187,8 +187,8 @@ def test_unet_hybrid_parity():
 
 def test_papernet_rejects_training_and_bad_shapes():
     from paper_2109_09363_amd import _lib as L
-    with pytest.raises(L.HypError):
-        hp.Projector(64, 64, 1 / 64, arch="multiscale", train=True)
+    with pytest.raises(L.HypError):  # the paper's networks train in FP32 only
+        hp.Projector(64, 64, 1 / 64, precision="bf16", arch="multiscale", train=True)
     with pytest.raises(L.HypError):
         hp.Projector(64, 64, 1 / 64, channels=32, arch="multiscale")
     with pytest.raises(L.HypError):  # the Unet trains in FP32 only

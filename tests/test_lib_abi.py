@@ -50,7 +50,7 @@ def test_host_side_rejections():
     assert lib.hyp_create(ctypes.byref(ctx), ctypes.byref(bad)) == -1
     bad = L.NetDesc(0, 32, 0, 0)
     assert lib.hyp_create(ctypes.byref(ctx), ctypes.byref(bad)) == -1
-    # the cascaded networks: fixed widths, inference only, known parameter totals
+    # the cascaded networks: fixed widths, known parameter totals, training in FP32 only
     for arch, C, n in ((1, 64, 419459), (2, 32, 126819)):
         c2 = ctypes.c_void_p()
         assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(0, 0, 1, 0, arch))) == 0
@@ -60,7 +60,9 @@ def test_host_side_rejections():
         lib.hyp_destroy(c2)
         assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(3, C + 32, 0, 0, arch))) == -1
         assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(4, C, 0, 0, arch))) == -1
-        assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(3, C, 0, 1, arch))) == -2
+        assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(3, C, 0, 1, arch))) == 0
+        lib.hyp_destroy(c2)
+        assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(3, C, 1, 1, arch))) == -2
     c2 = ctypes.c_void_p()
     assert lib.hyp_create(ctypes.byref(c2), ctypes.byref(L.NetDesc(0, 0, 1, 0, 3))) == 0
     assert lib.hyp_param_count(c2) == 443441  # the Unet
