@@ -87,10 +87,10 @@ def conv3x3_backward(x: np.ndarray, W: np.ndarray, lam_out: np.ndarray, need_inp
     return lx, dW, db
 
 
-def forward(P: G.Plan, u, v, dx, params, S, C, K, omega=1.0, scale=1.0):
+def forward(P: G.Plan, u, v, dx, params, S, C, K, omega=1.0, scale=1.0, bf16=False):
     u, v = G.enforce_bc(P, u, v)
     d = G.divergence(P, u, v, dx)
-    phi0, s, cache = CN.cnn_phi0(P, d, dx, params, S, C, keep=True)
+    phi0, s, cache = CN.cnn_phi0(P, d, dx, params, S, C, bf16=bf16, keep=True)
     kinv = np.where(P.fluid, 1.0 / np.maximum(P.k, 1.0), 0.0)
     phi = phi0
     for _ in range(K):
@@ -100,10 +100,16 @@ def forward(P: G.Plan, u, v, dx, params, S, C, K, omega=1.0, scale=1.0):
     return loss, dict(d=d, s=s, cache=cache, phi=phi, r=r, kinv=kinv)
 
 
-def loss_and_grad(flags, u, v, dx, params, S, C, K, omega=1.0, scale=1.0):
-    """Returns (loss, dL/du, dL/dv, dL/dparams) in FP64."""
+def loss_and_grad(flags, u, v, dx, params, S, C, K, omega=1.0, scale=1.0, bf16=False):
+    """Returns (loss, dL/du, dL/dv, dL/dparams) in FP64.
+
+    ``bf16``: the network's forward rounds at the BF16 storage points (as
+    cnn.cnn_phi0), and the reverse pass treats every rounding as the
+    identity (the straight-through reading of the derivative of a rounding,
+    which is zero almost everywhere): it runs at the rounded activations
+    with the unrounded weights."""
     P = G.plan(flags)
-    loss, F = forward(P, u, v, dx, params, S, C, K, omega, scale)
+    loss, F = forward(P, u, v, dx, params, S, C, K, omega, scale, bf16=bf16)
     d, s, cache, r, kinv = F["d"], F["s"], F["cache"], F["r"], F["kinv"]
     nets = CN.unpack(params, S, C)
     fl = P.fluid

@@ -71,14 +71,24 @@ def test_backward_matches_oracle(n, ny, S, C, K, omega, seed):
     assert rel_l2(g["dv"], gv) <= 1e-4
 
 
-def test_backward_bf16_close_to_fp64():
-    sc, u, v = state(64, 4, 1)
-    w = f32(scenes.random_weights(3, 32, 4))
-    g = Run(sc, 3, 32, "bf16")(u, v, w, 4)
-    loss, gu, gv, gp = AJ.loss_and_grad(sc.flags, u, v, sc.dx, w, 3, 32, 4)
-    say("  bf16 rel L2 dparams", rel_l2(g["dp"], gp), "du", rel_l2(g["du"], gu))
-    # BF16 activations: the straight-through gradient of the BF16 forward
-    assert rel_l2(g["dp"], gp) <= 0.15 and rel_l2(g["du"], gu) <= 0.15
+@pytest.mark.parametrize("n,S,C,K,seed", [(64, 3, 32, 4, 4), (128, 4, 64, 8, 6)])
+def test_backward_bf16_matches_emulated_oracle(n, S, C, K, seed):
+    """The BF16 network's gradient (what training with --precision bf16
+    uses) against the oracle's gradient of the same BF16-emulated forward
+    with the straight-through reverse pass (rounded activations, unrounded
+    weights): differences come from FP32 against FP64 accumulation and the
+    few roundings that the two take differently; the unemulated FP64
+    gradient is further away."""
+    sc, u, v = state(n, seed, 2)
+    w = f32(scenes.random_weights(S, C, seed))
+    g = Run(sc, S, C, "bf16")(u, v, w, K)
+    loss, gu, gv, gp = AJ.loss_and_grad(sc.flags, u, v, sc.dx, w, S, C, K, bf16=True)
+    _l64, gu64, _gv64, gp64 = AJ.loss_and_grad(sc.flags, u, v, sc.dx, w, S, C, K)
+    ep, eu, ev = rel_l2(g["dp"], gp), rel_l2(g["du"], gu), rel_l2(g["dv"], gv)
+    say(f"  bf16 vs emulated: dparams {ep:.2e} du {eu:.2e} dv {ev:.2e}; vs FP64 network: dparams "
+        f"{rel_l2(g['dp'], gp64):.2e} du {rel_l2(g['du'], gu64):.2e}; loss {g['loss']:.6e} vs {loss:.6e}")
+    assert g["loss"] == pytest.approx(loss, rel=1e-3)
+    assert ep <= 1e-2 and eu <= 1e-2 and ev <= 1e-2
 
 
 def test_backward_deterministic_and_accumulate():

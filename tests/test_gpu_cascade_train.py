@@ -106,7 +106,8 @@ def test_cascade_training_gain():
     w, hist = TR.train(data, n, 0, 0, "fp32", steps=300, batch=4, lr=1e-3, sweeps=8, seed=2,
                        log=say, log_every=50, arch=arch)
     say("loss history", hist)
-    assert hist[-1][1] < 0.5 * hist[0][1]
+    # single-batch losses are noisy: the mean of the last three logged ones
+    assert np.mean([h[1] for h in hist[-3:]]) < 0.5 * hist[0][1]
     held = TR.plume_states(n, 6, 30, seed=777)
     zero = w.copy()
     zero[-33:] = 0.0  # the finest branch's output layer 0: the guess is 0, plain Jacobi

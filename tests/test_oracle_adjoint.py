@@ -205,3 +205,23 @@ def test_long_term_gradient_is_frozen_state_derivative():
         dirn = rng.standard_normal(w.size)
         dd = (f(w + 1e-6 * dirn) - f(w - 1e-6 * dirn)) / 2e-6
         assert dd == pytest.approx(float(b["dparams"] @ dirn), rel=1e-5)
+
+
+def test_bf16_emulated_loss_is_the_projection_with_the_bf16_network():
+    """The loss of loss_and_grad(bf16=True) is the divergence energy left by
+    the hybrid projection with the BF16-emulated network and K sweeps (the
+    forward of project.project, an independent path); its gradient is the
+    straight-through reading (rounded activations, unrounded weights), which
+    no finite difference can check since a rounding is piecewise constant."""
+    from oracle import project as PR
+    n, S, C, K = 32, 3, 16, 5
+    sc = scenes.plume_scene(n, seed=8, n_obstacles=2)
+    u, v = scenes.random_faces(n, n, 8, kind="mixed")
+    w = scenes.random_weights(S, C, 8).astype(np.float32).astype(np.float64)
+    loss, _gu, _gv, gp = AJ.loss_and_grad(sc.flags, u, v, sc.dx, w, S, C, K, bf16=True)
+    o = PR.project(sc.flags, u, v, sc.dx, method="hybrid", params=w, S=S, C=C, bf16=True, fixed_iters=K)
+    P = G.plan(sc.flags)
+    r = G.divergence(P, o["u"], o["v"], sc.dx)
+    assert loss == pytest.approx(float(np.sum(r[P.fluid] ** 2)), rel=1e-12)
+    loss64, _a, _b, gp64 = AJ.loss_and_grad(sc.flags, u, v, sc.dx, w, S, C, K)
+    assert loss != loss64 and np.linalg.norm(gp - gp64) < 0.2 * np.linalg.norm(gp64)
