@@ -385,7 +385,9 @@ hipError_t batch_setup(void* area, int n, int ntiles, size_t cnn_bytes, const BI
     // work-groups of each launch shape
     const int nc = B.nx * B.ny, nu = B.ny * (B.nx + 1), nv = (B.ny + 1) * B.nx;
     int cnt[RK_COUNT] = {0};
-    cnt[RK_CELL] = (nc + 255) / 256;
+    // the cell kernels stride over their instance's cells: a bounded grid
+    // keeps each instance's FP64 block partials few (as the single-grid launches)
+    cnt[RK_CELL] = (nc + 255) / 256 < kStreamGrid ? (nc + 255) / 256 : kStreamGrid;
     cnt[RK_FACE] = (nu + nv + 255) / 256;
     cnt[RK_ADV] = (nc + nu + nv + 255) / 256;
     cnt[RK_REG] = B.S > 0 ? ((B.nx + 31) / 32) * ((B.ny + 31) / 32) : 0;

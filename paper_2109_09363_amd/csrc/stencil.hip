@@ -201,6 +201,23 @@ hipError_t run_plan(const Device& dev, int nx, int ny, const uint8_t* flags, con
 // so that the single-grid launches and the batched ones (one launch over
 // all instances, batch.h) share them.
 // ---------------------------------------------------------------------------
+// Grid-stride walk over the cells of an nx-wide grid that keeps the column
+// and row incrementally: one division per thread instead of one per cell.
+struct CellWalk {
+  int c, i, j, di, dj, stride;
+  __device__ CellWalk(int c0, int stride_, int nx)
+      : c(c0), i(c0 % nx), j(c0 / nx), di(stride_ % nx), dj(stride_ / nx), stride(stride_) {}
+  __device__ void next(int nx) {
+    c += stride;
+    i += di;
+    j += dj;
+    if (i >= nx) {
+      i -= nx;
+      ++j;
+    }
+  }
+};
+
 __device__ __forceinline__ void div_body(int lb, int nb, int nx, int ny, float inv_dx,
                                          const uint8_t* __restrict__ cell, float* u, float* v,
                                          float* __restrict__ d, double* __restrict__ blockpart,
@@ -214,9 +231,9 @@ __device__ __forceinline__ void div_body(int lb, int nb, int nx, int ny, float i
   // grid-stride: a bounded grid keeps the per-block reduction cheap at
   // DRAM-resident sizes; faces are written back only where masking changed them
 #pragma unroll 4
-  for (int c = c0; c < nx * ny; c += stride) {
+  for (CellWalk w(c0, stride, nx); w.c < nx * ny; w.next(nx)) {
+    const int c = w.c, i = w.i, j = w.j, U = nx + 1;
     phi_acc[c] = 0.f;
-    const int i = c % nx, j = c / nx, U = nx + 1;
     const uint8_t ci = cell[c];
     const bool fl = !(ci & C_SOLID);
     const float uw0 = u[j * U + i], ue = u[j * U + i + 1];
@@ -321,8 +338,8 @@ __device__ __forceinline__ void grad_body(int lb, int nb, int nx, int ny, float 
                                           float* __restrict__ p, const float* __restrict__ ce,
                                           const float* __restrict__ cn) {
 #pragma unroll 4
-  for (int c = lb * blockDim.x + threadIdx.x; c < nx * ny; c += nb * blockDim.x) {
-    const int i = c % nx, j = c / nx, U = nx + 1;
+  for (CellWalk w(lb * blockDim.x + threadIdx.x, nb * blockDim.x, nx); w.c < nx * ny; w.next(nx)) {
+    const int c = w.c, i = w.i, j = w.j, U = nx + 1;
     const uint8_t ci = cell[c];
     const bool fl = !(ci & C_SOLID);
     const float pc = phi[c];
@@ -392,8 +409,8 @@ __device__ __forceinline__ void check_body(int lb, int nb, int nx, int ny, float
                                            double* __restrict__ blockpart, double* red) {
   double a = 0.0, m = 0.0;
 #pragma unroll 4
-  for (int c = lb * blockDim.x + threadIdx.x; c < nx * ny; c += nb * blockDim.x) {
-    const int i = c % nx, j = c / nx, U = nx + 1;
+  for (CellWalk w(lb * blockDim.x + threadIdx.x, nb * blockDim.x, nx); w.c < nx * ny; w.next(nx)) {
+    const int c = w.c, i = w.i, j = w.j, U = nx + 1;
     if (!(cell[c] & C_SOLID)) {
       const float dv = ((u[j * U + i + 1] - u[j * U + i]) + (v[(j + 1) * nx + i] - v[j * nx + i])) * inv_dx;
       const double ad = fabs((double)dv);
@@ -508,8 +525,8 @@ __global__ __launch_bounds__(256) void coef_batch(const BInst* __restrict__ I, c
   const BLoc l = batch_loc(first, n);
   const BInst& B = I[l.i];
   if (!B.var) return;
-  coef_body(l.lb * blockDim.x + threadIdx.x, B.nx, B.ny, B.rho0, B.w.cell, B.rho, B.w.coef_e,
-            B.w.coef_n);
+  for (int c = l.lb * blockDim.x + threadIdx.x; c < B.nx * B.ny; c += l.nb * blockDim.x)
+    coef_body(c, B.nx, B.ny, B.rho0, B.w.cell, B.rho, B.w.coef_e, B.w.coef_n);
 }
 
 hipError_t run_coef_batch(const BInst* I, const BatchRanges& R, hipStream_t s) {
@@ -521,8 +538,7 @@ __global__ __launch_bounds__(256) void init_phi_batch(const BInst* __restrict__ 
                                                       int n) {
   const BLoc l = batch_loc(first, n);
   const BInst& B = I[l.i];
-  const int c = l.lb * blockDim.x + threadIdx.x;
-  if (c < B.nx * B.ny) B.w.phi[c] = 0.f;
+  for (int c = l.lb * blockDim.x + threadIdx.x; c < B.nx * B.ny; c += l.nb * blockDim.x) B.w.phi[c] = 0.f;
 }
 
 hipError_t run_init_phi_batch(const BInst* I, const BatchRanges& R, hipStream_t s) {
