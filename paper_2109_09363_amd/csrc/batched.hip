@@ -81,13 +81,13 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
     if (col_in && gy >= 0 && gy < I.ny) {
       // the loads are independent (masked afterwards): one round trip
       const int g = gy * I.nx + gx;
-      const uint8_t ci = I.cell[g];
-      const float dv = I.d[g];
-      const float pv = from_phi ? I.phi[g] : ld_agent(src + g);
+      const uint8_t ci = gld(I.cell + g);
+      const float dv = gld(I.d + g);
+      const float pv = from_phi ? gld(I.phi + g) : ld_agent(src + g);
       if (!(ci & C_SOLID)) {
         if constexpr (VAR) {
-          const float e_ = (ci & C_E) ? I.ce[g] : 0.f, w_ = (ci & C_W) ? I.ce[g - 1] : 0.f;
-          const float n_ = (ci & C_N) ? I.cn[g] : 0.f, s_ = (ci & C_S) ? I.cn[g - I.nx] : 0.f;
+          const float e_ = (ci & C_E) ? gld(I.ce + g) : 0.f, w_ = (ci & C_W) ? gld(I.ce + g - 1) : 0.f;
+          const float n_ = (ci & C_N) ? gld(I.cn + g) : 0.f, s_ = (ci & C_S) ? gld(I.cn + g - I.nx) : 0.f;
           const float k = (e_ + w_) + (n_ + s_);
           const float sc = I.omega / k;
           be[r] = e_ * sc; bw[r] = w_ * sc; bn[r] = n_ * sc; bs[r] = s_ * sc;
@@ -195,11 +195,11 @@ __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
   for (int nb = 0;; ++nb) {
     // phase A: sweep every tile of a running instance
     for (int t = blockIdx.x; t < P.ntiles; t += G) {
-      const int i = P.tile_inst[t];
-      const BatchInstDev& I = P.inst[i];
-      const int sti = __hip_atomic_load(&P.st[i].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int i = cld_int(P.tile_inst + t);
+      const BatchInstDev I = cld(P.inst, i);
+      const int sti = ld_agent(&P.st[i].status);
       if (sti >= 0) continue;
-      const int k = __hip_atomic_load(&P.st[i].iters, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int k = ld_agent(&P.st[i].iters);
       const int b = nb == 0 ? 0 : min(B, I.max_iters - k);
       const float* src = I.exch + (size_t)par * I.nx * I.ny;
       float* dst = I.exch + (size_t)(par ^ 1) * I.nx * I.ny;
@@ -213,11 +213,11 @@ __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
     }
     // phase B: one work-group per instance sums its tiles in order and decides
     for (int i = blockIdx.x; i < P.ninst; i += G) {
-      const BatchInstDev& I = P.inst[i];
-      if (__hip_atomic_load(&P.st[i].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) continue;
+      const BatchInstDev I = cld(P.inst, i);
+      if (ld_agent(&P.st[i].status) >= 0) continue;
       const double tot = sum_partials(P.tile_part + (size_t)(par ^ 1) * P.ntiles + I.tile0, I.ntiles, red);
       if (threadIdx.x == 0) {
-        int k = P.st[i].iters;
+        int k = ld_agent(&P.st[i].iters);
         if (nb > 0) k += min(B, I.max_iters - k);
         const int nF = I.sc->nF;
         const double E = nF > 0 ? tot / nF : 0.0;
@@ -227,9 +227,9 @@ __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
         else if (k >= I.max_iters) st = HYP_STATUS_MAXITER;
         if (nb == 0) I.sc->e1_cnn = E;
         P.st[i].E = E;
-        __hip_atomic_store(&P.st[i].fpar, par ^ 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&P.st[i].iters, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&P.st[i].status, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st_agent(&P.st[i].fpar, par ^ 1);
+        st_agent(&P.st[i].iters, k);
+        st_agent(&P.st[i].status, st);
         if (st >= 0) {
           I.sc->iters = k;
           I.sc->status = st;
@@ -244,22 +244,22 @@ __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
     }
     int running = 0;
     for (int i = threadIdx.x; i < P.ninst; i += blockDim.x)
-      running += __hip_atomic_load(&P.st[i].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0;
+      running += ld_agent(&P.st[i].status) < 0;
     running = (int)block_sum((double)running, red);
     par ^= 1;
     if (running == 0) break;
   }
   // epilogue: the returned iterate of every tile into the instance's phi
   for (int t = blockIdx.x; t < P.ntiles; t += G) {
-    const int i = P.tile_inst[t];
-    const BatchInstDev& I = P.inst[i];
-    const int fp = __hip_atomic_load(&P.st[i].fpar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int i = cld_int(P.tile_inst + t);
+    const BatchInstDev I = cld(P.inst, i);
+    const int fp = ld_agent(&P.st[i].fpar);
     const float* src = I.exch + (size_t)fp * I.nx * I.ny;
     const int TW = 64 - 2 * kBatchH, TH = 4 * I.R - 2 * kBatchH;
     const int lt = t - I.tile0, bx = lt % I.ntx, by = lt / I.ntx;
     for (int e = threadIdx.x; e < TW * TH; e += blockDim.x) {
       const int gx = bx * TW + e % TW, gy = by * TH + e / TW;
-      if (gx < I.nx && gy < I.ny) I.phi[gy * I.nx + gx] = ld_agent(src + gy * I.nx + gx);
+      if (gx < I.nx && gy < I.ny) gst(I.phi + gy * I.nx + gx, ld_agent(src + gy * I.nx + gx));
     }
   }
 }

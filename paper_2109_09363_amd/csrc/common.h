@@ -17,6 +17,34 @@ enum : uint8_t {
   C_SOLID = 1, C_INFLOW = 2, C_E = 4, C_W = 8, C_N = 16, C_S = 32
 };
 
+// ---- global-memory access through pointers held in descriptors ------------
+// A pointer read from memory (a descriptor table, a struct picked by a
+// run-time index) is generic to the compiler, which then emits flat loads
+// and stores.  Flat operations also count against the LDS wait counter, so
+// every LDS wait of the kernel waits for them too: a prefetch issued before
+// LDS-fed math stalls the first LDS read.  These accessors state that the
+// memory is global.
+template <typename T> using gmem = __attribute__((address_space(1))) T;
+template <typename T> __device__ __forceinline__ T gld(const T* p) { return *(const gmem<T>*)p; }
+template <typename T> __device__ __forceinline__ void gst(T* p, const T& v) { *(gmem<T>*)p = v; }
+// Read-only data that every lane of a wave reads at one address (launch
+// descriptors, also those indexed at run time): the constant address space
+// gives scalar loads.
+// Structs are copied word by word (a class copy cannot bind a reference in
+// another address space).
+template <typename T> using cmem = __attribute__((address_space(4))) T;
+template <typename T> __device__ __forceinline__ T cld(const T* p) {
+  static_assert(sizeof(T) % 4 == 0 && alignof(T) >= 4, "whole aligned words");
+  T v;
+  const cmem<uint32_t>* s = (const cmem<uint32_t>*)p;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = s[i];
+  return v;
+}
+template <typename T> __device__ __forceinline__ T cld(const T* p, int i) { return cld(p + i); }
+__device__ __forceinline__ int cld_int(const int* p) { return *(const cmem<int>*)p; }
+
 __device__ __forceinline__ int cell_k(uint8_t c) { return __popc((c >> 2) & 15u); }
 __device__ __forceinline__ bool cell_fluid(uint8_t c) { return !(c & C_SOLID); }
 
@@ -193,47 +221,53 @@ __device__ __forceinline__ void grid_barrier(unsigned* sync, unsigned n, unsigne
   (void)grid_barrier_bounded(sync, n, nblocks);
 }
 
+// Relaxed agent-scope loads and stores of global memory (data that other
+// work-groups read or wrote), in the global address space like gld/gst.
 __device__ __forceinline__ void st_agent(float* p, float v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((gmem<float>*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ float ld_agent(const float* p) {
-  return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((gmem<float>*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_agent(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
-                     static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((gmem<unsigned long long>*)p, static_cast<unsigned long long>(__double_as_longlong(v)),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double ld_agent(const double* p) {
-  return __longlong_as_double(static_cast<long long>(__hip_atomic_load(
-      reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED,
-      __HIP_MEMORY_SCOPE_AGENT)));
+  return __longlong_as_double(static_cast<long long>(
+      __hip_atomic_load((gmem<unsigned long long>*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
 }
 __device__ __forceinline__ void st_agent(uint8_t* p, uint8_t v) {
   // byte stores: go through a 32-bit atomic OR/AND pair on the containing word
-  unsigned* w = reinterpret_cast<unsigned*>(reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3);
+  gmem<unsigned>* w = (gmem<unsigned>*)(reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3);
   const unsigned sh = (unsigned)(reinterpret_cast<uintptr_t>(p) & 3) * 8;
   __hip_atomic_fetch_and(w, ~(0xFFu << sh), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_fetch_or(w, (unsigned)v << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint8_t ld_agent(const uint8_t* p) {
-  const unsigned* w = reinterpret_cast<const unsigned*>(reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3);
+  gmem<unsigned>* w = (gmem<unsigned>*)(reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3);
   const unsigned sh = (unsigned)(reinterpret_cast<uintptr_t>(p) & 3) * 8;
-  return (uint8_t)(__hip_atomic_load(const_cast<unsigned*>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> sh);
+  return (uint8_t)(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> sh);
 }
 
+__device__ __forceinline__ void st_agent(int* p, int v) {
+  __hip_atomic_store((gmem<int>*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_agent(const int* p) {
+  return __hip_atomic_load((gmem<int>*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void st_agent(unsigned* p, unsigned v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((gmem<unsigned>*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ unsigned ld_agent(const unsigned* p) {
-  return __hip_atomic_load(const_cast<unsigned*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((gmem<unsigned>*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((gmem<uint64_t>*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
-  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((gmem<uint64_t>*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // lane l receives x from lane l-1 (lane 0 receives 0): DPP wave_shr:1 with
@@ -250,10 +284,7 @@ __device__ __forceinline__ float from_right(float x) {
 // fixed order, so that every work-group obtains the bit-identical value.
 __device__ __forceinline__ double sum_partials(const double* part, int n, double* scratch) {
   double v = 0.0;
-  const unsigned long long* p = reinterpret_cast<const unsigned long long*>(part);
-  for (int i = threadIdx.x; i < n; i += blockDim.x)
-    v += __longlong_as_double(static_cast<long long>(
-        __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += ld_agent(part + i);
   return block_sum(v, scratch);
 }
 

@@ -14,6 +14,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "common.h"
 #include "internal.h"
 
 namespace hyp {
@@ -22,6 +23,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   // round to nearest even (finite inputs)
@@ -255,8 +257,8 @@ __device__ __forceinline__ void conv_prefetch(const ScaleDesc& S, int x0, int y0
       const int pix = e / PCH, piece = e % PCH;
       const int gy = min(max(y0 - HALO + pix / EW, 0), S.H - 1);
       const int gx = min(max(x0 - HALO + pix % EW, 0), S.W - 1);
-      pf[i] = *reinterpret_cast<const u32x4*>(
-          reinterpret_cast<const char*>(in + ((size_t)gy * S.W + gx) * CIN) + piece * 16);
+      pf[i] = gld(reinterpret_cast<const u32x4*>(
+          reinterpret_cast<const char*>(in + ((size_t)gy * S.W + gx) * CIN) + piece * 16));
     }
   }
 }
@@ -299,20 +301,39 @@ __global__ __launch_bounds__((ConvGeom<T, KS, CIN, COUT>::NT)) void conv_mfma(Co
     __syncthreads();
     constexpr int RP = Gm::WSTR * Gm::ELT / 16;  // 16-byte pieces per row
     constexpr int N16 = Gm::CT * RP;
-    const uint4* src = reinterpret_cast<const uint4*>(S.wimg) + ((size_t)ch * COUT + co0) * RP;
-    uint4* dstl = reinterpret_cast<uint4*>(wl);
-#pragma unroll 8
-    for (int e = threadIdx.x; e < N16; e += Gm::NT) {
-      const int R = e / RP, r = R & 15;
-      const int c = (Gm::CT / 4) * (r >> 2) + 4 * (R >> 4) + (r & 3);
-      dstl[e] = src[c * RP + e % RP];
+    const u32x4* src = reinterpret_cast<const u32x4*>(S.wimg) + ((size_t)ch * COUT + co0) * RP;
+    u32x4* dstl = reinterpret_cast<u32x4*>(wl);
+    // piece e of the LDS image comes from piece src_piece(e) of the rows
+    // (16 rows per pass: the identity)
+    auto src_piece = [](int e) {
+      if constexpr (Gm::CT == 16) {
+        return e;
+      } else {
+        const int R = e / RP, r = R & 15;
+        return ((Gm::CT / 4) * (r >> 2) + 4 * (R >> 4) + (r & 3)) * RP + e % RP;
+      }
+    };
+    // NB loads in flight per thread before their LDS writes
+    constexpr int NB = 8;
+    for (int e0 = threadIdx.x; e0 < N16; e0 += NB * Gm::NT) {
+      u32x4 v[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const int e = e0 + k * Gm::NT;
+        if (e < N16) v[k] = gld(src + src_piece(e));
+      }
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const int e = e0 + k * Gm::NT;
+        if (e < N16) dstl[e] = v[k];
+      }
     }
     // the epilogue's parameters (every bias, then the head's weights and
     // bias), once per tile: they serve all passes
     if (ch == 0 && co0 == 0) {
-      for (int e = threadIdx.x; e < COUT; e += Gm::NT) pl[e] = S.b[e];
+      for (int e = threadIdx.x; e < COUT; e += Gm::NT) pl[e] = gld(S.b + e);
       if constexpr (HEAD)
-        for (int e = threadIdx.x; e <= COUT; e += Gm::NT) pl[COUT + e] = S.hw[e];
+        for (int e = threadIdx.x; e <= COUT; e += Gm::NT) pl[COUT + e] = gld(S.hw + e);
     }
   };
   // input tile (channels of chunk ch) with a HALO-pixel replicated border
@@ -324,7 +345,7 @@ __global__ __launch_bounds__((ConvGeom<T, KS, CIN, COUT>::NT)) void conv_mfma(Co
         const int gx = min(max(x0 - HALO + e % EW, 0), S.W - 1);
         const T* src = in + ((size_t)gy * S.W + gx) * CIN;
 #pragma unroll
-        for (int c = 0; c < CIN; ++c) xl[e * Gm::PSTR + c] = src[c];
+        for (int c = 0; c < CIN; ++c) xl[e * Gm::PSTR + c] = gld(src + c);
       }
     } else {
       constexpr int CH = Gm::CC * sizeof(T) / 16;  // 16-byte pieces per pixel
@@ -333,9 +354,9 @@ __global__ __launch_bounds__((ConvGeom<T, KS, CIN, COUT>::NT)) void conv_mfma(Co
         const int pix = e / CH, piece = e % CH;
         const int gy = min(max(y0 - HALO + pix / EW, 0), S.H - 1);
         const int gx = min(max(x0 - HALO + pix % EW, 0), S.W - 1);
-        const uint4 v = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(
-            in + ((size_t)gy * S.W + gx) * CIN + ch * Gm::CC) + piece * 16);
-        *reinterpret_cast<uint4*>(reinterpret_cast<char*>(xl + pix * Gm::PSTR) + piece * 16) = v;
+        const u32x4 v = gld(reinterpret_cast<const u32x4*>(reinterpret_cast<const char*>(
+            in + ((size_t)gy * S.W + gx) * CIN + ch * Gm::CC) + piece * 16));
+        *reinterpret_cast<u32x4*>(reinterpret_cast<char*>(xl + pix * Gm::PSTR) + piece * 16) = v;
       }
     }
   };
@@ -355,14 +376,14 @@ __global__ __launch_bounds__((ConvGeom<T, KS, CIN, COUT>::NT)) void conv_mfma(Co
       int lo = 0, hi = L.ndesc;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (L.table[mid].tile0 <= t) lo = mid;
+        if (cld_int(&L.table[mid].tile0) <= t) lo = mid;
         else hi = mid;
       }
-      D = L.table[lo];
+      D = cld(L.table, lo);
     } else {
       int k = 0;
-      while (k + 1 < L.nscales && t >= L.sc[k + 1].tile0) ++k;
-      D = L.sc[k];
+      while (k + 1 < L.nscales && t >= cld_int(&L.sc[k + 1].tile0)) ++k;
+      D = cld(L.sc, k);
     }
     const int lt = t - D.tile0;
     x0 = (lt % D.tiles_x) * TW;
@@ -446,20 +467,19 @@ __global__ __launch_bounds__((ConvGeom<T, KS, CIN, COUT>::NT)) void conv_mfma(Co
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
           for (int mb = 0; mb < Gm::MB; ++mb)
-            *reinterpret_cast<float4*>(dst + 4 * mb) = make_float4(v[mb][0], v[mb][1], v[mb][2], v[mb][3]);
+            gst(reinterpret_cast<floatx4*>(dst + 4 * mb), floatx4{v[mb][0], v[mb][1], v[mb][2], v[mb][3]});
         } else {
           // 8 channels (16 bytes) per store
 #pragma unroll
           for (int h = 0; h < Gm::MB; h += 2) {
-            uint4 pk;
-            pk.x = (uint32_t)f2bf(v[h][0]) | ((uint32_t)f2bf(v[h][1]) << 16);
-            pk.y = (uint32_t)f2bf(v[h][2]) | ((uint32_t)f2bf(v[h][3]) << 16);
+            const uint32_t p0 = (uint32_t)f2bf(v[h][0]) | ((uint32_t)f2bf(v[h][1]) << 16);
+            const uint32_t p1 = (uint32_t)f2bf(v[h][2]) | ((uint32_t)f2bf(v[h][3]) << 16);
             if (h + 1 < Gm::MB) {
-              pk.z = (uint32_t)f2bf(v[h + 1][0]) | ((uint32_t)f2bf(v[h + 1][1]) << 16);
-              pk.w = (uint32_t)f2bf(v[h + 1][2]) | ((uint32_t)f2bf(v[h + 1][3]) << 16);
-              *reinterpret_cast<uint4*>(dst + 4 * h) = pk;
+              const uint32_t p2 = (uint32_t)f2bf(v[h + 1][0]) | ((uint32_t)f2bf(v[h + 1][1]) << 16);
+              const uint32_t p3 = (uint32_t)f2bf(v[h + 1][2]) | ((uint32_t)f2bf(v[h + 1][3]) << 16);
+              gst(reinterpret_cast<u32x4*>(dst + 4 * h), u32x4{p0, p1, p2, p3});
             } else {
-              *reinterpret_cast<uint2*>(dst + 4 * h) = make_uint2(pk.x, pk.y);
+              gst(reinterpret_cast<u32x2*>(dst + 4 * h), u32x2{p0, p1});
             }
           }
         }
@@ -473,7 +493,7 @@ __global__ __launch_bounds__((ConvGeom<T, KS, CIN, COUT>::NT)) void conv_mfma(Co
         hs += __shfl_xor(hs, 16);
         hs += __shfl_xor(hs, 32);
         const int gy = y0 + wave * Gm::RPW + nb, gx = x0 + col;
-        if (g == 0 && gy < S.H && gx < S.W) S.y[(size_t)gy * S.W + gx] = hs + pl[2 * COUT];
+        if (g == 0 && gy < S.H && gx < S.W) gst(S.y + (size_t)gy * S.W + gx, hs + pl[2 * COUT]);
       }
     }
     __syncthreads();
