@@ -58,6 +58,7 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
   L.phi = take(4 * n);
   L.phi_acc = take(4 * n);
   L.exch = take(8 * n);
+  L.exch64 = take(16 * n);
   L.coef = take(8 * n);
   L.ncell = n;
   L.adv = take(4 * 2 * (n + (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx));
@@ -134,6 +135,7 @@ Ws ws_view(void* base, const WsLayout& L) {
   w.phi = (float*)(b + L.phi);
   w.phi_acc = (float*)(b + L.phi_acc);
   w.exch = (float*)(b + L.exch);
+  w.exch64 = (uint64_t*)(b + L.exch64);
   w.coef_e = (float*)(b + L.coef);
   w.coef_n = w.coef_e + L.ncell;
   w.pcg = nullptr;

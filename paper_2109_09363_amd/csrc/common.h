@@ -146,14 +146,9 @@ __device__ __forceinline__ double block_max(double v, double* scratch) {
 // group counter, say) measurably slow every work-group's stores.  Barrier
 // number n (1, 2, ...) passes when all `nblocks` work-groups have arrived n
 // times.  Slot i of the sync area is the word sync[32 i]: 0 top counter,
-// 1 flag, 2 + g group g, kFlagSlot0 + b the neighbour line of work-group b;
-// all are zeroed before a launch (sync_clear; sync_clear_words for the
-// neighbour lines, which use 8 words each).
+// 1 flag, 2 + g group g; all are zeroed before a launch (sync_clear).
 __device__ __forceinline__ void sync_clear(unsigned* sync, int i) {
   if (i >= 0 && i < kSyncSlots) sync[32 * i] = 0;
-}
-__device__ __forceinline__ void sync_clear_words(unsigned* sync, int i) {
-  if (i >= 0 && i < kSyncAllSlots * 8) sync[32 * (i >> 3) + (i & 7)] = 0;
 }
 
 // Every wait is bounded (kSpinTicks of the constant 100 MHz wall clock):
@@ -178,38 +173,6 @@ __device__ __forceinline__ bool grid_barrier_bounded(unsigned* sync, unsigned n,
     while (__hip_atomic_load(sync + 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n) {
       if ((uint64_t)wall_clock64() - t0 > kSpinTicks) { ok = 0; break; }
       __builtin_amdgcn_s_sleep(2);
-    }
-  }
-  return __syncthreads_and(ok) != 0;
-}
-
-// Neighbour synchronisation: each work-group owns one 128-byte line of the
-// sync area (slot kFlagSlot0 + b) holding 8 words, one per adjacent tile in
-// the order of a 3 x 3 block without its centre.  At step `step` (1, 2, ...)
-// lane o < 8 of wave 0 writes `step` into word 7 - o of the line of its o-th
-// neighbour `nb` (-1: none), which is where this work-group sits as seen from
-// there; then wave 0 polls its own line until every word whose neighbour
-// exists has reached `step`.  A neighbour is at most one step ahead (it
-// waits for this work-group's next word), so the words only grow.  The
-// writes follow the same s_waitcnt 0 as the barrier's arrival.  Bounded like
-// the barrier.
-__device__ __forceinline__ bool neighbour_wait_bounded(unsigned* sync, unsigned step, int nb) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  int ok = 1;
-  if (threadIdx.x < kWave) {
-    const int o = threadIdx.x;
-    if (o < 8 && nb >= 0)
-      __hip_atomic_store(sync + 32 * (kFlagSlot0 + nb) + (7 - o), step, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    unsigned* own = sync + 32 * (kFlagSlot0 + blockIdx.x) + (o & 7);
-    const uint64_t t0 = (uint64_t)wall_clock64();
-    for (;;) {
-      const bool mine = o >= 8 || nb < 0 ||
-                        __hip_atomic_load(own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= step;
-      if (__all(mine)) break;
-      if ((uint64_t)wall_clock64() - t0 > kSpinTicks) { ok = 0; break; }
-      __builtin_amdgcn_s_sleep(1);
     }
   }
   return __syncthreads_and(ok) != 0;

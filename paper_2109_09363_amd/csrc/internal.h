@@ -23,7 +23,9 @@ struct Scalars {
   int32_t status;
   int32_t plan_rounds;
   unsigned bar;       // grid-barrier counter (zeroed before each launch)
-  unsigned pad[3];
+  unsigned epoch;     // tag epoch of the Jacobi halo words: 0 after planning,
+                      // then 1 .. kEpochs, advanced once per projection
+  unsigned pad[2];
   double lam_s;       // adjoint of the CNN input scale s
   double loss;        // last backward's loss
 };
@@ -34,12 +36,11 @@ constexpr int kMaxCheckpoints = 64;    // Jacobi checkpoint planes per projectio
 // kSyncGroup blocks, each on its own 128-byte line (common.h)
 constexpr int kSyncGroup = 16;
 constexpr int kSyncSlots = 2 + kMaxCoopBlocks / kSyncGroup;
-// followed by one line per work-group holding the step words its 8 adjacent
-// tiles write (neighbour synchronisation of the persistent Jacobi kernel);
 // the whole area is zeroed before every launch that uses it
-constexpr int kFlagSlot0 = kSyncSlots;
-constexpr int kSyncAllSlots = kSyncSlots + kMaxCoopBlocks;
-constexpr int kSyncBytes = kSyncAllSlots * 128;
+constexpr int kSyncBytes = kSyncSlots * 128;
+// Tag epochs of the Jacobi halo words (12 bits): at the wrap to 1 the
+// kernel clears the words before its first exchange.
+constexpr unsigned kEpochs = 4095;
 constexpr int kStatusRunning = -1;     // Scalars::status while a solve is in progress
 constexpr int kStreamBlock = 256;      // threads of the streaming kernels
 constexpr int kStreamGrid = 2048;      // at most this many blocks in the reducing streaming kernels
@@ -54,7 +55,7 @@ constexpr int kWgBlocks = 128;  // pixel-chunk blocks of the weight-gradient red
 
 // Byte offsets into the caller's workspace (all 256-byte aligned).
 struct WsLayout {
-  size_t cell = 0, d = 0, phi = 0, phi_acc = 0, exch = 0, blockpart = 0, partial = 0,
+  size_t cell = 0, d = 0, phi = 0, phi_acc = 0, exch = 0, exch64 = 0, blockpart = 0, partial = 0,
          scalars = 0, reach = 0, pcg = 0, adv = 0, sync = 0, coef = 0;
   size_t ncell = 0;
   size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0, cnn_cat = 0;
@@ -77,7 +78,8 @@ struct Ws {
   float* d;
   float* phi;
   float* phi_acc;     // pressure folded into the faces by defect-correction folds
-  float* exch;        // 2 x nx*ny (halo exchange ping-pong)
+  float* exch;        // 2 x nx*ny (halo exchange ping-pong of the batched kernel)
+  uint64_t* exch64;   // 2 x nx*ny tagged halo words of the Jacobi and PCG kernels
   double* blockpart;  // streaming-kernel block partials
   size_t blockpart_n; // capacity of blockpart in doubles
   double* partial;    // 6 x kMaxCoopBlocks cooperative partials

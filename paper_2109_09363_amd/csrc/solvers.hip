@@ -66,7 +66,7 @@ struct JacParams {
   float* phi_acc;       // pressure folded into the faces
   float* u;             // faces, corrected at a fold
   float* v;
-  float* exch;          // 2 x nx*ny halo exchange planes
+  uint64_t* exch64;     // 2 x nx*ny tagged halo words (Jacobi)
   double* partial;      // 2 x kMaxCoopBlocks partial sums
   Scalars* sc;
   unsigned* sync;       // grid barrier
@@ -180,23 +180,41 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
     if (threadIdx.x == 0) abort_solve(p.sc);
     return false;
   };
-  // The halo of a tile lies in the interiors of its (up to) 8 adjacent tiles
-  // when H <= TW and H <= TH (the host sets nbsync only then).  Lane o < 8 of
-  // wave 0 waits for the o-th of them.
-  int nb = -1;
-  if (p.nbsync && wave == 0 && lane < 8) {
-    const int o = lane < 4 ? lane : lane + 1;  // 3 x 3 block without its centre
-    const int tx = bx + o % 3 - 1, ty = by + o / 3 - 1;
-    if (tx >= 0 && tx < p.ntx && ty >= 0 && ty < p.nty) nb = ty * p.ntx + tx;
+  // Halo exchange through tagged words: each published value carries the
+  // epoch of the launch and the step in its upper 32 bits, so a reader polls
+  // the words it needs until their tags match instead of loading them after
+  // a step flag, and a writer does not wait for its stores to complete before
+  // raising that flag.  Flow control: every tile publishes all its
+  // in-domain interior cells and reads all its in-domain halo cells, solid
+  // ones included (they hold +0 on both sides), so a tile and each adjacent
+  // tile read at least one word of each other's every step.  A tile
+  // rewrites the plane of step j at step j + 2 only after reading its
+  // neighbours' words of step j + 1, which they publish only after their
+  // reads of step j have returned: no word is overwritten before it is read.
+  // When the halo reaches beyond the adjacent tiles (nbsync 0) every step
+  // also crosses the grid barrier.
+  const unsigned epoch = p.sc->epoch;
+  if (epoch == 1u) {
+    // first launch after planning or an epoch wrap: no word may carry an
+    // older tag of this epoch
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if ((imask >> r) & 1u) {
+        const size_t g = (size_t)(gy0 + r) * p.nx + gx;
+        st_agent(p.exch64 + g, (uint64_t)0);
+        st_agent(p.exch64 + plane + g, (uint64_t)0);
+      }
+    if (!barrier()) return;
   }
+  auto tag_of = [&](unsigned step) { return (epoch << 20) | (step & 0xFFFFFu); };
   for (;;) {
-    // publish the interior of the state after j steps (read by the
-    // neighbours after the barrier)
-    float* ex = p.exch + (size_t)(j & 1u) * plane;
+    // publish the interior of the state after j steps
+    uint64_t* ex = p.exch64 + (size_t)(j & 1u) * plane;
     if (j > 0) {
+      const uint64_t tag = (uint64_t)tag_of(j) << 32;
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (((imask >> r) & 1u) && kk[r] > 0.f) st_agent(ex + (size_t)(gy0 + r) * p.nx + gx, ph[r]);
+        if ((imask >> r) & 1u) st_agent(ex + (size_t)(gy0 + r) * p.nx + gx, tag | __float_as_uint(ph[r]));
     }
     const bool test = k == k0 || (p.fixed_iters > 0 ? k >= end : (k % p.check_every == 0 || k >= end));
     // E_1 of the current state: the interior and the ring around it are
@@ -217,24 +235,39 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
       if (threadIdx.x == 0) st_agent(part + blockIdx.x, loc);
     }
     // A step with a test (or, in fixed-sweep mode, a possible fold) crosses
-    // the grid barrier.  Any other step only needs the adjacent tiles' state
-    // of step j: their words.  The exchange plane of step j is rewritten at
-    // step j + 2, after the writer has seen its neighbours' words of step
-    // j + 1, which they raise only after reading their halo of step j (or
-    // after a grid barrier that follows those reads).
+    // the grid barrier; any other step only polls its halo words.
     const bool full = test || !p.nbsync ||
                       (p.fixed_iters > 0 && p.fold_window > 0 && k - k_ref >= p.fold_window);
-    if (full) {
-      if (!barrier()) return;
-    } else if (!neighbour_wait_bounded(p.sync, j, nb)) {
-      if (threadIdx.x == 0) abort_solve(p.sc);
-      return;
-    }
-    // one round trip: the halo (every non-interior fluid cell) and the partials
+    if (full && !barrier()) return;
+    // the halo of step j: every in-domain cell outside the interior, polled
+    // until its tag is this step's (bounded like the barrier)
     if (j > 0) {
+      const unsigned want = tag_of(j);
+      unsigned need = dmask & ~imask;
+      int ok = 1;
+      const uint64_t t0 = (uint64_t)wall_clock64();
+      for (;;) {
+        // every load of a pass is issued before the first tag is compared
+        uint64_t wd[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (!((imask >> r) & 1u) && kk[r] > 0.f) ph[r] = ld_agent(ex + (size_t)(gy0 + r) * p.nx + gx);
+        for (int r = 0; r < R; ++r)
+          wd[r] = ((need >> r) & 1u) ? ld_agent(ex + (size_t)(gy0 + r) * p.nx + gx) : 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (((need >> r) & 1u) && (unsigned)(wd[r] >> 32) == want) {
+            ph[r] = __uint_as_float((unsigned)wd[r]);
+            need &= ~(1u << r);
+          }
+        if (__all(need == 0u)) break;
+        if ((uint64_t)wall_clock64() - t0 > kSpinTicks) {
+          ok = 0;
+          break;
+        }
+      }
+      if (!__syncthreads_and(ok)) {
+        if (threadIdx.x == 0) abort_solve(p.sc);
+        return;
+      }
     }
     int st = -1;
     double E = 0.0;
@@ -397,7 +430,7 @@ struct PcgParams {
   float* phi_acc;       // pressure folded into the faces
   float* u;             // faces, corrected at a fold
   float* v;
-  float* exch;          // 2 x nx*ny
+  uint64_t* exch64;     // 2 x nx*ny tagged halo words (u, x)
   double* partial;      // 2 x 3 x kMaxCoopBlocks
   Scalars* sc;
   unsigned* sync;
@@ -450,6 +483,42 @@ __device__ __forceinline__ void apply_A_var(const float (&v)[R], const float (&k
   }
 }
 
+// One tagged halo exchange of v (see pcg_reg): publish the interior fluid
+// cells with tag `want`, poll the halo fluid cells until their tags match.
+template <int R>
+__device__ __forceinline__ bool pcg_exchange(float (&v)[R], uint64_t* ex, unsigned want,
+                                                  unsigned imask, unsigned dmask, const float (&kk)[R],
+                                                  int gy0, int gx, int nx) {
+  const uint64_t tag = (uint64_t)want << 32;
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+    if ((imask >> i) & 1u) st_agent(ex + (size_t)(gy0 + i) * nx + gx, tag | __float_as_uint(v[i]));
+  unsigned need = 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+    if (((dmask >> i) & 1u) && !((imask >> i) & 1u) && kk[i] > 0.f) need |= 1u << i;
+  int ok = 1;
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  for (;;) {
+    // every load of a pass is issued before the first tag is compared
+    uint64_t wd[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      wd[i] = ((need >> i) & 1u) ? ld_agent(ex + (size_t)(gy0 + i) * nx + gx) : 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (((need >> i) & 1u) && (unsigned)(wd[i] >> 32) == want) {
+        v[i] = __uint_as_float((unsigned)wd[i]);
+        need &= ~(1u << i);
+      }
+    if (__all(need == 0u)) break;
+    if ((uint64_t)wall_clock64() - t0 > kSpinTicks) {
+      ok = 0;
+      break;
+    }
+  }
+  return __syncthreads_and(ok) != 0;
+}
 template <int R, bool VAR>
 __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
   __shared__ float edge[2][2][4][64];
@@ -495,8 +564,8 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
   const bool first = k == 0;
   unsigned nbar = 0;
   const size_t plane = (size_t)p.nx * p.ny;
-  float* uex = p.exch;
-  float* xex = p.exch + plane;
+  uint64_t* uex = p.exch64;
+  uint64_t* xex = p.exch64 + plane;
   int par = 0;
   float below, above;
 
@@ -505,31 +574,38 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
     if (threadIdx.x == 0) abort_solve(p.sc);
     return false;
   };
-  // refresh the halo of v from the neighbours' interiors
-  // The one-cell halo lies in the 8 adjacent tiles' interiors, so an exchange
-  // waits for their step words only (lane o < 8 of wave 0 for the o-th).
-  // Every exchange is followed by the merged reduction's grid barrier before
-  // its plane is written again, so no tile overwrites a plane that another
-  // is still reading.
-  int nb = -1;
-  if (wave == 0 && lane < 8) {
-    const int o = lane < 4 ? lane : lane + 1;  // 3 x 3 block without its centre
-    const int tx = bx + o % 3 - 1, ty = by + o / 3 - 1;
-    if (tx >= 0 && tx < p.ntx && ty >= 0 && ty < p.nty) nb = ty * p.ntx + tx;
+  // refresh the halo of v from the neighbours' interiors: the words carry
+  // the epoch and the exchange count in their upper 32 bits, and a tile polls
+  // its halo words until their tags match (the writer does not wait for its
+  // stores).  Every exchange is followed by the merged reduction's grid
+  // barrier before its plane is written again, so no tile overwrites a word
+  // that another has yet to read.
+  const unsigned epoch = p.sc->epoch;
+  if (epoch == 1u) {
+    // first launch after planning or an epoch wrap: no word may carry an
+    // older tag of this epoch
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if ((imask >> i) & 1u) {
+        const size_t g = (size_t)(gy0 + i) * p.nx + gx;
+        st_agent(uex + g, (uint64_t)0);
+        st_agent(xex + g, (uint64_t)0);
+      }
+    if (!barrier()) return;
   }
   unsigned nex = 0;
-  auto exchange = [&](float (&v)[R], float* ex) -> bool {
-#pragma unroll
-    for (int i = 0; i < R; ++i)
-      if ((imask >> i) & 1u) st_agent(ex + (size_t)(gy0 + i) * p.nx + gx, v[i]);
-    if (!neighbour_wait_bounded(p.sync, ++nex, nb)) {
-      if (threadIdx.x == 0) abort_solve(p.sc);
-      return false;
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i)
-      if (!((imask >> i) & 1u) && kk[i] > 0.f) v[i] = ld_agent(ex + (size_t)(gy0 + i) * p.nx + gx);
-    return true;
+  // up to R = 12 inlined; the larger tiles leave the call out of line, where
+  // inlining would spill more of the kernel's register arrays
+  auto exchange_call = [&](float (&v)[R], uint64_t* ex, unsigned want) __attribute__((noinline)) -> bool {
+    return pcg_exchange<R>(v, ex, want, imask, dmask, kk, gy0, gx, p.nx);
+  };
+  auto exchange = [&](float (&v)[R], uint64_t* ex) __attribute__((always_inline)) -> bool {
+    const unsigned want = (epoch << 20) | (++nex & 0xFFFFFu);
+    bool ok;
+    if constexpr (R <= 12) ok = pcg_exchange<R>(v, ex, want, imask, dmask, kk, gy0, gx, p.nx);
+    else ok = exchange_call(v, ex, want);
+    if (!ok && threadIdx.x == 0) abort_solve(p.sc);
+    return ok;
   };
   // merged reduction of (r.u, w.u, sum|r| or max|r|) over the interior; forced
   // inline, since an out-of-line call takes r, u, w by reference and moves
@@ -852,7 +928,7 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
   p.ckpt_every = phi_ckpt ? checkpoint_every : 0;
   p.ckpt = phi_ckpt;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.phi_acc = w.phi_acc; p.u = u; p.v = v;
-  p.exch = w.exch; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
+  p.exch64 = w.exch64; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
   p.ce = var ? w.coef_e : nullptr;
   p.cn = var ? w.coef_n : nullptr;
   const int G = ntx * nty;
@@ -888,7 +964,7 @@ hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int
   p.thr = thr;
   p.max_iters = max_iters; p.check_every = check_every; p.fixed_iters = fixed_iters;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.phi_acc = w.phi_acc; p.u = u; p.v = v;
-  p.exch = w.exch; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
+  p.exch64 = w.exch64; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
   p.ce = var ? w.coef_e : nullptr;
   p.cn = var ? w.coef_n : nullptr;
   const int G = ntx * nty;

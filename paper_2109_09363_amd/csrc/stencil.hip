@@ -64,6 +64,7 @@ __global__ __launch_bounds__(256) void plan_init(int nx, int ny, int ntx, const 
   sync_clear(sync, c);
   if (c == 0) {
     sc->bar = 0;
+    sc->epoch = 0;
     sc->nF = 0;
     sc->plan_rounds = 0;
   }
@@ -225,7 +226,7 @@ __device__ __forceinline__ void div_body(int lb, int nb, int nx, int ny, float i
                                          double* red) {
   const int c0 = lb * blockDim.x + threadIdx.x;
   const int stride = nb * blockDim.x;
-  for (int i = c0; i < kSyncAllSlots * 8; i += stride) sync_clear_words(sync, i);
+  for (int i = c0; i < kSyncSlots; i += stride) sync_clear(sync, i);
   if (c0 == 0) sc->bar = 0;
   double a = 0.0, q = 0.0;
   // grid-stride: a bounded grid keeps the per-block reduction cheap at
@@ -277,6 +278,7 @@ __device__ __forceinline__ void div_finish_body(int nblocks, const double* __res
     sc->e1_cnn = sc->e1_init;
     sc->iters = 0;
     sc->status = kStatusRunning;
+    sc->epoch = sc->epoch % kEpochs + 1;
   }
 }
 

@@ -361,3 +361,47 @@ def test_jacobi_block_length_does_not_change_the_iterates(n, rows):
             continue
         assert g["res"].iters == thr_ref["res"].iters
         assert np.array_equal(g["p"], thr_ref["p"])
+
+
+def test_tagged_halo_words_across_epochs_and_solvers():
+    """The Jacobi and PCG kernels exchange halos through words tagged with a
+    launch epoch (advanced once per projection, 4,095 values) and the step.
+    4,100 projections on one workspace cross the epoch's wrap, where the
+    kernels clear the words again, and alternate Jacobi (three block
+    lengths) with PCG on the same words; every checked result is bit for bit
+    the one the first projection of its kind gave."""
+    import torch
+    import paper_2109_09363_amd as hp
+    from tests.gpu_util import to_dev
+    n = 96
+    sc, u, v = plume_state(n, 11, 2)
+    pr = hp.Projector(n, n, sc.dx, 1.0, 1.0)
+    tf = to_dev(sc.flags, torch.uint8)
+    pr.plan(tf)
+    u0, v0 = to_dev(u), to_dev(v)
+    tu, tv = torch.empty_like(u0), torch.empty_like(v0)
+    p = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    kinds = [("jacobi", 8), ("jacobi", 3), ("pcg", 0), ("jacobi", 12)]
+    ref = {}
+    checked = 0
+    for i in range(4100):
+        method, block = kinds[i % len(kinds)]
+        tu.copy_(u0)
+        tv.copy_(v0)
+        pr.project_async(tu, tv, tf, p, 0.0, method=method, block_sweeps=block,
+                         fixed_iters=37 if method == "jacobi" else 19)
+        if i < len(kinds) or i % 97 == 0 or 4090 <= i <= 4099:
+            torch.cuda.synchronize()
+            res = pr.result()
+            assert res.status == 0, (i, method, res.status)
+            got = (p.cpu().numpy(), tu.cpu().numpy(), tv.cpu().numpy())
+            key = (method, block)
+            if key not in ref:
+                ref[key] = got
+            else:
+                assert all(np.array_equal(a, b) for a, b in zip(got, ref[key])), (i, key)
+                checked += 1
+    say("checked", checked, "projections against the first of their kind")
+    # the three block lengths give the same Jacobi iterate as well
+    assert np.array_equal(ref[("jacobi", 8)][0], ref[("jacobi", 3)][0])
+    assert np.array_equal(ref[("jacobi", 8)][0], ref[("jacobi", 12)][0])
