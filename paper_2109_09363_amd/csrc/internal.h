@@ -78,7 +78,7 @@ struct Ws {
   float* d;
   float* phi;
   float* phi_acc;     // pressure folded into the faces by defect-correction folds
-  float* exch;        // 2 x nx*ny (halo exchange ping-pong of the batched kernel)
+  float* exch;        // 2 x nx*ny FP32 halo planes (batched kernel; Jacobi tested every step)
   uint64_t* exch64;   // 2 x nx*ny tagged halo words of the Jacobi and PCG kernels
   double* blockpart;  // streaming-kernel block partials
   size_t blockpart_n; // capacity of blockpart in doubles

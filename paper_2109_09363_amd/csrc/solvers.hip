@@ -66,7 +66,8 @@ struct JacParams {
   float* phi_acc;       // pressure folded into the faces
   float* u;             // faces, corrected at a fold
   float* v;
-  uint64_t* exch64;     // 2 x nx*ny tagged halo words (Jacobi)
+  uint64_t* exch64;     // 2 x nx*ny tagged halo words (steps between tests)
+  float* exch;          // 2 x nx*ny halo planes (launches that test every step)
   double* partial;      // 2 x kMaxCoopBlocks partial sums
   Scalars* sc;
   unsigned* sync;       // grid barrier
@@ -89,7 +90,10 @@ __device__ __forceinline__ void abort_solve(Scalars* sc) {
                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int R, bool VAR>
+// TAGGED: steps between E_1 tests exchange their halo through tagged words
+// (below); otherwise every step ends at a test and crosses the grid barrier,
+// after which the halo is read as plain FP32 values.
+template <int R, bool VAR, bool TAGGED>
 __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacParams p) {
   __shared__ float edge[2][2][4][64];  // [parity][low row / high row][wave][lane]
   __shared__ double red[4];
@@ -196,7 +200,8 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
   const unsigned epoch = p.sc->epoch;
   if (epoch == 1u) {
     // first launch after planning or an epoch wrap: no word may carry an
-    // older tag of this epoch
+    // older tag of this epoch (whichever solver or exchange form the
+    // projection at the wrap uses, it clears the words)
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if ((imask >> r) & 1u) {
@@ -210,11 +215,16 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
   for (;;) {
     // publish the interior of the state after j steps
     uint64_t* ex = p.exch64 + (size_t)(j & 1u) * plane;
-    if (j > 0) {
+    float* ex32 = p.exch + (size_t)(j & 1u) * plane;
+    if (TAGGED && j > 0) {
       const uint64_t tag = (uint64_t)tag_of(j) << 32;
 #pragma unroll
       for (int r = 0; r < R; ++r)
         if ((imask >> r) & 1u) st_agent(ex + (size_t)(gy0 + r) * p.nx + gx, tag | __float_as_uint(ph[r]));
+    } else if (j > 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (((imask >> r) & 1u) && kk[r] > 0.f) st_agent(ex32 + (size_t)(gy0 + r) * p.nx + gx, ph[r]);
     }
     const bool test = k == k0 || (p.fixed_iters > 0 ? k >= end : (k % p.check_every == 0 || k >= end));
     // E_1 of the current state: the interior and the ring around it are
@@ -236,12 +246,18 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
     }
     // A step with a test (or, in fixed-sweep mode, a possible fold) crosses
     // the grid barrier; any other step only polls its halo words.
-    const bool full = test || !p.nbsync ||
+    const bool full = !TAGGED || test || !p.nbsync ||
                       (p.fixed_iters > 0 && p.fold_window > 0 && k - k_ref >= p.fold_window);
     if (full && !barrier()) return;
     // the halo of step j: every in-domain cell outside the interior, polled
-    // until its tag is this step's (bounded like the barrier)
-    if (j > 0) {
+    // until its tag is this step's (bounded like the barrier); without tags
+    // the fluid halo cells after the barrier, in the same round trip as the
+    // partials
+    if (!TAGGED && j > 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (!((imask >> r) & 1u) && kk[r] > 0.f) ph[r] = ld_agent(ex32 + (size_t)(gy0 + r) * p.nx + gx);
+    } else if (j > 0) {
       const unsigned want = tag_of(j);
       unsigned need = dmask & ~imask;
       int ok = 1;
@@ -798,6 +814,12 @@ static int jacobi_block_len(int check_every, int fixed_iters, int block) {
 
 static const int kRows[] = {4, 8, 12, 16, 24, 32};
 
+template <int R>
+static const void* jacobi_kernel(bool var, bool tagged) {
+  if (var) return tagged ? (const void*)jacobi_reg<R, true, true> : (const void*)jacobi_reg<R, true, false>;
+  return tagged ? (const void*)jacobi_reg<R, false, true> : (const void*)jacobi_reg<R, false, false>;
+}
+
 // Work-groups of jacobi_reg<r> that one CU holds at once (registers, LDS),
 // at most 2; every one of them must be resident for the grid barrier.
 static int jacobi_per_cu(int r, bool var) {
@@ -809,18 +831,22 @@ static int jacobi_per_cu(int r, bool var) {
   std::atomic<int>& slot = cache[var ? 1 : 0][i];
   int c = slot.load(std::memory_order_relaxed);
   if (c == 0) {
-    const void* k = nullptr;
-    switch (r) {
-      case 4: k = var ? (const void*)jacobi_reg<4, true> : (const void*)jacobi_reg<4, false>; break;
-      case 8: k = var ? (const void*)jacobi_reg<8, true> : (const void*)jacobi_reg<8, false>; break;
-      case 12: k = var ? (const void*)jacobi_reg<12, true> : (const void*)jacobi_reg<12, false>; break;
-      case 16: k = var ? (const void*)jacobi_reg<16, true> : (const void*)jacobi_reg<16, false>; break;
-      case 24: k = var ? (const void*)jacobi_reg<24, true> : (const void*)jacobi_reg<24, false>; break;
-      default: k = var ? (const void*)jacobi_reg<32, true> : (const void*)jacobi_reg<32, false>; break;
+    // the smaller of the two exchange forms (they choose between them later)
+    c = 2;
+    for (int tagged = 0; tagged < 2; ++tagged) {
+      const void* k = nullptr;
+      switch (r) {
+        case 4: k = jacobi_kernel<4>(var, tagged); break;
+        case 8: k = jacobi_kernel<8>(var, tagged); break;
+        case 12: k = jacobi_kernel<12>(var, tagged); break;
+        case 16: k = jacobi_kernel<16>(var, tagged); break;
+        case 24: k = jacobi_kernel<24>(var, tagged); break;
+        default: k = jacobi_kernel<32>(var, tagged); break;
+      }
+      int n = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, 0) != hipSuccess || n < 1) n = 1;
+      if (n < c) c = n;
     }
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, 0) != hipSuccess || n < 1) n = 1;
-    c = n > 2 ? 2 : n;
     slot.store(c, std::memory_order_relaxed);
   }
   return c;
@@ -899,10 +925,15 @@ bool solver_fits(const Device& dev, int nx, int ny, bool pcg, int check_every, i
   return jacobi_geom(dev, nx, ny, check_every, fixed_iters, tile_rows, block, var, &R, &H, &ntx, &nty);
 }
 
+// Tagged halo words pay off on steps between tests; a launch whose every
+// step ends at a test (check_every up to the block length, or a halo that
+// reaches beyond the adjacent tiles) crosses the grid barrier each step and
+// reads plain FP32 halo values after it.
 template <int R>
 static hipError_t launch_jacobi(JacParams& p, int G, hipStream_t s) {
   void* args[] = {&p};
-  const void* k = p.ce ? (const void*)jacobi_reg<R, true> : (const void*)jacobi_reg<R, false>;
+  const bool every_step_tested = p.fixed_iters <= 0 && p.check_every <= p.H - 1;
+  const void* k = jacobi_kernel<R>(p.ce != nullptr, p.nbsync && !every_step_tested);
   return hipLaunchCooperativeKernel(k, dim3(G), dim3(256), args, 0, s);
 }
 
@@ -928,7 +959,7 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
   p.ckpt_every = phi_ckpt ? checkpoint_every : 0;
   p.ckpt = phi_ckpt;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.phi_acc = w.phi_acc; p.u = u; p.v = v;
-  p.exch64 = w.exch64; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
+  p.exch64 = w.exch64; p.exch = w.exch; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
   p.ce = var ? w.coef_e : nullptr;
   p.cn = var ? w.coef_n : nullptr;
   const int G = ntx * nty;

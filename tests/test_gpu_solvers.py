@@ -365,11 +365,14 @@ def test_jacobi_block_length_does_not_change_the_iterates(n, rows):
 
 def test_tagged_halo_words_across_epochs_and_solvers():
     """The Jacobi and PCG kernels exchange halos through words tagged with a
-    launch epoch (advanced once per projection, 4,095 values) and the step.
-    4,100 projections on one workspace cross the epoch's wrap, where the
-    kernels clear the words again, and alternate Jacobi (three block
-    lengths) with PCG on the same words; every checked result is bit for bit
-    the one the first projection of its kind gave."""
+    launch epoch (advanced once per projection, 4,095 values) and the step;
+    a Jacobi launch that tests E_1 at every step reads plain FP32 planes
+    instead.  4,100 projections on one workspace cross the epoch's wrap,
+    where the kernels clear the tagged words (here the plain form lands on
+    the first epoch both after planning and at the wrap, so the tagged
+    launches rely on its clearing), and alternate Jacobi (three block
+    lengths, both exchange forms) with PCG on the same words; every checked
+    result is bit for bit the one the first projection of its kind gave."""
     import torch
     import paper_2109_09363_amd as hp
     from tests.gpu_util import to_dev
@@ -381,27 +384,32 @@ def test_tagged_halo_words_across_epochs_and_solvers():
     u0, v0 = to_dev(u), to_dev(v)
     tu, tv = torch.empty_like(u0), torch.empty_like(v0)
     p = torch.empty((n, n), dtype=torch.float32, device="cuda")
-    kinds = [("jacobi", 8), ("jacobi", 3), ("pcg", 0), ("jacobi", 12)]
+    # (method, options, expected status): the first runs to max_iters with a
+    # test every 8 sweeps (every step tested: the plain form)
+    kinds = [("jacobi", dict(max_iters=40, check_every=8), 1),
+             ("jacobi", dict(fixed_iters=37, block_sweeps=8), 0),
+             ("jacobi", dict(fixed_iters=37, block_sweeps=3), 0),
+             ("pcg", dict(fixed_iters=19), 0),
+             ("jacobi", dict(fixed_iters=37, block_sweeps=12), 0)]
+    assert 4095 % len(kinds) == 0
     ref = {}
     checked = 0
     for i in range(4100):
-        method, block = kinds[i % len(kinds)]
+        k = i % len(kinds)
+        method, opts, status = kinds[k]
         tu.copy_(u0)
         tv.copy_(v0)
-        pr.project_async(tu, tv, tf, p, 0.0, method=method, block_sweeps=block,
-                         fixed_iters=37 if method == "jacobi" else 19)
+        pr.project_async(tu, tv, tf, p, 0.0, method=method, **opts)
         if i < len(kinds) or i % 97 == 0 or 4090 <= i <= 4099:
             torch.cuda.synchronize()
             res = pr.result()
-            assert res.status == 0, (i, method, res.status)
+            assert res.status == status, (i, method, opts, res.status)
             got = (p.cpu().numpy(), tu.cpu().numpy(), tv.cpu().numpy())
-            key = (method, block)
-            if key not in ref:
-                ref[key] = got
+            if k not in ref:
+                ref[k] = got
             else:
-                assert all(np.array_equal(a, b) for a, b in zip(got, ref[key])), (i, key)
+                assert all(np.array_equal(a, b) for a, b in zip(got, ref[k])), (i, method, opts)
                 checked += 1
     say("checked", checked, "projections against the first of their kind")
     # the three block lengths give the same Jacobi iterate as well
-    assert np.array_equal(ref[("jacobi", 8)][0], ref[("jacobi", 3)][0])
-    assert np.array_equal(ref[("jacobi", 8)][0], ref[("jacobi", 12)][0])
+    assert np.array_equal(ref[1][0], ref[2][0]) and np.array_equal(ref[1][0], ref[4][0])
