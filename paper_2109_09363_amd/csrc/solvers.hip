@@ -814,6 +814,19 @@ static int jacobi_block_len(int check_every, int fixed_iters, int block) {
 
 static const int kRows[] = {4, 8, 12, 16, 24, 32};
 
+// The persistent solvers need every work-group resident (grid barriers):
+// a cooperative launch checks that.  Inside stream capture (a hipGraph of a
+// projection or time step) the launch is a plain one of the same grid, whose
+// size the occupancy query bounds, so that all its work-groups are resident
+// when the graph runs alone on the GPU; a barrier that is not reached within
+// its bound ends the solve with ABORTED instead of hanging.
+static hipError_t launch_persistent(const void* k, int G, void** args, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return hipErrorInvalidValue;
+  if (cs == hipStreamCaptureStatusActive) return hipLaunchKernel(k, dim3(G), dim3(256), args, 0, s);
+  return hipLaunchCooperativeKernel(k, dim3(G), dim3(256), args, 0, s);
+}
+
 template <int R>
 static const void* jacobi_kernel(bool var, bool tagged) {
   if (var) return tagged ? (const void*)jacobi_reg<R, true, true> : (const void*)jacobi_reg<R, true, false>;
@@ -934,7 +947,7 @@ static hipError_t launch_jacobi(JacParams& p, int G, hipStream_t s) {
   void* args[] = {&p};
   const bool every_step_tested = p.fixed_iters <= 0 && p.check_every <= p.H - 1;
   const void* k = jacobi_kernel<R>(p.ce != nullptr, p.nbsync && !every_step_tested);
-  return hipLaunchCooperativeKernel(k, dim3(G), dim3(256), args, 0, s);
+  return launch_persistent(k, G, args, s);
 }
 
 hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, float omega,
@@ -978,7 +991,7 @@ template <int R>
 static hipError_t launch_pcg(PcgParams& p, int G, hipStream_t s) {
   void* args[] = {&p};
   const void* k = p.ce ? (const void*)pcg_reg<R, true> : (const void*)pcg_reg<R, false>;
-  return hipLaunchCooperativeKernel(k, dim3(G), dim3(256), args, 0, s);
+  return launch_persistent(k, G, args, s);
 }
 
 hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int max_iters,

@@ -232,3 +232,53 @@ def test_step_bad_arguments():
     t = torch.zeros((32, 32), dtype=torch.float32, device="cuda")
     with pytest.raises(ValueError):
         pr.step_async(t, t, t, t, t, t, 1e-3, g=1.0, drho=0.01)
+
+
+@pytest.mark.parametrize("method", ["hybrid", "pcg"])
+def test_captured_step_replays_match_eager_steps(method):
+    """A time step captured as a hipGraph (torch.cuda.graph around the
+    library call: the persistent solver becomes a plain launch of the same
+    grid) and replayed with a new inflow noise each time, with eager work
+    and synchronisations between the replays: every replay's state and
+    result equal those of the eager step from the same state, bit for bit."""
+    n = 256
+    sc = scenes.plume_scene(n, seed=21, n_obstacles=2)
+    w = torch.from_numpy(np.load(WEIGHTS, allow_pickle=False).astype(np.float32)).cuda()
+    pr = hp.Projector(n, n, sc.dx, 1.0, sc.rho0, 4, 64, "bf16")
+    pr.set_weights(w)
+    flags = to_dev(sc.flags, torch.uint8)
+    pr.plan(flags)
+    rho = torch.full((n, n), sc.rho0, dtype=torch.float32, device="cuda")
+    u = torch.zeros((n, n + 1), dtype=torch.float32, device="cuda")
+    v = torch.zeros((n + 1, n), dtype=torch.float32, device="cuda")
+    p = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    xb = torch.empty((n,), dtype=torch.float32, device="cuda")
+
+    def step(x, meth):
+        pr.step_async(rho, u, v, flags, p, x, 1e-3, g=sc.g, drho=sc.drho, u_in=sc.u_in, cfl=0.5,
+                      method=meth, max_iters=200000, check_every=128 if meth == "hybrid" else 1)
+
+    for s in range(6):  # a developed plume
+        step(to_dev(scenes.inflow_noise(0, s, n)), "pcg")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step(xb, method)
+    torch.cuda.synchronize()
+    for s in range(6, 11):
+        x = to_dev(scenes.inflow_noise(0, s, n))
+        start = [t.clone() for t in (rho, u, v, p)]
+        step(x, method)  # eager
+        torch.cuda.synchronize()
+        r_e = pr.result()
+        eager = [t.clone() for t in (rho, u, v, p)]
+        for d, s_ in zip((rho, u, v, p), start):
+            d.copy_(s_)
+        xb.copy_(x)
+        g.replay()
+        torch.cuda.synchronize()
+        r_g = pr.result()
+        say(method, "step", s, "iters", r_e.iters, r_g.iters, "status", r_e.status, r_g.status)
+        assert r_g.status == r_e.status == 0 and r_g.iters == r_e.iters
+        assert r_g.e1_final == r_e.e1_final and r_g.dt == r_e.dt
+        assert all(torch.equal(a, b) for a, b in zip(eager, (rho, u, v, p)))
