@@ -256,7 +256,13 @@ int hyp_plan(hyp_ctx* ctx, const hyp_grid* g, const uint8_t* flags,
  * guess, iterate until E_1 < threshold (strict; tested before the first
  * update, every check_every updates and at max_iters), subtract the
  * gradient, write p and the result.  `res` must be device memory or
- * host-pinned memory; it is valid once `stream` has completed the call. */
+ * host-pinned memory; it is valid once `stream` has completed the call.
+ * The call may be recorded by stream capture (as may hyp_step): the
+ * persistent solver is then a plain launch of the same grid, sized by the
+ * occupancy query, so a replay must run with the GPU otherwise idle for its
+ * work-groups to be resident; a grid barrier that is not reached within 2 s
+ * ends the solve with HYP_STATUS_ABORTED instead of hanging.  A captured
+ * call replays with the pointers and options it was recorded with. */
 int hyp_project(hyp_ctx* ctx, const hyp_grid* g, const hyp_fields* f,
                 double threshold, const hyp_opts* o, void* ws,
                 size_t ws_bytes, hipStream_t stream, hyp_result* res);
