@@ -73,39 +73,63 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
   // face weights beta' = omega beta / k
   float ph[R], aa[R], bb[R];
   float be[VAR ? R : 1], bw[VAR ? R : 1], bn[VAR ? R : 1], bs[VAR ? R : 1];
+  // every load of the tile is issued before the first is used (one round
+  // trip; with the uses in the same loop the compiler waited row by row):
+  // flags, d and phi of the in-domain rows, then the face coefficients of
+  // the variable-density operator (a second round trip, they depend on the
+  // flags)
+  // (out-of-domain rows load cell 0 and are masked, so that no branch
+  // separates the loads)
+  unsigned dmask = 0;
+  uint8_t ci[R];
+  float dv[R];
+  const float* sp = from_phi ? I.phi : src;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int er = wave * R + r, gy = gy0 + r;
-    float a_ = 0.f, b_ = 0.f, p_ = 0.f;
-    if constexpr (VAR) be[r] = bw[r] = bn[r] = bs[r] = 0.f;
-    if (col_in && gy >= 0 && gy < I.ny) {
-      // the loads are independent (masked afterwards): one round trip
-      const int g = gy * I.nx + gx;
-      const uint8_t ci = gld(I.cell + g);
-      const float dv = gld(I.d + g);
-      const float pv = from_phi ? gld(I.phi + g) : ld_agent(src + g);
-      if (!(ci & C_SOLID)) {
-        if constexpr (VAR) {
-          const float e_ = (ci & C_E) ? gld(I.ce + g) : 0.f, w_ = (ci & C_W) ? gld(I.ce + g - 1) : 0.f;
-          const float n_ = (ci & C_N) ? gld(I.cn + g) : 0.f, s_ = (ci & C_S) ? gld(I.cn + g - I.nx) : 0.f;
-          const float k = (e_ + w_) + (n_ + s_);
-          const float sc = I.omega / k;
-          be[r] = e_ * sc; bw[r] = w_ * sc; bn[r] = n_ * sc; bs[r] = s_ * sc;
-          a_ = k;
-          b_ = -(I.wfac / k) * dv;
-        } else {
-          const float k = (float)cell_k(ci);
-          a_ = I.omega / k;
-          b_ = -(I.wfac / k) * dv;
-        }
-        p_ = pv;
-      }
-      if (lane_int && er >= H && er < H + TH) {
-        imask |= 1u << r;
-        if (!(ci & C_SOLID)) fmask |= 1u << r;
+    const int gy = gy0 + r;
+    const bool in = col_in && gy >= 0 && gy < I.ny;
+    const int g = in ? gy * I.nx + gx : 0;
+    dmask |= in ? 1u << r : 0u;
+    const uint8_t c_ = gld(I.cell + g);
+    const float d_ = gld(I.d + g), p_ = ld_agent(sp + g);
+    ci[r] = in ? c_ : (uint8_t)C_SOLID;
+    dv[r] = d_;
+    ph[r] = p_;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int er = wave * R + r, g = (gy0 + r) * I.nx + gx;
+    const bool fl = !(ci[r] & C_SOLID);
+    float a_ = 0.f, b_ = 0.f;
+    if constexpr (VAR) {
+      be[r] = bw[r] = bn[r] = bs[r] = 0.f;
+      if (fl) {
+        be[r] = (ci[r] & C_E) ? gld(I.ce + g) : 0.f;
+        bw[r] = (ci[r] & C_W) ? gld(I.ce + g - 1) : 0.f;
+        bn[r] = (ci[r] & C_N) ? gld(I.cn + g) : 0.f;
+        bs[r] = (ci[r] & C_S) ? gld(I.cn + g - I.nx) : 0.f;
       }
     }
-    ph[r] = p_; aa[r] = a_; bb[r] = b_;
+    if (fl) {
+      if constexpr (VAR) {
+        const float k = (be[r] + bw[r]) + (bn[r] + bs[r]);
+        const float sc = I.omega / k;
+        be[r] *= sc; bw[r] *= sc; bn[r] *= sc; bs[r] *= sc;
+        a_ = k;
+        b_ = -(I.wfac / k) * dv[r];
+      } else {
+        const float k = (float)cell_k(ci[r]);
+        a_ = I.omega / k;
+        b_ = -(I.wfac / k) * dv[r];
+      }
+    } else {
+      ph[r] = 0.f;
+    }
+    if (((dmask >> r) & 1u) && lane_int && er >= H && er < H + TH) {
+      imask |= 1u << r;
+      if (fl) fmask |= 1u << r;
+    }
+    aa[r] = a_; bb[r] = b_;
   }
   int q = 0;
   float below, above;

@@ -339,22 +339,58 @@ __device__ __forceinline__ void grad_body(int lb, int nb, int nx, int ny, float 
                                           const float* __restrict__ phi_acc, float* u, float* v,
                                           float* __restrict__ p, const float* __restrict__ ce,
                                           const float* __restrict__ cn) {
-#pragma unroll 4
-  for (CellWalk w(lb * blockDim.x + threadIdx.x, nb * blockDim.x, nx); w.c < nx * ny; w.next(nx)) {
-    const int c = w.c, i = w.i, j = w.j, U = nx + 1;
-    const uint8_t ci = cell[c];
-    const bool fl = !(ci & C_SOLID);
-    const float pc = phi[c];
-    if constexpr (VAR) {
-      if (fl && (ci & C_W)) u[j * U + i] -= ce[c - 1] * ((pc - phi[c - 1]) * inv_dx);
-      if (fl && (ci & C_S)) v[j * nx + i] -= cn[c - nx] * ((pc - phi[c - nx]) * inv_dx);
-      if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= cn[c] * ((0.f - pc) * inv_dx);
-    } else {
-      if (fl && (ci & C_W)) u[j * U + i] -= (pc - phi[c - 1]) * inv_dx;
-      if (fl && (ci & C_S)) v[j * nx + i] -= (pc - phi[c - nx]) * inv_dx;
-      if (j == ny - 1 && fl && (ci & C_N)) v[ny * nx + i] -= (0.f - pc) * inv_dx;
+  // four cells per pass: all their loads (clamped neighbour indices) are
+  // issued before any of their stores, so that they share one round trip;
+  // each cell stores its own west and south faces unconditionally,
+  // corrected or as they were (no other thread writes them), and the solid
+  // cells' pressure is masked with a bit-and (selects and conditional stores
+  // let the compiler move loads behind branches, one round trip per cell)
+  constexpr int UN = 4;
+  const int n = nx * ny, U = nx + 1;
+  CellWalk w(lb * blockDim.x + threadIdx.x, nb * blockDim.x, nx);
+  while (w.c < n) {
+    int cc[UN], ii[UN], jj[UN];
+    bool ok[UN];
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+      ok[k] = w.c < n;
+      cc[k] = ok[k] ? w.c : 0;
+      ii[k] = ok[k] ? w.i : 0;
+      jj[k] = ok[k] ? w.j : 0;
+      w.next(nx);
     }
-    p[c] = fl ? (phi_acc[c] + pc) * p_scale : 0.f;
+    uint8_t ci[UN];
+    float pc[UN], pw[UN], ps[UN], pa[UN], uw[UN], vs[UN], vt[UN], bw[UN], bs[UN], bn[UN];
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+      const int c = cc[k], cw = c > 0 ? c - 1 : 0, cs = c >= nx ? c - nx : 0;
+      ci[k] = cell[c];
+      pc[k] = phi[c];
+      pw[k] = phi[cw];
+      ps[k] = phi[cs];
+      pa[k] = phi_acc[c];
+      uw[k] = u[jj[k] * U + ii[k]];
+      vs[k] = v[jj[k] * nx + ii[k]];
+      vt[k] = v[ny * nx + ii[k]];
+      bw[k] = bs[k] = bn[k] = 1.f;
+      if constexpr (VAR) {
+        bw[k] = ce[cw];
+        bs[k] = cn[cs];
+        bn[k] = cn[c];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+      if (!ok[k]) continue;
+      const int c = cc[k], i = ii[k], j = jj[k];
+      const bool fl = !(ci[k] & C_SOLID);
+      const bool cw_ = fl && (ci[k] & C_W), cs_ = fl && (ci[k] & C_S);
+      u[j * U + i] = cw_ ? uw[k] - bw[k] * ((pc[k] - pw[k]) * inv_dx) : uw[k];
+      v[j * nx + i] = cs_ ? vs[k] - bs[k] * ((pc[k] - ps[k]) * inv_dx) : vs[k];
+      if (j == ny - 1 && fl && (ci[k] & C_N)) v[ny * nx + i] = vt[k] - bn[k] * ((0.f - pc[k]) * inv_dx);
+      const int keep = -(int)fl;
+      p[c] = __int_as_float(__float_as_int((pa[k] + pc[k]) * p_scale) & keep);
+    }
   }
 }
 
@@ -413,12 +449,15 @@ __device__ __forceinline__ void check_body(int lb, int nb, int nx, int ny, float
 #pragma unroll 4
   for (CellWalk w(lb * blockDim.x + threadIdx.x, nb * blockDim.x, nx); w.c < nx * ny; w.next(nx)) {
     const int c = w.c, i = w.i, j = w.j, U = nx + 1;
-    if (!(cell[c] & C_SOLID)) {
-      const float dv = ((u[j * U + i + 1] - u[j * U + i]) + (v[(j + 1) * nx + i] - v[j * nx + i])) * inv_dx;
-      const double ad = fabs((double)dv);
-      a += ad;
-      m = fmax(m, ad);
-    }
+    // loads issued before the flags decide: the solid cells' value is masked
+    // with a bit-and (a select would be turned into a branch around the
+    // loads, and every unrolled cell would wait for its own)
+    const uint8_t ci = cell[c];
+    const float dv = ((u[j * U + i + 1] - u[j * U + i]) + (v[(j + 1) * nx + i] - v[j * nx + i])) * inv_dx;
+    const long long keep = -(long long)((ci & C_SOLID) == 0);
+    const double ad = __longlong_as_double(__double_as_longlong(fabs((double)dv)) & keep);
+    a += ad;
+    m = fmax(m, ad);
   }
   const double sum = block_sum(a, red);
   const double mx = block_max(m, red);
