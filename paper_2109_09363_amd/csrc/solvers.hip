@@ -114,41 +114,53 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
   // keeps kk = a = omega / k and ww = b = -omega dx^2 d / k; VAR keeps
   // kk = k (the sum of the betas), ww = b and the face weights
   // beta' = omega beta / k.  kk > 0 marks fluid cells in both.
-  float ph[R], dd[R], kk[R], ww[R];
+  float ph[R], kk[R], ww[R];
   float be[R], bw[R], bn[R], bs[R];  // VAR only
+  // every row's flags, d and phi are loaded before the first is used (one
+  // round trip; out-of-domain rows load cell 0 and are masked), then the
+  // coefficients; the face betas of the variable-density operator depend on
+  // the flags (a second round trip)
+  uint8_t ci[R];
+  float dv[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int er = wave * R + r, gy = gy0 + r;
-    float d_ = 0.f, k_ = 0.f, w_ = 0.f, p_ = 0.f;
+    const int gy = gy0 + r;
+    const bool in = col_in && gy >= 0 && gy < p.ny;
+    const int g = in ? gy * p.nx + gx : 0;
+    dmask |= in ? 1u << r : 0u;
+    const uint8_t c_ = p.cell[g];
+    dv[r] = p.d[g];
+    ph[r] = p.phi[g];
+    ci[r] = in ? c_ : (uint8_t)C_SOLID;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int er = wave * R + r, g = (gy0 + r) * p.nx + gx;
+    const bool fl = !(ci[r] & C_SOLID);
+    float k_ = 0.f, w_ = 0.f;
     be[r] = bw[r] = bn[r] = bs[r] = 0.f;
-    if (col_in && gy >= 0 && gy < p.ny) {
-      dmask |= 1u << r;
-      const int g = gy * p.nx + gx;
-      const uint8_t ci = p.cell[g];
-      if (!(ci & C_SOLID)) {
-        if constexpr (VAR) {
-          face_betas(p.ce, p.cn, g, p.nx, ci, be[r], bw[r], bn[r], bs[r]);
-          k_ = (be[r] + bw[r]) + (bn[r] + bs[r]);
-        } else {
-          k_ = (float)cell_k(ci);
-        }
-        d_ = p.d[g];
-        w_ = -(p.wfac / k_) * d_;
-        p_ = p.phi[g];
-        d_ = 0.f;
-        if constexpr (VAR) {
-          const float sc = p.omega / k_;
-          be[r] *= sc; bw[r] *= sc; bn[r] *= sc; bs[r] *= sc;
-        } else {
-          k_ = p.omega / k_;
-        }
+    if (fl) {
+      if constexpr (VAR) {
+        face_betas(p.ce, p.cn, g, p.nx, ci[r], be[r], bw[r], bn[r], bs[r]);
+        k_ = (be[r] + bw[r]) + (bn[r] + bs[r]);
+      } else {
+        k_ = (float)cell_k(ci[r]);
       }
-      if (lane_int && er >= H && er < H + TH) {
-        imask |= 1u << r;
-        if (!(ci & C_SOLID)) fmask |= 1u << r;
+      w_ = -(p.wfac / k_) * dv[r];
+      if constexpr (VAR) {
+        const float sc = p.omega / k_;
+        be[r] *= sc; bw[r] *= sc; bn[r] *= sc; bs[r] *= sc;
+      } else {
+        k_ = p.omega / k_;
       }
+    } else {
+      ph[r] = 0.f;
     }
-    ph[r] = p_; dd[r] = d_; kk[r] = k_; ww[r] = w_;
+    if (((dmask >> r) & 1u) && lane_int && er >= H && er < H + TH) {
+      imask |= 1u << r;
+      if (fl) fmask |= 1u << r;
+    }
+    kk[r] = k_; ww[r] = w_;
   }
   // the tile's loads are complete before the loop (so that its publish
   // stores need not wait for them on every step)
@@ -552,28 +564,41 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
   unsigned dmask = 0, imask = 0;
   float x[R], r[R], u[R], w[R], pp[R], ss[R], kk[R], bb[R];
   float be[R], bw[R], bn[R], bs[R];  // VAR only
+  // every row's flags, d and phi are loaded before the first is used (one
+  // round trip; out-of-domain rows load cell 0 and are masked), then the
+  // coefficients (face betas: a second round trip)
+  uint8_t ci[R];
+  float dv[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const int er = wave * R + i, gy = gy0 + i;
-    float k_ = 0.f, b_ = 0.f, x_ = 0.f;
+    const int gy = gy0 + i;
+    const bool in = col_in && gy >= 0 && gy < p.ny;
+    const int g = in ? gy * p.nx + gx : 0;
+    dmask |= in ? 1u << i : 0u;
+    const uint8_t c_ = p.cell[g];
+    dv[i] = p.d[g];
+    x[i] = p.phi[g];
+    ci[i] = in ? c_ : (uint8_t)C_SOLID;
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int er = wave * R + i, g = (gy0 + i) * p.nx + gx;
+    const bool fl = !(ci[i] & C_SOLID);
+    float k_ = 0.f, b_ = 0.f;
     be[i] = bw[i] = bn[i] = bs[i] = 0.f;
-    if (col_in && gy >= 0 && gy < p.ny) {
-      dmask |= 1u << i;
-      const int g = gy * p.nx + gx;
-      const uint8_t ci = p.cell[g];
-      if (!(ci & C_SOLID)) {
-        if constexpr (VAR) {
-          face_betas(p.ce, p.cn, g, p.nx, ci, be[i], bw[i], bn[i], bs[i]);
-          k_ = (be[i] + bw[i]) + (bn[i] + bs[i]);
-        } else {
-          k_ = (float)cell_k(ci);
-        }
-        b_ = -p.dx2 * p.d[g];
-        x_ = p.phi[g];
+    if (fl) {
+      if constexpr (VAR) {
+        face_betas(p.ce, p.cn, g, p.nx, ci[i], be[i], bw[i], bn[i], bs[i]);
+        k_ = (be[i] + bw[i]) + (bn[i] + bs[i]);
+      } else {
+        k_ = (float)cell_k(ci[i]);
       }
-      if (lane_int && er >= 1 && er < 1 + TH) imask |= 1u << i;
+      b_ = -p.dx2 * dv[i];
+    } else {
+      x[i] = 0.f;
     }
-    kk[i] = k_; bb[i] = b_; x[i] = x_;
+    if (((dmask >> i) & 1u) && lane_int && er >= 1 && er < 1 + TH) imask |= 1u << i;
+    kk[i] = k_; bb[i] = b_;
     r[i] = 0.f; u[i] = 0.f; w[i] = 0.f; pp[i] = 0.f; ss[i] = 0.f;
   }
   int q = 0, k = p.sc->iters, nfold = 0;
