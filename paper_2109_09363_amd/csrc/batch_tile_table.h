@@ -11,12 +11,14 @@ struct BatchTileEntry {
 };
 
 constexpr BatchTileEntry kBatchTileTable[] = {
-    {128, 128, 8},  // 0.979 ms
-    {192, 192, 16},  // 1.458 ms
-    {256, 256, 16},  // 1.561 ms
-    {384, 384, 16},  // 2.341 ms
-    {512, 512, 16},  // 3.193 ms
+    {128, 128, 8},  // 0.811 ms
+    {192, 192, 8},  // 1.106 ms
+    {256, 256, 16},  // 1.324 ms
+    {384, 384, 16},  // 1.972 ms
+    {512, 512, 16},  // 2.847 ms
+    {768, 768, 16},  // 5.142 ms
+    {1024, 1024, 16},  // 8.831 ms
 };
-constexpr int kBatchTileTableSize = 5;
+constexpr int kBatchTileTableSize = 7;
 
 }  // namespace hyp

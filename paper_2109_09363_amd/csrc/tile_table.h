@@ -12,13 +12,13 @@ struct TileEntry {
 };
 
 constexpr TileEntry kTileTable[] = {
-    {128, 128, 13, 8},  // 1.050 ms
-    {192, 192, 17, 12},  // 1.066 ms
-    {256, 256, 17, 12},  // 1.075 ms
-    {384, 384, 17, 16},  // 1.142 ms
-    {512, 512, 9, 8},  // 1.310 ms
-    {768, 768, 13, 24},  // 1.806 ms
-    {1024, 1024, 9, 32},  // 2.595 ms
+    {128, 128, 17, 12},  // 1.014 ms
+    {192, 192, 17, 12},  // 1.015 ms
+    {256, 256, 17, 12},  // 1.030 ms
+    {384, 384, 17, 16},  // 1.163 ms
+    {512, 512, 9, 8},  // 1.245 ms
+    {768, 768, 13, 24},  // 2.024 ms
+    {1024, 1024, 9, 32},  // 2.772 ms
 };
 constexpr int kTileTableSize = 7;
 
