@@ -9,7 +9,7 @@ python bench.py [--gpus 1] [--steps K] [--warmup W]
 Workload: 512x512 unit-square plume (walls left/right/bottom, open top,
 inflow width 0.16, drho 0.01, Ri 0.1), 0-3 random disks drawn from seed 0;
 4-scale 64-channel BF16 CNN (FP32 accumulation, FP32 output layer) and FP32
-Jacobi (omega 1, E_1 tested every 128 sweeps).  The plume is first developed for
+Jacobi (omega 1, E_1 tested every 384 sweeps).  The plume is first developed for
 `warmup` untimed steps projected by PCG (every step converged), then `steps`
 hybrid steps are timed from that state; the same `steps` are then replayed
 from the same state with PCG.  All inputs are seeded and synthetic.  On
@@ -33,11 +33,13 @@ sys.path.insert(0, ROOT)
 N = 512
 SCALES, CHANNELS = 4, 64
 THRESHOLD = 1e-3
-# E_1 test interval: the hybrid's test (residual, grid reduction) costs about
-# two sweeps, so at ~4,000 sweeps per step a test every 128 sweeps minimises
-# test cost plus overshoot (measured on held-out plumes: experiments checks);
-# PCG's merged reduction carries E_1 every iteration at no extra cost
-CHECK_EVERY = {"hybrid": 128, "pcg": 1}
+# E_1 test interval: the hybrid's test (residual, grid reduction and its
+# round trip) costs several sweeps' time against the steps between tests,
+# which exchange tagged halo words only, so at ~3,000-4,000 sweeps per step a
+# test every 384 sweeps minimises test cost plus overshoot (measured on
+# held-out plumes: experiments checks); PCG's merged reduction carries E_1
+# every iteration at no extra cost
+CHECK_EVERY = {"hybrid": 384, "pcg": 1}
 MAX_ITERS = 1000000
 BYTES_PER_CELL_SWEEP = 13   # phi read + write (8), d (4), flags (1)
 HBM_PEAK_GBS = 8000.0
@@ -149,7 +151,10 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--check-every", type=int, default=CHECK_EVERY["hybrid"],
+                    help="sweeps between the hybrid's E_1 tests")
     args = ap.parse_args()
+    CHECK_EVERY["hybrid"] = args.check_every
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU sharding is a design "
               "note, not a code path (run with --gpus 1)", file=sys.stderr)
@@ -295,9 +300,10 @@ def main():
         "value": round(value, 3), "unit": "timesteps/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": round(1e3 * t_h / K, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "512x512 plume, 0-3 disks (seed 0), developed by PCG-projected steps; hybrid "
-                               "4-scale 64-ch BF16 CNN + FP32 Jacobi to mean|div|<1e-3 (E_1 tested every 128 sweeps; PCG every iteration), "
-                               "per full time step incl. advection",
+        "config": {"workload": ("512x512 plume, 0-3 disks (seed 0), developed by PCG-projected steps; hybrid "
+                                "4-scale 64-ch BF16 CNN + FP32 Jacobi to mean|div|<1e-3 (E_1 tested every %d "
+                                "sweeps; PCG every iteration), per full time step incl. advection"
+                                % CHECK_EVERY["hybrid"]),
                    "plume_age_steps": W,
                    "launch": "each method's time step captured once as a hipGraph and replayed per step",
                    "cnn_dtype": "bf16", "solver_dtype": "f32", "weights": w_kind,
