@@ -355,9 +355,13 @@ int hyp_advect(hyp_ctx* ctx, const hyp_grid* g, const hyp_physics* ph, const hyp
  * faces + divergence, the network's input, convolution layers and
  * upsample-sum, the gradient correction and the final check), and the
  * Jacobi sweeps of every instance run in ONE persistent launch over a
- * global tile list, with per-instance E_1 tests (every 8 sweeps; finished
- * instances drop out).  Methods HYBRID (HYP_ARCH_PARALLEL networks) and
- * JACOBI; check_every and fold_window are not used; criterion E_1 only.
+ * global tile list, with per-instance E_1 tests (finished instances drop
+ * out).  The tiles sweep 8 times between halo exchanges; o->check_every
+ * (>= 1) is rounded up to whole exchanges of 8 sweeps, and E_1 is tested
+ * at that interval, on the network's output and at max_iters (an instance
+ * that meets the threshold between tests sweeps on until the next one).
+ * Methods HYBRID (HYP_ARCH_PARALLEL networks) and JACOBI; fold_window is
+ * not used; criterion E_1 only.
  * o->variable_density applies the variable-density operator of
  * hyp_opts.variable_density to every instance (each with its own rho).
  * o->tile_rows: 0 (the tuned tile rows per grid side), or 8 or 16 for every

@@ -251,7 +251,7 @@ class Batch:
     def __init__(self, instances, threshold: float = 1e-3, method: str = "hybrid",
                  params=None, scales: int = 0, channels: int = 0, precision: str = "fp32",
                  max_iters: int = 200000, omega: float = 1.0, device=None,
-                 variable_density: bool = False, tile_rows: int = 0):
+                 variable_density: bool = False, tile_rows: int = 0, check_every: int = 8):
         self.lib = L.lib()
         self.device = torch.device("cuda" if device is None else device)
         ctx = ctypes.c_void_p()
@@ -295,7 +295,7 @@ class Batch:
                 self.lib.hyp_batch_workspace_size(self.ctx, self.n, G, ctypes.byref(nbytes)))
         self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         self.res = torch.zeros(self.n * ctypes.sizeof(L.Result), dtype=torch.uint8, device=self.device)
-        o = L.Opts(L.METHODS[method], int(max_iters), 8, 0, float(omega), 0, 0, int(tile_rows),
+        o = L.Opts(L.METHODS[method], int(max_iters), int(check_every), 0, float(omega), 0, 0, int(tile_rows),
                    1 if variable_density else 0, 0)
         b = ctypes.c_void_p()
         torch.cuda.synchronize()

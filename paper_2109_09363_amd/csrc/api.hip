@@ -485,6 +485,7 @@ struct hyp_batch {
   size_t cnn_bytes = 0;
   int cnn_tiles[4] = {0, 0, 0, 0};
   int tile_mode = 0;  // tile variants of the persistent Jacobi launch
+  int test_passes = 1, max_iters = 0;  // E_1 test interval in passes of 8 sweeps
   bool cnn = false, var = false, physics = false;
   std::vector<WsLayout> layouts;
   std::vector<Ws> ws;
@@ -535,6 +536,7 @@ int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_s
   if (o->criterion != HYP_CRIT_E1) return HYP_EUNSUPPORTED;
   if (o->variable_density != 0 && o->variable_density != 1) return HYP_EINVAL;
   if (o->max_iters < 0 || !(o->omega > 0.f) || o->checkpoint_every != 0) return HYP_EINVAL;
+  if (o->check_every < 1) return HYP_EINVAL;
   if (o->tile_rows != 0 && o->tile_rows != 8 && o->tile_rows != 16) return HYP_EINVAL;
   if (o->block_sweeps != 0) return HYP_EINVAL;  // the batch sweeps 8 per exchange
   const bool cnn = o->method == HYP_METHOD_HYBRID;
@@ -573,6 +575,8 @@ int hyp_batch_create(hyp_ctx* ctx, int32_t n, const hyp_grid* grids, const hyp_s
   b->var = var;
   b->physics = physics != nullptr;
   b->area = ws;
+  b->test_passes = (o->check_every + kBatchSweeps - 1) / kBatchSweeps;
+  b->max_iters = o->max_iters;
   std::vector<BInst> binst(n);
   std::vector<int> rows(n);
   int ntiles = 0;
@@ -647,8 +651,8 @@ static int batch_enqueue(hyp_batch* b, bool step, hipStream_t s, hyp_result* res
   } else if (run_init_phi_batch(I, R, s) != hipSuccess) {
     return HYP_EHIP;
   }
-  if (run_jacobi_batch(ctx->dev, b->area, b->n, b->ntiles, b->cnn_bytes, b->tile_mode, cooperative,
-                       s) != hipSuccess)
+  if (run_jacobi_batch(ctx->dev, b->area, b->n, b->ntiles, b->cnn_bytes, b->tile_mode,
+                       b->test_passes, b->max_iters, cooperative, s) != hipSuccess)
     return HYP_EHIP;
   if (run_grad_finish_batch(I, R, step, b->var, s) != hipSuccess) return HYP_EHIP;
   if (hipMemcpyAsync(res, b->dev.results, sizeof(hyp_result) * b->n, hipMemcpyDefault, s) != hipSuccess)

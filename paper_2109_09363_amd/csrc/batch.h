@@ -12,6 +12,7 @@
 namespace hyp {
 
 constexpr int kBatchMaxScales = 5;
+constexpr int kBatchSweeps = 8;  // Jacobi sweeps of a tile between halo exchanges
 
 // Work ranges: per instance, the number of work-groups of each launch shape.
 enum BatchRange {
@@ -80,7 +81,8 @@ hipError_t batch_setup(void* area, int n, int ntiles, size_t cnn_bytes, const BI
                        BatchDevice* out);
 int batch_tile_mode(int n, const int* rows, bool var);
 hipError_t run_jacobi_batch(const Device& dev, void* area, int n, int ntiles, size_t cnn_bytes,
-                            int mode, bool cooperative, hipStream_t s);
+                            int mode, int test_passes, int max_iters, bool cooperative,
+                            hipStream_t s);
 hipError_t run_div_batch(const BInst* I, const BatchRanges& R, hipStream_t s);
 hipError_t run_coef_batch(const BInst* I, const BatchRanges& R, hipStream_t s);
 hipError_t run_init_phi_batch(const BInst* I, const BatchRanges& R, hipStream_t s);

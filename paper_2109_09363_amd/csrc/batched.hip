@@ -26,7 +26,7 @@
 
 namespace hyp {
 
-constexpr int kBatchH = 9;  // halo: 8 sweeps per pass
+constexpr int kBatchH = kBatchSweeps + 1;  // halo of a pass
 
 struct BatchInstDev {
   int nx, ny, ntx, tile0, ntiles, max_iters, R, var;
@@ -53,12 +53,14 @@ struct BatchParams {
   double* tile_part;     // [2][ntiles]
   BatchState* st;
   unsigned* sync;
+  int test_passes;       // E_1 tested every test_passes passes of B sweeps,
+  int max_iters;         // on the first pass and once B * pass >= max_iters
 };
 
 template <int R, bool VAR>
 __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int B, const float* src,
-                                             float* dst, bool from_phi, float (*edge)[2][4][64],
-                                             double* red) {
+                                             float* dst, bool from_phi, bool test,
+                                             float (*edge)[2][4][64], double* red) {
   constexpr int H = kBatchH;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int TW = 64 - 2 * H, TH = 4 * R - 2 * H;
@@ -161,17 +163,20 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
 #pragma unroll
     for (int r = 0; r < R; ++r) ph[r] = tmp[r];
   }
-  edges_of(ph);
-  double acc;
-  if constexpr (VAR)
-    acc = jac_resid_var_scaled<R>(ph, aa, be, bw, bn, bs, bb, below, above, I.omega, I.inv_dx2, fmask,
-                                  false);
-  else
-    acc = jac_resid_scaled<R>(ph, aa, bb, below, above, I.omega, I.inv_dx2, fmask, false);
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if ((imask >> r) & 1u) st_agent(dst + (size_t)(gy0 + r) * I.nx + gx, ph[r]);
-  const double t = block_sum(acc, red);
+  double t = 0.0;
+  if (test) {
+    edges_of(ph);
+    double acc;
+    if constexpr (VAR)
+      acc = jac_resid_var_scaled<R>(ph, aa, be, bw, bn, bs, bb, below, above, I.omega, I.inv_dx2,
+                                    fmask, false);
+    else
+      acc = jac_resid_scaled<R>(ph, aa, bb, below, above, I.omega, I.inv_dx2, fmask, false);
+    t = block_sum(acc, red);
+  }
   __syncthreads();  // edge[] and red[] are reused by the next tile
   return t;
 }
@@ -193,15 +198,16 @@ constexpr int kTileR16 = 1, kTileR8 = 2, kTileVar = 4;
 template <int MODE>
 __device__ __forceinline__ double batch_tile_any(const BatchInstDev& I, int lt, int B,
                                                  const float* src, float* dst, bool from_phi,
-                                                 float (*edge)[2][4][64], double* red) {
+                                                 bool test, float (*edge)[2][4][64], double* red) {
   if constexpr ((MODE & kTileVar) != 0) {
-    if (I.var) return batch_tile<8, true>(I, lt, B, src, dst, from_phi, edge, red);
+    if (I.var) return batch_tile<8, true>(I, lt, B, src, dst, from_phi, test, edge, red);
   }
   if constexpr ((MODE & kTileR8) != 0) {
     if ((MODE & kTileR16) == 0 || I.R == 8)
-      return batch_tile<8, false>(I, lt, B, src, dst, from_phi, edge, red);
+      return batch_tile<8, false>(I, lt, B, src, dst, from_phi, test, edge, red);
   }
-  if constexpr ((MODE & kTileR16) != 0) return batch_tile<16, false>(I, lt, B, src, dst, from_phi, edge, red);
+  if constexpr ((MODE & kTileR16) != 0)
+    return batch_tile<16, false>(I, lt, B, src, dst, from_phi, test, edge, red);
   return 0.0;
 }
 
@@ -217,23 +223,31 @@ __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
   unsigned nbar = 0;
   int par = 0;  // plane read this block (written by the previous one)
   for (int nb = 0;; ++nb) {
+    // an instance still running has swept on every pass so far: before
+    // pass nb > 0 it holds min(B (nb - 1), max_iters) sweeps.  Statuses
+    // change only on test passes; the others sweep and pass one barrier.
+    const bool test = nb == 0 || nb % P.test_passes == 0 || B * nb >= P.max_iters;
     // phase A: sweep every tile of a running instance
     for (int t = blockIdx.x; t < P.ntiles; t += G) {
       const int i = cld_int(P.tile_inst + t);
       const BatchInstDev I = cld(P.inst, i);
       const int sti = ld_agent(&P.st[i].status);
       if (sti >= 0) continue;
-      const int k = ld_agent(&P.st[i].iters);
+      const int k = nb == 0 ? 0 : min(B * (nb - 1), I.max_iters);
       const int b = nb == 0 ? 0 : min(B, I.max_iters - k);
       const float* src = I.exch + (size_t)par * I.nx * I.ny;
       float* dst = I.exch + (size_t)(par ^ 1) * I.nx * I.ny;
       const int lt = t - I.tile0;
-      const double s = batch_tile_any<MODE>(I, lt, b, src, dst, nb == 0, edge, red);
-      if (threadIdx.x == 0) st_agent(P.tile_part + (size_t)(par ^ 1) * P.ntiles + t, s);
+      const double s = batch_tile_any<MODE>(I, lt, b, src, dst, nb == 0, test, edge, red);
+      if (test && threadIdx.x == 0) st_agent(P.tile_part + (size_t)(par ^ 1) * P.ntiles + t, s);
     }
     if (!grid_barrier_bounded(P.sync, ++nbar, (unsigned)G)) {
       batch_abort(P);
       return;
+    }
+    if (!test) {
+      par ^= 1;
+      continue;
     }
     // phase B: one work-group per instance sums its tiles in order and decides
     for (int i = blockIdx.x; i < P.ninst; i += G) {
@@ -241,8 +255,7 @@ __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
       if (ld_agent(&P.st[i].status) >= 0) continue;
       const double tot = sum_partials(P.tile_part + (size_t)(par ^ 1) * P.ntiles + I.tile0, I.ntiles, red);
       if (threadIdx.x == 0) {
-        int k = ld_agent(&P.st[i].iters);
-        if (nb > 0) k += min(B, I.max_iters - k);
+        const int k = nb == 0 ? 0 : min(B * nb, I.max_iters);
         const int nF = I.sc->nF;
         const double E = nF > 0 ? tot / nF : 0.0;
         int st = -1;
@@ -443,7 +456,8 @@ static const void* jacobi_batch_kernel(int mode) {
 }
 
 hipError_t run_jacobi_batch(const Device& dev, void* area, int n, int ntiles, size_t cnn_bytes,
-                            int mode, bool cooperative, hipStream_t s) {
+                            int mode, int test_passes, int max_iters, bool cooperative,
+                            hipStream_t s) {
   const void* kern = jacobi_batch_kernel(mode);
   if (!kern) return hipErrorInvalidValue;
   BatchArea A = carve(area, n, ntiles, cnn_bytes);
@@ -453,6 +467,8 @@ hipError_t run_jacobi_batch(const Device& dev, void* area, int n, int ntiles, si
   BatchParams P{};
   P.inst = A.inst; P.tile_inst = A.tile_inst; P.ninst = n; P.ntiles = ntiles;
   P.tile_part = A.tile_part; P.st = A.st; P.sync = A.sync;
+  P.test_passes = test_passes > 0 ? test_passes : 1;
+  P.max_iters = max_iters;
   // as many work-groups per CU as fit (up to 4), so that one work-group's
   // loads overlap another's sweeps; the occupancy query accounts for
   // registers and LDS, so all of them are resident when the GPU runs

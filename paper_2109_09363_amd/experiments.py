@@ -301,13 +301,15 @@ def cmd_batch(a, dev):
         return float(np.median(ts))
 
     out = {"what": "batch", "instances": len(inst), "cells": cells, "threshold": 1e-3,
-           "sides": sorted(set(d["nx"] for d in inst)), "variable_density": bool(a.var)}
+           "sides": sorted(set(d["nx"] for d in inst)), "variable_density": bool(a.var),
+           "check_every": a.check_every}
     saver = Saver(a.save, "batch")
     sample = list(range(0, len(inst), 8))  # the instances whose results are saved
     cases = {i: [] for i in sample}
     for method in ("hybrid", "jacobi"):
         b = hp.Batch(inst, threshold=1e-3, method=method, params=w, scales=S4, channels=C64,
-                     precision="bf16", max_iters=400000, variable_density=bool(a.var))
+                     precision="bf16", max_iters=400000, variable_density=bool(a.var),
+                     check_every=a.check_every)
         restore(snap_proj)
         b.project_async()          # warm
         torch.cuda.synchronize()
@@ -315,7 +317,8 @@ def cmd_batch(a, dev):
         res = b.results()
         for i in sample:
             cases[i].append(dict(method=method, precision="bf16", weights="trained" if method == "hybrid"
-                                 else "none", threshold=1e-3, iters=int(res[i].iters), check_every=8,
+                                 else "none", threshold=1e-3, iters=int(res[i].iters),
+                                 check_every=a.check_every,
                                  variable_density=bool(a.var), p=inst[i]["p"].cpu().numpy().copy()))
         it = np.array([r.iters for r in res], dtype=np.float64)
         row = {"ms_per_projection_of_all": round(ms_proj, 3),
@@ -352,7 +355,7 @@ def cmd_dram(a, dev):
                  u=torch.from_numpy(u.astype(np.float32)).to(dev),
                  v=torch.from_numpy(v.astype(np.float32)).to(dev),
                  p=torch.zeros((n, n), dtype=torch.float32, device=dev))]
-    b = hp.Batch(inst, threshold=0.0, method="jacobi", max_iters=a.sweeps)
+    b = hp.Batch(inst, threshold=0.0, method="jacobi", max_iters=a.sweeps, check_every=a.check_every)
     b.project_async()
     torch.cuda.synchronize()
     times = []
@@ -367,6 +370,7 @@ def cmd_dram(a, dev):
     ms = float(np.median(times))
     algo = 13.0 * n * n * r.iters
     emit({"what": "dram", "n": n, "sweeps": int(r.iters), "status": int(r.status),
+          "check_every": a.check_every,
           "ms_per_projection": round(ms, 3), "us_per_sweep": round(1e3 * ms / max(r.iters, 1), 3),
           "algorithmic_GBps": round(algo / (ms * 1e-3) / 1e9, 1), "hbm_peak_GBps": 8000.0,
           "note": "the projection also runs the divergence, gradient and check passes"})
@@ -488,10 +492,15 @@ def main():
     ap.add_argument("--sweeps", type=int, default=800)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--var", action="store_true", help="batch: variable-density operator")
+    ap.add_argument("--check-every", type=int, default=None,
+                    help="batch, dram: E_1 test interval in sweeps, rounded up to whole exchanges of 8 "
+                         "(default: batch 64, dram only at the end)")
     ap.add_argument("--save", default=None,
                     help="thresholds, gain, batch: write the first step's projection inputs and "
                          "pressures under this folder (for the error against the FP64 oracle)")
     a = ap.parse_args()
+    if a.check_every is None:
+        a.check_every = a.sweeps if a.what == "dram" else 64
     if a.seeds is None:
         a.seeds = list(range(100, 108)) if a.what in ("validate", "checks") else [0, 1, 2, 3, 4]
     dev = torch.device("cuda")

@@ -63,7 +63,11 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--sweeps", type=int, default=4096)
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--check-every", type=int, default=None,
+                    help="batch, dram: E_1 test interval (default: only at the end)")
     a = ap.parse_args()
+    if a.check_every is None:
+        a.check_every = max(a.sweeps, 1)
     dev = torch.device("cuda")
     n = a.n
     if a.what == "copy":
@@ -87,7 +91,8 @@ def main():
                              u=torch.from_numpy(u.astype(np.float32)).to(dev),
                              v=torch.from_numpy(v.astype(np.float32)).to(dev),
                              p=torch.zeros((s, s), dtype=torch.float32, device=dev)))
-        b = hp.Batch(inst, threshold=0.0, method="jacobi", max_iters=a.sweeps)
+        b = hp.Batch(inst, threshold=0.0, method="jacobi", max_iters=a.sweeps,
+                     check_every=a.check_every)
         cells = sum(d["nx"] * d["ny"] for d in inst)
         for _ in range(a.reps + 1):
             b.project_async()
@@ -102,12 +107,13 @@ def main():
                      u=torch.from_numpy(u.astype(np.float32)).to(dev),
                      v=torch.from_numpy(v.astype(np.float32)).to(dev),
                      p=torch.zeros((n, n), dtype=torch.float32, device=dev))]
-        b = hp.Batch(inst, threshold=0.0, method="jacobi", max_iters=a.sweeps)
+        b = hp.Batch(inst, threshold=0.0, method="jacobi", max_iters=a.sweeps,
+                     check_every=a.check_every)
         for _ in range(a.reps + 1):
             b.project_async()
         torch.cuda.synchronize()
-        print(f"dram: {a.reps + 1} projections of {a.sweeps} sweeps at {n}^2; algorithmic bytes "
-              f"per jacobi_batch launch {13 * n * n * a.sweeps}")
+        print(f"dram: {a.reps + 1} projections of {a.sweeps} sweeps at {n}^2 (E_1 tested every "
+              f"{a.check_every}); algorithmic bytes per jacobi_batch launch {13 * n * n * a.sweeps}")
         return
     pr, flags, u, v, p, tw = plume_state(n, dev)
     uu, vv = u.clone(), v.clone()
