@@ -245,9 +245,21 @@ __device__ __forceinline__ float from_right(float x) {
 
 // Sum of `n` doubles in global memory written by other work-groups, in a
 // fixed order, so that every work-group obtains the bit-identical value.
+// Each thread adds its strided share in index order; the loads go out
+// eight at a time before the adds, so that a long list costs n / (8 x
+// threads) round trips instead of n / threads (same order, same result).
 __device__ __forceinline__ double sum_partials(const double* part, int n, double* scratch) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v += ld_agent(part + i);
+  const int T = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 7 * T < n; i += 8 * T) {
+    double t[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] = ld_agent(part + i + k * T);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += t[k];
+  }
+  for (; i < n; i += T) v += ld_agent(part + i);
   return block_sum(v, scratch);
 }
 
