@@ -17,9 +17,11 @@ template <int R, bool OMEGA1>
 __device__ __forceinline__ void jac_rows_scaled(const float (&src)[R], float (&dst)[R],
                                                 const float (&aa)[R], const float (&bb)[R],
                                                 float below, float above, float om1) {
+  // each add takes at most one shifted operand, so that the shift folds
+  // into it (v_add_f32 with a DPP source: four VALU operations per cell)
   auto cell = [&](int r, float s, float n) {
     const float c = src[r];
-    const float S = (from_right(c) + from_left(c)) + (n + s);
+    const float S = from_right(c) + (from_left(c) + (n + s));
     const float y = fmaf(S, aa[r], bb[r]);
     return OMEGA1 ? y : fmaf(om1, c, y);
   };
@@ -44,7 +46,7 @@ __device__ __forceinline__ double jac_resid_scaled(const float (&ph)[R], const f
     const float c = ph[r];
     const float s = r > 0 ? ph[r - 1] : below;
     const float n = (r + 1 < R) ? ph[r + 1] : above;
-    const float S = (from_right(c) + from_left(c)) + (n + s);
+    const float S = from_right(c) + (from_left(c) + (n + s));
     const float num = fmaf(-aa[r], S, fmaf(omega, c, -bb[r]));
     if ((rmask >> r) & 1u) {
       const double res = fabsf(num * (__builtin_amdgcn_rcpf(aa[r]) * inv_dx2));
