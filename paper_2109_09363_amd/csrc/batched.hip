@@ -60,7 +60,7 @@ struct BatchParams {
 template <int R, bool VAR>
 __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int B, const float* src,
                                              float* dst, bool from_phi, bool test,
-                                             float (*edge)[2][4][64], double* red) {
+                                             BandEdges* edge, double* red) {
   constexpr int H = kBatchH;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int TW = 64 - 2 * H, TH = 4 * R - 2 * H;
@@ -135,14 +135,7 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
   }
   int q = 0;
   float below, above;
-  auto edges_of = [&](const float (&v)[R]) {
-    edge[q][0][wave][lane] = v[0];
-    edge[q][1][wave][lane] = v[R - 1];
-    __syncthreads();
-    below = wave > 0 ? edge[q][1][wave - 1][lane] : 0.f;
-    above = wave < 3 ? edge[q][0][wave + 1][lane] : 0.f;
-    q ^= 1;
-  };
+  auto edges_of = [&](const float (&v)[R]) { band_exchange<R>(v, edge, q, wave, lane, below, above); };
   auto rows = [&](const float (&s_)[R], float (&d_)[R], float om1) {
     if constexpr (VAR) jac_rows_var_scaled<R, false>(s_, d_, be, bw, bn, bs, bb, below, above, om1);
     else jac_rows_scaled<R, false>(s_, d_, aa, bb, below, above, om1);
@@ -198,7 +191,7 @@ constexpr int kTileR16 = 1, kTileR8 = 2, kTileVar = 4;
 template <int MODE>
 __device__ __forceinline__ double batch_tile_any(const BatchInstDev& I, int lt, int B,
                                                  const float* src, float* dst, bool from_phi,
-                                                 bool test, float (*edge)[2][4][64], double* red) {
+                                                 bool test, BandEdges* edge, double* red) {
   if constexpr ((MODE & kTileVar) != 0) {
     if (I.var) return batch_tile<8, true>(I, lt, B, src, dst, from_phi, test, edge, red);
   }
@@ -216,8 +209,9 @@ __device__ __forceinline__ double batch_tile_any(const BatchInstDev& I, int lt, 
 // slower)
 template <int MODE>
 __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
-  __shared__ float edge[2][2][4][64];
+  __shared__ BandEdges edge[2];
   __shared__ double red[4];
+  band_edges_clear(edge, threadIdx.x >> 6, threadIdx.x & 63);
   const int G = gridDim.x;
   const int B = kBatchH - 1;
   unsigned nbar = 0;

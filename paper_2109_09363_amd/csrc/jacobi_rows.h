@@ -7,6 +7,28 @@
 
 namespace hyp {
 
+// Band edges of a four-wave tile through LDS, edge[parity][low row / high
+// row][wave + 1][lane]: a wave writes its first and last rows and reads the
+// rows next to its band from slots wave and wave + 2.  Slot 0 of the high
+// rows and slot 5 of the low rows stay zero (the rows beyond the first and
+// last waves), so that every wave reads unconditionally: no branch splits
+// a sweep, which lets the east/west shifts fold into the adds.
+typedef float BandEdges[2][6][64];
+__device__ __forceinline__ void band_edges_clear(BandEdges* edge, int wave, int lane) {
+  if (wave == 0) edge[0][1][0][lane] = edge[1][1][0][lane] = 0.f;
+  if (wave == 3) edge[0][0][5][lane] = edge[1][0][5][lane] = 0.f;
+}
+template <int R>
+__device__ __forceinline__ void band_exchange(const float (&v)[R], BandEdges* edge, int& q, int wave,
+                                              int lane, float& below, float& above) {
+  edge[q][0][wave + 1][lane] = v[0];
+  edge[q][1][wave + 1][lane] = v[R - 1];
+  __syncthreads();
+  below = edge[q][1][wave][lane];
+  above = edge[q][0][wave + 2][lane];
+  q ^= 1;
+}
+
 // Constant-coefficient sweep in scaled form.  With a = omega / k and
 // b = -omega dx^2 d / k on fluid cells (0 elsewhere, so those cells stay 0),
 // the weighted Jacobi update phi - omega dx^2 r / k, r = d - (S - k phi) / dx^2

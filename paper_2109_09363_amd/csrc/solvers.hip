@@ -95,9 +95,10 @@ __device__ __forceinline__ void abort_solve(Scalars* sc) {
 // after which the halo is read as plain FP32 values.
 template <int R, bool VAR, bool TAGGED>
 __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacParams p) {
-  __shared__ float edge[2][2][4][64];  // [parity][low row / high row][wave][lane]
+  __shared__ BandEdges edge[2];
   __shared__ double red[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  band_edges_clear(edge, wave, lane);
   const int H = p.H, TW = 64 - 2 * H, TH = 4 * R - 2 * H;
   const int G = gridDim.x;
   const int bx = blockIdx.x % p.ntx, by = blockIdx.x / p.ntx;
@@ -173,12 +174,7 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
   double E_ref = 0.0;
   bool ref_set = false;
   auto edges_of = [&](const float (&v)[R], float* below, float* above) {
-    edge[q][0][wave][lane] = v[0];
-    edge[q][1][wave][lane] = v[R - 1];
-    __syncthreads();
-    *below = wave > 0 ? edge[q][1][wave - 1][lane] : 0.f;
-    *above = wave < 3 ? edge[q][0][wave + 1][lane] : 0.f;
-    q ^= 1;
+    band_exchange<R>(v, edge, q, wave, lane, *below, *above);
   };
   auto edges = [&](float* below, float* above) { edges_of(ph, below, above); };
   auto finish = [&](int st, double E) {
@@ -466,17 +462,6 @@ struct PcgParams {
   const float* cn;      // ... north face
 };
 
-template <int R>
-__device__ __forceinline__ void band_edges(float (&a)[R], float (*edge)[2][4][64], int& q, int wave,
-                                           int lane, float* below, float* above) {
-  edge[q][0][wave][lane] = a[0];
-  edge[q][1][wave][lane] = a[R - 1];
-  __syncthreads();
-  *below = wave > 0 ? edge[q][1][wave - 1][lane] : 0.f;
-  *above = wave < 3 ? edge[q][0][wave + 1][lane] : 0.f;
-  q ^= 1;
-}
-
 // y = A v on the rows of a lane (k v - sum of the four neighbours; 0 where k = 0)
 template <int R>
 __device__ __forceinline__ void apply_A(const float (&v)[R], const float (&kk)[R], float below,
@@ -549,9 +534,10 @@ __device__ __forceinline__ bool pcg_exchange(float (&v)[R], uint64_t* ex, unsign
 }
 template <int R, bool VAR>
 __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
-  __shared__ float edge[2][2][4][64];
+  __shared__ BandEdges edge[2];
   __shared__ double red3[12];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  band_edges_clear(edge, wave, lane);
   const int TW = 62, TH = 4 * R - 2;
   const int G = gridDim.x;
   const int bx = blockIdx.x % p.ntx, by = blockIdx.x / p.ntx;
@@ -697,7 +683,7 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
       ss[i] = 0.f;
     }
     if (!exchange(u, uex)) return false;
-    band_edges<R>(u, edge, q, wave, lane, &below, &above);
+    band_exchange<R>(u, edge, q, wave, lane, below, above);
     if constexpr (VAR) apply_A_var<R>(u, kk, be, bw, bn, bs, below, above, w);
     else apply_A<R>(u, kk, below, above, w);
     if (!reduce3()) return false;
@@ -709,7 +695,7 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
   auto true_residual = [&]() -> bool {
     if (!exchange(x, xex)) return false;
     float ax[R];
-    band_edges<R>(x, edge, q, wave, lane, &below, &above);
+    band_exchange<R>(x, edge, q, wave, lane, below, above);
     if constexpr (VAR) apply_A_var<R>(x, kk, be, bw, bn, bs, below, above, ax);
     else apply_A<R>(x, kk, below, above, ax);
 #pragma unroll
@@ -729,7 +715,7 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
   // defect-correction fold of the current x (its halo is fresh from the
   // true-residual exchange): faces, phi_acc, d recomputed from the faces
   auto fold = [&]() -> bool {
-    band_edges<R>(x, edge, q, wave, lane, &below, &above);
+    band_exchange<R>(x, edge, q, wave, lane, below, above);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const float west = from_left(x[i]);
@@ -811,7 +797,7 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
       u[i] = kk[i] > 0.f ? r[i] / kk[i] : 0.f;
     }
     if (!exchange(u, uex)) return;
-    band_edges<R>(u, edge, q, wave, lane, &below, &above);
+    band_exchange<R>(u, edge, q, wave, lane, below, above);
     if constexpr (VAR) apply_A_var<R>(u, kk, be, bw, bn, bs, below, above, w);
     else apply_A<R>(u, kk, below, above, w);
     const double gam_old = gam;

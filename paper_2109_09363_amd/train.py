@@ -30,6 +30,7 @@ python -m paper_2109_09363_amd.train --n 512 --init w.npy --random 0 \
 from __future__ import annotations
 
 import argparse
+import math
 import time
 
 import numpy as np
@@ -145,9 +146,12 @@ def initial_weights(arch: str, scales: int, channels: int, seed: int):
 def train(samples, n: int, scales: int, channels: int, precision: str = "fp32",
           steps: int = 200, batch: int = 4, lr: float = 1e-3, sweeps: int = 4,
           params0=None, seed: int = 0, device="cuda", log=print, log_every: int = 20,
-          alpha: float = 1.0, beta: float = 0.0, arch: str = "parallel"):
+          alpha: float = 1.0, beta: float = 0.0, arch: str = "parallel", lr_end=None):
     """Adam on  alpha * short-term + beta * long-term  normalised divergence
-    losses (beta = 0: the single-step loss); returns (params, loss history)."""
+    losses (beta = 0: the single-step loss); returns (params, loss history).
+    lr_end: None keeps lr constant; otherwise the rate follows a cosine from
+    lr at the first step to lr_end at the last (so that the returned weights
+    are not those of a single noisy late step)."""
     dx = 1.0 / n
     pr = api.Projector(n, n, dx, 1.0, 1.0, scales, channels, precision, device=device, train=True,
                        arch=arch)
@@ -190,7 +194,10 @@ def train(samples, n: int, scales: int, channels: int, precision: str = "fp32",
             if logging:
                 acc_loss += (float(ls_dev.item()) if alpha != 0.0 else 0.0) + \
                             (float(ll_dev.item()) if beta != 0.0 else 0.0)
-        api.adam_async(params, grads, m, v2, it, lr=lr)
+        lr_it = lr
+        if lr_end is not None and steps > 1:
+            lr_it = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * (it - 1) / (steps - 1)))
+        api.adam_async(params, grads, m, v2, it, lr=lr_it)
         if logging:
             hist.append((it, acc_loss))
             log(f"step {it:5d}  loss {acc_loss:.5f}  ({time.time() - t0:.1f} s)")
@@ -246,6 +253,8 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-end", type=float, default=None,
+                    help="cosine decay of the rate to this value at the last step (default: constant)")
     ap.add_argument("--sweeps", type=int, default=4)
     ap.add_argument("--scenes", type=int, default=12)
     ap.add_argument("--seed", type=int, default=0)
@@ -271,7 +280,7 @@ def main():
     data = generate_dataset(a.n, n_scenes=a.scenes, steps=a.sim_steps, n_random=a.random, seed=a.seed)
     w, hist = train(data, a.n, a.scales, a.channels, a.precision, steps=a.steps, batch=a.batch,
                     lr=a.lr, sweeps=a.sweeps, seed=a.seed, params0=params0, alpha=a.alpha,
-                    beta=a.beta, arch=a.arch)
+                    beta=a.beta, arch=a.arch, lr_end=a.lr_end)
     if held:
         m, mx = evaluate(held, a.n, a.scales, a.channels, a.precision, w, arch=a.arch)
         print(f"eval after: mean sweeps to 1e-3 {m:.1f} (max {mx}) on {len(held)} held-out states",

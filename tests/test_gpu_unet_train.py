@@ -106,10 +106,14 @@ def test_unet_gradient_matches_its_own_central_differences():
     run = UnetRun(sc)
     g = run(u, v, w, 3)
     for i in list(range(w.size - 17, w.size - 13)) + [w.size - 1]:
-        # the loss is quadratic in these parameters, so a large step leaves
-        # no truncation error and keeps the FP32 noise of the loss small
-        # against the difference; the perturbed values are FP32 numbers
-        h = 2.0 ** -5
+        # the loss is quadratic in these parameters (the output layer is
+        # affine in them and everything after it linear up to the squared
+        # divergence), so a large step leaves no truncation error and keeps
+        # the FP32 noise of the loss small against the difference (at
+        # 2^-5 the bias's difference was noise-limited: 14.911 against the
+        # FP64 oracle's 14.8893 and the adjoint's 14.8905); the perturbed
+        # values are FP32 numbers
+        h = 2.0 ** -1
         wp, wm = f32(w.copy()), f32(w.copy())
         wp[i] = f32(w[i] + h)
         wm[i] = f32(w[i] - h)
@@ -152,8 +156,10 @@ def test_unet_training_gain():
     from paper_2109_09363_amd import train as TR
     n = 64
     data = TR.generate_dataset(n, n_scenes=6, steps=20, keep_every=2, n_random=24, seed=5, log=say)
+    # the rate decays to 1e-4 by the last step: with a constant 1e-3 the
+    # returned weights are those of whichever single late step, noisy
     w, hist = TR.train(data, n, 0, 0, "fp32", steps=300, batch=4, lr=1e-3, sweeps=8, seed=2,
-                       log=say, log_every=50, arch="unet")
+                       log=say, log_every=50, arch="unet", lr_end=1e-4)
     say("loss history", hist)
     # single-batch losses are noisy: the mean of the last three logged ones
     assert np.mean([h[1] for h in hist[-3:]]) < 0.5 * hist[0][1]
