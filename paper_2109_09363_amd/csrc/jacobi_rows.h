@@ -29,6 +29,31 @@ __device__ __forceinline__ void band_exchange(const float (&v)[R], BandEdges* ed
   q ^= 1;
 }
 
+// Two rows per band edge, for two sweeps per exchange:
+// edge[parity][low 0, low 1, high 0, high 1][wave + 1][lane]; the high rows
+// of slot 0 and the low rows of slot 5 stay zero.
+typedef float BandEdges2[4][6][64];
+__device__ __forceinline__ void band_edges2_clear(BandEdges2* edge, int wave, int lane) {
+  if (wave == 0) edge[0][2][0][lane] = edge[0][3][0][lane] = edge[1][2][0][lane] = edge[1][3][0][lane] = 0.f;
+  if (wave == 3) edge[0][0][5][lane] = edge[0][1][5][lane] = edge[1][0][5][lane] = edge[1][1][5][lane] = 0.f;
+}
+// b0, b1: rows -2 and -1 of the band (the lower wave's last two); a0, a1:
+// rows R and R + 1 (the upper wave's first two)
+template <int R>
+__device__ __forceinline__ void band_exchange2(const float (&v)[R], BandEdges2* edge, int& q, int wave,
+                                               int lane, float& b0, float& b1, float& a0, float& a1) {
+  edge[q][0][wave + 1][lane] = v[0];
+  edge[q][1][wave + 1][lane] = v[1];
+  edge[q][2][wave + 1][lane] = v[R - 2];
+  edge[q][3][wave + 1][lane] = v[R - 1];
+  __syncthreads();
+  b0 = edge[q][2][wave][lane];
+  b1 = edge[q][3][wave][lane];
+  a0 = edge[q][0][wave + 2][lane];
+  a1 = edge[q][1][wave + 2][lane];
+  q ^= 1;
+}
+
 // Constant-coefficient sweep in scaled form.  With a = omega / k and
 // b = -omega dx^2 d / k on fluid cells (0 elsewhere, so those cells stay 0),
 // the weighted Jacobi update phi - omega dx^2 r / k, r = d - (S - k phi) / dx^2
@@ -51,6 +76,29 @@ __device__ __forceinline__ void jac_rows_scaled(const float (&src)[R], float (&d
   for (int r = 1; r + 1 < R; ++r) dst[r] = cell(r, src[r - 1], src[r + 1]);
   dst[0] = cell(0, below, src[1]);
   dst[R - 1] = cell(R - 1, src[R - 2], above);
+}
+
+// Two constant-coefficient sweeps from one band exchange (ph -> tmp -> ph):
+// with rows -2, -1 and R, R + 1 of the neighbouring waves (b0, b1, a0, a1),
+// the first sweep also updates rows -1 and R (their coefficients gk_b,
+// gw_b and gk_a, gw_a; zero beyond the tile, so that those rows stay zero
+// there), which is what the second sweep takes from the neighbours.  The
+// neighbour rows are updated by the same operations as in their own wave,
+// so the result equals two sweeps with an exchange each, bit for bit.
+template <int R, bool OMEGA1>
+__device__ __forceinline__ void jac_pair_ghost(float (&ph)[R], float (&tmp)[R], const float (&aa)[R],
+                                               const float (&bb)[R], float gk_b, float gw_b,
+                                               float gk_a, float gw_a, float b0, float b1, float a0,
+                                               float a1, float om1) {
+  auto upd = [&](float c, float s, float n, float a, float b) {
+    const float S = from_right(c) + (from_left(c) + (n + s));
+    const float y = fmaf(S, a, b);
+    return OMEGA1 ? y : fmaf(om1, c, y);
+  };
+  const float tb = upd(b1, b0, ph[0], gk_b, gw_b);      // row -1 after the first sweep
+  const float ta = upd(a0, ph[R - 1], a1, gk_a, gw_a);  // row R after the first sweep
+  jac_rows_scaled<R, OMEGA1>(ph, tmp, aa, bb, b1, a0, om1);
+  jac_rows_scaled<R, OMEGA1>(tmp, ph, aa, bb, tb, ta, om1);
 }
 
 // The residual r = d - (S - k phi) / dx^2 of the scaled form, from

@@ -96,9 +96,11 @@ __device__ __forceinline__ void abort_solve(Scalars* sc) {
 template <int R, bool VAR, bool TAGGED>
 __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacParams p) {
   __shared__ BandEdges edge[2];
+  __shared__ BandEdges2 edge2[2];  // two rows per edge: two sweeps per exchange
   __shared__ double red[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   band_edges_clear(edge, wave, lane);
+  band_edges2_clear(edge2, wave, lane);
   const int H = p.H, TW = 64 - 2 * H, TH = 4 * R - 2 * H;
   const int G = gridDim.x;
   const int bx = blockIdx.x % p.ntx, by = blockIdx.x / p.ntx;
@@ -169,8 +171,20 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
   const int k0 = p.sc->iters;
   const int end = p.fixed_iters > 0 ? p.fixed_iters : p.max_iters;
   const size_t plane = (size_t)p.nx * p.ny;
-  int k = k0, q = 0, k_ref = k0;
+  int k = k0, q = 0, q2 = 0, k_ref = k0;
   unsigned j = 0, t = 0, nbar = 0;
+  // Sweeps in pairs with one two-row band exchange (constant coefficients,
+  // tagged form: there the waves drift apart between the tile exchanges,
+  // and a block barrier per sweep costs more than the two extra rows that
+  // the first sweep of a pair updates; in the plain form, every step behind
+  // a grid barrier, it does not).  The coefficients of the rows next to the
+  // band (the neighbouring waves' edge rows; zero beyond the tile):
+  constexpr bool GHOST = !VAR && R <= 16 && TAGGED;
+  float gk_b = 0.f, gw_b = 0.f, gk_a = 0.f, gw_a = 0.f;
+  if constexpr (GHOST) {
+    band_exchange<R>(kk, edge, q, wave, lane, gk_b, gk_a);
+    band_exchange<R>(ww, edge, q, wave, lane, gw_b, gw_a);
+  }
   double E_ref = 0.0;
   bool ref_set = false;
   auto edges_of = [&](const float (&v)[R], float* below, float* above) {
@@ -374,6 +388,8 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
         }
         ph[r] = 0.f;
       }
+      // the rows next to the band take the new right-hand sides too
+      if constexpr (GHOST) band_exchange<R>(ww, edge, q, wave, lane, gw_b, gw_a);
     }
     // every load of the step (halo, partials, faces) is complete here: the
     // sweeps need the halo at once, and no path back to the publish stores
@@ -399,6 +415,15 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
         const float om1 = 1.f - p.omega;
         float tmp[R];
         int s = 0;
+        if constexpr (GHOST) {
+          // one exchange of two rows per pair of sweeps
+          constexpr bool O1 = decltype(one)::value;
+          for (; s + 2 <= B; s += 2) {
+            float b0, b1, a0, a1;
+            band_exchange2<R>(ph, edge2, q2, wave, lane, b0, b1, a0, a1);
+            jac_pair_ghost<R, O1>(ph, tmp, kk, ww, gk_b, gw_b, gk_a, gw_a, b0, b1, a0, a1, om1);
+          }
+        }
         for (; PAIRS && s + 2 <= B; s += 2) {
           float below, above;
           edges_of(ph, &below, &above);
