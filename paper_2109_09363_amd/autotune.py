@@ -1,7 +1,7 @@
 """Tile autotuner of the persistent Jacobi kernels.
 
 Single grids: for each grid size, time a number of sweeps (E_1 tested every
-128, as in the benchmark) with every
+--check-every, 384 by default as in the benchmark) with every
 tile height R that fits the GPU and every block length B (sweeps between
 halo exchanges, halo B + 1) of --blocks, and keep the fastest pair; the
 result is the C header the library compiles (csrc/tile_table.h), and grids
@@ -35,7 +35,7 @@ from paper_2109_09363_amd import _lib as L  # noqa: E402
 ROWS = (4, 8, 12, 16, 24, 32)
 
 
-def time_rows(n, rows, sweeps, reps, dev, block=8):
+def time_rows(n, rows, sweeps, reps, dev, block=8, check_every=384):
     sc = scenes.plume_scene(n, seed=0, n_obstacles=2)
     u, v = scenes.random_faces(n, n, 0, kind="mixed")
     pr = hp.Projector(n, n, sc.dx, 1.0, 1.0, 0, 0, "fp32", device=dev)
@@ -52,11 +52,11 @@ def time_rows(n, rows, sweeps, reps, dev, block=8):
                 uu, vv = u0.clone(), v0.clone()
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record()
-                # the benchmark's pattern: E_1 tested every 128 sweeps (a
-                # grid barrier), the others neighbour-synchronised; a zero
-                # threshold runs to max_iters, no folds
+                # the benchmark's pattern: E_1 tested every check_every
+                # sweeps (a grid barrier), the others neighbour-synchronised;
+                # a zero threshold runs to max_iters, no folds
                 pr.project_async(uu, vv, flags, p, 0.0, method="jacobi", max_iters=sweeps,
-                                 check_every=128, fold_window=1 << 30, tile_rows=r,
+                                 check_every=check_every, fold_window=1 << 30, tile_rows=r,
                                  block_sweeps=block)
                 b.record()
                 torch.cuda.synchronize()
@@ -162,6 +162,7 @@ def main():
     ap.add_argument("--blocks", type=int, nargs="*", default=[8, 12, 16],
                     help="block lengths (sweeps between halo exchanges) to try")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--check-every", type=int, default=384)
     ap.add_argument("--out", default=None)
     ap.add_argument("--batch", action="store_true", help="tune the batched kernel's rows per side")
     ap.add_argument("--per-batch", type=int, default=16, help="--batch: plumes per timed batch")
@@ -185,7 +186,8 @@ def main():
     for n in a.sizes:
         t = {}
         for b in a.blocks:
-            for r, ms in time_rows(n, ROWS, a.sweeps, a.reps, dev, block=b).items():
+            times = time_rows(n, ROWS, a.sweeps, a.reps, dev, block=b, check_every=a.check_every)
+            for r, ms in times.items():
                 t[(b, r)] = ms
         if not t:
             print(json.dumps({"n": n, "fits": False}), flush=True)

@@ -94,20 +94,25 @@ __device__ __forceinline__ void abort_solve(Scalars* sc) {
 // (below); otherwise every step ends at a test and crosses the grid barrier,
 // after which the halo is read as plain FP32 values.
 template <int R, bool VAR, bool TAGGED>
-__global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacParams p) {
+__global__ __launch_bounds__(256, (R <= 8 && (VAR || TAGGED) ? 2 : 1)) void jacobi_reg(JacParams p) {
   __shared__ BandEdges edge[2];
   __shared__ BandEdges2 edge2[2];  // two rows per edge: two sweeps per exchange
   __shared__ double red[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   band_edges_clear(edge, wave, lane);
   band_edges2_clear(edge2, wave, lane);
+  // Tile bx, by covers columns bx TW .. bx TW + 63 and rows by TH .. by TH +
+  // 4R - 1; its interior leaves H cells to each side that has a neighbouring
+  // tile and none at the grid's edges, where the cells outside stay zero
+  // (so the first and last tiles of a row or column own H more cells)
   const int H = p.H, TW = 64 - 2 * H, TH = 4 * R - 2 * H;
   const int G = gridDim.x;
   const int bx = blockIdx.x % p.ntx, by = blockIdx.x / p.ntx;
-  const int gx = bx * TW - H + lane;
-  const int gy0 = by * TH - H + wave * R;
-  const bool col_in = gx >= 0 && gx < p.nx;
-  const bool lane_int = lane >= H && lane < H + TW && col_in;
+  const int gx = bx * TW + lane;
+  const int gy0 = by * TH + wave * R;
+  const bool col_in = gx < p.nx;
+  const bool lane_int = lane >= (bx == 0 ? 0 : H) && lane < (bx == p.ntx - 1 ? 64 : 64 - H) && col_in;
+  const int row_lo = by == 0 ? 0 : H, row_hi = by == p.nty - 1 ? 4 * R : 4 * R - H;
   const int nF = p.sc->nF;
   if (p.sc->status >= 0) return;  // nothing to do (status already final)
   // rows of this thread inside the domain (dmask), inside the tile interior
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
     } else {
       ph[r] = 0.f;
     }
-    if (((dmask >> r) & 1u) && lane_int && er >= H && er < H + TH) {
+    if (((dmask >> r) & 1u) && lane_int && er >= row_lo && er < row_hi) {
       imask |= 1u << r;
       if (fl) fmask |= 1u << r;
     }
@@ -276,9 +281,22 @@ __global__ __launch_bounds__(256, (VAR && R <= 8 ? 2 : 1)) void jacobi_reg(JacPa
     // the fluid halo cells after the barrier, in the same round trip as the
     // partials
     if (!TAGGED && j > 0) {
+      // every row's load is issued before the first is used (at the lane's
+      // own column and a row clamped into the grid), the halo's fluid cells
+      // then taken by a bit mask: with the loads under the conditions the
+      // compiler waited row by row
+      const int gxc = gx < p.nx ? gx : p.nx - 1;
+      float hv[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (!((imask >> r) & 1u) && kk[r] > 0.f) ph[r] = ld_agent(ex32 + (size_t)(gy0 + r) * p.nx + gx);
+      for (int r = 0; r < R; ++r) {
+        const int gy = gy0 + r, gyc = gy < 0 ? 0 : (gy < p.ny ? gy : p.ny - 1);
+        hv[r] = ld_agent(ex32 + (size_t)gyc * p.nx + gxc);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const unsigned take = -(unsigned)((((imask >> r) & 1u) == 0u) & (kk[r] > 0.f));
+        ph[r] = __uint_as_float((__float_as_uint(hv[r]) & take) | (__float_as_uint(ph[r]) & ~take));
+      }
     } else if (j > 0) {
       const unsigned want = tag_of(j);
       unsigned need = dmask & ~imask;
@@ -908,7 +926,10 @@ static bool jacobi_fit(const Device& dev, int nx, int ny, int r, int h, bool var
   if (tw < 1 || th < 1) return false;
   int cap = dev.cu * (multi ? jacobi_per_cu(r, var) : 1);
   cap = cap < kMaxCoopBlocks ? cap : kMaxCoopBlocks;
-  const int tx = (nx + tw - 1) / tw, ty = (ny + th - 1) / th;
+  // tile t starts at t tw (columns) and t th (rows); the last one reaches
+  // the grid's edge (the tile layout of jacobi_reg)
+  const int tx = 1 + (nx > 64 ? (nx - 64 + tw - 1) / tw : 0);
+  const int ty = 1 + (ny > 4 * r ? (ny - 4 * r + th - 1) / th : 0);
   if (tx * ty > cap) return false;
   *ntx = tx;
   *nty = ty;

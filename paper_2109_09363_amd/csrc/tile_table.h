@@ -12,13 +12,13 @@ struct TileEntry {
 };
 
 constexpr TileEntry kTileTable[] = {
-    {128, 128, 17, 12},  // 1.014 ms
-    {192, 192, 17, 12},  // 1.015 ms
-    {256, 256, 17, 12},  // 1.030 ms
-    {384, 384, 17, 16},  // 1.163 ms
-    {512, 512, 9, 8},  // 1.245 ms
-    {768, 768, 13, 24},  // 2.024 ms
-    {1024, 1024, 9, 32},  // 2.772 ms
+    {128, 128, 13, 12},  // 0.822 ms
+    {192, 192, 13, 12},  // 0.828 ms
+    {256, 256, 13, 12},  // 0.850 ms
+    {384, 384, 13, 12},  // 0.912 ms
+    {512, 512, 17, 16},  // 0.983 ms
+    {768, 768, 13, 24},  // 1.919 ms
+    {1024, 1024, 9, 32},  // 2.622 ms
 };
 constexpr int kTileTableSize = 7;
 
