@@ -63,12 +63,16 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
                                              BandEdges* edge, double* red) {
   constexpr int H = kBatchH;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // tile bx, by covers columns bx TW .. bx TW + 63 and rows by TH .. by TH +
+  // 4R - 1, its interior H cells short of each side with a neighbouring
+  // tile (none at the grid's edges, where the cells outside stay zero)
   const int TW = 64 - 2 * H, TH = 4 * R - 2 * H;
-  const int bx = lt % I.ntx, by = lt / I.ntx;
-  const int gx = bx * TW - H + lane;
-  const int gy0 = by * TH - H + wave * R;
-  const bool col_in = gx >= 0 && gx < I.nx;
-  const bool lane_int = lane >= H && lane < H + TW && col_in;
+  const int bx = lt % I.ntx, by = lt / I.ntx, nty = I.ntiles / I.ntx;
+  const int gx = bx * TW + lane;
+  const int gy0 = by * TH + wave * R;
+  const bool col_in = gx < I.nx;
+  const bool lane_int = lane >= (bx == 0 ? 0 : H) && lane < (bx == I.ntx - 1 ? 64 : 64 - H) && col_in;
+  const int row_lo = by == 0 ? 0 : H, row_hi = by == nty - 1 ? 4 * R : 4 * R - H;
   unsigned imask = 0, fmask = 0;
   // scaled forms of the update (jacobi_rows.h): constant coefficients keep
   // aa = omega / k and bb = -omega dx^2 d / k; VAR keeps aa = k, bb and the
@@ -127,7 +131,7 @@ __device__ __forceinline__ double batch_tile(const BatchInstDev& I, int lt, int 
     } else {
       ph[r] = 0.f;
     }
-    if (((dmask >> r) & 1u) && lane_int && er >= H && er < H + TH) {
+    if (((dmask >> r) & 1u) && lane_int && er >= row_lo && er < row_hi) {
       imask |= 1u << r;
       if (fl) fmask |= 1u << r;
     }
@@ -286,11 +290,16 @@ __global__ __launch_bounds__(256, 4) void jacobi_batch(BatchParams P) {
     const BatchInstDev I = cld(P.inst, i);
     const int fp = ld_agent(&P.st[i].fpar);
     const float* src = I.exch + (size_t)fp * I.nx * I.ny;
-    const int TW = 64 - 2 * kBatchH, TH = 4 * I.R - 2 * kBatchH;
-    const int lt = t - I.tile0, bx = lt % I.ntx, by = lt / I.ntx;
-    for (int e = threadIdx.x; e < TW * TH; e += blockDim.x) {
-      const int gx = bx * TW + e % TW, gy = by * TH + e / TW;
-      if (gx < I.nx && gy < I.ny) gst(I.phi + gy * I.nx + gx, ld_agent(src + gy * I.nx + gx));
+    const int H = kBatchH, TW = 64 - 2 * H, TH = 4 * I.R - 2 * H;
+    const int lt = t - I.tile0, bx = lt % I.ntx, by = lt / I.ntx, nty = I.ntiles / I.ntx;
+    // the tile's interior (as in batch_tile)
+    const int c0 = bx == 0 ? 0 : bx * TW + H, r0 = by == 0 ? 0 : by * TH + H;
+    const int c1 = min(I.nx, bx * TW + (bx == I.ntx - 1 ? 64 : 64 - H));
+    const int r1 = min(I.ny, by * TH + (by == nty - 1 ? 4 * I.R : 4 * I.R - H));
+    const int w = c1 - c0;
+    for (int e = threadIdx.x; e < w * (r1 - r0); e += blockDim.x) {
+      const int gx = c0 + e % w, gy = r0 + e / w;
+      gst(I.phi + gy * I.nx + gx, ld_agent(src + gy * I.nx + gx));
     }
   }
 }
@@ -324,9 +333,16 @@ int batch_tile_mode(int n, const int* rows, bool var) {
   return m;
 }
 
+// tiles across a row of nx cells: tile t starts at column t TW, the last
+// reaches the grid's edge
+static int batch_tiles_x(int nx) {
+  const int TW = 64 - 2 * kBatchH;
+  return 1 + (nx > 64 ? (nx - 64 + TW - 1) / TW : 0);
+}
+
 int batch_tiles_of(int nx, int ny, int R) {
   const int TW = 64 - 2 * kBatchH, TH = 4 * R - 2 * kBatchH;
-  return ((nx + TW - 1) / TW) * ((ny + TH - 1) / TH);
+  return batch_tiles_x(nx) * (1 + (ny > 4 * R ? (ny - 4 * R + TH - 1) / TH : 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -393,7 +409,6 @@ hipError_t batch_setup(void* area, int n, int ntiles, size_t cnn_bytes, const BI
   std::vector<BatchInstDev> hi(n);
   std::vector<int> ht(ntiles);
   std::vector<int> hr((size_t)RK_COUNT * (n + 1), 0);
-  const int TW = 64 - 2 * kBatchH;
   int t0 = 0;
   for (int i = 0; i < n; ++i) {
     const BInst& B = binst[i];
@@ -401,7 +416,7 @@ hipError_t batch_setup(void* area, int n, int ntiles, size_t cnn_bytes, const BI
     I.nx = B.nx; I.ny = B.ny;
     I.R = rows[i];
     I.var = B.var;
-    I.ntx = (B.nx + TW - 1) / TW;
+    I.ntx = batch_tiles_x(B.nx);
     I.tile0 = t0;
     I.ntiles = batch_tiles_of(B.nx, B.ny, I.R);
     I.max_iters = max_iters;
