@@ -9,7 +9,7 @@ python bench.py [--gpus 1] [--steps K] [--warmup W]
 Workload: 512x512 unit-square plume (walls left/right/bottom, open top,
 inflow width 0.16, drho 0.01, Ri 0.1), 0-3 random disks drawn from seed 0;
 4-scale 64-channel BF16 CNN (FP32 accumulation, FP32 output layer) and FP32
-Jacobi (omega 1, E_1 tested every 384 sweeps).  The plume is first developed for
+Jacobi (omega 1, E_1 tested every 768 sweeps).  The plume is first developed for
 `warmup` untimed steps projected by PCG (every step converged), then `steps`
 hybrid steps are timed from that state; the same `steps` are then replayed
 from the same state with PCG.  All inputs are seeded and synthetic.  On
@@ -36,10 +36,10 @@ THRESHOLD = 1e-3
 # E_1 test interval: the hybrid's test (residual, grid reduction and its
 # round trip) costs several sweeps' time against the steps between tests,
 # which exchange tagged halo words only, so at ~3,000-4,000 sweeps per step a
-# test every 384 sweeps minimises test cost plus overshoot (measured on
+# test every 768 sweeps minimises test cost plus overshoot (measured on
 # held-out plumes: experiments checks); PCG's merged reduction carries E_1
 # every iteration at no extra cost
-CHECK_EVERY = {"hybrid": 384, "pcg": 1}
+CHECK_EVERY = {"hybrid": 768, "pcg": 1}
 MAX_ITERS = 1000000
 BYTES_PER_CELL_SWEEP = 13   # phi read + write (8), d (4), flags (1)
 HBM_PEAK_GBS = 8000.0

@@ -1,7 +1,7 @@
 """Tile autotuner of the persistent Jacobi kernels.
 
 Single grids: for each grid size, time a number of sweeps (E_1 tested every
---check-every, 384 by default as in the benchmark) with every
+--check-every, 384 by default) with every
 tile height R that fits the GPU and every block length B (sweeps between
 halo exchanges, halo B + 1) of --blocks, and keep the fastest pair; the
 result is the C header the library compiles (csrc/tile_table.h), and grids

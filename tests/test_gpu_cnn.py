@@ -82,11 +82,11 @@ def test_zero_weights_hybrid_is_jacobi_bitwise():
 
 
 # the last cases are the benchmark's configuration: 512^2, 4 scales of 64
-# channels in BF16, E_1 tested every 128 or (the benchmark's) 384 sweeps
+# channels in BF16, E_1 tested every 128 or (the benchmark's) 768 sweeps
 # (tagged halo exchanges between the tests, two work-groups per CU)
 @pytest.mark.parametrize("n,S,C,prec,seed,thr_rel,ce", [
     (128, 3, 32, "fp32", 0, 0.05, 4), (256, 3, 32, "fp32", 1, 0.1, 4), (128, 4, 64, "bf16", 2, 0.05, 4),
-    (512, 4, 64, "bf16", 3, 0.2, 128), (512, 4, 64, "bf16", 4, 0.2, 384)])
+    (512, 4, 64, "bf16", 3, 0.2, 128), (512, 4, 64, "bf16", 4, 0.2, 768)])
 def test_hybrid_parity(n, S, C, prec, seed, thr_rel, ce):
     say("hybrid", n, S, C, prec, ce)
     sc, u, v = state(n, n, seed, 2)
