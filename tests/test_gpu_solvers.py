@@ -325,6 +325,37 @@ def test_project_call_plans_only_when_the_flags_change():
     assert outs[0] == outs[1]
 
 
+@pytest.mark.parametrize("nx,ny", [(60, 50), (64, 64), (65, 130), (200, 97), (512, 512)])
+def test_jacobi_tile_shape_does_not_change_the_iterates(nx, ny):
+    """Tiles of R rows per wave and B sweeps per exchange, the first and
+    last of a row or column without a halo on the grid's side: every shape
+    that fits gives the same iterate bit for bit (one tile across 60 or 64
+    cells, a one-cell last tile at 65), and the oracle's Jacobi at that
+    count."""
+    say("tile shapes", nx, ny)
+    sc = scenes.plume_scene(nx, seed=7, n_obstacles=2, ny=ny)
+    u, v = scenes.random_faces(nx, ny, 7, kind="mixed")
+    u, v = f32(u), f32(v)
+    ref, runs = None, 0
+    for rows, block in [(8, 8), (4, 2), (12, 12), (16, 16), (8, 5), (24, 8), (32, 16)]:
+        try:
+            g = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="jacobi", fixed_iters=101,
+                            tile_rows=rows, block_sweeps=block, check_every=1 << 20,
+                            fold_window=1 << 30)
+        except L.HypError as e:  # these tiles do not fit
+            say("  R", rows, "B", block, "skipped:", e)
+            continue
+        runs += 1
+        if ref is None:
+            ref = g
+            o = PR.project(sc.flags, u, v, sc.dx, method="jacobi", fixed_iters=101)
+            assert rel_l2(g["p"], o["p"], o["plan"].fluid) <= 1e-5
+            continue
+        assert np.array_equal(g["p"], ref["p"]) and np.array_equal(g["u"], ref["u"])
+        assert np.array_equal(g["v"], ref["v"])
+    assert runs >= 3
+
+
 @pytest.mark.parametrize("n,rows", [(512, 0), (512, 12), (256, 16), (200, 24)])
 def test_jacobi_block_length_does_not_change_the_iterates(n, rows):
     """Sweeps between halo exchanges (halo B + 1 recomputed per tile) only
