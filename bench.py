@@ -267,7 +267,9 @@ def main():
                 "bytes_per_cell_sweep": BYTES_PER_CELL_SWEEP,
                 "regime": ("synchronisation latency: the 1 MB state stays in registers between tile "
                            "exchanges, so achieved counts algorithmic bytes (13 B/cell/sweep), not DRAM "
-                           "traffic; the DRAM-resident streaming kernel is measured at 8192^2 separately"),
+                           "traffic, and can exceed the HBM peak (frac > 1); dram_gbs is the counted "
+                           "DRAM traffic; the DRAM-resident streaming kernel is measured at 8192^2 "
+                           "separately"),
                 "dram_gbs": None if dram is None else round(dram, 1),
                 "dram_frac": None if dram is None else round(dram / HBM_PEAK_GBS, 4)}
 

@@ -46,6 +46,7 @@ WsLayout make_layout(int nx, int ny, const NetShape& net) {
   L.scalars = take(sizeof(Scalars));
   L.sync = take(kSyncBytes);
   L.partial = take(sizeof(double) * 6 * kMaxCoopBlocks);
+  L.lagflag = take(sizeof(unsigned) * 2 * kMaxCoopBlocks);
   // block partials: two per cell-grid block, or one per face-grid block (CFL)
   const size_t nfaces = (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx;
   const size_t nb_faces = (nfaces + kStreamBlock - 1) / kStreamBlock;
@@ -127,6 +128,7 @@ Ws ws_view(void* base, const WsLayout& L) {
   w.sc = (Scalars*)(b + L.scalars);
   w.sync = (unsigned*)(b + L.sync);
   w.partial = (double*)(b + L.partial);
+  w.lagflag = (unsigned*)(b + L.lagflag);
   w.blockpart = (double*)(b + L.blockpart);
   w.blockpart_n = L.blockpart_n;
   w.cell = (uint8_t*)(b + L.cell);

@@ -56,7 +56,7 @@ constexpr int kWgBlocks = 128;  // pixel-chunk blocks of the weight-gradient red
 // Byte offsets into the caller's workspace (all 256-byte aligned).
 struct WsLayout {
   size_t cell = 0, d = 0, phi = 0, phi_acc = 0, exch = 0, exch64 = 0, blockpart = 0, partial = 0,
-         scalars = 0, reach = 0, pcg = 0, adv = 0, sync = 0, coef = 0;
+         lagflag = 0, scalars = 0, reach = 0, pcg = 0, adv = 0, sync = 0, coef = 0;
   size_t ncell = 0;
   size_t cnn_in = 0, cnn_act0 = 0, cnn_act1 = 0, cnn_y = 0, cnn_t = 0, cnn_w = 0, cnn_cat = 0;
   size_t cnn_save = 0, bw_cells = 0, bw_t = 0, bw_x = 0, bw_a = 0, bw_b = 0, bw_part = 0;
@@ -83,6 +83,7 @@ struct Ws {
   double* blockpart;  // streaming-kernel block partials
   size_t blockpart_n; // capacity of blockpart in doubles
   double* partial;    // 6 x kMaxCoopBlocks cooperative partials
+  unsigned* lagflag;  // 2 x kMaxCoopBlocks tags of the Jacobi kernel's lagged E_1 partials
   Scalars* sc;
   unsigned* sync;     // grid barrier: counter at [0], generation flag at [32]
   uint64_t* reach;   // planner bit words: fluid, then linked (plan_bytes)

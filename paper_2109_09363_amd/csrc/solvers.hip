@@ -68,7 +68,10 @@ struct JacParams {
   float* v;
   uint64_t* exch64;     // 2 x nx*ny tagged halo words (steps between tests)
   float* exch;          // 2 x nx*ny halo planes (launches that test every step)
-  double* partial;      // 2 x kMaxCoopBlocks partial sums
+  double* partial;      // 4 x kMaxCoopBlocks partial sums (two parities each of the
+                        // tests and of the lagged tests)
+  unsigned* lagflag;    // 2 x kMaxCoopBlocks tags of the lagged partials
+  int lag;              // 1: tests between the first and the last are lagged (below)
   Scalars* sc;
   unsigned* sync;       // grid barrier
   const float* ce;      // variable density: beta of each cell's east face
@@ -196,12 +199,16 @@ __global__ __launch_bounds__(256, (R <= 8 && (VAR || TAGGED) ? 2 : 1)) void jaco
     band_exchange<R>(v, edge, q, wave, lane, *below, *above);
   };
   auto edges = [&](float* below, float* above) { edges_of(ph, below, above); };
-  auto finish = [&](int st, double E) {
+  // kf: the sweep count of the returned iterate; a lagged stop returns the
+  // iterate stored at its test, not the current one
+  auto finish = [&](int st, double E, int kf, bool store) {
+    if (store) {
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      if ((imask >> r) & 1u) p.phi[(size_t)(gy0 + r) * p.nx + gx] = ph[r];
+      for (int r = 0; r < R; ++r)
+        if ((imask >> r) & 1u) p.phi[(size_t)(gy0 + r) * p.nx + gx] = ph[r];
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-      p.sc->iters = k;
+      p.sc->iters = kf;
       p.sc->e1_solve = E;
       __hip_atomic_fetch_max(&p.sc->status, (int32_t)st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -236,9 +243,26 @@ __global__ __launch_bounds__(256, (R <= 8 && (VAR || TAGGED) ? 2 : 1)) void jaco
         st_agent(p.exch64 + g, (uint64_t)0);
         st_agent(p.exch64 + plane + g, (uint64_t)0);
       }
+    if (threadIdx.x == 0) {
+      st_agent(p.lagflag + blockIdx.x, 0u);
+      st_agent(p.lagflag + kMaxCoopBlocks + blockIdx.x, 0u);
+    }
     if (!barrier()) return;
   }
   auto tag_of = [&](unsigned step) { return (epoch << 20) | (step & 0xFFFFFu); };
+  // Lagged tests (tagged form, tests after the first and before max_iters
+  // that cannot fold): a tile publishes its partial at step jL with a tag
+  // word written after it and stores its interior as the candidate result,
+  // then goes on without the grid barrier; one step later every tile reads
+  // all partials (polling their tags), sums them in the same order and
+  // takes the same decision: stop with the stored iterate and its sweep
+  // count, or go on.  The host allows it only when tests are further apart
+  // (in steps) than a tile can run ahead of any other (the neighbour
+  // synchronisation bounds that by the tile grid's extent), so a partial is
+  // read before its slot (two parities) is written again.
+  bool pend = false;
+  int kL = 0;
+  unsigned jL = 0, nl = 0;
   for (;;) {
     // publish the interior of the state after j steps
     uint64_t* ex = p.exch64 + (size_t)(j & 1u) * plane;
@@ -253,10 +277,68 @@ __global__ __launch_bounds__(256, (R <= 8 && (VAR || TAGGED) ? 2 : 1)) void jaco
       for (int r = 0; r < R; ++r)
         if (((imask >> r) & 1u) && kk[r] > 0.f) st_agent(ex32 + (size_t)(gy0 + r) * p.nx + gx, ph[r]);
     }
-    const bool test = k == k0 || (p.fixed_iters > 0 ? k >= end : (k % p.check_every == 0 || k >= end));
+    // the decision of a lagged test, one step after it
+    if (TAGGED && pend) {
+      const unsigned want = tag_of(jL);
+      const size_t sl = (size_t)(nl & 1u) * kMaxCoopBlocks;
+      double a = 0.0;
+      int ok = 1;
+      const uint64_t t0 = (uint64_t)wall_clock64();
+      for (int i = threadIdx.x; i < G; i += blockDim.x) {
+        while (ld_agent(p.lagflag + sl + i) != want) {
+          if ((uint64_t)wall_clock64() - t0 > kSpinTicks) {
+            ok = 0;
+            break;
+          }
+        }
+        const double x = ld_agent(p.partial + 2 * kMaxCoopBlocks + sl + i);
+        a = p.einf ? fmax(a, x) : a + x;
+      }
+      if (!__syncthreads_and(ok)) {
+        if (threadIdx.x == 0) abort_solve(p.sc);
+        return;
+      }
+      const double tot = p.einf ? block_max(a, red) : block_sum(a, red);
+      const double EL = p.einf ? tot : (nF > 0 ? tot / nF : 0.0);
+      const int stL = decide(kL, EL, p.thr, p.max_iters, p.check_every, p.fixed_iters);
+      pend = false;
+      if (stL != -1) {
+        finish(stL, EL, kL, false);
+        return;
+      }
+    }
+    const bool at_test = k == k0 || (p.fixed_iters > 0 ? k >= end : (k % p.check_every == 0 || k >= end));
+    const bool lagged = TAGGED && p.lag && at_test && k != k0 && k < end &&
+                        !(p.fold_window > 0 && k - k_ref >= p.fold_window);
+    const bool test = at_test && !lagged;
     // E_1 of the current state: the interior and the ring around it are
     // valid, so the residual needs no fresh halo
     double* part = p.partial + (size_t)((t + 1) & 1u) * kMaxCoopBlocks;
+    if (lagged) {
+      float below, above;
+      edges(&below, &above);
+      double part_loc;
+      if constexpr (VAR)
+        part_loc = jac_resid_var_scaled<R>(ph, kk, be, bw, bn, bs, ww, below, above, p.omega,
+                                           p.inv_dx2, fmask, p.einf != 0);
+      else
+        part_loc = jac_resid_scaled<R>(ph, kk, ww, below, above, p.omega, p.inv_dx2, fmask,
+                                       p.einf != 0);
+      const double loc = p.einf ? block_max(part_loc, red) : block_sum(part_loc, red);
+      ++nl;
+      const size_t sl = (size_t)(nl & 1u) * kMaxCoopBlocks;
+      if (threadIdx.x == 0) {
+        st_agent(p.partial + 2 * kMaxCoopBlocks + sl + blockIdx.x, loc);
+        __builtin_amdgcn_s_waitcnt(0);  // the partial is visible before its tag
+        st_agent(p.lagflag + sl + blockIdx.x, tag_of(j));
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if ((imask >> r) & 1u) p.phi[(size_t)(gy0 + r) * p.nx + gx] = ph[r];
+      pend = true;
+      kL = k;
+      jL = j;
+    }
     if (test) {
       float below, above;
       edges(&below, &above);
@@ -348,7 +430,7 @@ __global__ __launch_bounds__(256, (R <= 8 && (VAR || TAGGED) ? 2 : 1)) void jaco
       E_ref = E;
     }
     if (st != -1) {
-      finish(st, E);
+      finish(st, E, k, true);
       return;
     }
     if (fold) {
@@ -499,6 +581,7 @@ struct PcgParams {
   float* v;
   uint64_t* exch64;     // 2 x nx*ny tagged halo words (u, x)
   double* partial;      // 2 x 3 x kMaxCoopBlocks
+  unsigned* lagflag;    // cleared with the halo words (the Jacobi kernel's lagged tags)
   Scalars* sc;
   unsigned* sync;
   const float* ce;      // variable density: beta of each cell's east face
@@ -661,6 +744,10 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
         st_agent(uex + g, (uint64_t)0);
         st_agent(xex + g, (uint64_t)0);
       }
+    if (threadIdx.x == 0) {  // the Jacobi kernel's lagged-test tags, too
+      st_agent(p.lagflag + blockIdx.x, 0u);
+      st_agent(p.lagflag + kMaxCoopBlocks + blockIdx.x, 0u);
+    }
     if (!barrier()) return;
   }
   unsigned nex = 0;
@@ -1030,6 +1117,14 @@ hipError_t run_jacobi(const Device& dev, int nx, int ny, double dx, double thr, 
   p.ckpt = phi_ckpt;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.phi_acc = w.phi_acc; p.u = u; p.v = v;
   p.exch64 = w.exch64; p.exch = w.exch; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
+  p.lagflag = w.lagflag;
+  {
+    // lagged tests: tagged form, and tests further apart in steps than the
+    // tile grid's extent (the furthest one tile can run ahead of another)
+    const bool tagged = p.nbsync && !(fixed_iters <= 0 && check_every <= H - 1);
+    const int steps = (check_every + H - 2) / (H - 1);
+    p.lag = (tagged && fixed_iters <= 0 && steps >= (ntx > nty ? ntx : nty) + 2) ? 1 : 0;
+  }
   p.ce = var ? w.coef_e : nullptr;
   p.cn = var ? w.coef_n : nullptr;
   const int G = ntx * nty;
@@ -1065,7 +1160,7 @@ hipError_t run_pcg(const Device& dev, int nx, int ny, double dx, double thr, int
   p.thr = thr;
   p.max_iters = max_iters; p.check_every = check_every; p.fixed_iters = fixed_iters;
   p.cell = w.cell; p.d = w.d; p.phi = w.phi; p.phi_acc = w.phi_acc; p.u = u; p.v = v;
-  p.exch64 = w.exch64; p.partial = w.partial; p.sc = w.sc; p.sync = w.sync;
+  p.exch64 = w.exch64; p.partial = w.partial; p.lagflag = w.lagflag; p.sc = w.sc; p.sync = w.sync;
   p.ce = var ? w.coef_e : nullptr;
   p.cn = var ? w.coef_n : nullptr;
   const int G = ntx * nty;
