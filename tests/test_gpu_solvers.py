@@ -325,6 +325,33 @@ def test_project_call_plans_only_when_the_flags_change():
     assert outs[0] == outs[1]
 
 
+@pytest.mark.parametrize("k_stop", [768, 2304])
+def test_lagged_test_stop_equals_the_iterate_at_its_count(k_stop):
+    """Jacobi at 512^2 with E_1 tested every 768 sweeps: the tests after the
+    first are lagged (the tiles go on and decide one step later from tagged
+    partials, the candidate iterate stored at the test).  A threshold placed
+    between E_1 at k_stop - 768 and at k_stop stops at k_stop, after a
+    lagged "go on" for 2304, with the iterate, faces and E_1 of a fixed run
+    to k_stop, bit for bit."""
+    say("lagged stop", k_stop)
+    sc, u, v = plume_state(512, 3, 2)
+    runs = {}
+    for k in {k_stop - 768, k_stop} - {0}:
+        runs[k] = gpu_project(sc.flags, u, v, sc.dx, thr=0.0, method="jacobi", fixed_iters=k,
+                              fold_window=1 << 30)
+    e_hi = 2.0 * runs[k_stop]["res"].e1_final if k_stop == 768 else runs[k_stop - 768]["res"].e1_final
+    e_lo = runs[k_stop]["res"].e1_final
+    thr = float(np.sqrt(e_hi * e_lo))
+    g = gpu_project(sc.flags, u, v, sc.dx, thr=thr, method="jacobi", check_every=768,
+                    fold_window=1 << 30, max_iters=100000)
+    say("  thr", thr, "iters", g["res"].iters, "status", g["res"].status)
+    assert g["res"].status == 0 and g["res"].iters == k_stop
+    f = runs[k_stop]
+    assert np.array_equal(g["p"], f["p"]) and np.array_equal(g["u"], f["u"])
+    assert np.array_equal(g["v"], f["v"])
+    assert g["res"].e1_final == f["res"].e1_final
+
+
 @pytest.mark.parametrize("nx,ny", [(60, 50), (64, 64), (65, 130), (200, 97), (512, 512)])
 def test_jacobi_tile_shape_does_not_change_the_iterates(nx, ny):
     """Tiles of R rows per wave and B sweeps per exchange, the first and
