@@ -664,13 +664,16 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
   __shared__ double red3[12];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   band_edges_clear(edge, wave, lane);
+  // tiles as in jacobi_reg with a one-cell halo: tile bx, by starts at
+  // column 62 bx and row (4R - 2) by, no halo on the grid's sides
   const int TW = 62, TH = 4 * R - 2;
   const int G = gridDim.x;
   const int bx = blockIdx.x % p.ntx, by = blockIdx.x / p.ntx;
-  const int gx = bx * TW - 1 + lane;
-  const int gy0 = by * TH - 1 + wave * R;
-  const bool col_in = gx >= 0 && gx < p.nx;
-  const bool lane_int = lane >= 1 && lane < 1 + TW && col_in;
+  const int gx = bx * TW + lane;
+  const int gy0 = by * TH + wave * R;
+  const bool col_in = gx < p.nx;
+  const bool lane_int = lane >= (bx == 0 ? 0 : 1) && lane < (bx == p.ntx - 1 ? 64 : 63) && col_in;
+  const int row_lo = by == 0 ? 0 : 1, row_hi = by == p.nty - 1 ? 4 * R : 4 * R - 1;
   const int nF = p.sc->nF;
   if (p.sc->status >= 0) return;
   unsigned dmask = 0, imask = 0;
@@ -709,7 +712,7 @@ __global__ __launch_bounds__(256) void pcg_reg(PcgParams p) {
     } else {
       x[i] = 0.f;
     }
-    if (((dmask >> i) & 1u) && lane_int && er >= 1 && er < 1 + TH) imask |= 1u << i;
+    if (((dmask >> i) & 1u) && lane_int && er >= row_lo && er < row_hi) imask |= 1u << i;
     kk[i] = k_; bb[i] = b_;
     r[i] = 0.f; u[i] = 0.f; w[i] = 0.f; pp[i] = 0.f; ss[i] = 0.f;
   }
@@ -1060,10 +1063,10 @@ static bool jacobi_geom(const Device& dev, int nx, int ny, int check_every, int 
 
 // PCG: halo 1, tile interior 62 x (4R - 2), the smallest R that fits.
 static bool pcg_geom(const Device& dev, int nx, int ny, int* R, int* ntx, int* nty) {
-  const int tx = (nx + 61) / 62;
+  const int tx = 1 + (nx > 64 ? (nx - 64 + 61) / 62 : 0);
   const int cap = dev.cu < kMaxCoopBlocks ? dev.cu : kMaxCoopBlocks;
   for (int r : kRows) {
-    const int ty = (ny + 4 * r - 3) / (4 * r - 2);
+    const int ty = 1 + (ny > 4 * r ? (ny - 4 * r + 4 * r - 3) / (4 * r - 2) : 0);
     if (tx * ty <= cap) {
       *R = r; *ntx = tx; *nty = ty;
       return true;
